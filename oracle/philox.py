@@ -1,0 +1,137 @@
+"""Philox4x32-10 and the protocol's random draws (test infrastructure only).
+
+The paper only says that P0 and P1 "generate ... using seed_01" (Alg. 7 steps
+1, 6, 7), that P2's response is a fresh sharing (step 10) and that the Beaver
+triple comes from seed_02 / seed_12 (Alg. 8, preprocessing).  It fixes no
+generator.  This module is the build's definition, written from the
+published description of Philox4x32 (Salmon, Moraes, Dror, Shaw, "Parallel
+Random Numbers: As Easy as 1, 2, 3", SC'11):
+
+* state: four 32-bit counter words (c0, c1, c2, c3), key (k0, k1);
+* one round: (hi0, lo0) = M0 * c0, (hi1, lo1) = M1 * c2 (full 64-bit
+  products), new state = (hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0);
+* ten rounds; before every round after the first the key is bumped by the
+  Weyl constants (k0 += W0, k1 += W1 mod 2^32).
+
+Counter layout, for element index g (< 2^48), a tag, and a block index b:
+  c0 = g mod 2^32,  c1 = (g >> 32) | tag << 16 | b << 24,
+  c2 = nonce mod 2^32,  c3 = nonce >> 32,   key = (seed mod 2^32, seed >> 32).
+Every draw is therefore a pure function of (seed, nonce, g, tag, b): the same
+element gets the same randomness alone, in a batch, or under any schedule.
+
+Draws (all multiply-shift, no rejection; bias at most p / 2^32, or p / 2^64
+for p > 2^32):
+  TAG_SHUFFLE (seed_01): word j%4 of block j//4 is the sort key of position
+    j: key_j = (word & ~63) | j.  Slot s of the shuffled array receives the
+    position with the s-th smallest key.  t = bit 0 of word 0 of block 0
+    (disjoint from the key bits of position 0).
+  TAG_MASK (seed_01), p < 2^32: block s//2 words 2(s%2), 2(s%2)+1 are
+    (R, Z) of slot s;  r_s = 1 + floor(R (p-1) / 2^32) in Z_p^*,
+    z_s = floor(Z p / 2^32) in Z_p.   p > 2^32: block s gives 64-bit
+    R = w0 | w1 << 32, Z = w2 | w3 << 32 and the same formulas over 2^64.
+  TAG_RESP (seed_02): rho = (w0 | w1 << 32) mod 2^l of block 0.
+  TAG_BEAVER: seed_02 block 0 -> [a]_0 = w0|w1<<32, [b]_0 = w2|w3<<32;
+    seed_02 block 1 -> [c]_0 = w0|w1<<32;  seed_12 block 0 -> [a]_1, [b]_1.
+"""
+
+import numpy as np
+
+from .ring import U64, red
+
+M0 = 0xD2511F53
+M1 = 0xCD9E8D57
+W0 = 0x9E3779B9
+W1 = 0xBB67AE85
+
+TAG_SHUFFLE = 1
+TAG_MASK = 2
+TAG_RESP = 3
+TAG_BEAVER = 4
+
+_M32 = U64(0xFFFFFFFF)
+
+
+def philox4x32_10(c0, c1, c2, c3, key0: int, key1: int):
+    """Ten Philox4x32 rounds on uint64 arrays that hold 32-bit words."""
+    c0, c1, c2, c3 = (np.asarray(c, dtype=U64) & _M32 for c in (c0, c1, c2, c3))
+    k0, k1 = key0 & 0xFFFFFFFF, key1 & 0xFFFFFFFF
+    for rnd in range(10):
+        if rnd:
+            k0 = (k0 + W0) & 0xFFFFFFFF
+            k1 = (k1 + W1) & 0xFFFFFFFF
+        p0 = c0 * U64(M0)          # < 2^64: exact
+        p1 = c2 * U64(M1)
+        hi0, lo0 = p0 >> U64(32), p0 & _M32
+        hi1, lo1 = p1 >> U64(32), p1 & _M32
+        c0, c1, c2, c3 = hi1 ^ c1 ^ U64(k0), lo1, hi0 ^ c3 ^ U64(k1), lo0
+    return c0, c1, c2, c3
+
+
+def block(seed: int, nonce: int, g, tag: int, b: int):
+    """The four words of block b of stream `tag` for element indices g."""
+    g = np.asarray(g, dtype=U64)
+    c0 = g & _M32
+    c1 = ((g >> U64(32)) & U64(0xFFFF)) | U64(tag << 16) | U64(b << 24)
+    c2 = np.full_like(g, nonce & 0xFFFFFFFF)
+    c3 = np.full_like(g, (nonce >> 32) & 0xFFFFFFFF)
+    return philox4x32_10(c0, c1, c2, c3, seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+
+
+def _words(seed, nonce, g, tag, count):
+    """The first `count` words of a stream, shape (len(g), count)."""
+    out = []
+    for b in range((count + 3) // 4):
+        out.extend(block(seed, nonce, g, tag, b))
+    return np.stack(out[:count], axis=1)
+
+
+def draw_shuffle(seed01: int, nonce: int, g, n: int):
+    """t (uint64 0/1 per element) and sigma (N x n): sigma[:, s] is the window
+    position placed in slot s by the shuffle of Alg. 7 step 6."""
+    w = _words(seed01, nonce, g, TAG_SHUFFLE, n)
+    t = w[:, 0] & U64(1)
+    keys = (w & U64(0xFFFFFFC0)) | np.arange(n, dtype=U64)[None, :]
+    sigma = np.argsort(keys, axis=1, kind="stable").astype(np.int64)
+    return t, sigma
+
+
+def draw_masks(seed01: int, nonce: int, g, n: int, p: int):
+    """r (in Z_p^*) and z (in Z_p), shape (N, n), indexed by slot."""
+    g = np.asarray(g, dtype=U64)
+    if p < (1 << 32):
+        w = _words(seed01, nonce, g, TAG_MASK, 2 * n)
+        R, Z = w[:, 0::2], w[:, 1::2]
+        r = U64(1) + ((R * U64(p - 1)) >> U64(32))
+        z = (Z * U64(p)) >> U64(32)
+        return r, z
+    r = np.empty((g.size, n), dtype=object)
+    z = np.empty((g.size, n), dtype=object)
+    for s in range(n):
+        b = block(seed01, nonce, g, TAG_MASK, s)
+        R = b[0].astype(object) | (b[1].astype(object) << 32)
+        Z = b[2].astype(object) | (b[3].astype(object) << 32)
+        r[:, s] = 1 + ((R * (p - 1)) >> 64)
+        z[:, s] = (Z * p) >> 64
+    return r, z
+
+
+def _u64_pair(lo, hi):
+    return lo | (hi << U64(32))
+
+
+def draw_rho(seed02: int, nonce: int, g, ell: int):
+    b = block(seed02, nonce, g, TAG_RESP, 0)
+    return red(_u64_pair(b[0], b[1]), ell)
+
+
+def draw_beaver(seed02: int, seed12: int, nonce: int, g, ell: int):
+    """([a]_0, [b]_0, [c]_0) from seed_02 and ([a]_1, [b]_1) from seed_12."""
+    b0 = block(seed02, nonce, g, TAG_BEAVER, 0)
+    b1 = block(seed02, nonce, g, TAG_BEAVER, 1)
+    b2 = block(seed12, nonce, g, TAG_BEAVER, 0)
+    a0 = red(_u64_pair(b0[0], b0[1]), ell)
+    bb0 = red(_u64_pair(b0[2], b0[3]), ell)
+    c0 = red(_u64_pair(b1[0], b1[1]), ell)
+    a1 = red(_u64_pair(b2[0], b2[1]), ell)
+    bb1 = red(_u64_pair(b2[2], b2[3]), ell)
+    return a0, bb0, c0, a1, bb1

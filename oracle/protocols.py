@@ -1,0 +1,223 @@
+"""The paper's share-local protocols, written out plainly (test infrastructure only).
+
+Shares are NumPy uint64 arrays with canonical values.  Party P_j holds
+[x]_j; all three parties are evaluated here side by side, and each step is
+labelled with the party that performs it.
+
+Readings of the paper taken here (each is listed in the design doc):
+* Alg. 1 / Alg. 4 / Alg. 5, P1's line: "2^l - [x]_1" is reduced mod 2^l
+  before the cut, i.e. P1 cuts -[x]_1 mod 2^l (the worked examples of Sec. 1
+  and Sec. 5.1 write cut(-[x]_1, .)).
+* Alg. 5 input: k1 low bits and k2 high bits are dropped (the worked example
+  of Sec. 5.1 with k1 = 4, k2 = 1 fixes this; the algorithm's input line has
+  the two words swapped).
+* Alg. 7 step 3 with key bits (Sec. 6.1): window i is trc(x, k_lo+i,
+  l-l_x-k_lo-i), i = 0..l_x.
+* Alg. 7 step 4: the constant -1 is added by P0 only; u_{l_x+1} := 0.
+* Alg. 7 step 6-8: r_i and z_i are indexed by the slot after the shuffle;
+  the reshare is w0 += z, w1 -= z with z uniform in Z_p from seed_01.
+* Alg. 7 step 10: P2 shares its bit as (rho, D' - rho) with rho from seed_02.
+* Alg. 7 step 11 and Alg. 8 step 5: P0 adds the public constants (t, de).
+* Alg. 8: [c]_1 is sent once, in preprocessing; the d-shares are exchanged
+  between P0 and P1.
+"""
+
+import numpy as np
+
+from . import philox
+from .params import check_drelu
+from .ring import U64, add, cut, mul, neg, red, sub
+
+
+# ---------------------------------------------------------------- truncation
+
+
+def trunc_prob(x0, x1, ell: int, k: int):
+    """Alg. 1 (SecureML truncation): outputs in Z_{2^l}.
+
+    P0: cut([x]_0, k) mod 2^l.   P1: 2^l - cut(2^l - [x]_1, k) mod 2^l.
+    """
+    y0 = red(cut(x0, k, 0, ell), ell)
+    y1 = neg(cut(neg(x1, ell), k, 0, ell), ell)
+    return y0, y1
+
+
+def trunc_det(x0, x1, ell: int, k1: int, k2: int = 0):
+    """Alg. 4 (k2 = 0) and Alg. 5: outputs in Z_{2^(l-k1-k2)}.
+
+    P0: cut([x]_0, k1, k2) mod 2^(l-k1-k2).
+    P1: 2^l - cut(2^l - [x]_1, k1, k2) mod 2^(l-k1-k2).
+    """
+    m = ell - k1 - k2
+    if not (0 <= k1 and 0 <= k2 and m >= 1):
+        raise ValueError("need k1, k2 >= 0 and k1 + k2 < l")
+    y0 = cut(x0, k1, k2, ell)
+    y1 = neg(cut(neg(x1, ell), k1, k2, ell), m)
+    return y0, y1
+
+
+# -------------------------------------------------------------- modulo switch
+
+
+def mod_switch(a0, a1, ell_in: int, p: int):
+    """Alg. 6: shares in Z_{2^l'} -> shares in Z_p, log2 p = l' + 1.
+
+    P0: 2^l' mod p if [x]_0 = 0, else [x]_0 mod p.
+    P1: p + [x]_1 - 2^l' mod p.
+    Works elementwise on arrays of any shape.
+    """
+    a0 = red(a0, ell_in).astype(object)
+    a1 = red(a1, ell_in).astype(object)
+    two = pow(2, ell_in, p)
+    s0 = np.where(a0 == 0, two, a0 % p)
+    s1 = (p + a1 - (1 << ell_in)) % p
+    if p < (1 << 63):
+        return s0.astype(U64), s1.astype(U64)
+    return s0, s1
+
+
+def _mulmod(a, b, p):
+    if p < (1 << 32):
+        return (np.asarray(a, dtype=U64) * np.asarray(b, dtype=U64)) % U64(p)
+    return (np.asarray(a, dtype=object) * np.asarray(b, dtype=object)) % p
+
+
+# -------------------------------------------------------------------- DReLU
+
+
+def drelu_round1(x0, x1, ell, lx, k_lo, p, t, sigma, r, z):
+    """Alg. 7 steps 1-8 for P0 and P1: the messages [w]_0, [w]_1 (N x n,
+    in slot order) that they send to P2."""
+    check_drelu(ell, lx, k_lo, p)
+    n = lx + 1
+    x0, x1 = red(x0, ell), red(x1, ell)
+    N = x0.size
+    flip = np.asarray(t, dtype=U64).astype(bool)
+    # steps 1-2 (P0, P1): [x] := (-1)^t [x]
+    a0 = np.where(flip, neg(x0, ell), x0)
+    a1 = np.where(flip, neg(x1, ell), x1)
+    # step 3 (P0, P1): u_i = trc(x, k_lo+i, l-l_x-k_lo-i), i = 0..l_x
+    u0 = np.zeros((N, n + 1), dtype=U64)      # column n is u_{l_x+1} := 0
+    u1 = np.zeros((N, n + 1), dtype=U64)
+    for i in range(n):
+        k1 = k_lo + i
+        u0[:, i], u1[:, i] = trunc_det(a0, a1, ell, k1, ell - lx - k1)
+    # step 4: v_i = u_i + u_{i+1} - 1 (P0 subtracts the 1), mod 2^l_x
+    v0 = red(u0[:, :n] + u0[:, 1:] - U64(1), lx)
+    v1 = red(u1[:, :n] + u1[:, 1:], lx)
+    # step 5: Alg. 6 on every v_i
+    s0, s1 = mod_switch(v0, v1, lx, p)
+    # step 6: shuffle with seed_01; slot j receives position sigma[:, j]
+    s0 = np.take_along_axis(s0, sigma, axis=1)
+    s1 = np.take_along_axis(s1, sigma, axis=1)
+    # step 7: mask with r_j in Z_p^* (same r for both parties)
+    w0 = _mulmod(s0, r, p)
+    w1 = _mulmod(s1, r, p)
+    # step 8: reshare with z_j and send to P2
+    if p < (1 << 32):
+        z = np.asarray(z, dtype=U64)
+        w0 = (w0 + z) % U64(p)
+        w1 = (w1 + (U64(p) - z)) % U64(p)
+    else:
+        w0 = (w0 + z) % p
+        w1 = (w1 - z) % p
+    return w0, w1
+
+
+def p2_zero_test(w0, w1, p):
+    """Alg. 7 step 9 (P2): reconstruct w_j and set D' = 1 iff some w_j = 0."""
+    if p < (1 << 32):
+        w = (np.asarray(w0, dtype=U64) + np.asarray(w1, dtype=U64)) % U64(p)
+    else:
+        w = (np.asarray(w0, dtype=object) + np.asarray(w1, dtype=object)) % p
+    return np.any(w == 0, axis=1).astype(U64)
+
+
+def drelu_core(x0, x1, ell, lx, k_lo, p, t, sigma, r, z, rho):
+    """Alg. 7 with the random values passed in.  Returns (y0, y1, w0, w1)."""
+    w0, w1 = drelu_round1(x0, x1, ell, lx, k_lo, p, t, sigma, r, z)
+    dp = p2_zero_test(w0, w1, p)
+    # step 10 (P2): respond with a fresh sharing of D' in Z_{2^l}
+    d0 = red(rho, ell)
+    d1 = sub(dp, d0, ell)
+    # step 11 (P0, P1): DReLU = D' xor t = t + (1-2t) D'
+    flip = np.asarray(t, dtype=U64).astype(bool)
+    y0 = np.where(flip, sub(U64(1), d0, ell), d0)
+    y1 = np.where(flip, neg(d1, ell), d1)
+    return y0, y1, w0, w1
+
+
+def relu_core(x0, x1, ell, lx, k_lo, p, t, sigma, r, z, a0, b0, c0, a1, b1):
+    """Alg. 8 (UBL ReLU) with the random values passed in.
+
+    Returns (y0, y1, w0, w1)."""
+    x0, x1 = red(x0, ell), red(x1, ell)
+    # preprocessing (P2): [c]_1 = ([a]_0 + [a]_1)([b]_0 + [b]_1) - [c]_0
+    c1 = sub(mul(add(a0, a1, ell), add(b0, b1, ell), ell), c0, ell)
+    # step 1: Alg. 7 steps 1-8; step 2 (P2): the zero test
+    w0, w1 = drelu_round1(x0, x1, ell, lx, k_lo, p, t, sigma, r, z)
+    dp = p2_zero_test(w0, w1, p)
+    # step 3 (P2): e = D' - b
+    e = sub(dp, add(b0, b1, ell), ell)
+    # step 4 (P0, P1): d = x - a, reconstructed from both parties' shares
+    d = add(sub(x0, a0, ell), sub(x1, a1, ell), ell)
+    # step 5: [x D'] = de + d[b] + e[a] + [c];  ReLU = t[x] + (1-2t)[x D']
+    m0 = add(add(add(mul(d, e, ell), mul(d, b0, ell), ell), mul(e, a0, ell), ell), c0, ell)
+    m1 = add(add(mul(d, b1, ell), mul(e, a1, ell), ell), c1, ell)
+    flip = np.asarray(t, dtype=U64).astype(bool)
+    y0 = np.where(flip, sub(x0, m0, ell), m0)
+    y1 = np.where(flip, sub(x1, m1, ell), m1)
+    return y0, y1, w0, w1
+
+
+def _indices(n_elems, elem_base, g):
+    if g is not None:
+        return np.asarray(g, dtype=U64)
+    return U64(elem_base) + np.arange(n_elems, dtype=U64)
+
+
+def drelu(x0, x1, ell, lx, k_lo, p, seeds, nonce, elem_base=0, g=None):
+    """Alg. 7 with randomness drawn from the seeds (see ``philox``).
+
+    seeds = (seed_01, seed_02, seed_12); g = global element indices (default
+    elem_base + arange(N)).  Returns (y0, y1, w0, w1)."""
+    seed01, seed02, _ = seeds
+    g = _indices(np.asarray(x0).size, elem_base, g)
+    n = lx + 1
+    t, sigma = philox.draw_shuffle(seed01, nonce, g, n)
+    r, z = philox.draw_masks(seed01, nonce, g, n, p)
+    rho = philox.draw_rho(seed02, nonce, g, ell)
+    return drelu_core(x0, x1, ell, lx, k_lo, p, t, sigma, r, z, rho)
+
+
+def relu(x0, x1, ell, lx, k_lo, p, seeds, nonce, elem_base=0, g=None):
+    """Alg. 8 with randomness drawn from the seeds.  Returns (y0, y1, w0, w1)."""
+    seed01, seed02, seed12 = seeds
+    g = _indices(np.asarray(x0).size, elem_base, g)
+    n = lx + 1
+    t, sigma = philox.draw_shuffle(seed01, nonce, g, n)
+    r, z = philox.draw_masks(seed01, nonce, g, n, p)
+    a0, b0, c0, a1, b1 = philox.draw_beaver(seed02, seed12, nonce, g, ell)
+    return relu_core(x0, x1, ell, lx, k_lo, p, t, sigma, r, z, a0, b0, c0, a1, b1)
+
+
+# ------------------------------------------------------ message accounting
+
+LINKS = ("P0->P2", "P1->P2", "P2->P0", "P2->P1", "P0->P1", "P1->P0")
+
+
+def msg_bits(op: str, ell: int, lx: int, p: int):
+    """Theoretical bits per element on each link, and the online rounds.
+
+    Round 1: each of P0, P1 sends n = l_x + 1 values of Z_p, i.e.
+    (l_x + 1) * ceil(log2 p) = (l_x + 1)^2 bits (Tab. 1, Sec. 5.4).
+    DReLU round 2: one Z_{2^l} share to each of P0, P1.
+    ReLU: e to P0 and P1, [c]_1 to P1 (preprocessing), d-shares both ways
+    between P0 and P1 (concurrent with round 1, so still 2 rounds).
+    """
+    wbits = (lx + 1) * p.bit_length()
+    if op == "drelu":
+        return [wbits, wbits, ell, ell, 0, 0], 2
+    if op == "relu":
+        return [wbits, wbits, ell, 2 * ell, ell, ell], 2
+    raise ValueError(op)
