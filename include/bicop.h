@@ -1,0 +1,193 @@
+/*
+ * bicop.h -- C ABI of the Bicoptor 2.0 share-local DReLU/ReLU hot path on
+ * AMD MI355X (gfx950).  Implemented by libbicop.so.
+ *
+ * Three parties are simulated on one GPU.  P0 holds share [x]_0, P1 holds
+ * [x]_1, P2 is the helper.  Every call takes both share-holders' arrays;
+ * P2's view exists only inside the library.  Round-1 messages live in
+ * registers and are counted in bytes (bc_msg_account).  A caller-provided
+ * capture buffer can materialise them for inspection.
+ *
+ * Conventions for every entry point below:
+ *  - Pointers named x*, y*, capture and out are DEVICE pointers owned by the
+ *    caller.  None of these calls allocates or frees device memory, and
+ *    none retains a pointer after it returns.
+ *  - Storage width follows the ring.  An element of Z_{2^l} is a uint32_t
+ *    when l <= 32, else a uint64_t.  An element of Z_p is a uint32_t when
+ *    p < 2^32, else a uint64_t.  Inputs are read modulo 2^l, so bits above
+ *    l are ignored.  Outputs are canonical: each value is < the modulus.
+ *  - Arrays are dense, element i at index i.  Every pointer must be aligned
+ *    to its element size.
+ *  - y may equal x (in place).  Partial overlap is not allowed.
+ *  - Calls are asynchronous.  They validate arguments on the host, enqueue
+ *    one kernel on `stream` (a hipStream_t; NULL is the null stream) and
+ *    return.  n == 0 enqueues nothing and returns BC_OK.
+ *  - Calls are stateless and thread-safe.  No C++ exception crosses the ABI.
+ *  - Element indices: element i of a call has global index elem_base + i.
+ *    It must be < 2^48.  All randomness of an element is a pure function of
+ *    (seeds, nonce, global index).  The same element therefore gets the same
+ *    result alone, inside a batch, or under any launch configuration.
+ */
+#ifndef BICOP_H
+#define BICOP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ error codes */
+#define BC_OK              0
+#define BC_ERR_NULL       -1  /* a required pointer is NULL                      */
+#define BC_ERR_RING       -2  /* l outside [1, 64], or k1 + k2 >= l              */
+#define BC_ERR_WINDOW     -3  /* l_x outside [1, 32], or k_lo + 2 l_x > l        */
+#define BC_ERR_PRIME      -4  /* p not prime, or p outside (2^l', 2^(l'+1))      */
+#define BC_ERR_ALIGN      -5  /* a pointer is not aligned to its element size    */
+#define BC_ERR_HIP        -6  /* a HIP call failed; bc_last_error() has detail   */
+#define BC_ERR_WORKSPACE  -7  /* workspace / plan buffer too small               */
+#define BC_ERR_ARG        -8  /* other invalid argument (op, n, index range)     */
+
+#define BC_OP_DRELU 0u
+#define BC_OP_RELU  1u
+
+/* DReLU/ReLU setting (Alg. 7 "Setting" plus the key-bit window of Sec. 6.1).
+ *   ell  : ring bit length l, shares in Z_{2^l}, 1..64
+ *   lx   : window width l_x, 1..32.  The protocol looks at n = l_x + 1
+ *          windows of l_x bits.
+ *   k_lo : low bits dropped below the key-bit window.  Window i (0..l_x) is
+ *          the deterministic truncation trc(x, k_lo+i, l-l_x-k_lo-i)
+ *          (Alg. 5).  Requires k_lo + 2 l_x <= l.
+ *   p    : prime of the modulo switch (Alg. 6), 2^l_x < p < 2^(l_x+1).
+ *          0 selects the largest prime below 2^(l_x+1) (bc_default_prime). */
+typedef struct {
+    uint32_t ell;
+    uint32_t lx;
+    uint32_t k_lo;
+    uint32_t reserved;   /* must be 0 */
+    uint64_t p;
+} bc_drelu_params;
+
+/* Pre-shared seeds (Sec. 2.1): seed01 of P0/P1, seed02 of P0/P2, seed12 of
+ * P1/P2.  nonce separates calls that reuse the seeds; it is per call/job. */
+typedef struct {
+    uint64_t seed01;
+    uint64_t seed02;
+    uint64_t seed12;
+    uint64_t nonce;
+} bc_seeds;
+
+/* Links, in this order: P0->P2, P1->P2, P2->P0, P2->P1, P0->P1, P1->P0. */
+#define BC_NLINKS 6
+typedef struct {
+    uint64_t bits[BC_NLINKS];          /* theoretical bits for the whole call  */
+    uint64_t stored_bytes[BC_NLINKS];  /* bytes the values occupy in storage   */
+    uint32_t rounds;                   /* online communication rounds          */
+    uint32_t reserved;
+} bc_msg_acct;
+
+/* ----------------------------------------------------------- diagnostics */
+
+/* Library version string (static storage). */
+const char* bc_version(void);
+
+/* Text of an error code (static storage). */
+const char* bc_strerror(int code);
+
+/* Detail of the last error raised in the calling thread (thread-local
+ * storage, valid until the next call from that thread). */
+const char* bc_last_error(void);
+
+/* Largest prime below 2^(lx+1), for lx in [1, 32]; 0 otherwise.  This is
+ * the reading of "a prime whose bit length is l_x + 1" (notation table). */
+uint64_t bc_default_prime(uint32_t lx);
+
+/* Validate a DReLU/ReLU setting.  If `resolved` is not NULL it receives
+ * the setting with p filled in.  Returns BC_OK or the error code the
+ * compute calls would return.  Host only. */
+int bc_check_params(const bc_drelu_params* prm, bc_drelu_params* resolved);
+
+/* Message accounting for one call of `op` (BC_OP_DRELU / BC_OP_RELU) on n
+ * elements.  Round 1: each of P0, P1 sends l_x + 1 values of Z_p, i.e.
+ * (l_x+1)^2 bits per element (Tab. 1, Sec. 5.4 step 8).  DReLU round 2: one
+ * Z_{2^l} share to each of P0 and P1 (step 10).  ReLU (Alg. 8): e to P0 and
+ * P1, [c]_1 to P1 (preprocessing), d-shares between P0 and P1.  Host only. */
+int bc_msg_account(uint32_t op, const bc_drelu_params* prm, uint64_t n, bc_msg_acct* acct);
+
+/* Raw Philox4x32-10 blocks, for checking the generator.  Writes
+ * out[(i * nblocks + b) * 4 + w], the word w of block b of stream `tag` for
+ * the element with global index elem_base + i, under key `seed` and
+ * `nonce`.  The counter layout is the one used by the protocol kernels:
+ * c0 = g mod 2^32, c1 = (g >> 32) | tag << 16 | b << 24, (c2, c3) = nonce.
+ * nblocks in [1, 256], tag in [0, 255].  out is n * nblocks * 4 uint32_t. */
+int bc_prg_blocks(uint32_t* out, uint64_t n, uint32_t nblocks, uint64_t seed,
+                  uint64_t nonce, uint32_t tag, uint64_t elem_base, void* stream);
+
+/* --------------------------------------------------------- truncation */
+
+/* Deterministic truncation, Alg. 4 (k2 = 0) and Alg. 5 (Sec. 5.1).
+ * In  : x0, x1 -- n shares of Z_{2^ell} (width of ell).
+ * Out : y0, y1 -- n shares of Z_{2^(ell-k1-k2)} (width of ell-k1-k2):
+ *       P0: y0 = cut(x0, k1, k2) mod 2^(ell-k1-k2)
+ *       P1: y1 = -cut(-x1 mod 2^ell, k1, k2) mod 2^(ell-k1-k2)
+ *       They reconstruct to floor(x / 2^k1) + e0 in the smaller ring, with
+ *       e0 in {0, 1} and no e1 term.
+ * k1 low bits and k2 high bits are dropped; requires k1 + k2 < ell. */
+int bc_trunc_det(const void* x0, const void* x1, void* y0, void* y1, uint64_t n,
+                 uint32_t ell, uint32_t k1, uint32_t k2, void* stream);
+
+/* SecureML probabilistic truncation, Alg. 1 (Sec. 2.4).
+ * In/out shares of Z_{2^ell} (same width):
+ *   P0: y0 = cut(x0, k) mod 2^ell;  P1: y1 = -cut(-x1 mod 2^ell, k) mod 2^ell.
+ * Fails (the e1 term of Sec. 3) with probability |x| / 2^ell over the mask.
+ * Requires k < ell. */
+int bc_trunc_prob(const void* x0, const void* x1, void* y0, void* y1, uint64_t n,
+                  uint32_t ell, uint32_t k, void* stream);
+
+/* ------------------------------------------------------- modulo switch */
+
+/* Modulo switch Z_{2^ell_in} -> Z_p, Alg. 6 (Sec. 5.3).
+ * In  : x0, x1 -- n shares of Z_{2^ell_in}, ell_in in [1, 63].
+ * Out : y0, y1 -- n shares of Z_p (uint32_t if p < 2^32, else uint64_t):
+ *       P0: y0 = 2^ell_in mod p if x0 = 0, else x0 mod p
+ *       P1: y1 = p + x1 - 2^ell_in mod p
+ *       They reconstruct to 0 mod p exactly when x = 0 mod 2^ell_in.
+ * p must be prime with 2^ell_in < p < 2^(ell_in+1). */
+int bc_mod_switch(const void* x0, const void* x1, void* y0, void* y1, uint64_t n,
+                  uint32_t ell_in, uint64_t p, void* stream);
+
+/* ---------------------------------------------------------- DReLU / ReLU */
+
+/* Bicoptor 2.0 DReLU, Alg. 7 (Sec. 5.4), all three parties in one kernel.
+ * In  : x0, x1 -- n shares of x in Z_{2^ell}.
+ * Out : y0, y1 -- n shares of DReLU(x) in Z_{2^ell}.  With k_lo = 0,
+ *       DReLU(x) = [x > 0] for 0 < |x| < 2^(l_x-1), and DReLU(0) = t (the
+ *       random flip).  With key bits, the band |x| < 2^k_lo follows the
+ *       carry of the dropped bits.
+ * Randomness: t and the shuffle from seed01 (steps 1, 6), r_i in Z_p^* and
+ *       z_i in Z_p from seed01 (steps 7, 8), P2's resharing from seed02 (step
+ *       10).  Draws are documented with bc_prg_blocks.
+ * capture: NULL, or a device buffer of 2 * n * (l_x + 1) elements of Z_p
+ *       (uint32_t if p < 2^32, else uint64_t).  It receives the round-1
+ *       messages [w]_0 then [w]_1, element-major, in slot (post-shuffle)
+ *       order: capture[(party * n + i) * (l_x+1) + slot].
+ * acct: NULL, or receives bc_msg_account(BC_OP_DRELU, prm, n). */
+int bc_drelu(const void* x0, const void* x1, void* y0, void* y1, uint64_t n,
+             const bc_drelu_params* prm, const bc_seeds* seeds, uint64_t elem_base,
+             void* capture, bc_msg_acct* acct, void* stream);
+
+/* UBL Bicoptor 2.0 ReLU, Alg. 8 (appendix): Alg. 7 steps 1-9, then the
+ * Beaver multiplication x * DReLU(x).  [a]_0, [b]_0 and [c]_0 come from
+ * seed02; [a]_1 and [b]_1 come from seed12; P2 forms [c]_1.  Outputs are
+ * shares of x * DReLU(x) in Z_{2^ell}, with x at full precision.
+ * Arguments as bc_drelu. */
+int bc_relu(const void* x0, const void* x1, void* y0, void* y1, uint64_t n,
+            const bc_drelu_params* prm, const bc_seeds* seeds, uint64_t elem_base,
+            void* capture, bc_msg_acct* acct, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BICOP_H */

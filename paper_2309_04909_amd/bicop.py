@@ -1,0 +1,251 @@
+"""Thin ctypes binding of libbicop.so (include/bicop.h).
+
+Argument marshalling only: every step of the protocols runs in the HIP
+kernels behind the C ABI.  Shares are torch tensors on the GPU whose element
+size matches the ring (4 bytes for l <= 32, else 8; uint32/int32 or
+uint64/int64 storage), contiguous.  Calls enqueue on the current torch
+stream unless a stream is given.  If the library is not built, importing
+this module raises ImportError: there is no fallback path.
+"""
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbicop.so")
+
+BC_OP_DRELU = 0
+BC_OP_RELU = 1
+LINKS = ("P0->P2", "P1->P2", "P2->P0", "P2->P1", "P0->P1", "P1->P0")
+
+
+class BicopError(RuntimeError):
+    def __init__(self, code, where, detail):
+        super().__init__(f"{where}: error {code} ({detail})")
+        self.code = code
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("ell", ctypes.c_uint32), ("lx", ctypes.c_uint32), ("k_lo", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("p", ctypes.c_uint64)]
+
+
+class _Seeds(ctypes.Structure):
+    _fields_ = [("seed01", ctypes.c_uint64), ("seed02", ctypes.c_uint64), ("seed12", ctypes.c_uint64),
+                ("nonce", ctypes.c_uint64)]
+
+
+class _Acct(ctypes.Structure):
+    _fields_ = [("bits", ctypes.c_uint64 * 6), ("stored_bytes", ctypes.c_uint64 * 6), ("rounds", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+_P = ctypes.c_void_p
+_U64 = ctypes.c_uint64
+_U32 = ctypes.c_uint32
+
+_SIGS = {
+    "bc_version": ([], ctypes.c_char_p),
+    "bc_strerror": ([ctypes.c_int], ctypes.c_char_p),
+    "bc_last_error": ([], ctypes.c_char_p),
+    "bc_default_prime": ([_U32], _U64),
+    "bc_check_params": ([ctypes.POINTER(_Params), ctypes.POINTER(_Params)], ctypes.c_int),
+    "bc_msg_account": ([_U32, ctypes.POINTER(_Params), _U64, ctypes.POINTER(_Acct)], ctypes.c_int),
+    "bc_prg_blocks": ([_P, _U64, _U32, _U64, _U64, _U32, _U64, _P], ctypes.c_int),
+    "bc_trunc_det": ([_P, _P, _P, _P, _U64, _U32, _U32, _U32, _P], ctypes.c_int),
+    "bc_trunc_prob": ([_P, _P, _P, _P, _U64, _U32, _U32, _P], ctypes.c_int),
+    "bc_mod_switch": ([_P, _P, _P, _P, _U64, _U32, _U64, _P], ctypes.c_int),
+    "bc_drelu": ([_P, _P, _P, _P, _U64, ctypes.POINTER(_Params), ctypes.POINTER(_Seeds), _U64, _P,
+                  ctypes.POINTER(_Acct), _P], ctypes.c_int),
+    "bc_relu": ([_P, _P, _P, _P, _U64, ctypes.POINTER(_Params), ctypes.POINTER(_Seeds), _U64, _P,
+                 ctypes.POINTER(_Acct), _P], ctypes.c_int),
+}
+
+EXPORTED = tuple(_SIGS)
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "or python -m paper_2309_04909_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (args, res) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+lib = _load()
+
+
+def _check(rc, where):
+    if rc != 0:
+        raise BicopError(rc, where, f"{lib.bc_strerror(rc).decode()}: {lib.bc_last_error().decode()}")
+
+
+# ------------------------------------------------------------------ settings
+
+
+@dataclass(frozen=True)
+class Params:
+    """DReLU/ReLU setting: ring bits ell, window width lx, key-bit offset k_lo,
+    prime p (0 = largest prime below 2^(lx+1))."""
+    ell: int
+    lx: int
+    k_lo: int = 0
+    p: int = 0
+
+    def c(self):
+        return _Params(self.ell, self.lx, self.k_lo, 0, self.p)
+
+    @property
+    def npos(self):
+        return self.lx + 1
+
+    def resolved(self):
+        out = _Params()
+        _check(lib.bc_check_params(ctypes.byref(self.c()), ctypes.byref(out)), "check_params")
+        return Params(out.ell, out.lx, out.k_lo, out.p)
+
+
+@dataclass(frozen=True)
+class Seeds:
+    seed01: int
+    seed02: int
+    seed12: int
+    nonce: int = 0
+
+    def c(self):
+        m = (1 << 64) - 1
+        return _Seeds(self.seed01 & m, self.seed02 & m, self.seed12 & m, self.nonce & m)
+
+
+def version():
+    return lib.bc_version().decode()
+
+
+def default_prime(lx):
+    return int(lib.bc_default_prime(lx))
+
+
+def msg_account(op, params: Params, n):
+    a = _Acct()
+    _check(lib.bc_msg_account(op, ctypes.byref(params.c()), n, ctypes.byref(a)), "msg_account")
+    return {"bits": dict(zip(LINKS, list(a.bits))), "stored_bytes": dict(zip(LINKS, list(a.stored_bytes))),
+            "rounds": a.rounds}
+
+
+# ------------------------------------------------------------------- helpers
+
+
+def ring_width(ell):
+    return 4 if ell <= 32 else 8
+
+
+def ring_dtype(ell):
+    return torch.uint32 if ell <= 32 else torch.uint64
+
+
+def field_dtype(p):
+    return torch.uint32 if p < (1 << 32) else torch.uint64
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check_shares(x0, x1, width, what="shares"):
+    for t in (x0, x1):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{what} must be CUDA tensors")
+        if t.element_size() != width:
+            raise TypeError(f"{what}: expected {width}-byte elements, got {t.dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{what} must be contiguous")
+    if x0.numel() != x1.numel():
+        raise ValueError("share arrays differ in length")
+
+
+def _out(x, like_width, dtype, out):
+    if out is not None:
+        if out.numel() != x.numel() or out.element_size() != like_width or not out.is_contiguous():
+            raise ValueError("bad output tensor")
+        return out
+    return torch.empty(x.shape, dtype=dtype, device=x.device)
+
+
+# ------------------------------------------------------------------ protocols
+
+
+def trunc_det(x0, x1, ell, k1, k2=0, out=None, stream=None):
+    """Alg. 4/5: shares of Z_{2^ell} -> shares of Z_{2^(ell-k1-k2)}."""
+    _check_shares(x0, x1, ring_width(ell))
+    m = ell - k1 - k2
+    y0 = _out(x0, ring_width(m), ring_dtype(m), None if out is None else out[0])
+    y1 = _out(x1, ring_width(m), ring_dtype(m), None if out is None else out[1])
+    _check(lib.bc_trunc_det(x0.data_ptr(), x1.data_ptr(), y0.data_ptr(), y1.data_ptr(), x0.numel(), ell, k1, k2,
+                            _stream(stream)), "trunc_det")
+    return y0, y1
+
+
+def trunc_prob(x0, x1, ell, k, out=None, stream=None):
+    """Alg. 1: shares of Z_{2^ell} -> shares of Z_{2^ell}."""
+    _check_shares(x0, x1, ring_width(ell))
+    y0 = _out(x0, ring_width(ell), ring_dtype(ell), None if out is None else out[0])
+    y1 = _out(x1, ring_width(ell), ring_dtype(ell), None if out is None else out[1])
+    _check(lib.bc_trunc_prob(x0.data_ptr(), x1.data_ptr(), y0.data_ptr(), y1.data_ptr(), x0.numel(), ell, k,
+                             _stream(stream)), "trunc_prob")
+    return y0, y1
+
+
+def mod_switch(x0, x1, ell_in, p, out=None, stream=None):
+    """Alg. 6: shares of Z_{2^ell_in} -> shares of Z_p."""
+    _check_shares(x0, x1, ring_width(ell_in))
+    w = 4 if p < (1 << 32) else 8
+    y0 = _out(x0, w, field_dtype(p), None if out is None else out[0])
+    y1 = _out(x1, w, field_dtype(p), None if out is None else out[1])
+    _check(lib.bc_mod_switch(x0.data_ptr(), x1.data_ptr(), y0.data_ptr(), y1.data_ptr(), x0.numel(), ell_in, p,
+                             _stream(stream)), "mod_switch")
+    return y0, y1
+
+
+def _drelu_like(fn, name, x0, x1, params, seeds, elem_base, capture, out, stream):
+    _check_shares(x0, x1, ring_width(params.ell))
+    y0 = _out(x0, ring_width(params.ell), ring_dtype(params.ell), None if out is None else out[0])
+    y1 = _out(x1, ring_width(params.ell), ring_dtype(params.ell), None if out is None else out[1])
+    cap = None
+    if capture:
+        p = params.resolved().p
+        cap = torch.empty((2, x0.numel(), params.npos), dtype=field_dtype(p), device=x0.device)
+    acct = _Acct()
+    _check(fn(x0.data_ptr(), x1.data_ptr(), y0.data_ptr(), y1.data_ptr(), x0.numel(), ctypes.byref(params.c()),
+              ctypes.byref(seeds.c()), elem_base, None if cap is None else cap.data_ptr(), ctypes.byref(acct),
+              _stream(stream)), name)
+    if capture:
+        return y0, y1, cap
+    return y0, y1
+
+
+def drelu(x0, x1, params: Params, seeds: Seeds, elem_base=0, capture=False, out=None, stream=None):
+    """Alg. 7.  Returns (y0, y1) or (y0, y1, capture[2, n, lx+1])."""
+    return _drelu_like(lib.bc_drelu, "drelu", x0, x1, params, seeds, elem_base, capture, out, stream)
+
+
+def relu(x0, x1, params: Params, seeds: Seeds, elem_base=0, capture=False, out=None, stream=None):
+    """Alg. 8.  Returns (y0, y1) or (y0, y1, capture[2, n, lx+1])."""
+    return _drelu_like(lib.bc_relu, "relu", x0, x1, params, seeds, elem_base, capture, out, stream)
+
+
+def prg_blocks(n, nblocks, seed, nonce, tag, elem_base=0, device="cuda", stream=None):
+    """Raw Philox4x32-10 words, shape (n, nblocks, 4), uint32."""
+    out = torch.empty((n, nblocks, 4), dtype=torch.uint32, device=device)
+    m = (1 << 64) - 1
+    _check(lib.bc_prg_blocks(out.data_ptr(), n, nblocks, seed & m, nonce & m, tag, elem_base, _stream(stream)),
+           "prg_blocks")
+    return out

@@ -1,0 +1,83 @@
+"""Build libbicop.so (the C ABI of include/bicop.h) for gfx950 with hipcc.
+
+Every .hip file under csrc/ is compiled to an object in _build/ (in parallel),
+then the objects are linked into paper_2309_04909_amd/libbicop.so.  The
+packed-fp32 target feature is switched off for all device code.
+
+    python -m paper_2309_04909_amd.build [-j N] [--asm]
+"""
+
+import argparse
+import os
+import shutil
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libbicop.so")
+ARCH = "gfx950"
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else "hipcc")
+FLAGS = [
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-command-line-argument",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+]
+
+
+def sources():
+    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    # hipcc's host pass does not know the packed-fp32 feature; that warning is harmless
+    out = "\n".join(l for l in r.stdout.splitlines() if "packed-fp32-ops" not in l and l.strip())
+    return r.returncode, out
+
+
+def build(jobs: int | None = None, verbose: bool = False, asm: bool = False) -> str:
+    """Compile every HIP source and link libbicop.so.  Returns the library path."""
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = sources()
+    jobs = jobs or min(len(srcs), max(1, min(16, os.cpu_count() or 4)))
+
+    def compile_one(src):
+        obj = os.path.join(BUILD, os.path.basename(src).replace(".hip", ".o"))
+        rc, out = _run([HIPCC, *FLAGS, "-c", src, "-o", obj])
+        if rc == 0 and asm:
+            s = os.path.join(BUILD, os.path.basename(src).replace(".hip", ".s"))
+            _run([HIPCC, *FLAGS, "--cuda-device-only", "-S", src, "-o", s])
+        return src, obj, rc, out
+
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        results = list(ex.map(compile_one, srcs))
+    errors = [(s, o) for s, _, rc, o in results if rc != 0]
+    for s, _, rc, out in results:
+        if out and (verbose or rc != 0):
+            print(f"--- {os.path.basename(s)}\n{out}", file=sys.stderr)
+    if errors:
+        raise RuntimeError("hipcc failed for: " + ", ".join(os.path.basename(s) for s, _ in errors))
+    tmp = LIB + ".tmp"
+    rc, out = _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *[o for _, o, _, _ in results]])
+    if rc != 0:
+        raise RuntimeError("link failed:\n" + out)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def clean():
+    shutil.rmtree(BUILD, ignore_errors=True)
+    if os.path.exists(LIB):
+        os.remove(LIB)
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("-j", type=int, default=None)
+    ap.add_argument("-v", action="store_true")
+    ap.add_argument("--asm", action="store_true", help="also write device assembly next to the objects")
+    a = ap.parse_args()
+    print(build(a.j, a.v, a.asm))

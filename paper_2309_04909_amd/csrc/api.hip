@@ -1,0 +1,297 @@
+// C ABI of libbicop.so (declared in include/bicop.h): argument validation,
+// parameter derivation, message accounting and kernel launches.  Every check
+// runs on the host before anything is enqueued; no exception crosses the ABI.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+
+#include "internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(BC_ERR_HIP, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+// ---------------------------------------------------------------- primes
+
+uint64_t mulmod64(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((unsigned __int128)a * b % m); }
+
+uint64_t powmod64(uint64_t a, uint64_t e, uint64_t m) {
+    uint64_t r = 1 % m;
+    a %= m;
+    while (e) {
+        if (e & 1) r = mulmod64(r, a, m);
+        a = mulmod64(a, a, m);
+        e >>= 1;
+    }
+    return r;
+}
+
+// Deterministic Miller-Rabin: these twelve bases decide every n < 3.3e24.
+bool is_prime64(uint64_t n) {
+    static const uint64_t bases[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+    if (n < 2) return false;
+    for (uint64_t q : bases)
+        if (n % q == 0) return n == q;
+    uint64_t d = n - 1;
+    int s = 0;
+    while ((d & 1) == 0) {
+        d >>= 1;
+        ++s;
+    }
+    for (uint64_t a : bases) {
+        uint64_t x = powmod64(a, d, n);
+        if (x == 1 || x == n - 1) continue;
+        bool comp = true;
+        for (int i = 1; i < s; ++i) {
+            x = mulmod64(x, x, n);
+            if (x == n - 1) {
+                comp = false;
+                break;
+            }
+        }
+        if (comp) return false;
+    }
+    return true;
+}
+
+uint64_t default_prime(uint32_t lx) {
+    if (lx < 1 || lx > 32) return 0;
+    uint64_t c = (1ull << (lx + 1)) - 1;
+    while (!is_prime64(c)) --c;
+    return c;
+}
+
+// ------------------------------------------------------------ validation
+
+uint32_t width_of_ring(uint32_t ell) { return ell <= 32 ? 4u : 8u; }
+
+bool aligned(const void* p, uint32_t w) { return ((uintptr_t)p % w) == 0; }
+
+int check_params(const bc_drelu_params* prm, bc_drelu_params* out) {
+    if (!prm) return fail(BC_ERR_NULL, "params is NULL");
+    if (prm->reserved != 0) return fail(BC_ERR_ARG, "params.reserved must be 0");
+    if (prm->ell < 1 || prm->ell > 64) return fail(BC_ERR_RING, "ell = %u outside [1, 64]", prm->ell);
+    if (prm->lx < 1 || prm->lx > 32) return fail(BC_ERR_WINDOW, "lx = %u outside [1, 32]", prm->lx);
+    if ((uint64_t)prm->k_lo + 2ull * prm->lx > prm->ell)
+        return fail(BC_ERR_WINDOW, "k_lo + 2 lx = %u exceeds ell = %u", prm->k_lo + 2 * prm->lx, prm->ell);
+    uint64_t p = prm->p ? prm->p : default_prime(prm->lx);
+    const uint64_t lo = 1ull << prm->lx, hi = 1ull << (prm->lx + 1);
+    if (!(lo < p && p < hi) || !is_prime64(p))
+        return fail(BC_ERR_PRIME, "p = %llu is not a prime in (2^%u, 2^%u)", (unsigned long long)p, prm->lx, prm->lx + 1);
+    if (out) {
+        *out = *prm;
+        out->p = p;
+    }
+    return BC_OK;
+}
+
+int account(uint32_t op, const bc_drelu_params& r, uint64_t n, bc_msg_acct* a) {
+    memset(a, 0, sizeof(*a));
+    const uint64_t npos = r.lx + 1;
+    const uint64_t pbits = 64 - (uint64_t)__builtin_clzll(r.p);      // ceil(log2 p) = l_x + 1
+    const uint64_t wbits = npos * pbits;                              // (l_x + 1)^2
+    const uint64_t pbytes = r.p < (1ull << 32) ? 4 : 8;
+    const uint64_t rbytes = width_of_ring(r.ell);
+    a->bits[0] = a->bits[1] = wbits * n;
+    a->stored_bytes[0] = a->stored_bytes[1] = npos * pbytes * n;
+    a->bits[2] = a->bits[3] = (uint64_t)r.ell * n;
+    a->stored_bytes[2] = a->stored_bytes[3] = rbytes * n;
+    if (op == BC_OP_RELU) {
+        a->bits[3] += (uint64_t)r.ell * n;                           // [c]_1, preprocessing
+        a->stored_bytes[3] += rbytes * n;
+        a->bits[4] = a->bits[5] = (uint64_t)r.ell * n;                // d-shares
+        a->stored_bytes[4] = a->stored_bytes[5] = rbytes * n;
+    }
+    a->rounds = 2;
+    return BC_OK;
+}
+
+bc::StreamKey stream_key(uint64_t seed, uint64_t nonce) {
+    return bc::StreamKey{(uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)nonce, (uint32_t)(nonce >> 32)};
+}
+
+constexpr uint64_t kMaxIndex = 1ull << 48;
+
+int grid_cap(int per_cu) { return bc::device_cus() * per_cu; }
+
+int drelu_common(uint32_t op, const void* x0, const void* x1, void* y0, void* y1, uint64_t n,
+                 const bc_drelu_params* prm, const bc_seeds* seeds, uint64_t elem_base, void* capture,
+                 bc_msg_acct* acct, void* stream) {
+    bc_drelu_params r;
+    int rc = check_params(prm, &r);
+    if (rc) return rc;
+    if (!seeds) return fail(BC_ERR_NULL, "seeds is NULL");
+    if (elem_base > kMaxIndex || n > kMaxIndex - elem_base)
+        return fail(BC_ERR_ARG, "element indices must stay below 2^48");
+    if (acct) account(op, r, n, acct);
+    if (n == 0) return BC_OK;
+    if (!x0 || !x1 || !y0 || !y1) return fail(BC_ERR_NULL, "share pointer is NULL");
+    const uint32_t w = width_of_ring(r.ell);
+    if (!aligned(x0, w) || !aligned(x1, w) || !aligned(y0, w) || !aligned(y1, w))
+        return fail(BC_ERR_ALIGN, "share pointers must be %u-byte aligned", w);
+    if (capture && !aligned(capture, r.p < (1ull << 32) ? 4 : 8))
+        return fail(BC_ERR_ALIGN, "capture buffer misaligned");
+    bc::DreluLaunch L;
+    L.x0 = x0;
+    L.x1 = x1;
+    L.y0 = y0;
+    L.y1 = y1;
+    L.cap = capture;
+    L.n = n;
+    L.elem_base = elem_base;
+    L.ell = r.ell;
+    L.lx = r.lx;
+    L.k_lo = r.k_lo;
+    L.npos = r.lx + 1;
+    L.p = r.p;
+    L.s01 = stream_key(seeds->seed01, seeds->nonce);
+    L.s02 = stream_key(seeds->seed02, seeds->nonce);
+    L.s12 = stream_key(seeds->seed12, seeds->nonce);
+    L.block = 256;
+    uint64_t grid = (n + 255) / 256;
+    const uint64_t cap = (uint64_t)grid_cap(16);
+    L.grid = (int)(grid < cap ? grid : cap);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if (r.ell > 32)
+        e = op == BC_OP_RELU ? bc::launch_relu_u64(L, st) : bc::launch_drelu_u64(L, st);
+    else
+        e = op == BC_OP_RELU ? bc::launch_relu_u32(L, st) : bc::launch_drelu_u32(L, st);
+    if (e != hipSuccess) return hip_fail(e, op == BC_OP_RELU ? "relu launch" : "drelu launch");
+    return BC_OK;
+}
+
+}  // namespace
+
+namespace bc {
+
+int device_cus() {
+    static std::mutex mu;
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!cache[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+        cache[dev] = v;
+    }
+    return cache[dev];
+}
+
+}  // namespace bc
+
+extern "C" {
+
+const char* bc_version(void) { return "bicop 0.1 (gfx950)"; }
+
+const char* bc_strerror(int code) {
+    switch (code) {
+        case BC_OK: return "ok";
+        case BC_ERR_NULL: return "null pointer";
+        case BC_ERR_RING: return "invalid ring (l outside [1,64] or k1 + k2 >= l)";
+        case BC_ERR_WINDOW: return "invalid window (l_x outside [1,32] or k_lo + 2 l_x > l)";
+        case BC_ERR_PRIME: return "invalid prime (not prime or outside (2^l', 2^(l'+1)))";
+        case BC_ERR_ALIGN: return "misaligned pointer";
+        case BC_ERR_HIP: return "HIP error";
+        case BC_ERR_WORKSPACE: return "workspace too small";
+        case BC_ERR_ARG: return "invalid argument";
+        default: return "unknown error";
+    }
+}
+
+const char* bc_last_error(void) { return g_err; }
+
+uint64_t bc_default_prime(uint32_t lx) { return default_prime(lx); }
+
+int bc_check_params(const bc_drelu_params* prm, bc_drelu_params* resolved) { return check_params(prm, resolved); }
+
+int bc_msg_account(uint32_t op, const bc_drelu_params* prm, uint64_t n, bc_msg_acct* acct) {
+    if (!acct) return fail(BC_ERR_NULL, "acct is NULL");
+    if (op != BC_OP_DRELU && op != BC_OP_RELU) return fail(BC_ERR_ARG, "unknown op %u", op);
+    bc_drelu_params r;
+    int rc = check_params(prm, &r);
+    if (rc) return rc;
+    return account(op, r, n, acct);
+}
+
+int bc_prg_blocks(uint32_t* out, uint64_t n, uint32_t nblocks, uint64_t seed, uint64_t nonce, uint32_t tag,
+                  uint64_t elem_base, void* stream) {
+    if (nblocks < 1 || nblocks > 256) return fail(BC_ERR_ARG, "nblocks = %u outside [1, 256]", nblocks);
+    if (tag > 255) return fail(BC_ERR_ARG, "tag = %u outside [0, 255]", tag);
+    if (elem_base > kMaxIndex || n > kMaxIndex - elem_base) return fail(BC_ERR_ARG, "element indices must stay below 2^48");
+    if (n == 0) return BC_OK;
+    if (!out) return fail(BC_ERR_NULL, "out is NULL");
+    if (!aligned(out, 4)) return fail(BC_ERR_ALIGN, "out misaligned");
+    hipError_t e = bc::launch_prg_blocks(out, n, nblocks, stream_key(seed, nonce), tag, elem_base, grid_cap(16),
+                                         (hipStream_t)stream);
+    return e == hipSuccess ? BC_OK : hip_fail(e, "prg launch");
+}
+
+int bc_trunc_det(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, uint32_t ell, uint32_t k1, uint32_t k2,
+                 void* stream) {
+    if (ell < 1 || ell > 64) return fail(BC_ERR_RING, "ell = %u outside [1, 64]", ell);
+    if ((uint64_t)k1 + k2 >= ell) return fail(BC_ERR_RING, "k1 + k2 = %u must be < ell = %u", k1 + k2, ell);
+    if (n == 0) return BC_OK;
+    if (!x0 || !x1 || !y0 || !y1) return fail(BC_ERR_NULL, "share pointer is NULL");
+    const uint32_t wi = width_of_ring(ell), wo = width_of_ring(ell - k1 - k2);
+    if (!aligned(x0, wi) || !aligned(x1, wi) || !aligned(y0, wo) || !aligned(y1, wo))
+        return fail(BC_ERR_ALIGN, "share pointers misaligned");
+    hipError_t e = bc::launch_trunc_det(x0, x1, y0, y1, n, ell, k1, k2, grid_cap(8), (hipStream_t)stream);
+    return e == hipSuccess ? BC_OK : hip_fail(e, "trunc_det launch");
+}
+
+int bc_trunc_prob(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, uint32_t ell, uint32_t k,
+                  void* stream) {
+    if (ell < 1 || ell > 64) return fail(BC_ERR_RING, "ell = %u outside [1, 64]", ell);
+    if (k >= ell) return fail(BC_ERR_RING, "k = %u must be < ell = %u", k, ell);
+    if (n == 0) return BC_OK;
+    if (!x0 || !x1 || !y0 || !y1) return fail(BC_ERR_NULL, "share pointer is NULL");
+    const uint32_t w = width_of_ring(ell);
+    if (!aligned(x0, w) || !aligned(x1, w) || !aligned(y0, w) || !aligned(y1, w))
+        return fail(BC_ERR_ALIGN, "share pointers misaligned");
+    hipError_t e = bc::launch_trunc_prob(x0, x1, y0, y1, n, ell, k, grid_cap(8), (hipStream_t)stream);
+    return e == hipSuccess ? BC_OK : hip_fail(e, "trunc_prob launch");
+}
+
+int bc_mod_switch(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, uint32_t ell_in, uint64_t p,
+                  void* stream) {
+    if (ell_in < 1 || ell_in > 63) return fail(BC_ERR_RING, "ell_in = %u outside [1, 63]", ell_in);
+    const uint64_t lo = 1ull << ell_in;
+    const uint64_t hi = ell_in == 63 ? ~0ull : (1ull << (ell_in + 1));
+    if (!(lo < p && (p < hi || (ell_in == 63))) || !is_prime64(p))
+        return fail(BC_ERR_PRIME, "p = %llu is not a prime in (2^%u, 2^%u)", (unsigned long long)p, ell_in, ell_in + 1);
+    if (n == 0) return BC_OK;
+    if (!x0 || !x1 || !y0 || !y1) return fail(BC_ERR_NULL, "share pointer is NULL");
+    const uint32_t wi = width_of_ring(ell_in), wo = p < (1ull << 32) ? 4u : 8u;
+    if (!aligned(x0, wi) || !aligned(x1, wi) || !aligned(y0, wo) || !aligned(y1, wo))
+        return fail(BC_ERR_ALIGN, "share pointers misaligned");
+    hipError_t e = bc::launch_mod_switch(x0, x1, y0, y1, n, ell_in, p, grid_cap(8), (hipStream_t)stream);
+    return e == hipSuccess ? BC_OK : hip_fail(e, "mod_switch launch");
+}
+
+int bc_drelu(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, const bc_drelu_params* prm,
+             const bc_seeds* seeds, uint64_t elem_base, void* capture, bc_msg_acct* acct, void* stream) {
+    return drelu_common(BC_OP_DRELU, x0, x1, y0, y1, n, prm, seeds, elem_base, capture, acct, stream);
+}
+
+int bc_relu(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, const bc_drelu_params* prm,
+            const bc_seeds* seeds, uint64_t elem_base, void* capture, bc_msg_acct* acct, void* stream) {
+    return drelu_common(BC_OP_RELU, x0, x1, y0, y1, n, prm, seeds, elem_base, capture, acct, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,235 @@
+// Device building blocks of the DReLU/ReLU kernels (gfx950, wave64).
+//
+//  * Philox4x32-10 (Salmon et al., SC'11): the counter-based generator behind
+//    every "generate ... using seed" of Alg. 7 and Alg. 8.
+//  * Modular multiplication in Z_p for the four prime sizes the window width
+//    l_x produces (p has l_x + 1 bits, notation table):
+//      FieldSmall  p < 2^12   products < 2^24: one 24-bit multiply, fp32 quotient
+//      Field24     p < 2^24   48-bit products from two 24-bit multiplies,
+//                             Mersenne fold or fp64 quotient
+//      Field32     p < 2^32   64-bit products, Barrett with a 64-bit reciprocal
+//      Field64     p < 2^34   l_x = 32; 66-bit products, fp64 quotient
+//  * A Batcher odd-even merge sorting network over NMAX keys, generated at
+//    compile time, used to turn the per-position random keys into the
+//    shuffle of Alg. 7 step 6 without any dynamically indexed register array.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bc {
+
+// ------------------------------------------------------------------ Philox
+
+constexpr uint32_t PHILOX_M0 = 0xD2511F53u;
+constexpr uint32_t PHILOX_M1 = 0xCD9E8D57u;
+constexpr uint32_t PHILOX_W0 = 0x9E3779B9u;
+constexpr uint32_t PHILOX_W1 = 0xBB67AE85u;
+
+constexpr uint32_t TAG_SHUFFLE = 1;
+constexpr uint32_t TAG_MASK = 2;
+constexpr uint32_t TAG_RESP = 3;
+constexpr uint32_t TAG_BEAVER = 4;
+
+struct Words4 {
+    uint32_t w0, w1, w2, w3;
+};
+
+// Ten rounds.  Round r uses key (k0 + r W0, k1 + r W1).  One round maps
+// (c0, c1, c2, c3) to (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0)).
+__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)PHILOX_M0 * c0;
+        const uint64_t p1 = (uint64_t)PHILOX_M1 * c2;
+        const uint32_t rk0 = k0 + (uint32_t)r * PHILOX_W0;
+        const uint32_t rk1 = k1 + (uint32_t)r * PHILOX_W1;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ rk0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ rk1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+    }
+    return {c0, c1, c2, c3};
+}
+
+// Counter of block b of stream `tag` for global element index g.
+struct Stream {
+    uint32_t k0, k1;   // key = seed
+    uint32_t n0, n1;   // (c2, c3) = nonce
+    __device__ __forceinline__ Words4 block(uint64_t g, uint32_t tag, uint32_t b) const {
+        const uint32_t c1 = ((uint32_t)(g >> 32) & 0xFFFFu) | (tag << 16) | (b << 24);
+        return philox4x32_10((uint32_t)g, c1, n0, n1, k0, k1);
+    }
+};
+
+__device__ __forceinline__ uint64_t join64(uint32_t lo, uint32_t hi) {
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// ------------------------------------------------------------ Z_p arithmetic
+
+// p < 2^12.  a, b < p, so a*b < 2^24 is exact in one v_mul_u32_u24 and in
+// fp32.  The fp32 quotient is within one of floor(x / p); two corrections.
+struct FieldSmall {
+    using T = uint32_t;
+    uint32_t p;
+    float pinv;
+    __device__ __forceinline__ uint32_t reduce24(uint32_t x) const {   // x < 2^24
+        const uint32_t q = (uint32_t)((float)x * pinv);
+        int32_t r = (int32_t)(x - __umul24(q, p));
+        r = r < 0 ? r + (int32_t)p : r;
+        r = r >= (int32_t)p ? r - (int32_t)p : r;
+        return (uint32_t)r;
+    }
+    __device__ __forceinline__ uint32_t mul(uint32_t a, uint32_t b) const { return reduce24(__umul24(a, b)); }
+};
+
+// p < 2^24.  a*b < 2^48 from the low and high halves of the 24-bit multiply.
+// Mersenne primes 2^k - 1 fold the product once: since a, b < p,
+// (x mod 2^k) + (x >> k) < 2p.  Other primes take an fp64 quotient (the
+// product is exact in fp64) that is within one of floor(x / p).
+struct Field24 {
+    using T = uint32_t;
+    uint32_t p;
+    uint32_t mers_k;   // k if p = 2^k - 1, else 0
+    double pd, pinv;
+    __device__ __forceinline__ uint32_t mul(uint32_t a, uint32_t b) const {
+        const uint64_t x = (uint64_t)(a & 0xFFFFFFu) * (uint64_t)(b & 0xFFFFFFu);
+        if (mers_k) {
+            const uint32_t lo = (uint32_t)x & p;
+            const uint32_t hi = (uint32_t)(x >> mers_k);
+            const uint32_t s = lo + hi;
+            return s >= p ? s - p : s;
+        }
+        const double xd = (double)x;
+        const double q = __builtin_floor(xd * pinv);
+        double r = __builtin_fma(-q, pd, xd);
+        r = r < 0.0 ? r + pd : r;
+        r = r >= pd ? r - pd : r;
+        return (uint32_t)r;
+    }
+};
+
+// p < 2^32.  Barrett: mu = floor((2^64 - 1) / p); q = mulhi64(x, mu) is within
+// two of floor(x / p).
+struct Field32 {
+    using T = uint32_t;
+    uint32_t p;
+    uint64_t mu;
+    __device__ __forceinline__ uint32_t mul(uint32_t a, uint32_t b) const {
+        const uint64_t x = (uint64_t)a * b;
+        const uint64_t q = __umul64hi(x, mu);
+        uint64_t r = x - q * p;
+        r = r >= p ? r - p : r;
+        r = r >= p ? r - p : r;
+        return (uint32_t)r;
+    }
+};
+
+// 2^32 < p < 2^34 (l_x = 32).  x = a*b < 2^68 as a 128-bit product; an fp64
+// quotient of x / p (< 2^34, relative error 2^-51) is within one of the floor.
+struct Field64 {
+    using T = uint64_t;
+    uint64_t p;
+    double pd, pinv;
+    __device__ __forceinline__ uint64_t mul(uint64_t a, uint64_t b) const {
+        const uint64_t lo = a * b;
+        const uint64_t hi = __umul64hi(a, b);
+        const double xd = __builtin_fma((double)hi, 18446744073709551616.0, (double)lo);
+        const double qd = __builtin_floor(xd * pinv);
+        const uint64_t q = (uint64_t)qd;
+        int64_t r = (int64_t)(lo - q * p);   // true remainder in (-p, 2p): exact mod 2^64
+        r = r < 0 ? r + (int64_t)p : r;
+        r = r >= (int64_t)p ? r - (int64_t)p : r;
+        return (uint64_t)r;
+    }
+};
+
+template <typename F>
+__device__ __forceinline__ typename F::T addmod(typename F::T a, typename F::T b, const F& f) {
+    const typename F::T s = a + b;   // a, b <= p and p < 2^34: no wrap
+    return s >= f.p ? s - f.p : s;
+}
+
+// r_s in Z_p^* and z_s in Z_p by multiply-shift of uniform words.
+template <typename F>
+struct Draw;
+template <>
+struct Draw<FieldSmall> {
+    __device__ static __forceinline__ uint32_t r(uint32_t R, const FieldSmall& f) { return 1u + __umulhi(R, f.p - 1u); }
+    __device__ static __forceinline__ uint32_t z(uint32_t Z, const FieldSmall& f) { return __umulhi(Z, f.p); }
+};
+template <>
+struct Draw<Field24> {
+    __device__ static __forceinline__ uint32_t r(uint32_t R, const Field24& f) { return 1u + __umulhi(R, f.p - 1u); }
+    __device__ static __forceinline__ uint32_t z(uint32_t Z, const Field24& f) { return __umulhi(Z, f.p); }
+};
+template <>
+struct Draw<Field32> {
+    __device__ static __forceinline__ uint32_t r(uint32_t R, const Field32& f) { return 1u + __umulhi(R, f.p - 1u); }
+    __device__ static __forceinline__ uint32_t z(uint32_t Z, const Field32& f) { return __umulhi(Z, f.p); }
+};
+
+// ---------------------------------------------------------- sorting network
+
+// Batcher's odd-even merge sort over the next power of two >= N, keeping only
+// comparators whose both ends are < N (entries >= N would hold +inf and never
+// move).  Comparator c puts min at a[c], max at b[c].
+template <int N>
+struct SortNet {
+    static constexpr int P = N <= 1 ? 1 : (N <= 2 ? 2 : (N <= 4 ? 4 : (N <= 8 ? 8 : (N <= 16 ? 16 : (N <= 32 ? 32 : 64)))));
+    static constexpr int count() {
+        int c = 0;
+        for (int p = 1; p < P; p *= 2)
+            for (int k = p; k >= 1; k /= 2)
+                for (int j = k % p; j + k < P; j += 2 * k)
+                    for (int i = 0; i < k && i + j + k < P; ++i)
+                        if ((i + j) / (2 * p) == (i + j + k) / (2 * p) && i + j + k < N) ++c;
+        return c;
+    }
+    static constexpr int C = count();
+    struct Table {
+        int a[C > 0 ? C : 1];
+        int b[C > 0 ? C : 1];
+    };
+    static constexpr Table table() {
+        Table t{};
+        int c = 0;
+        for (int p = 1; p < P; p *= 2)
+            for (int k = p; k >= 1; k /= 2)
+                for (int j = k % p; j + k < P; j += 2 * k)
+                    for (int i = 0; i < k && i + j + k < P; ++i)
+                        if ((i + j) / (2 * p) == (i + j + k) / (2 * p) && i + j + k < N) {
+                            t.a[c] = i + j;
+                            t.b[c] = i + j + k;
+                            ++c;
+                        }
+        return t;
+    }
+    static constexpr Table tab = table();
+};
+
+template <int N, int C, int I = 0>
+struct ApplyNet {
+    __device__ static __forceinline__ void run(uint32_t (&k)[N]) {
+        if constexpr (I < C) {
+            constexpr int a = SortNet<N>::tab.a[I];
+            constexpr int b = SortNet<N>::tab.b[I];
+            const uint32_t lo = k[a] < k[b] ? k[a] : k[b];
+            const uint32_t hi = k[a] < k[b] ? k[b] : k[a];
+            k[a] = lo;
+            k[b] = hi;
+            ApplyNet<N, C, I + 1>::run(k);
+        }
+    }
+};
+
+template <int N>
+__device__ __forceinline__ void sort_keys(uint32_t (&k)[N]) {
+    ApplyNet<N, SortNet<N>::C>::run(k);
+}
+
+}  // namespace bc

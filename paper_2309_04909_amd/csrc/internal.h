@@ -1,0 +1,50 @@
+// Host-side declarations shared by the C-ABI layer and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/bicop.h"
+
+namespace bc {
+
+// Counter-based stream handle passed by value to kernels (key and nonce).
+struct StreamKey {
+    uint32_t k0, k1, n0, n1;
+};
+
+// Fully validated DReLU/ReLU launch description.
+struct DreluLaunch {
+    const void* x0;
+    const void* x1;
+    void* y0;
+    void* y1;
+    void* cap;
+    uint64_t n;
+    uint64_t elem_base;
+    uint32_t ell, lx, k_lo, npos;
+    uint64_t p;
+    StreamKey s01, s02, s12;
+    int grid;
+    int block;
+};
+
+// Kernel launchers (one per op and storage width); return the launch status.
+hipError_t launch_drelu_u64(const DreluLaunch& L, hipStream_t st);
+hipError_t launch_relu_u64(const DreluLaunch& L, hipStream_t st);
+hipError_t launch_drelu_u32(const DreluLaunch& L, hipStream_t st);
+hipError_t launch_relu_u32(const DreluLaunch& L, hipStream_t st);
+
+hipError_t launch_trunc_det(const void* x0, const void* x1, void* y0, void* y1, uint64_t n,
+                            uint32_t ell, uint32_t k1, uint32_t k2, int grid, hipStream_t st);
+hipError_t launch_trunc_prob(const void* x0, const void* x1, void* y0, void* y1, uint64_t n,
+                             uint32_t ell, uint32_t k, int grid, hipStream_t st);
+hipError_t launch_mod_switch(const void* x0, const void* x1, void* y0, void* y1, uint64_t n,
+                             uint32_t ell_in, uint64_t p, int grid, hipStream_t st);
+hipError_t launch_prg_blocks(uint32_t* out, uint64_t n, uint32_t nblocks, StreamKey key, uint32_t tag,
+                             uint64_t elem_base, int grid, hipStream_t st);
+
+// Number of compute units of the current device (cached per device).
+int device_cus();
+
+}  // namespace bc

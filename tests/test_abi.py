@@ -1,0 +1,113 @@
+"""The C ABI on the CPU: the library loads, exports every function that
+include/bicop.h declares, and its host-only logic (prime choice, parameter
+validation, message accounting) agrees with the oracle.  No kernel runs here."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from oracle import params as OP
+from oracle import protocols as OPR
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "bicop.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(bc_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2309_04909_amd import bicop as B
+    lib = ctypes.CDLL(B.LIB_PATH)
+    names = _declared()
+    assert "bc_drelu" in names and "bc_relu" in names and "bc_trunc_det" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) <= set(B.EXPORTED)
+
+
+@pytest.mark.parametrize("lx", range(1, 33))
+def test_default_prime_matches_oracle(lx):
+    from paper_2309_04909_amd import bicop as B
+    assert B.default_prime(lx) == OP.default_prime(lx)
+
+
+def test_default_prime_out_of_range():
+    from paper_2309_04909_amd import bicop as B
+    assert B.default_prime(0) == 0 and B.default_prime(33) == 0
+
+
+CASES_OK = [(64, 7, 11, 0), (64, 18, 13, 0), (64, 32, 0, 0), (51, 11, 13, 0), (24, 7, 10, 0), (32, 8, 8, 509),
+            (2, 1, 0, 3)]
+CASES_BAD = [((65, 7, 0, 0), -2), ((0, 1, 0, 0), -2), ((64, 0, 0, 0), -3), ((64, 33, 0, 0), -3),
+             ((64, 18, 29, 0), -3), ((64, 7, 0, 257), -4), ((64, 7, 0, 255), -4), ((64, 7, 0, 509), -4)]
+
+
+def test_check_params_accepts_and_resolves():
+    from paper_2309_04909_amd import bicop as B
+    for ell, lx, k, p in CASES_OK:
+        r = B.Params(ell, lx, k, p).resolved()
+        assert r.p == (p or OP.default_prime(lx))
+        OP.check_drelu(ell, lx, k, r.p)          # the oracle accepts the same setting
+
+
+def test_check_params_rejects_like_oracle():
+    from paper_2309_04909_amd import bicop as B
+    for (ell, lx, k, p), code in CASES_BAD:
+        with pytest.raises(B.BicopError) as ei:
+            B.Params(ell, lx, k, p).resolved()
+        assert ei.value.code == code
+        with pytest.raises(ValueError):
+            OP.check_drelu(ell, lx, k, p or (OP.default_prime(lx) if 1 <= lx <= 32 else 3))
+
+
+@pytest.mark.parametrize("op", ["drelu", "relu"])
+@pytest.mark.parametrize("ell,lx,k", [(64, 7, 11), (64, 18, 13), (64, 31, 0), (64, 32, 0), (24, 7, 10)])
+def test_msg_account_matches_oracle(op, ell, lx, k):
+    from paper_2309_04909_amd import bicop as B
+    n = 1000
+    a = B.msg_account(B.BC_OP_DRELU if op == "drelu" else B.BC_OP_RELU, B.Params(ell, lx, k), n)
+    bits, rounds = OPR.msg_bits(op, ell, lx, OP.default_prime(lx))
+    assert [a["bits"][l] for l in B.LINKS] == [b * n for b in bits]
+    assert a["rounds"] == rounds
+    wbytes = 4 if OP.default_prime(lx) < (1 << 32) else 8
+    assert a["stored_bytes"]["P0->P2"] == (lx + 1) * wbytes * n
+
+
+def test_tab1_row_through_the_abi():
+    from paper_2309_04909_amd import bicop as B
+    a = B.msg_account(B.BC_OP_DRELU, B.Params(64, 7, 11), 1)
+    assert a["bits"]["P0->P2"] == 64 and a["rounds"] == 2
+
+
+def test_error_paths_without_gpu():
+    """Invalid arguments are rejected on the host before any GPU work.  Every call
+    here fails validation (or has n = 0), so nothing is launched even on a GPU machine."""
+    from paper_2309_04909_amd import bicop as B
+    L = B.lib
+    assert L.bc_trunc_det(None, None, None, None, 10, 65, 1, 0, None) == -2
+    assert L.bc_trunc_det(None, None, None, None, 10, 64, 40, 24, None) == -2
+    assert L.bc_trunc_det(None, None, None, None, 10, 64, 13, 0, None) == -1
+    assert L.bc_trunc_det(None, None, None, None, 0, 64, 13, 0, None) == 0
+    assert L.bc_trunc_prob(None, None, None, None, 10, 64, 64, None) == -2
+    assert L.bc_mod_switch(None, None, None, None, 10, 7, 256, None) == -4
+    assert L.bc_mod_switch(None, None, None, None, 10, 7, 251, None) == -1
+    assert L.bc_mod_switch(None, None, None, None, 10, 64, 3, None) == -2
+    assert L.bc_prg_blocks(None, 10, 0, 1, 2, 3, 0, None) == -8
+    assert L.bc_prg_blocks(None, 10, 1, 1, 2, 256, 0, None) == -8
+    prm = B.Params(64, 7, 11).c()
+    sd = B.Seeds(1, 2, 3).c()
+    assert L.bc_drelu(None, None, None, None, 10, ctypes.byref(prm), None, 0, None, None, None) == -1
+    assert L.bc_drelu(None, None, None, None, 10, ctypes.byref(prm), ctypes.byref(sd), 0, None, None, None) == -1
+    assert L.bc_drelu(None, None, None, None, 10, ctypes.byref(prm), ctypes.byref(sd), (1 << 48) - 5, None, None,
+                      None) == -8
+    assert L.bc_relu(None, None, None, None, 0, ctypes.byref(prm), ctypes.byref(sd), 0, None, None, None) == 0
+    L.bc_drelu(None, None, None, None, 10, ctypes.byref(prm), ctypes.byref(sd), 1 << 48, None, None, None)
+    assert "2^48" in B.lib.bc_last_error().decode()
+    bad = B.Params(64, 7, 0, 0).c()
+    bad.reserved = 1
+    assert L.bc_drelu(None, None, None, None, 1, ctypes.byref(bad), ctypes.byref(sd), 0, None, None, None) == -8

@@ -1,0 +1,216 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, bit-exact.
+
+All arithmetic is integer, so the bar is equality of every output share and
+every captured round-1 message (tolerance 0).  Sizes span several thread
+blocks and a ragged tail; unaligned views exercise the scalar path of the
+streaming kernels; element indices cross 2^32.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import philox as OPH
+from oracle import protocols as OPR
+from oracle.params import default_prime
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_04909_amd import bicop
+    return bicop
+
+
+def dev(a):
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.uint64:
+        return torch.from_numpy(a.view(np.int64)).cuda()
+    if a.dtype == np.uint32:
+        return torch.from_numpy(a.view(np.int32)).cuda()
+    raise TypeError(a.dtype)
+
+
+def host(t):
+    t = t.detach().cpu()
+    if t.element_size() == 8:
+        return t.view(torch.int64).numpy().view(np.uint64)
+    return t.view(torch.int32).numpy().view(np.uint32)
+
+
+def rand_ring(rng, n, ell):
+    v = rng.integers(0, 1 << 63, size=n, dtype=np.uint64) * np.uint64(2) + rng.integers(0, 2, size=n, dtype=np.uint64)
+    if ell < 64:
+        v &= np.uint64((1 << ell) - 1)
+    return v.astype(W.storage_dtype(ell))
+
+
+SIZES = [1, 7, 256, 1023, 4097, 65537]
+
+
+# --------------------------------------------------------------------- PRG
+
+
+@pytest.mark.parametrize("tag", [1, 2, 3, 4, 200])
+def test_prg_blocks_match_oracle(B, tag):
+    for elem_base, n, nb in [(0, 5000, 3), ((1 << 32) - 100, 300, 2), ((1 << 47) + 12345, 64, 9)]:
+        seed, nonce = 0xDEADBEEF12345678 ^ tag, 0x0123456789ABCDEF + elem_base
+        got = host(B.prg_blocks(n, nb, seed, nonce, tag, elem_base)).reshape(n, nb, 4)
+        g = np.arange(n, dtype=np.uint64) + np.uint64(elem_base)
+        for b in range(nb):
+            exp = np.stack(OPH.block(seed, nonce, g, tag, b), axis=1).astype(np.uint32)
+            assert np.array_equal(got[:, b, :], exp), (elem_base, b)
+
+
+# ----------------------------------------------------------- streaming kernels
+
+
+TRUNC_CASES = [(64, 13, 0), (64, 13, 5), (64, 40, 0), (64, 33, 8), (51, 13, 0), (40, 8, 0), (32, 8, 0),
+               (32, 4, 4), (24, 3, 1), (16, 4, 0), (8, 4, 1), (63, 1, 61), (64, 0, 0)]
+
+
+@pytest.mark.parametrize("ell,k1,k2", TRUNC_CASES)
+def test_trunc_det_parity(B, ell, k1, k2):
+    rng = np.random.default_rng(ell * 100 + k1 * 10 + k2)
+    for n in SIZES:
+        x0, x1 = rand_ring(rng, n, ell), rand_ring(rng, n, ell)
+        y0, y1 = B.trunc_det(dev(x0), dev(x1), ell, k1, k2)
+        e0, e1 = OPR.trunc_det(x0.astype(np.uint64), x1.astype(np.uint64), ell, k1, k2)
+        assert np.array_equal(host(y0).astype(np.uint64), e0) and np.array_equal(host(y1).astype(np.uint64), e1)
+
+
+@pytest.mark.parametrize("ell,k", [(64, 13), (64, 26), (64, 63), (51, 13), (32, 8), (20, 7), (8, 4)])
+def test_trunc_prob_parity(B, ell, k):
+    rng = np.random.default_rng(ell + k)
+    for n in SIZES:
+        x0, x1 = rand_ring(rng, n, ell), rand_ring(rng, n, ell)
+        y0, y1 = B.trunc_prob(dev(x0), dev(x1), ell, k)
+        e0, e1 = OPR.trunc_prob(x0.astype(np.uint64), x1.astype(np.uint64), ell, k)
+        assert np.array_equal(host(y0).astype(np.uint64), e0) and np.array_equal(host(y1).astype(np.uint64), e1)
+
+
+@pytest.mark.parametrize("ell", [2, 7, 11, 18, 24, 31, 32, 33, 40, 62])
+def test_mod_switch_parity(B, ell):
+    rng = np.random.default_rng(ell)
+    p = default_prime(ell) if ell <= 32 else _prime_above(ell)
+    for n in SIZES:
+        x0, x1 = rand_ring(rng, n, ell), rand_ring(rng, n, ell)
+        x0[: n // 4] = 0                                          # exercise the P0 zero case
+        y0, y1 = B.mod_switch(dev(x0), dev(x1), ell, p)
+        e0, e1 = OPR.mod_switch(x0.astype(np.uint64), x1.astype(np.uint64), ell, p)
+        assert np.array_equal(host(y0).astype(object), np.asarray(e0, dtype=object))
+        assert np.array_equal(host(y1).astype(object), np.asarray(e1, dtype=object))
+
+
+def _prime_above(ell):
+    import sympy
+    return int(sympy.prevprime(1 << (ell + 1)))
+
+
+def test_streaming_unaligned_views_and_inplace(B):
+    rng = np.random.default_rng(9)
+    n = 10001
+    x0, x1 = rand_ring(rng, n + 1, 64), rand_ring(rng, n + 1, 64)
+    d0, d1 = dev(x0), dev(x1)
+    y0, y1 = B.trunc_det(d0[1:], d1[1:], 64, 13, 0)               # 8-byte, not 16-byte aligned
+    e0, e1 = OPR.trunc_det(x0[1:], x1[1:], 64, 13, 0)
+    assert np.array_equal(host(y0), e0) and np.array_equal(host(y1), e1)
+    z0, z1 = d0.clone(), d1.clone()
+    B.trunc_prob(z0, z1, 64, 13, out=(z0, z1))                     # in place
+    e0, e1 = OPR.trunc_prob(x0, x1, 64, 13)
+    assert np.array_equal(host(z0), e0) and np.array_equal(host(z1), e1)
+
+
+def test_zero_length_is_noop(B):
+    e = torch.empty(0, dtype=torch.int64, device="cuda")
+    y0, y1 = B.trunc_det(e, e, 64, 13)
+    assert y0.numel() == 0
+    y0, y1 = B.drelu(e, e, B.Params(64, 7, 11), B.Seeds(1, 2, 3))
+    assert y0.numel() == 0
+
+
+# ------------------------------------------------------------- DReLU / ReLU
+
+# (ell, lx, k_lo): every window-count bucket of both storage widths
+DRELU_CASES = [(64, 7, 11), (64, 7, 0), (64, 11, 13), (64, 15, 10), (64, 18, 13), (64, 22, 5), (64, 27, 0),
+               (64, 31, 0), (64, 32, 0), (51, 11, 13), (40, 19, 2), (33, 16, 1),
+               (32, 8, 8), (24, 7, 10), (32, 15, 2), (32, 16, 0), (16, 5, 3), (8, 3, 1)]
+
+
+def _inputs(rng, n, ell, lx, k_lo):
+    """Half inside the guard domain, a band near zero, the rest arbitrary ring elements."""
+    bound = 1 << (k_lo + lx - 1)
+    xs = rng.integers(-bound + 1, bound, size=n)
+    x = np.array([v % (1 << ell) for v in xs.tolist()], dtype=np.uint64)
+    x[: n // 8] = np.array([v % (1 << ell) for v in rng.integers(-(1 << k_lo) - 2, (1 << k_lo) + 3, size=n // 8).tolist()],
+                           dtype=np.uint64)
+    arb = rand_ring(rng, n, ell).astype(np.uint64)
+    x[n // 2:] = arb[n // 2:]
+    x[0] = 0
+    R = rand_ring(rng, n, ell).astype(np.uint64)
+    m = np.uint64((1 << ell) - 1) if ell < 64 else np.uint64(0xFFFFFFFFFFFFFFFF)
+    x0 = (x + R) & m
+    x1 = ((~R) + np.uint64(1)) & m
+    dt = W.storage_dtype(ell)
+    return x0.astype(dt), x1.astype(dt)
+
+
+@pytest.mark.parametrize("op", ["drelu", "relu"])
+@pytest.mark.parametrize("ell,lx,k_lo", DRELU_CASES)
+def test_drelu_relu_parity_with_capture(B, op, ell, lx, k_lo):
+    rng = np.random.default_rng(ell * 1000 + lx * 10 + k_lo)
+    p = default_prime(lx)
+    seeds = (0x9E3779B97F4A7C15 + lx, 0xC2B2AE3D27D4EB4F + ell, 0x165667B19E3779F9 + k_lo)
+    nonce = 0xFEEDFACECAFEBEEF ^ (ell << 8)
+    prm, sd = B.Params(ell, lx, k_lo), B.Seeds(*seeds, nonce)
+    for n, elem_base in [(1, 0), (257, 3), (3001, (1 << 32) - 1500)]:
+        x0, x1 = _inputs(rng, n, ell, lx, k_lo)
+        fn = B.drelu if op == "drelu" else B.relu
+        y0, y1, cap = fn(dev(x0), dev(x1), prm, sd, elem_base=elem_base, capture=True)
+        ofn = OPR.drelu if op == "drelu" else OPR.relu
+        e0, e1, w0, w1 = ofn(x0.astype(np.uint64), x1.astype(np.uint64), ell, lx, k_lo, p, seeds, nonce,
+                             elem_base=elem_base)
+        assert np.array_equal(host(y0).astype(np.uint64), e0), (n, elem_base)
+        assert np.array_equal(host(y1).astype(np.uint64), e1), (n, elem_base)
+        c = host(cap).astype(object).reshape(2, n, lx + 1)
+        assert np.array_equal(c[0], np.asarray(w0, dtype=object)), "P0 messages"
+        assert np.array_equal(c[1], np.asarray(w1, dtype=object)), "P1 messages"
+        # the same call without capture gives the same outputs
+        z0, z1 = fn(dev(x0), dev(x1), prm, sd, elem_base=elem_base)
+        assert torch.equal(z0, y0) and torch.equal(z1, y1)
+
+
+def test_drelu_explicit_prime_and_inplace(B):
+    rng = np.random.default_rng(77)
+    ell, lx, k_lo, p = 64, 18, 13, 524269          # a non-Mersenne prime in (2^18, 2^19)
+    import sympy
+    assert sympy.isprime(p)
+    n = 5000
+    x0, x1 = _inputs(rng, n, ell, lx, k_lo)
+    seeds = (11, 22, 33)
+    d0, d1 = dev(x0), dev(x1)
+    y0, y1 = B.drelu(d0, d1, B.Params(ell, lx, k_lo, p), B.Seeds(*seeds, 44), out=(d0, d1))
+    e0, e1, _, _ = OPR.drelu(x0, x1, ell, lx, k_lo, p, seeds, 44)
+    assert np.array_equal(host(d0), e0) and np.array_equal(host(d1), e1)
+
+
+def test_drelu_semantics_on_gpu(B):
+    """Reconstructed GPU DReLU equals the sign bit outside the key-bit band (guard domain)."""
+    rng = np.random.default_rng(5)
+    ell, lx, k_lo = 64, 18, 13
+    n = 200000
+    xi = W.keybit_values(rng, n)
+    x = W.encode(xi, 64)
+    x0, x1 = W.share(x, 64, rng)
+    y0, y1 = B.drelu(dev(x0), dev(x1), B.Params(ell, lx, k_lo), B.Seeds(1, 2, 3, 4))
+    y = host(y0) + host(y1)
+    outside = np.abs(xi) >= (1 << k_lo)
+    assert np.array_equal(y[outside], (xi[outside] > 0).astype(np.uint64))
+    r0, r1 = B.relu(dev(x0), dev(x1), B.Params(ell, lx, k_lo), B.Seeds(1, 2, 3, 4))
+    r = host(r0) + host(r1)
+    assert np.array_equal(r, x * y)
