@@ -167,10 +167,17 @@ int drelu_common(uint32_t op, const void* x0, const void* x1, void* y0, void* y1
     L.grid = (int)(grid < cap ? grid : cap);
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
-    if (r.ell > 32)
-        e = op == BC_OP_RELU ? bc::launch_relu_u64(L, st) : bc::launch_drelu_u64(L, st);
-    else
-        e = op == BC_OP_RELU ? bc::launch_relu_u32(L, st) : bc::launch_drelu_u32(L, st);
+    const bool relu = op == BC_OP_RELU;
+    if (r.ell > 32) {
+        if (L.npos <= 12)
+            e = relu ? bc::launch_relu_u64_lo(L, st) : bc::launch_drelu_u64_lo(L, st);
+        else if (L.npos <= 24)
+            e = relu ? bc::launch_relu_u64_mid(L, st) : bc::launch_drelu_u64_mid(L, st);
+        else
+            e = relu ? bc::launch_relu_u64_hi(L, st) : bc::launch_drelu_u64_hi(L, st);
+    } else {
+        e = relu ? bc::launch_relu_u32(L, st) : bc::launch_drelu_u32(L, st);
+    }
     if (e != hipSuccess) return hip_fail(e, op == BC_OP_RELU ? "relu launch" : "drelu launch");
     return BC_OK;
 }

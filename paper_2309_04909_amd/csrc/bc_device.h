@@ -5,8 +5,8 @@
 //  * Modular multiplication in Z_p for the four prime sizes the window width
 //    l_x produces (p has l_x + 1 bits, notation table):
 //      FieldSmall  p < 2^12   products < 2^24: one 24-bit multiply, fp32 quotient
-//      Field24     p < 2^24   48-bit products from two 24-bit multiplies,
-//                             Mersenne fold or fp64 quotient
+//      FieldMersenne<K>  p = 2^K - 1 < 2^24: one fold
+//      Field24     p < 2^24   products exact in fp64, fp64 quotient
 //      Field32     p < 2^32   64-bit products, Barrett with a 64-bit reciprocal
 //      Field64     p < 2^34   l_x = 32; 66-bit products, fp64 quotient
 //  * A Batcher odd-even merge sorting network over NMAX keys, generated at
@@ -61,7 +61,13 @@ struct Stream {
     uint32_t n0, n1;   // (c2, c3) = nonce
     __device__ __forceinline__ Words4 block(uint64_t g, uint32_t tag, uint32_t b) const {
         const uint32_t c1 = ((uint32_t)(g >> 32) & 0xFFFFu) | (tag << 16) | (b << 24);
-        return philox4x32_10((uint32_t)g, c1, n0, n1, k0, k1);
+        // The key is uniform.  Passing it through an empty asm stops the
+        // compiler from hoisting all round keys of every seed out of the
+        // element loop (which exhausts SGPRs); each block recomputes its round
+        // keys with scalar adds instead.
+        uint32_t a = k0, c = k1;
+        asm volatile("" : "+s"(a), "+s"(c));
+        return philox4x32_10((uint32_t)g, c1, n0, n1, a, c);
     }
 };
 
@@ -75,6 +81,7 @@ __device__ __forceinline__ uint64_t join64(uint32_t lo, uint32_t hi) {
 // fp32.  The fp32 quotient is within one of floor(x / p); two corrections.
 struct FieldSmall {
     using T = uint32_t;
+    static constexpr bool kWrap = false;
     uint32_t p;
     float pinv;
     __device__ __forceinline__ uint32_t reduce24(uint32_t x) const {   // x < 2^24
@@ -87,24 +94,30 @@ struct FieldSmall {
     __device__ __forceinline__ uint32_t mul(uint32_t a, uint32_t b) const { return reduce24(__umul24(a, b)); }
 };
 
-// p < 2^24.  a*b < 2^48 from the low and high halves of the 24-bit multiply.
-// Mersenne primes 2^k - 1 fold the product once: since a, b < p,
-// (x mod 2^k) + (x >> k) < 2p.  Other primes take an fp64 quotient (the
-// product is exact in fp64) that is within one of floor(x / p).
+// p < 2^24, p = 2^K - 1 (Mersenne).  a*b < 2^48 from one 64-bit multiply;
+// since a, b < p, (x mod 2^K) + (x >> K) < 2p, so one fold and one
+// conditional subtraction reduce it.
+template <int K>
+struct FieldMersenne {
+    using T = uint32_t;
+    static constexpr bool kWrap = false;
+    uint32_t p;   // 2^K - 1
+    __device__ __forceinline__ uint32_t mul(uint32_t a, uint32_t b) const {
+        const uint64_t x = (uint64_t)a * b;
+        const uint32_t s = ((uint32_t)x & p) + (uint32_t)(x >> K);
+        return s >= p ? s - p : s;
+    }
+};
+
+// p < 2^24, any prime.  a*b < 2^48 is exact in fp64; an fp64 quotient is
+// within one of floor(x / p), and the remainder from an fma is exact.
 struct Field24 {
     using T = uint32_t;
+    static constexpr bool kWrap = false;
     uint32_t p;
-    uint32_t mers_k;   // k if p = 2^k - 1, else 0
     double pd, pinv;
     __device__ __forceinline__ uint32_t mul(uint32_t a, uint32_t b) const {
-        const uint64_t x = (uint64_t)(a & 0xFFFFFFu) * (uint64_t)(b & 0xFFFFFFu);
-        if (mers_k) {
-            const uint32_t lo = (uint32_t)x & p;
-            const uint32_t hi = (uint32_t)(x >> mers_k);
-            const uint32_t s = lo + hi;
-            return s >= p ? s - p : s;
-        }
-        const double xd = (double)x;
+        const double xd = (double)a * (double)b;
         const double q = __builtin_floor(xd * pinv);
         double r = __builtin_fma(-q, pd, xd);
         r = r < 0.0 ? r + pd : r;
@@ -117,6 +130,7 @@ struct Field24 {
 // two of floor(x / p).
 struct Field32 {
     using T = uint32_t;
+    static constexpr bool kWrap = true;   // p may exceed 2^31: a + b can wrap
     uint32_t p;
     uint64_t mu;
     __device__ __forceinline__ uint32_t mul(uint32_t a, uint32_t b) const {
@@ -133,6 +147,7 @@ struct Field32 {
 // quotient of x / p (< 2^34, relative error 2^-51) is within one of the floor.
 struct Field64 {
     using T = uint64_t;
+    static constexpr bool kWrap = false;
     uint64_t p;
     double pd, pinv;
     __device__ __forceinline__ uint64_t mul(uint64_t a, uint64_t b) const {
@@ -148,30 +163,19 @@ struct Field64 {
     }
 };
 
+// a < p, b <= p.  When p may exceed 2^31 the 32-bit sum can wrap; a wrapped
+// sum is >= 2^32 > p, so it also takes the subtraction (exact mod 2^32).
 template <typename F>
 __device__ __forceinline__ typename F::T addmod(typename F::T a, typename F::T b, const F& f) {
-    const typename F::T s = a + b;   // a, b <= p and p < 2^34: no wrap
+    const typename F::T s = a + b;
+    if constexpr (F::kWrap) return (s < a || s >= f.p) ? s - f.p : s;
     return s >= f.p ? s - f.p : s;
 }
 
-// r_s in Z_p^* and z_s in Z_p by multiply-shift of uniform words.
-template <typename F>
-struct Draw;
-template <>
-struct Draw<FieldSmall> {
-    __device__ static __forceinline__ uint32_t r(uint32_t R, const FieldSmall& f) { return 1u + __umulhi(R, f.p - 1u); }
-    __device__ static __forceinline__ uint32_t z(uint32_t Z, const FieldSmall& f) { return __umulhi(Z, f.p); }
-};
-template <>
-struct Draw<Field24> {
-    __device__ static __forceinline__ uint32_t r(uint32_t R, const Field24& f) { return 1u + __umulhi(R, f.p - 1u); }
-    __device__ static __forceinline__ uint32_t z(uint32_t Z, const Field24& f) { return __umulhi(Z, f.p); }
-};
-template <>
-struct Draw<Field32> {
-    __device__ static __forceinline__ uint32_t r(uint32_t R, const Field32& f) { return 1u + __umulhi(R, f.p - 1u); }
-    __device__ static __forceinline__ uint32_t z(uint32_t Z, const Field32& f) { return __umulhi(Z, f.p); }
-};
+// r_s in Z_p^* and z_s in Z_p by multiply-shift of uniform 32-bit words
+// (p < 2^32): r = 1 + floor(R (p - 1) / 2^32), z = floor(Z p / 2^32).
+__device__ __forceinline__ uint32_t draw_r(uint32_t R, uint32_t p) { return 1u + __umulhi(R, p - 1u); }
+__device__ __forceinline__ uint32_t draw_z(uint32_t Z, uint32_t p) { return __umulhi(Z, p); }
 
 // ---------------------------------------------------------- sorting network
 

@@ -14,7 +14,8 @@
 // ReLU replaces steps 10-11 by the Beaver product of Alg. 8 with the
 // triple generated from seed_02 / seed_12 and the unflipped input shares.
 //
-// The l_x + 1 window values never leave VGPRs.  The shuffle is applied by
+// The l_x + 1 window values never leave VGPRs.  Kernels are instantiated per
+// window count N = l_x + 1, so every loop over windows is unrolled.  The shuffle is applied by
 // computing, for slot s, the window of the position the sorted key names:
 // the message in slot s is v_{sigma(s)} r_s + z_s, exactly the shuffled and
 // masked array of steps 6-8.  With a capture pointer the same code also
@@ -37,26 +38,28 @@ struct DreluKArgs {
     uint64_t n;
     uint64_t elem_base;
     uint64_t ring_mask;   // 2^l - 1
-    uint32_t lx, k_lo, npos, pad;
+    uint32_t k_lo, pad;
     Stream s01, s02, s12;
 };
 
-template <typename T, int NMAX, typename F, bool RELU, bool CAP>
+// N = l_x + 1 windows, fixed at compile time: every loop over windows and
+// slots is unrolled and all window masks are constants.
+template <typename T, int N, typename F, bool RELU, bool CAP>
 __global__ __launch_bounds__(256) void k_drelu(DreluKArgs A, F f) {
     using FT = typename F::T;
+    constexpr int LX = N - 1;
     constexpr bool WIDE = std::is_same<FT, uint64_t>::value;
+    constexpr FT TWO_LX = (FT)1 << LX;                   // 2^l_x mod p = 2^l_x
+    constexpr FT WIN = TWO_LX - 1;                       // Z_{2^l_x}
+    constexpr FT WIN1 = (FT)((2ull << LX) - 1);          // l_x + 1 bits
+    static_assert(WIDE == (N == 33), "64-bit field elements exactly when l_x = 32");
     const T* __restrict__ X0 = static_cast<const T*>(A.x0);
     const T* __restrict__ X1 = static_cast<const T*>(A.x1);
     T* Y0 = static_cast<T*>(A.y0);
     T* Y1 = static_cast<T*>(A.y1);
     const T mask = (T)A.ring_mask;
-    const uint32_t lx = A.lx;
     const uint32_t k_lo = A.k_lo;
-    const uint32_t npos = A.npos;
-    const FT two_lx = (FT)1 << lx;                       // 2^l_x mod p = 2^l_x
-    const FT p_minus_two = f.p - two_lx;
-    const FT win_mask = two_lx - 1;                      // Z_{2^l_x}
-    const FT win1_mask = WIDE ? (FT)((1ull << 33) - 1) : (FT)((two_lx << 1) - 1);   // l_x + 1 bits
+    const FT p_minus_two = f.p - TWO_LX;
 
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < A.n; e += stride) {
@@ -65,26 +68,18 @@ __global__ __launch_bounds__(256) void k_drelu(DreluKArgs A, F f) {
         const T in1 = X1[e] & mask;
 
         // Steps 1 and 6 (randomness): t and the shuffle keys from seed_01.
-        uint32_t key[NMAX];
+        uint32_t key[N];
         uint32_t t = 0;
 #pragma unroll
-        for (int b = 0; b < (NMAX + 3) / 4; ++b) {
-            if (4 * b < (int)npos) {
-                const Words4 w = A.s01.block(g, TAG_SHUFFLE, b);
-                if (b == 0) t = w.w0 & 1u;
-                const uint32_t ws[4] = {w.w0, w.w1, w.w2, w.w3};
+        for (int b = 0; b < (N + 3) / 4; ++b) {
+            const Words4 w = A.s01.block(g, TAG_SHUFFLE, b);
+            if (b == 0) t = w.w0 & 1u;
+            const uint32_t ws[4] = {w.w0, w.w1, w.w2, w.w3};
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (4 * b + q < NMAX)
-                        key[4 * b + q] = (4 * b + q < (int)npos) ? ((ws[q] & ~63u) | (uint32_t)(4 * b + q)) : 0xFFFFFFFFu;
-                }
-            } else {
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (4 * b + q < NMAX) key[4 * b + q] = 0xFFFFFFFFu;
-            }
+            for (int q = 0; q < 4; ++q)
+                if (4 * b + q < N) key[4 * b + q] = (ws[q] & ~63u) | (uint32_t)(4 * b + q);
         }
-        sort_keys<NMAX>(key);
+        sort_keys<N>(key);
 
         // Step 2: [x] := (-1)^t [x]  (both parties).
         const T a0 = t ? (T)((T)0 - in0) & mask : in0;
@@ -94,43 +89,41 @@ __global__ __launch_bounds__(256) void k_drelu(DreluKArgs A, F f) {
         bool zero = false;
         Words4 wm = {0, 0, 0, 0};
 #pragma unroll
-        for (int j = 0; j < NMAX; ++j) {
-            if (j < (int)npos) {
-                // Steps 7-8 randomness of slot j.
-                FT r, z;
-                if constexpr (WIDE) {
-                    const Words4 w = A.s01.block(g, TAG_MASK, (uint32_t)j);
-                    r = 1 + __umul64hi(join64(w.w0, w.w1), f.p - 1);
-                    z = __umul64hi(join64(w.w2, w.w3), f.p);
-                } else {
-                    if ((j & 1) == 0) wm = A.s01.block(g, TAG_MASK, (uint32_t)(j >> 1));
-                    r = Draw<F>::r((j & 1) ? wm.w2 : wm.w0, f);
-                    z = Draw<F>::z((j & 1) ? wm.w3 : wm.w1, f);
-                }
-                // Steps 3-4 for the position sigma(j) placed in slot j.
-                const uint32_t pos = key[j] & 63u;
-                const uint32_t s = k_lo + pos;
-                const bool last = pos == lx;                  // u_{l_x+1} := 0
-                const FT W0 = (FT)(a0 >> s) & win1_mask;      // bits [s, s + l_x]
-                const FT W1 = (FT)(nb1 >> s) & win1_mask;
-                const FT u0n = last ? (FT)0 : (W0 >> 1);      // u_{i+1} of P0
-                const FT u1n = last ? (FT)0 : (W1 >> 1);
-                const FT v0 = (W0 + u0n - 1) & win_mask;              // u_i + u_{i+1} - 1
-                const FT v1 = ((FT)0 - W1 - u1n) & win_mask;          // -(cut_i) - (cut_{i+1})
-                // Step 5: Alg. 6.
-                const FT s0 = v0 ? v0 : two_lx;
-                const FT s1 = v1 + p_minus_two;
-                // Steps 7-8: mask and reshare.
-                const FT w0 = addmod(f.mul(s0, r), z, f);
-                const FT w1 = addmod(f.mul(s1, r), (FT)(f.p - z), f);
-                if constexpr (CAP) {
-                    FT* C = static_cast<FT*>(A.cap);
-                    C[e * npos + (uint64_t)j] = w0;
-                    C[(A.n + e) * npos + (uint64_t)j] = w1;
-                }
-                // Step 9 (P2): reconstruct and test for zero.
-                zero |= addmod(w0, w1, f) == 0;
+        for (int j = 0; j < N; ++j) {
+            // Steps 7-8 randomness of slot j.
+            FT r, z;
+            if constexpr (WIDE) {
+                const Words4 w = A.s01.block(g, TAG_MASK, (uint32_t)j);
+                r = 1 + __umul64hi(join64(w.w0, w.w1), f.p - 1);
+                z = __umul64hi(join64(w.w2, w.w3), f.p);
+            } else {
+                if ((j & 1) == 0) wm = A.s01.block(g, TAG_MASK, (uint32_t)(j >> 1));
+                r = draw_r((j & 1) ? wm.w2 : wm.w0, f.p);
+                z = draw_z((j & 1) ? wm.w3 : wm.w1, f.p);
             }
+            // Steps 3-4 for the position sigma(j) placed in slot j.
+            const uint32_t pos = key[j] & 63u;
+            const uint32_t s = k_lo + pos;
+            const bool last = pos == (uint32_t)LX;        // u_{l_x+1} := 0
+            const FT W0 = (FT)(a0 >> s) & WIN1;           // bits [s, s + l_x]
+            const FT W1 = (FT)(nb1 >> s) & WIN1;
+            const FT u0n = last ? (FT)0 : (W0 >> 1);      // u_{i+1}
+            const FT u1n = last ? (FT)0 : (W1 >> 1);
+            const FT v0 = (W0 + u0n - 1) & WIN;           // u_i + u_{i+1} - 1
+            const FT v1 = ((FT)0 - W1 - u1n) & WIN;       // P1: -cut_i - cut_{i+1}
+            // Step 5: Alg. 6.
+            const FT s0 = v0 ? v0 : TWO_LX;
+            const FT s1 = v1 + p_minus_two;
+            // Steps 7-8: mask and reshare.
+            const FT w0 = addmod(f.mul(s0, r), z, f);
+            const FT w1 = addmod(f.mul(s1, r), (FT)(f.p - z), f);
+            if constexpr (CAP) {
+                FT* C = static_cast<FT*>(A.cap);
+                C[e * N + j] = w0;
+                C[(A.n + e) * N + j] = w1;
+            }
+            // Step 9 (P2): reconstruct and test for zero.
+            zero |= addmod(w0, w1, f) == 0;
         }
         const T dp = zero ? 1 : 0;
 
@@ -172,13 +165,7 @@ __global__ __launch_bounds__(256) void k_drelu(DreluKArgs A, F f) {
 
 // Host helpers: field parameters for each prime size.
 inline FieldSmall make_field_small(uint64_t p) { return FieldSmall{(uint32_t)p, 1.0f / (float)p}; }
-inline Field24 make_field24(uint64_t p) {
-    uint32_t k = 0;
-    if (((p + 1) & p) == 0) {   // p = 2^k - 1
-        while ((1ull << k) - 1 != p) ++k;
-    }
-    return Field24{(uint32_t)p, k, (double)p, 1.0 / (double)p};
-}
+inline Field24 make_field24(uint64_t p) { return Field24{(uint32_t)p, (double)p, 1.0 / (double)p}; }
 inline Field32 make_field32(uint64_t p) { return Field32{(uint32_t)p, UINT64_MAX / p}; }
 inline Field64 make_field64(uint64_t p) { return Field64{p, (double)p, 1.0 / (double)p}; }
 
@@ -192,9 +179,7 @@ inline DreluKArgs make_kargs(const DreluLaunch& L) {
     A.n = L.n;
     A.elem_base = L.elem_base;
     A.ring_mask = L.ell >= 64 ? ~0ull : ((1ull << L.ell) - 1);
-    A.lx = L.lx;
     A.k_lo = L.k_lo;
-    A.npos = L.npos;
     A.pad = 0;
     A.s01 = Stream{L.s01.k0, L.s01.k1, L.s01.n0, L.s01.n1};
     A.s02 = Stream{L.s02.k0, L.s02.k1, L.s02.n0, L.s02.n1};
@@ -202,14 +187,45 @@ inline DreluKArgs make_kargs(const DreluLaunch& L) {
     return A;
 }
 
-template <typename T, int NMAX, typename F, bool RELU>
-hipError_t launch_bucket(const DreluLaunch& L, const F& f, hipStream_t st) {
+template <typename T, int N, typename F, bool RELU>
+hipError_t launch_field(const DreluLaunch& L, const F& f, hipStream_t st) {
     const DreluKArgs A = make_kargs(L);
     if (L.cap)
-        hipLaunchKernelGGL((k_drelu<T, NMAX, F, RELU, true>), dim3(L.grid), dim3(L.block), 0, st, A, f);
+        hipLaunchKernelGGL((k_drelu<T, N, F, RELU, true>), dim3(L.grid), dim3(L.block), 0, st, A, f);
     else
-        hipLaunchKernelGGL((k_drelu<T, NMAX, F, RELU, false>), dim3(L.grid), dim3(L.block), 0, st, A, f);
+        hipLaunchKernelGGL((k_drelu<T, N, F, RELU, false>), dim3(L.grid), dim3(L.block), 0, st, A, f);
     return hipGetLastError();
+}
+
+constexpr bool mersenne_exponent(int k) { return k == 13 || k == 17 || k == 19; }   // 2^k - 1 prime, 12 < k <= 24
+
+// The field type follows from N = l_x + 1 (p has N bits), and from p itself
+// when p is a Mersenne prime.
+template <typename T, int N, bool RELU>
+hipError_t launch_exact(const DreluLaunch& L, hipStream_t st) {
+    if constexpr (N <= 12) {
+        return launch_field<T, N, FieldSmall, RELU>(L, make_field_small(L.p), st);
+    } else if constexpr (N <= 24) {
+        if constexpr (mersenne_exponent(N)) {
+            if (L.p == (1ull << N) - 1)
+                return launch_field<T, N, FieldMersenne<N>, RELU>(L, FieldMersenne<N>{(uint32_t)L.p}, st);
+        }
+        return launch_field<T, N, Field24, RELU>(L, make_field24(L.p), st);
+    } else if constexpr (N <= 32) {
+        return launch_field<T, N, Field32, RELU>(L, make_field32(L.p), st);
+    } else {
+        return launch_field<T, N, Field64, RELU>(L, make_field64(L.p), st);
+    }
+}
+
+template <typename T, bool RELU, int NLO, int NHI>
+hipError_t launch_range(const DreluLaunch& L, hipStream_t st) {
+    if constexpr (NLO > NHI) {
+        return hipErrorInvalidValue;
+    } else {
+        if (L.npos == (uint32_t)NLO) return launch_exact<T, NLO, RELU>(L, st);
+        return launch_range<T, RELU, NLO + 1, NHI>(L, st);
+    }
 }
 
 }  // namespace bc

@@ -29,10 +29,16 @@ struct DreluLaunch {
     int block;
 };
 
-// Kernel launchers (one per op and storage width); return the launch status.
-hipError_t launch_drelu_u64(const DreluLaunch& L, hipStream_t st);
-hipError_t launch_relu_u64(const DreluLaunch& L, hipStream_t st);
-hipError_t launch_drelu_u32(const DreluLaunch& L, hipStream_t st);
+// Kernel launchers, one per op, storage width and range of N = l_x + 1 (the
+// split only spreads compilation over several files).  Each returns
+// hipErrorInvalidValue when L.npos is outside its range.
+hipError_t launch_drelu_u64_lo(const DreluLaunch& L, hipStream_t st);    // N 2..12
+hipError_t launch_drelu_u64_mid(const DreluLaunch& L, hipStream_t st);   // N 13..24
+hipError_t launch_drelu_u64_hi(const DreluLaunch& L, hipStream_t st);    // N 25..33
+hipError_t launch_relu_u64_lo(const DreluLaunch& L, hipStream_t st);
+hipError_t launch_relu_u64_mid(const DreluLaunch& L, hipStream_t st);
+hipError_t launch_relu_u64_hi(const DreluLaunch& L, hipStream_t st);
+hipError_t launch_drelu_u32(const DreluLaunch& L, hipStream_t st);       // N 2..17
 hipError_t launch_relu_u32(const DreluLaunch& L, hipStream_t st);
 
 hipError_t launch_trunc_det(const void* x0, const void* x1, void* y0, void* y1, uint64_t n,
