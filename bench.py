@@ -201,12 +201,128 @@ def run_keybit(torch, B, inputs, steps, warmup):
     return wall, {"trunc_det": timer.avg_ms("trunc_det"), "drelu": timer.avg_ms("drelu")}
 
 
+def run_batched_vs_plain(torch, B, steps, warmup, batch=32):
+    """All 17 ReLU activation tensors of a ResNet-18 pass (batch 32, 224x224):
+    one persistent launch replayed from a HIP graph vs 17 plain launches."""
+    from paper_2309_04909_amd import batch as BT
+    prm = B.Params(64, 7, 11)
+    seeds = SEEDS
+    data = W.resnet18_relu(seed=4, batch=batch)
+    segs = []
+    for i, (_, (x0, x1)) in enumerate(data):
+        d0, d1 = to_dev(torch, x0), to_dev(torch, x1)
+        segs.append(BT.Segment(d0, d1, torch.empty_like(d0), torch.empty_like(d1), op=B.BC_OP_RELU, nonce=100 + i))
+    del data
+    total = sum(s.x0.numel() for s in segs)
+    rb = BT.RaggedBatch(prm, B.Seeds(*seeds), segs)
+    graph = rb.capture()
+
+    def plain():
+        for s in segs:
+            B.relu(s.x0, s.x1, prm, B.Seeds(*seeds, s.nonce), out=(s.y0, s.y1))
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    ms_plain = timed(plain)
+    ref = [(s.y0.clone(), s.y1.clone()) for s in segs]
+    ms_batch = timed(graph.replay)
+    same = all(torch.equal(a, s.y0) and torch.equal(b, s.y1) for (a, b), s in zip(ref, segs))
+    return {"workload": f"ResNet-18 ReLU activations, batch {batch}, 224x224: 17 tensors, {total} elements, "
+                        "l=64, k_lo=11, l_x=7 (p=251)",
+            "elements": total, "plain_ms": round(ms_plain, 4), "batched_ms": round(ms_batch, 4),
+            "plain_gelem_s": round(total / ms_plain / 1e6, 3), "batched_gelem_s": round(total / ms_batch / 1e6, 3),
+            "speedup": round(ms_plain / ms_batch, 4), "identical_outputs": bool(same),
+            "batched": "one persistent launch (bc_batch_run) replayed from a HIP graph",
+            "plain": "17 bc_relu launches"}
+
+
+def run_plain_drelu(torch, B, steps, warmup):
+    """l = 64 with no key-bit reduction: l_x = 32 (all windows of the 64-bit ring) and
+    the paper's default l_x = 31, 65,536 elements (latency-bound)."""
+    _, (x0, x1) = W.plain_drelu(seed=1)
+    d0, d1 = to_dev(torch, x0), to_dev(torch, x1)
+    y0, y1 = torch.empty_like(d0), torch.empty_like(d1)
+    out = {"workload": "plain DReLU, l=64, 65,536 elements, v ~ U(-64, 64), f=13"}
+    for lx in (32, 31):
+        prm = B.Params(64, lx, 0)
+        sd = B.Seeds(*SEEDS, 11)
+        for _ in range(warmup):
+            B.drelu(d0, d1, prm, sd, out=(y0, y1))
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            B.drelu(d0, d1, prm, sd, out=(y0, y1))
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        out[f"lx{lx}_us_per_call"] = round(ms * 1e3, 2)
+        out[f"lx{lx}_gelem_s"] = round(d0.numel() / ms / 1e6, 3)
+    return out
+
+
+SERVE_PARAMS = {64: (64, 18, 13), 32: (32, 8, 8)}
+POOL_LOG2 = 24
+
+
+def serving_jobs(S, rng_seed, rate, count, pool_n):
+    """Seeded Poisson jobs (sizes log-uniform in [2^10, 2^24], op and ring 50/50);
+    rate = None puts every arrival at t = 0 (saturation)."""
+    rng = np.random.default_rng(rng_seed)
+    arr = W.serving_arrivals(rng_seed, rate or 1.0, count)
+    jobs = []
+    for i, (t, n, op, ell) in enumerate(arr):
+        off = int(rng.integers(0, pool_n - n + 1))
+        jobs.append(S.Job(i, t if rate else 0.0, n, 0 if op == "drelu" else 1, ell, off, 0x5E5E0000 + i))
+    return jobs
+
+
+def run_serving(torch, B, count=600):
+    """Continuous batching under Poisson load at 0.3/0.6/0.9 of the saturated rate."""
+    from paper_2309_04909_amd import serve as S
+    pool_n = 1 << POOL_LOG2
+    pools = {}
+    for ell in (64, 32):
+        _, (x0, x1) = W.serving_values(100 + ell, pool_n, ell)
+        pools[ell] = (to_dev(torch, x0), to_dev(torch, x1))
+    params = {ell: B.Params(*SERVE_PARAMS[ell]) for ell in (64, 32)}
+    seeds = B.Seeds(*SEEDS)
+    budget = 64 << 30
+    srv = S.Server(pools, params, seeds, hbm_budget=budget, max_slots=256, nstreams=4)
+    srv.run(serving_jobs(S, 7, None, 50, pool_n))                         # warm-up
+    sat = S.summarize(srv.run(serving_jobs(S, 8, None, count, pool_n)))
+    mean_n = (2.0 ** 24 - 2.0 ** 10) / (14 * np.log(2.0))
+    out = {"workload": f"{count} jobs per rate, sizes log-uniform [2^10, 2^24], DReLU/ReLU 50/50, "
+                       "l in {32, 64} 50/50 (l=64: k_lo=13, l_x=18; l=32: k_lo=8, l_x=8), "
+                       "inputs resident in HBM, 64 GiB admission budget, 4 streams",
+           "saturated": sat}
+    for frac in (0.3, 0.6, 0.9):
+        rate = frac * sat["gelem_s"] * 1e9 / mean_n
+        res = S.summarize(srv.run(serving_jobs(S, 9 + int(frac * 10), rate, count, pool_n)))
+        res["offered_jobs_per_s"] = round(rate, 1)
+        out[f"load_{frac}"] = res
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--sections", default="cpu", help="comma list of extra sections: cpu")
+    ap.add_argument("--sections", default="cpu,batched,plain,serving",
+                    help="comma list of extra sections: cpu, batched, plain, serving")
     ap.add_argument("--cpu-sample", type=int, default=1 << 21)
     ap.add_argument("--cpu-workers", type=int, default=min(16, os.cpu_count() or 1))
     args = ap.parse_args()
@@ -255,6 +371,12 @@ def main():
                     "drelu_gelem_s": round(c["n"] / kern["drelu"] / 1e6, 3),
                     "trunc_det_gbs": round(td_gbs, 1), "trunc_det_hbm_frac": round(td_gbs / HBM_PEAK_GBS, 4)},
     }
+    if "batched" in sections:
+        line["batched_vs_plain"] = run_batched_vs_plain(torch, B, max(3, args.steps // 5), 2)
+    if "plain" in sections:
+        line["plain_drelu"] = run_plain_drelu(torch, B, args.steps, args.warmup)
+    if "serving" in sections:
+        line["serving"] = run_serving(torch, B)
     line.update(out)
     print(json.dumps(line), flush=True)
 

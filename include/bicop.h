@@ -186,6 +186,46 @@ int bc_relu(const void* x0, const void* x1, void* y0, void* y1, uint64_t n,
             const bc_drelu_params* prm, const bc_seeds* seeds, uint64_t elem_base,
             void* capture, bc_msg_acct* acct, void* stream);
 
+/* ------------------------------------------------------ ragged batching */
+
+/* One segment of a ragged batch: a share pair of its own length, op, nonce
+ * and global element offset.  Every element of a segment gets exactly the
+ * result of bc_drelu / bc_relu on that segment with seeds->nonce = nonce and
+ * the same elem_base.  Outputs of one segment must not overlap inputs or
+ * outputs of another. */
+typedef struct {
+    const void* x0;
+    const void* x1;
+    void* y0;
+    void* y1;
+    uint64_t n;          /* elements (0 allowed)                       */
+    uint64_t elem_base;  /* global index of element 0 (n + base <= 2^48) */
+    uint64_t nonce;      /* per-segment nonce                          */
+    uint32_t op;         /* BC_OP_DRELU or BC_OP_RELU                   */
+    uint32_t reserved;   /* must be 0                                  */
+} bc_segment;
+
+/* Bytes of the plan buffer for nseg segments: a 64-byte header, the segment
+ * table (64 bytes per segment) and the first tile of every segment
+ * (8 bytes per segment, plus one). */
+uint64_t bc_batch_plan_bytes(uint32_t nseg);
+
+/* Host only.  Validates every segment against `prm` (one setting for the
+ * whole batch) and writes the plan into host memory `plan`, of plan_bytes
+ * bytes.  Each segment is cut into tiles of tile_elems elements (0 = default
+ * 1024).  The caller then copies the plan, byte for byte, to device memory
+ * it owns.  nseg in [1, 2^20]. */
+int bc_batch_plan(const bc_segment* segs, uint32_t nseg, const bc_drelu_params* prm, uint32_t tile_elems,
+                  void* plan, uint64_t plan_bytes);
+
+/* One persistent launch over every tile of the plan.  dev_plan is the
+ * device copy of host_plan (the host copy selects the kernel; the kernel
+ * reads the device copy).  seeds->seed01/02/12 apply to all segments;
+ * seeds->nonce is ignored (each segment has its own).  grid = blocks of 256
+ * threads (0 = a default filling every compute unit).  Enqueues exactly one
+ * kernel and nothing else, so it can be captured into a HIP graph. */
+int bc_batch_run(const void* dev_plan, const void* host_plan, const bc_seeds* seeds, uint32_t grid, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

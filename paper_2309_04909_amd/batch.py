@@ -1,0 +1,72 @@
+"""Ragged batches: many DReLU/ReLU share pairs in one persistent launch.
+
+A batch shares one setting (ring, window, prime) and the three seeds; each
+segment has its own length, op, nonce and global element offset, and gets
+exactly the result of a single bc_drelu / bc_relu call on it.  The plan is
+built on the host by the C ABI (bc_batch_plan), copied to device memory once,
+and every run is a single kernel launch (bc_batch_run) that a HIP graph can
+capture.
+"""
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import bicop as B
+
+
+@dataclass
+class Segment:
+    x0: torch.Tensor
+    x1: torch.Tensor
+    y0: torch.Tensor
+    y1: torch.Tensor
+    op: int = B.BC_OP_RELU
+    nonce: int = 0
+    elem_base: int = 0
+
+
+class RaggedBatch:
+    def __init__(self, params: B.Params, seeds: B.Seeds, segments, tile_elems: int = 0, grid: int = 0):
+        self.params = params
+        self.seeds = seeds
+        self.segments = list(segments)
+        self.grid = grid
+        width = B.ring_width(params.ell)
+        nseg = len(self.segments)
+        recs = (B._Segment * nseg)()
+        for i, s in enumerate(self.segments):
+            B._check_shares(s.x0, s.x1, width)
+            B._check_shares(s.y0, s.y1, width, "outputs")
+            if s.x0.numel() != s.y0.numel():
+                raise ValueError("segment input and output lengths differ")
+            m = (1 << 64) - 1
+            recs[i] = B._Segment(s.x0.data_ptr(), s.x1.data_ptr(), s.y0.data_ptr(), s.y1.data_ptr(), s.x0.numel(),
+                                 s.elem_base, s.nonce & m, s.op, 0)
+        nbytes = int(B.lib.bc_batch_plan_bytes(nseg))
+        self.host_plan = (ctypes.c_uint8 * nbytes)()
+        B._check(B.lib.bc_batch_plan(recs, nseg, ctypes.byref(params.c()), tile_elems, self.host_plan, nbytes),
+                 "batch_plan")
+        dev = self.segments[0].x0.device
+        self.dev_plan = torch.frombuffer(bytearray(self.host_plan), dtype=torch.uint8).to(dev)
+        self._c_seeds = seeds.c()
+        self.elements = sum(s.x0.numel() for s in self.segments)
+
+    def run(self, stream=None):
+        """Enqueue the one persistent launch on `stream` (default: current)."""
+        B._check(B.lib.bc_batch_run(self.dev_plan.data_ptr(), ctypes.addressof(self.host_plan),
+                                    ctypes.byref(self._c_seeds), self.grid, B._stream(stream)), "batch_run")
+
+    def capture(self):
+        """Capture run() into a CUDA/HIP graph; returns the torch.cuda.CUDAGraph."""
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            self.run()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run()
+        return g

@@ -43,6 +43,12 @@ class _Acct(ctypes.Structure):
                 ("reserved", ctypes.c_uint32)]
 
 
+class _Segment(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_void_p), ("x1", ctypes.c_void_p), ("y0", ctypes.c_void_p), ("y1", ctypes.c_void_p),
+                ("n", ctypes.c_uint64), ("elem_base", ctypes.c_uint64), ("nonce", ctypes.c_uint64),
+                ("op", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
 _P = ctypes.c_void_p
 _U64 = ctypes.c_uint64
 _U32 = ctypes.c_uint32
@@ -62,6 +68,9 @@ _SIGS = {
                   ctypes.POINTER(_Acct), _P], ctypes.c_int),
     "bc_relu": ([_P, _P, _P, _P, _U64, ctypes.POINTER(_Params), ctypes.POINTER(_Seeds), _U64, _P,
                  ctypes.POINTER(_Acct), _P], ctypes.c_int),
+    "bc_batch_plan_bytes": ([_U32], _U64),
+    "bc_batch_plan": ([ctypes.POINTER(_Segment), _U32, ctypes.POINTER(_Params), _U32, _P, _U64], ctypes.c_int),
+    "bc_batch_run": ([_P, _P, ctypes.POINTER(_Seeds), _U32, _P], ctypes.c_int),
 }
 
 EXPORTED = tuple(_SIGS)

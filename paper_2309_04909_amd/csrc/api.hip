@@ -182,6 +182,85 @@ int drelu_common(uint32_t op, const void* x0, const void* x1, void* y0, void* y1
     return BC_OK;
 }
 
+int batch_plan(const bc_segment* segs, uint32_t nseg, const bc_drelu_params* prm, uint32_t tile_elems, void* plan,
+               uint64_t plan_bytes) {
+    if (!segs || !plan) return fail(BC_ERR_NULL, "segments or plan is NULL");
+    if (nseg < 1 || nseg > (1u << 20)) return fail(BC_ERR_ARG, "nseg = %u outside [1, 2^20]", nseg);
+    if (plan_bytes < bc_batch_plan_bytes(nseg)) return fail(BC_ERR_WORKSPACE, "plan buffer too small");
+    bc_drelu_params r;
+    int rc = check_params(prm, &r);
+    if (rc) return rc;
+    if (tile_elems == 0) tile_elems = 1024;
+    const uint32_t w = width_of_ring(r.ell);
+    uint8_t* base = static_cast<uint8_t*>(plan);
+    bc::BatchPlanHeader* h = reinterpret_cast<bc::BatchPlanHeader*>(base);
+    bc_segment* out = reinterpret_cast<bc_segment*>(base + sizeof(bc::BatchPlanHeader));
+    uint64_t* tb = reinterpret_cast<uint64_t*>(base + sizeof(bc::BatchPlanHeader) + sizeof(bc_segment) * nseg);
+    uint64_t tiles = 0, elems = 0;
+    for (uint32_t i = 0; i < nseg; ++i) {
+        const bc_segment& s = segs[i];
+        if (s.op != BC_OP_DRELU && s.op != BC_OP_RELU) return fail(BC_ERR_ARG, "segment %u: unknown op %u", i, s.op);
+        if (s.reserved) return fail(BC_ERR_ARG, "segment %u: reserved must be 0", i);
+        if (s.elem_base > kMaxIndex || s.n > kMaxIndex - s.elem_base)
+            return fail(BC_ERR_ARG, "segment %u: element indices must stay below 2^48", i);
+        if (s.n && (!s.x0 || !s.x1 || !s.y0 || !s.y1)) return fail(BC_ERR_NULL, "segment %u: NULL share pointer", i);
+        if (s.n && (!aligned(s.x0, w) || !aligned(s.x1, w) || !aligned(s.y0, w) || !aligned(s.y1, w)))
+            return fail(BC_ERR_ALIGN, "segment %u: share pointers must be %u-byte aligned", i, w);
+        out[i] = s;
+        tb[i] = tiles;
+        tiles += (s.n + tile_elems - 1) / tile_elems;
+        elems += s.n;
+    }
+    tb[nseg] = tiles;
+    memset(h, 0, sizeof(*h));
+    h->magic = bc::kBatchMagic;
+    h->nseg = nseg;
+    h->ell = r.ell;
+    h->lx = r.lx;
+    h->k_lo = r.k_lo;
+    h->tile_elems = tile_elems;
+    h->p = r.p;
+    h->total_tiles = tiles;
+    h->total_elems = elems;
+    return BC_OK;
+}
+
+int batch_run(const void* dev_plan, const void* host_plan, const bc_seeds* seeds, uint32_t grid, void* stream) {
+    if (!dev_plan || !host_plan || !seeds) return fail(BC_ERR_NULL, "plan or seeds is NULL");
+    const bc::BatchPlanHeader* h = static_cast<const bc::BatchPlanHeader*>(host_plan);
+    if (h->magic != bc::kBatchMagic) return fail(BC_ERR_ARG, "host_plan is not a plan from bc_batch_plan");
+    if (!aligned(dev_plan, 8)) return fail(BC_ERR_ALIGN, "dev_plan must be 8-byte aligned");
+    if (h->total_tiles == 0) return BC_OK;
+    const uint8_t* base = static_cast<const uint8_t*>(dev_plan);
+    bc::BatchLaunch L;
+    L.hdr = reinterpret_cast<const bc::BatchPlanHeader*>(base);
+    L.segs = reinterpret_cast<const bc_segment*>(base + sizeof(bc::BatchPlanHeader));
+    L.tile_begin = reinterpret_cast<const uint64_t*>(base + sizeof(bc::BatchPlanHeader) + sizeof(bc_segment) * h->nseg);
+    L.total_tiles = h->total_tiles;
+    L.tile_elems = h->tile_elems;
+    L.p = h->p;
+    L.ell = h->ell;
+    L.k_lo = h->k_lo;
+    L.npos = h->lx + 1;
+    L.nseg = h->nseg;
+    L.s01 = stream_key(seeds->seed01, 0);
+    L.s02 = stream_key(seeds->seed02, 0);
+    L.s12 = stream_key(seeds->seed12, 0);
+    uint64_t g = grid ? grid : (uint64_t)grid_cap(8);
+    if (g > h->total_tiles) g = h->total_tiles;
+    L.grid = (int)g;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if (h->ell > 32) {
+        if (L.npos <= 12) e = bc::launch_batch_u64_lo(L, st);
+        else if (L.npos <= 24) e = bc::launch_batch_u64_mid(L, st);
+        else e = bc::launch_batch_u64_hi(L, st);
+    } else {
+        e = bc::launch_batch_u32(L, st);
+    }
+    return e == hipSuccess ? BC_OK : hip_fail(e, "batch launch");
+}
+
 }  // namespace
 
 namespace bc {
@@ -294,6 +373,19 @@ int bc_mod_switch(const void* x0, const void* x1, void* y0, void* y1, uint64_t n
 int bc_drelu(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, const bc_drelu_params* prm,
              const bc_seeds* seeds, uint64_t elem_base, void* capture, bc_msg_acct* acct, void* stream) {
     return drelu_common(BC_OP_DRELU, x0, x1, y0, y1, n, prm, seeds, elem_base, capture, acct, stream);
+}
+
+uint64_t bc_batch_plan_bytes(uint32_t nseg) {
+    return sizeof(bc::BatchPlanHeader) + (uint64_t)sizeof(bc_segment) * nseg + 8ull * (nseg + 1ull);
+}
+
+int bc_batch_plan(const bc_segment* segs, uint32_t nseg, const bc_drelu_params* prm, uint32_t tile_elems, void* plan,
+                  uint64_t plan_bytes) {
+    return batch_plan(segs, nseg, prm, tile_elems, plan, plan_bytes);
+}
+
+int bc_batch_run(const void* dev_plan, const void* host_plan, const bc_seeds* seeds, uint32_t grid, void* stream) {
+    return batch_run(dev_plan, host_plan, seeds, grid, stream);
 }
 
 int bc_relu(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, const bc_drelu_params* prm,

@@ -42,10 +42,24 @@ struct DreluKArgs {
     Stream s01, s02, s12;
 };
 
-// N = l_x + 1 windows, fixed at compile time: every loop over windows and
-// slots is unrolled and all window masks are constants.
+struct BatchKArgs {
+    uint64_t total_tiles;
+    uint64_t tile_elems;
+    uint64_t ring_mask;
+    uint32_t nseg, k_lo;
+    uint32_t k01a, k01b, k02a, k02b, k12a, k12b;
+};
+
+// One element, all three parties.  N = l_x + 1 windows, fixed at compile
+// time: every loop over windows and slots is unrolled and all window masks
+// are constants.  Reads X0[e], X1[e], writes Y0[e], Y1[e]; the randomness
+// belongs to global index g.  With CAP, the round-1 messages go to
+// cap[e * N + slot] (P0) and cap[(ncap + e) * N + slot] (P1).
 template <typename T, int N, typename F, bool RELU, bool CAP>
-__global__ __launch_bounds__(256) void k_drelu(DreluKArgs A, F f) {
+__device__ __forceinline__ void drelu_element(const T* __restrict__ X0, const T* __restrict__ X1, T* Y0, T* Y1,
+                                              typename F::T* cap, uint64_t ncap, uint64_t e, uint64_t g, T mask,
+                                              uint32_t k_lo, const Stream& s01, const Stream& s02,
+                                              const Stream& s12, const F& f) {
     using FT = typename F::T;
     constexpr int LX = N - 1;
     constexpr bool WIDE = std::is_same<FT, uint64_t>::value;
@@ -53,113 +67,160 @@ __global__ __launch_bounds__(256) void k_drelu(DreluKArgs A, F f) {
     constexpr FT WIN = TWO_LX - 1;                       // Z_{2^l_x}
     constexpr FT WIN1 = (FT)((2ull << LX) - 1);          // l_x + 1 bits
     static_assert(WIDE == (N == 33), "64-bit field elements exactly when l_x = 32");
-    const T* __restrict__ X0 = static_cast<const T*>(A.x0);
-    const T* __restrict__ X1 = static_cast<const T*>(A.x1);
-    T* Y0 = static_cast<T*>(A.y0);
-    T* Y1 = static_cast<T*>(A.y1);
-    const T mask = (T)A.ring_mask;
-    const uint32_t k_lo = A.k_lo;
     const FT p_minus_two = f.p - TWO_LX;
 
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < A.n; e += stride) {
-        const uint64_t g = A.elem_base + e;
-        const T in0 = X0[e] & mask;
-        const T in1 = X1[e] & mask;
+    const T in0 = X0[e] & mask;
+    const T in1 = X1[e] & mask;
 
-        // Steps 1 and 6 (randomness): t and the shuffle keys from seed_01.
-        uint32_t key[N];
-        uint32_t t = 0;
+    // Steps 1 and 6 (randomness): t and the shuffle keys from seed_01.
+    uint32_t key[N];
+    uint32_t t = 0;
 #pragma unroll
-        for (int b = 0; b < (N + 3) / 4; ++b) {
-            const Words4 w = A.s01.block(g, TAG_SHUFFLE, b);
-            if (b == 0) t = w.w0 & 1u;
-            const uint32_t ws[4] = {w.w0, w.w1, w.w2, w.w3};
+    for (int b = 0; b < (N + 3) / 4; ++b) {
+        const Words4 w = s01.block(g, TAG_SHUFFLE, b);
+        if (b == 0) t = w.w0 & 1u;
+        const uint32_t ws[4] = {w.w0, w.w1, w.w2, w.w3};
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (4 * b + q < N) key[4 * b + q] = (ws[q] & ~63u) | (uint32_t)(4 * b + q);
-        }
-        sort_keys<N>(key);
+        for (int q = 0; q < 4; ++q)
+            if (4 * b + q < N) key[4 * b + q] = (ws[q] & ~63u) | (uint32_t)(4 * b + q);
+    }
+    sort_keys<N>(key);
 
-        // Step 2: [x] := (-1)^t [x]  (both parties).
-        const T a0 = t ? (T)((T)0 - in0) & mask : in0;
-        const T a1 = t ? (T)((T)0 - in1) & mask : in1;
-        const T nb1 = (T)((T)0 - a1) & mask;              // P1 cuts -[x]_1 mod 2^l
+    // Step 2: [x] := (-1)^t [x]  (both parties).
+    const T a0 = t ? (T)((T)0 - in0) & mask : in0;
+    const T a1 = t ? (T)((T)0 - in1) & mask : in1;
+    const T nb1 = (T)((T)0 - a1) & mask;                  // P1 cuts -[x]_1 mod 2^l
 
-        bool zero = false;
-        Words4 wm = {0, 0, 0, 0};
+    bool zero = false;
+    Words4 wm = {0, 0, 0, 0};
 #pragma unroll
-        for (int j = 0; j < N; ++j) {
-            // Steps 7-8 randomness of slot j.
-            FT r, z;
-            if constexpr (WIDE) {
-                const Words4 w = A.s01.block(g, TAG_MASK, (uint32_t)j);
-                r = 1 + __umul64hi(join64(w.w0, w.w1), f.p - 1);
-                z = __umul64hi(join64(w.w2, w.w3), f.p);
-            } else {
-                if ((j & 1) == 0) wm = A.s01.block(g, TAG_MASK, (uint32_t)(j >> 1));
-                r = draw_r((j & 1) ? wm.w2 : wm.w0, f.p);
-                z = draw_z((j & 1) ? wm.w3 : wm.w1, f.p);
-            }
-            // Steps 3-4 for the position sigma(j) placed in slot j.
-            const uint32_t pos = key[j] & 63u;
-            const uint32_t s = k_lo + pos;
-            const bool last = pos == (uint32_t)LX;        // u_{l_x+1} := 0
-            const FT W0 = (FT)(a0 >> s) & WIN1;           // bits [s, s + l_x]
-            const FT W1 = (FT)(nb1 >> s) & WIN1;
-            const FT u0n = last ? (FT)0 : (W0 >> 1);      // u_{i+1}
-            const FT u1n = last ? (FT)0 : (W1 >> 1);
-            const FT v0 = (W0 + u0n - 1) & WIN;           // u_i + u_{i+1} - 1
-            const FT v1 = ((FT)0 - W1 - u1n) & WIN;       // P1: -cut_i - cut_{i+1}
-            // Step 5: Alg. 6.
-            const FT s0 = v0 ? v0 : TWO_LX;
-            const FT s1 = v1 + p_minus_two;
-            // Steps 7-8: mask and reshare.
-            const FT w0 = addmod(f.mul(s0, r), z, f);
-            const FT w1 = addmod(f.mul(s1, r), (FT)(f.p - z), f);
-            if constexpr (CAP) {
-                FT* C = static_cast<FT*>(A.cap);
-                C[e * N + j] = w0;
-                C[(A.n + e) * N + j] = w1;
-            }
-            // Step 9 (P2): reconstruct and test for zero.
-            zero |= addmod(w0, w1, f) == 0;
-        }
-        const T dp = zero ? 1 : 0;
-
-        T y0, y1;
-        if constexpr (!RELU) {
-            // Step 10 (P2): fresh sharing (rho, D' - rho) with rho from seed_02.
-            const Words4 w = A.s02.block(g, TAG_RESP, 0);
-            const T rho = (T)join64(w.w0, w.w1) & mask;
-            const T d1 = (T)(dp - rho) & mask;
-            // Step 11: DReLU = t + (1 - 2t) D'.
-            y0 = t ? (T)((T)1 - rho) & mask : rho;
-            y1 = t ? (T)((T)0 - d1) & mask : d1;
+    for (int j = 0; j < N; ++j) {
+        // Steps 7-8 randomness of slot j.
+        FT r, z;
+        if constexpr (WIDE) {
+            const Words4 w = s01.block(g, TAG_MASK, (uint32_t)j);
+            r = 1 + __umul64hi(join64(w.w0, w.w1), f.p - 1);
+            z = __umul64hi(join64(w.w2, w.w3), f.p);
         } else {
-            // Alg. 8 preprocessing: [a]_0, [b]_0, [c]_0 from seed_02, [a]_1, [b]_1
-            // from seed_12; P2 forms [c]_1 = (a0 + a1)(b0 + b1) - c0.
-            const Words4 w0 = A.s02.block(g, TAG_BEAVER, 0);
-            const Words4 w1 = A.s02.block(g, TAG_BEAVER, 1);
-            const Words4 w2 = A.s12.block(g, TAG_BEAVER, 0);
-            const T ba0 = (T)join64(w0.w0, w0.w1) & mask;
-            const T bb0 = (T)join64(w0.w2, w0.w3) & mask;
-            const T bc0 = (T)join64(w1.w0, w1.w1) & mask;
-            const T ba1 = (T)join64(w2.w0, w2.w1) & mask;
-            const T bb1 = (T)join64(w2.w2, w2.w3) & mask;
-            const T bsum = (T)(bb0 + bb1);
-            const T bc1 = (T)((T)(ba0 + ba1) * bsum - bc0) & mask;
-            // Step 3 (P2): e = D' - b.  Step 4 (P0, P1): d = x - a, exchanged.
-            const T ee = (T)(dp - bsum) & mask;
-            const T dd = (T)((in0 - ba0) + (in1 - ba1)) & mask;
-            // Step 5: [x D'] = de + d[b] + e[a] + [c]; ReLU = t[x] + (1 - 2t)[x D'].
-            const T m0 = (T)(dd * ee + dd * bb0 + ee * ba0 + bc0) & mask;
-            const T m1 = (T)(dd * bb1 + ee * ba1 + bc1) & mask;
-            y0 = t ? (T)(in0 - m0) & mask : m0;
-            y1 = t ? (T)(in1 - m1) & mask : m1;
+            if ((j & 1) == 0) wm = s01.block(g, TAG_MASK, (uint32_t)(j >> 1));
+            r = draw_r((j & 1) ? wm.w2 : wm.w0, f.p);
+            z = draw_z((j & 1) ? wm.w3 : wm.w1, f.p);
         }
-        Y0[e] = y0;
-        Y1[e] = y1;
+        // Steps 3-4 for the position sigma(j) placed in slot j.
+        const uint32_t pos = key[j] & 63u;
+        const uint32_t s = k_lo + pos;
+        const bool last = pos == (uint32_t)LX;            // u_{l_x+1} := 0
+        const FT W0 = (FT)(a0 >> s) & WIN1;               // bits [s, s + l_x]
+        const FT W1 = (FT)(nb1 >> s) & WIN1;
+        const FT u0n = last ? (FT)0 : (W0 >> 1);          // u_{i+1}
+        const FT u1n = last ? (FT)0 : (W1 >> 1);
+        const FT v0 = (W0 + u0n - 1) & WIN;               // u_i + u_{i+1} - 1
+        const FT v1 = ((FT)0 - W1 - u1n) & WIN;           // P1: -cut_i - cut_{i+1}
+        // Step 5: Alg. 6.
+        const FT s0 = v0 ? v0 : TWO_LX;
+        const FT s1 = v1 + p_minus_two;
+        // Steps 7-8: mask and reshare.
+        const FT w0 = addmod(f.mul(s0, r), z, f);
+        const FT w1 = addmod(f.mul(s1, r), (FT)(f.p - z), f);
+        if constexpr (CAP) {
+            cap[e * N + j] = w0;
+            cap[(ncap + e) * N + j] = w1;
+        }
+        // Step 9 (P2): reconstruct and test for zero.
+        zero |= addmod(w0, w1, f) == 0;
+    }
+    const T dp = zero ? 1 : 0;
+
+    T y0, y1;
+    if constexpr (!RELU) {
+        // Step 10 (P2): fresh sharing (rho, D' - rho) with rho from seed_02.
+        const Words4 w = s02.block(g, TAG_RESP, 0);
+        const T rho = (T)join64(w.w0, w.w1) & mask;
+        const T d1 = (T)(dp - rho) & mask;
+        // Step 11: DReLU = t + (1 - 2t) D'.
+        y0 = t ? (T)((T)1 - rho) & mask : rho;
+        y1 = t ? (T)((T)0 - d1) & mask : d1;
+    } else {
+        // Alg. 8 preprocessing: [a]_0, [b]_0, [c]_0 from seed_02, [a]_1, [b]_1
+        // from seed_12; P2 forms [c]_1 = (a0 + a1)(b0 + b1) - c0.
+        const Words4 w0 = s02.block(g, TAG_BEAVER, 0);
+        const Words4 w1 = s02.block(g, TAG_BEAVER, 1);
+        const Words4 w2 = s12.block(g, TAG_BEAVER, 0);
+        const T ba0 = (T)join64(w0.w0, w0.w1) & mask;
+        const T bb0 = (T)join64(w0.w2, w0.w3) & mask;
+        const T bc0 = (T)join64(w1.w0, w1.w1) & mask;
+        const T ba1 = (T)join64(w2.w0, w2.w1) & mask;
+        const T bb1 = (T)join64(w2.w2, w2.w3) & mask;
+        const T bsum = (T)(bb0 + bb1);
+        const T bc1 = (T)((T)(ba0 + ba1) * bsum - bc0) & mask;
+        // Step 3 (P2): e = D' - b.  Step 4 (P0, P1): d = x - a, exchanged.
+        const T ee = (T)(dp - bsum) & mask;
+        const T dd = (T)((in0 - ba0) + (in1 - ba1)) & mask;
+        // Step 5: [x D'] = de + d[b] + e[a] + [c]; ReLU = t[x] + (1 - 2t)[x D'].
+        const T m0 = (T)(dd * ee + dd * bb0 + ee * ba0 + bc0) & mask;
+        const T m1 = (T)(dd * bb1 + ee * ba1 + bc1) & mask;
+        y0 = t ? (T)(in0 - m0) & mask : m0;
+        y1 = t ? (T)(in1 - m1) & mask : m1;
+    }
+    Y0[e] = y0;
+    Y1[e] = y1;
+}
+
+// One call: grid-stride over the n elements of one share pair.
+template <typename T, int N, typename F, bool RELU, bool CAP>
+__global__ __launch_bounds__(256) void k_drelu(DreluKArgs A, F f) {
+    const T* X0 = static_cast<const T*>(A.x0);
+    const T* X1 = static_cast<const T*>(A.x1);
+    T* Y0 = static_cast<T*>(A.y0);
+    T* Y1 = static_cast<T*>(A.y1);
+    typename F::T* cap = static_cast<typename F::T*>(A.cap);
+    const T mask = (T)A.ring_mask;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < A.n; e += stride)
+        drelu_element<T, N, F, RELU, CAP>(X0, X1, Y0, Y1, cap, A.n, e, A.elem_base + e, mask, A.k_lo, A.s01, A.s02,
+                                          A.s12, f);
+}
+
+// Ragged batch: a persistent grid walks the tiles of every segment.  Tile t
+// belongs to the segment s with tile_begin[s] <= t < tile_begin[s + 1]; each
+// segment has its own op, nonce and global element offset, so every element
+// gets exactly the randomness (and result) of a single call on its segment.
+// Each block takes tiles blockIdx.x, blockIdx.x + gridDim.x, ... until
+// total_tiles: every wave reaches the exit.
+template <typename T, int N, typename F>
+__global__ __launch_bounds__(256) void k_batch(const BatchPlanHeader* __restrict__ hdr,
+                                               const bc_segment* __restrict__ segs,
+                                               const uint64_t* __restrict__ tile_begin, BatchKArgs A, F f) {
+    const uint32_t nseg = A.nseg;
+    const uint64_t total = A.total_tiles;
+    const uint64_t tile = A.tile_elems;
+    const T mask = (T)A.ring_mask;
+    for (uint64_t t = blockIdx.x; t < total; t += gridDim.x) {
+        // segment of tile t: largest s with tile_begin[s] <= t (uniform search)
+        uint32_t lo = 0, hi = nseg;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (tile_begin[mid] <= t) lo = mid; else hi = mid;
+        }
+        const bc_segment& S = segs[lo];
+        const T* X0 = static_cast<const T*>(S.x0);
+        const T* X1 = static_cast<const T*>(S.x1);
+        T* Y0 = static_cast<T*>(S.y0);
+        T* Y1 = static_cast<T*>(S.y1);
+        const uint64_t e0 = (t - tile_begin[lo]) * tile;
+        const uint64_t e1 = e0 + tile < S.n ? e0 + tile : S.n;
+        const uint32_t n0 = (uint32_t)S.nonce, n1 = (uint32_t)(S.nonce >> 32);
+        const Stream s01{A.k01a, A.k01b, n0, n1}, s02{A.k02a, A.k02b, n0, n1}, s12{A.k12a, A.k12b, n0, n1};
+        const uint64_t base = S.elem_base;
+        if (S.op == BC_OP_RELU) {
+            for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x)
+                drelu_element<T, N, F, true, false>(X0, X1, Y0, Y1, nullptr, 0, e, base + e, mask, A.k_lo, s01, s02,
+                                                    s12, f);
+        } else {
+            for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x)
+                drelu_element<T, N, F, false, false>(X0, X1, Y0, Y1, nullptr, 0, e, base + e, mask, A.k_lo, s01, s02,
+                                                     s12, f);
+        }
     }
 }
 
@@ -215,6 +276,51 @@ hipError_t launch_exact(const DreluLaunch& L, hipStream_t st) {
         return launch_field<T, N, Field32, RELU>(L, make_field32(L.p), st);
     } else {
         return launch_field<T, N, Field64, RELU>(L, make_field64(L.p), st);
+    }
+}
+
+template <typename T, int N, typename F>
+hipError_t launch_batch_field(const BatchLaunch& L, const F& f, hipStream_t st) {
+    BatchKArgs A;
+    A.total_tiles = L.total_tiles;
+    A.tile_elems = L.tile_elems;
+    A.ring_mask = L.ell >= 64 ? ~0ull : ((1ull << L.ell) - 1);
+    A.nseg = L.nseg;
+    A.k_lo = L.k_lo;
+    A.k01a = L.s01.k0;
+    A.k01b = L.s01.k1;
+    A.k02a = L.s02.k0;
+    A.k02b = L.s02.k1;
+    A.k12a = L.s12.k0;
+    A.k12b = L.s12.k1;
+    hipLaunchKernelGGL((k_batch<T, N, F>), dim3(L.grid), dim3(256), 0, st, L.hdr, L.segs, L.tile_begin, A, f);
+    return hipGetLastError();
+}
+
+template <typename T, int N>
+hipError_t launch_batch_exact(const BatchLaunch& L, hipStream_t st) {
+    if constexpr (N <= 12) {
+        return launch_batch_field<T, N, FieldSmall>(L, make_field_small(L.p), st);
+    } else if constexpr (N <= 24) {
+        if constexpr (mersenne_exponent(N)) {
+            if (L.p == (1ull << N) - 1)
+                return launch_batch_field<T, N, FieldMersenne<N>>(L, FieldMersenne<N>{(uint32_t)L.p}, st);
+        }
+        return launch_batch_field<T, N, Field24>(L, make_field24(L.p), st);
+    } else if constexpr (N <= 32) {
+        return launch_batch_field<T, N, Field32>(L, make_field32(L.p), st);
+    } else {
+        return launch_batch_field<T, N, Field64>(L, make_field64(L.p), st);
+    }
+}
+
+template <typename T, int NLO, int NHI>
+hipError_t launch_batch_range(const BatchLaunch& L, hipStream_t st) {
+    if constexpr (NLO > NHI) {
+        return hipErrorInvalidValue;
+    } else {
+        if (L.npos == (uint32_t)NLO) return launch_batch_exact<T, NLO>(L, st);
+        return launch_batch_range<T, NLO + 1, NHI>(L, st);
     }
 }
 

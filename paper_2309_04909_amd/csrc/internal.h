@@ -29,6 +29,36 @@ struct DreluLaunch {
     int block;
 };
 
+// Device plan of a ragged batch: this header, then nseg bc_segment records,
+// then nseg + 1 uint64 tile offsets.
+struct BatchPlanHeader {
+    uint32_t magic;        // kBatchMagic
+    uint32_t nseg;
+    uint32_t ell, lx, k_lo, tile_elems;
+    uint64_t p;
+    uint64_t total_tiles;
+    uint64_t total_elems;
+    uint32_t reserved[4];
+};
+static_assert(sizeof(BatchPlanHeader) == 64, "plan header is 64 bytes");
+static_assert(sizeof(bc_segment) == 64, "segment record is 64 bytes");
+constexpr uint32_t kBatchMagic = 0x4C504342u;   // "BCPL"
+
+struct BatchLaunch {
+    const BatchPlanHeader* hdr;      // device
+    const bc_segment* segs;          // device
+    const uint64_t* tile_begin;      // device
+    uint64_t total_tiles, tile_elems, p;
+    uint32_t ell, k_lo, npos, nseg;
+    StreamKey s01, s02, s12;
+    int grid;
+};
+
+hipError_t launch_batch_u64_lo(const BatchLaunch& L, hipStream_t st);    // N 2..12
+hipError_t launch_batch_u64_mid(const BatchLaunch& L, hipStream_t st);   // N 13..24
+hipError_t launch_batch_u64_hi(const BatchLaunch& L, hipStream_t st);    // N 25..33
+hipError_t launch_batch_u32(const BatchLaunch& L, hipStream_t st);       // N 2..17
+
 // Kernel launchers, one per op, storage width and range of N = l_x + 1 (the
 // split only spreads compilation over several files).  Each returns
 // hipErrorInvalidValue when L.npos is outside its range.

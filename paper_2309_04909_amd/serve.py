@@ -1,0 +1,154 @@
+"""Continuous-batching request loop for DReLU/ReLU jobs.
+
+Jobs (op, ring, n elements) arrive over time.  Their input shares live in a
+device-resident pool (a job names a slice of it and carries its own nonce).
+The loop:
+  1. retires launches whose completion event has fired, freeing their slots
+     and HBM;
+  2. queues every job whose arrival time has passed;
+  3. admits queued jobs in arrival order while the in-flight HBM (input and
+     output shares of every admitted job) stays within the budget and slots
+     are free;
+  4. turns the newly admitted jobs into one ragged launch per ring
+     (RaggedBatch, one persistent kernel each) on the next of k streams, so
+     work admitted while earlier launches run overlaps with them on the GPU.
+Latency of a job = GPU completion time of its launch - its arrival time.
+Each job's result is exactly what a single call on it would give (per-job
+nonce, element indices 0..n-1), whichever launch it lands in.
+"""
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import torch
+
+from . import batch as BT
+from . import bicop as B
+
+
+@dataclass
+class Job:
+    jid: int
+    arrival: float          # seconds after the start of the run
+    n: int
+    op: int                 # B.BC_OP_DRELU / B.BC_OP_RELU
+    ell: int
+    offset: int             # first element of its input slice in the pool of its ring
+    nonce: int
+    y0: torch.Tensor = None
+    y1: torch.Tensor = None
+    done: float = None      # completion time (s after the start)
+    admitted: float = None
+
+
+@dataclass
+class Launch:
+    event: torch.cuda.Event
+    jobs: list
+    batches: list = field(default_factory=list)
+    bytes: int = 0
+
+
+class Server:
+    def __init__(self, pools, params, seeds: B.Seeds, hbm_budget: int, max_slots: int = 256, nstreams: int = 4,
+                 keep_outputs: bool = False):
+        """pools[ell] = (x0, x1) device share pools; params[ell] = B.Params of that ring."""
+        self.pools = pools
+        self.params = params
+        self.seeds = seeds
+        self.budget = hbm_budget
+        self.max_slots = max_slots
+        self.streams = [torch.cuda.Stream() for _ in range(nstreams)]
+        self.keep = keep_outputs
+
+    def job_bytes(self, j: Job) -> int:
+        return 4 * j.n * B.ring_width(j.ell)           # resident input shares + output shares
+
+    def _launch(self, jobs, stream):
+        ev = torch.cuda.Event(enable_timing=True)
+        L = Launch(ev, jobs)
+        with torch.cuda.stream(stream):
+            by_ell = {}
+            for j in jobs:
+                x0, x1 = self.pools[j.ell]
+                j.y0 = torch.empty(j.n, dtype=x0.dtype, device=x0.device)
+                j.y1 = torch.empty(j.n, dtype=x1.dtype, device=x1.device)
+                seg = BT.Segment(x0[j.offset:j.offset + j.n], x1[j.offset:j.offset + j.n], j.y0, j.y1, op=j.op,
+                                 nonce=j.nonce, elem_base=0)
+                by_ell.setdefault(j.ell, []).append(seg)
+                L.bytes += self.job_bytes(j)
+            for ell, segs in by_ell.items():
+                rb = BT.RaggedBatch(self.params[ell], self.seeds, segs)
+                rb.run(stream)
+                L.batches.append(rb)
+            ev.record(stream)
+        return L
+
+    def run(self, jobs):
+        """Serve `jobs` (arrival times relative to the start); returns them with
+        completion times filled in."""
+        pending = deque(sorted(jobs, key=lambda j: j.arrival))
+        waiting = deque()
+        inflight = []
+        used, slots, k = 0, 0, 0
+        torch.cuda.synchronize()
+        ref = torch.cuda.Event(enable_timing=True)
+        ref.record()
+        t0 = time.perf_counter()
+        finished = []
+        while pending or waiting or inflight:
+            now = time.perf_counter() - t0
+            still = []
+            for L in inflight:
+                if L.event.query():
+                    t_done = ref.elapsed_time(L.event) / 1e3
+                    for j in L.jobs:
+                        j.done = t_done
+                        if not self.keep:
+                            j.y0 = j.y1 = None
+                        finished.append(j)
+                    used -= L.bytes
+                    slots -= len(L.jobs)
+                else:
+                    still.append(L)
+            inflight = still
+            while pending and pending[0].arrival <= now:
+                waiting.append(pending.popleft())
+            admit = []
+            while waiting and slots + len(admit) < self.max_slots and len(inflight) < len(self.streams):
+                j = waiting[0]
+                b = self.job_bytes(j)
+                if used + b > self.budget and (used > 0 or admit):
+                    break
+                waiting.popleft()
+                j.admitted = now
+                used += b
+                admit.append(j)
+            if admit:
+                slots += len(admit)
+                inflight.append(self._launch(admit, self.streams[k % len(self.streams)]))
+                k += 1
+            elif not inflight and pending and not waiting:
+                gap = pending[0].arrival - (time.perf_counter() - t0)
+                if gap > 0:
+                    time.sleep(min(gap, 0.001))
+        torch.cuda.synchronize()
+        return finished
+
+
+def percentile(vals, q):
+    vals = sorted(vals)
+    if not vals:
+        return float("nan")
+    i = min(len(vals) - 1, max(0, int(round(q / 100.0 * (len(vals) - 1)))))
+    return vals[i]
+
+
+def summarize(jobs):
+    lat = [j.done - j.arrival for j in jobs]
+    elems = sum(j.n for j in jobs)
+    span = max(j.done for j in jobs) - min(j.arrival for j in jobs)
+    return {"jobs": len(jobs), "elements": elems, "p50_ms": round(percentile(lat, 50) * 1e3, 4),
+            "p99_ms": round(percentile(lat, 99) * 1e3, 4), "mean_ms": round(sum(lat) / len(lat) * 1e3, 4),
+            "gelem_s": round(elems / span / 1e9, 4), "span_s": round(span, 4)}

@@ -6,6 +6,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from oracle import params as OP
@@ -111,3 +112,39 @@ def test_error_paths_without_gpu():
     bad = B.Params(64, 7, 0, 0).c()
     bad.reserved = 1
     assert L.bc_drelu(None, None, None, None, 1, ctypes.byref(bad), ctypes.byref(sd), 0, None, None, None) == -8
+
+
+def test_batch_plan_validation_on_host():
+    """bc_batch_plan is host-only: it validates and fills a host buffer, never launches."""
+    from paper_2309_04909_amd import bicop as B
+    L = B.lib
+    prm = B.Params(64, 7, 11).c()
+    seg = (B._Segment * 2)()
+    seg[0] = B._Segment(0x1000, 0x2000, 0x3000, 0x4000, 5000, 0, 1, B.BC_OP_RELU, 0)
+    seg[1] = B._Segment(0x5000, 0x6000, 0x7000, 0x8000, 0, 99, 2, B.BC_OP_DRELU, 0)
+    nbytes = L.bc_batch_plan_bytes(2)
+    assert nbytes == 64 + 2 * 64 + 3 * 8
+    buf = (ctypes.c_uint8 * nbytes)()
+    assert L.bc_batch_plan(seg, 2, ctypes.byref(prm), 1024, buf, nbytes) == 0
+    words = np.frombuffer(bytes(buf), dtype=np.uint64)
+    tb = words[(64 + 128) // 8:]
+    assert list(tb) == [0, 5, 5]                                  # ceil(5000 / 1024) tiles, then the empty one
+    assert L.bc_batch_plan(seg, 2, ctypes.byref(prm), 1024, buf, nbytes - 1) == -7
+    assert L.bc_batch_plan(seg, 0, ctypes.byref(prm), 1024, buf, nbytes) == -8
+    seg[1].op = 5
+    assert L.bc_batch_plan(seg, 2, ctypes.byref(prm), 1024, buf, nbytes) == -8
+    seg[1].op = B.BC_OP_DRELU
+    seg[0].x0 = 0x1004                                              # not 8-byte aligned
+    assert L.bc_batch_plan(seg, 2, ctypes.byref(prm), 1024, buf, nbytes) == -5
+    seg[0].x0 = None
+    assert L.bc_batch_plan(seg, 2, ctypes.byref(prm), 1024, buf, nbytes) == -1
+    seg[0].x0 = 0x1000
+    seg[0].elem_base = (1 << 48) - 10
+    assert L.bc_batch_plan(seg, 2, ctypes.byref(prm), 1024, buf, nbytes) == -8
+    bad = B.Params(64, 7, 0, 257).c()
+    seg[0].elem_base = 0
+    assert L.bc_batch_plan(seg, 2, ctypes.byref(bad), 1024, buf, nbytes) == -4
+    # bc_batch_run refuses a buffer that is not a plan (checked before any launch)
+    junk = (ctypes.c_uint8 * nbytes)()
+    sd = B.Seeds(1, 2, 3).c()
+    assert L.bc_batch_run(ctypes.addressof(junk), junk, ctypes.byref(sd), 0, None) == -8

@@ -1,0 +1,116 @@
+"""Ragged batches on the GPU: one persistent launch gives, for every segment,
+exactly the result of a single call on it (and of the oracle), under any tile
+size or grid, and a captured graph replays it correctly."""
+
+import numpy as np
+import pytest
+
+from oracle import protocols as OPR
+from oracle.params import default_prime
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def M():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_04909_amd import batch, bicop
+    return bicop, batch
+
+
+def dev(a):
+    a = np.ascontiguousarray(a)
+    return torch.from_numpy(a.view(np.int64 if a.dtype == np.uint64 else np.int32)).cuda()
+
+
+def host(t):
+    t = t.detach().cpu()
+    return t.view(torch.int64).numpy().view(np.uint64) if t.element_size() == 8 else \
+        t.view(torch.int32).numpy().view(np.uint32)
+
+
+SIZES = [0, 1, 255, 256, 1023, 1024, 1025, 5000, 77777, 3]
+
+
+def _segments(B, bt, rng, ell, lx, k_lo, sizes, ops=None):
+    segs, inputs = [], []
+    base = 0
+    for i, n in enumerate(sizes):
+        bound = 1 << (k_lo + lx - 1)
+        x = np.array([v % (1 << ell) for v in rng.integers(-bound + 1, bound, size=n).tolist()], dtype=np.uint64)
+        x0, x1 = W.share(x, ell, rng)
+        op = (ops[i] if ops else (B.BC_OP_RELU if i % 2 else B.BC_OP_DRELU))
+        d0, d1 = dev(x0), dev(x1)
+        segs.append(bt.Segment(d0, d1, torch.empty_like(d0), torch.empty_like(d1), op=op, nonce=1000 + 7 * i,
+                               elem_base=base))
+        inputs.append((x0, x1))
+        base += n + 13
+    return segs, inputs
+
+
+@pytest.mark.parametrize("ell,lx,k_lo", [(64, 7, 11), (64, 18, 13), (32, 8, 8), (64, 32, 0)])
+def test_batch_equals_single_calls_and_oracle(M, ell, lx, k_lo):
+    B, bt = M
+    rng = np.random.default_rng(ell + lx)
+    prm, seeds = B.Params(ell, lx, k_lo), (5, 6, 7)
+    segs, inputs = _segments(B, bt, rng, ell, lx, k_lo, SIZES)
+    batch = bt.RaggedBatch(prm, B.Seeds(*seeds), segs)
+    batch.run()
+    p = default_prime(lx)
+    for s, (x0, x1) in zip(segs, inputs):
+        fn = B.relu if s.op == B.BC_OP_RELU else B.drelu
+        z0, z1 = fn(s.x0, s.x1, prm, B.Seeds(*seeds, s.nonce), elem_base=s.elem_base)
+        assert torch.equal(z0, s.y0) and torch.equal(z1, s.y1), (s.x0.numel(), s.op)
+        k = min(400, x0.size)
+        if k:
+            ofn = OPR.relu if s.op == B.BC_OP_RELU else OPR.drelu
+            e0, e1, _, _ = ofn(x0[:k].astype(np.uint64), x1[:k].astype(np.uint64), ell, lx, k_lo, p, seeds, s.nonce,
+                               elem_base=s.elem_base)
+            assert np.array_equal(host(s.y0)[:k].astype(np.uint64), e0)
+            assert np.array_equal(host(s.y1)[:k].astype(np.uint64), e1)
+
+
+def test_batch_schedule_invariance(M):
+    B, bt = M
+    rng = np.random.default_rng(3)
+    prm = B.Params(64, 7, 11)
+    segs, _ = _segments(B, bt, rng, 64, 7, 11, [3000, 10, 70000, 4096])
+    ref = None
+    for tile, grid in [(0, 0), (256, 1), (512, 3), (4096, 0), (100, 7)]:
+        for s in segs:
+            s.y0.zero_()
+            s.y1.zero_()
+        bt.RaggedBatch(prm, B.Seeds(1, 2, 3), segs, tile_elems=tile, grid=grid).run()
+        out = [(s.y0.clone(), s.y1.clone()) for s in segs]
+        if ref is None:
+            ref = out
+        else:
+            for (a0, a1), (b0, b1) in zip(ref, out):
+                assert torch.equal(a0, b0) and torch.equal(a1, b1), (tile, grid)
+
+
+def test_batch_graph_replays(M):
+    """Each replay of the captured launch reproduces the eager result, with eager
+    work (clearing the outputs, other kernels) between replays."""
+    B, bt = M
+    rng = np.random.default_rng(4)
+    prm = B.Params(64, 7, 11)
+    segs, _ = _segments(B, bt, rng, 64, 7, 11, [20000, 513, 0, 40000])
+    batch = bt.RaggedBatch(prm, B.Seeds(9, 8, 7), segs)
+    batch.run()
+    torch.cuda.synchronize()
+    eager = [(s.y0.clone(), s.y1.clone()) for s in segs]
+    g = batch.capture()
+    for rep in range(4):
+        for s in segs:
+            s.y0.zero_()
+            s.y1.zero_()
+        junk = torch.randn(4096, device="cuda").sum()          # unrelated eager work
+        g.replay()
+        torch.cuda.synchronize()
+        assert float(junk) == float(junk)
+        for (a0, a1), s in zip(eager, segs):
+            assert torch.equal(a0, s.y0) and torch.equal(a1, s.y1), rep

@@ -1,0 +1,62 @@
+"""Serving: every job's result is identical alone and in the mix (tolerance 0),
+and a sample of jobs matches the oracle."""
+
+import numpy as np
+import pytest
+
+from oracle import protocols as OPR
+from oracle.params import default_prime
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def dev(a):
+    a = np.ascontiguousarray(a)
+    return torch.from_numpy(a.view(np.int64 if a.dtype == np.uint64 else np.int32)).cuda()
+
+
+def host(t):
+    t = t.detach().cpu()
+    return t.view(torch.int64).numpy().view(np.uint64) if t.element_size() == 8 else \
+        t.view(torch.int32).numpy().view(np.uint32)
+
+
+def test_results_identical_alone_and_in_the_mix():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_04909_amd import bicop as B
+    from paper_2309_04909_amd import serve as S
+    pool_n = 1 << 18
+    settings = {64: (64, 18, 13), 32: (32, 8, 8)}
+    host_pools, pools = {}, {}
+    for ell in (64, 32):
+        _, (x0, x1) = W.serving_values(50 + ell, pool_n, ell)
+        host_pools[ell] = (x0, x1)
+        pools[ell] = (dev(x0), dev(x1))
+    params = {ell: B.Params(*settings[ell]) for ell in settings}
+    seeds = (31, 41, 59)
+    rng = np.random.default_rng(0)
+    arr = W.serving_arrivals(3, 20000.0, 60, min_log2=4, max_log2=16)
+    jobs = []
+    for i, (t, n, op, ell) in enumerate(arr):
+        jobs.append(S.Job(i, t, n, 0 if op == "drelu" else 1, ell, int(rng.integers(0, pool_n - n + 1)), 7000 + i))
+    # a tight budget and few slots force many small launches that overlap on 3 streams
+    srv = S.Server(pools, params, B.Seeds(*seeds), hbm_budget=1 << 22, max_slots=5, nstreams=3, keep_outputs=True)
+    done = srv.run(jobs)
+    assert len(done) == len(jobs) and all(j.done is not None and j.done >= j.arrival - 1e-3 for j in done)
+    for j in done:
+        x0, x1 = pools[j.ell]
+        fn = B.relu if j.op == B.BC_OP_RELU else B.drelu
+        a0, a1 = fn(x0[j.offset:j.offset + j.n], x1[j.offset:j.offset + j.n], params[j.ell], B.Seeds(*seeds, j.nonce))
+        assert torch.equal(a0, j.y0) and torch.equal(a1, j.y1), j.jid
+    for j in done[:6]:
+        ell, lx, k_lo = settings[j.ell]
+        h0, h1 = host_pools[j.ell]
+        k = min(j.n, 300)
+        ofn = OPR.relu if j.op == B.BC_OP_RELU else OPR.drelu
+        e0, e1, _, _ = ofn(h0[j.offset:j.offset + k].astype(np.uint64), h1[j.offset:j.offset + k].astype(np.uint64),
+                           ell, lx, k_lo, default_prime(lx), seeds, j.nonce)
+        assert np.array_equal(host(j.y0)[:k].astype(np.uint64), e0)
+        assert np.array_equal(host(j.y1)[:k].astype(np.uint64), e1)
