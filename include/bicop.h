@@ -186,6 +186,36 @@ int bc_relu(const void* x0, const void* x1, void* y0, void* y1, uint64_t n,
             const bc_drelu_params* prm, const bc_seeds* seeds, uint64_t elem_base,
             void* capture, bc_msg_acct* acct, void* stream);
 
+/* ------------------------------------------ precomputed randomness */
+
+/* Everything the parties draw from their seeds is independent of the input
+ * (Alg. 7 steps 1, 6, 7, 8 and 10; Alg. 8's preprocessing), so it can be
+ * expanded ahead of time and kept resident; the online call then streams
+ * shares plus this record.  Results and messages are bit-identical to
+ * bc_drelu / bc_relu with the same seeds, nonce and element indices.
+ *
+ * Record of n elements (structure of arrays, sections at 256-byte
+ * boundaries): the shuffle as bytes sigma(slot) packed four per uint32 with
+ * t in bit 7 of the first byte; r and z per slot (one uint32 r | z << 16 when
+ * p < 2^16, two uint32 when p < 2^32, two uint64 otherwise); then for DReLU
+ * P2's response share rho, for ReLU the triple [a]_0 [b]_0 [c]_0 [a]_1 [b]_1
+ * [c]_1 (ring width each, [c]_1 formed by P2). */
+
+/* Bytes of the record of `op` on n elements; 0 if the setting is invalid. */
+uint64_t bc_rand_bytes(uint32_t op, const bc_drelu_params* prm, uint64_t n);
+
+/* Offline: expand the seeds of elements elem_base .. elem_base + n - 1 into
+ * `rand` (device, 16-byte aligned, rand_bytes >= bc_rand_bytes). */
+int bc_rand_expand(void* rand, uint64_t rand_bytes, uint64_t n, uint32_t op, const bc_drelu_params* prm,
+                   const bc_seeds* seeds, uint64_t elem_base, void* stream);
+
+/* Online DReLU (Alg. 7) / ReLU (Alg. 8) from an expanded record of the same
+ * op, setting and n.  Other arguments as bc_drelu. */
+int bc_drelu_pre(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, const bc_drelu_params* prm,
+                 const void* rand, uint64_t rand_bytes, void* capture, bc_msg_acct* acct, void* stream);
+int bc_relu_pre(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, const bc_drelu_params* prm,
+                const void* rand, uint64_t rand_bytes, void* capture, bc_msg_acct* acct, void* stream);
+
 /* ------------------------------------------------------ ragged batching */
 
 /* One segment of a ragged batch: a share pair of its own length, op, nonce

@@ -71,6 +71,13 @@ _SIGS = {
     "bc_batch_plan_bytes": ([_U32], _U64),
     "bc_batch_plan": ([ctypes.POINTER(_Segment), _U32, ctypes.POINTER(_Params), _U32, _P, _U64], ctypes.c_int),
     "bc_batch_run": ([_P, _P, ctypes.POINTER(_Seeds), _U32, _P], ctypes.c_int),
+    "bc_rand_bytes": ([_U32, ctypes.POINTER(_Params), _U64], _U64),
+    "bc_rand_expand": ([_P, _U64, _U64, _U32, ctypes.POINTER(_Params), ctypes.POINTER(_Seeds), _U64, _P],
+                       ctypes.c_int),
+    "bc_drelu_pre": ([_P, _P, _P, _P, _U64, ctypes.POINTER(_Params), _P, _U64, _P, ctypes.POINTER(_Acct), _P],
+                     ctypes.c_int),
+    "bc_relu_pre": ([_P, _P, _P, _P, _U64, ctypes.POINTER(_Params), _P, _U64, _P, ctypes.POINTER(_Acct), _P],
+                    ctypes.c_int),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -258,3 +265,44 @@ def prg_blocks(n, nblocks, seed, nonce, tag, elem_base=0, device="cuda", stream=
     _check(lib.bc_prg_blocks(out.data_ptr(), n, nblocks, seed & m, nonce & m, tag, elem_base, _stream(stream)),
            "prg_blocks")
     return out
+
+
+# ------------------------------------------------- precomputed randomness
+
+
+def rand_bytes(op, params: Params, n):
+    return int(lib.bc_rand_bytes(op, ctypes.byref(params.c()), n))
+
+
+def rand_expand(op, params: Params, seeds: Seeds, n, elem_base=0, out=None, device="cuda", stream=None):
+    """Offline phase: the seeds' draws for n elements, as a device byte buffer."""
+    nb = rand_bytes(op, params, n)
+    if nb == 0 and n:
+        _check(lib.bc_check_params(ctypes.byref(params.c()), None), "rand_expand")
+    buf = out if out is not None else torch.empty(max(nb, 1), dtype=torch.uint8, device=device)
+    _check(lib.bc_rand_expand(buf.data_ptr(), buf.numel(), n, op, ctypes.byref(params.c()), ctypes.byref(seeds.c()),
+                              elem_base, _stream(stream)), "rand_expand")
+    return buf
+
+
+def _pre_like(fn, name, x0, x1, params, rand, capture, out, stream):
+    _check_shares(x0, x1, ring_width(params.ell))
+    y0 = _out(x0, ring_width(params.ell), ring_dtype(params.ell), None if out is None else out[0])
+    y1 = _out(x1, ring_width(params.ell), ring_dtype(params.ell), None if out is None else out[1])
+    cap = None
+    if capture:
+        cap = torch.empty((2, x0.numel(), params.npos), dtype=field_dtype(params.resolved().p), device=x0.device)
+    _check(fn(x0.data_ptr(), x1.data_ptr(), y0.data_ptr(), y1.data_ptr(), x0.numel(), ctypes.byref(params.c()),
+              rand.data_ptr(), rand.numel() * rand.element_size(), None if cap is None else cap.data_ptr(), None,
+              _stream(stream)), name)
+    return (y0, y1, cap) if capture else (y0, y1)
+
+
+def drelu_pre(x0, x1, params: Params, rand, capture=False, out=None, stream=None):
+    """Online Alg. 7 from a record made by rand_expand(BC_OP_DRELU, ...)."""
+    return _pre_like(lib.bc_drelu_pre, "drelu_pre", x0, x1, params, rand, capture, out, stream)
+
+
+def relu_pre(x0, x1, params: Params, rand, capture=False, out=None, stream=None):
+    """Online Alg. 8 from a record made by rand_expand(BC_OP_RELU, ...)."""
+    return _pre_like(lib.bc_relu_pre, "relu_pre", x0, x1, params, rand, capture, out, stream)

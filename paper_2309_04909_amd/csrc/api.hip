@@ -261,6 +261,65 @@ int batch_run(const void* dev_plan, const void* host_plan, const bc_seeds* seeds
     return e == hipSuccess ? BC_OK : hip_fail(e, "batch launch");
 }
 
+int pre_common(bool expand, uint32_t op, const void* x0, const void* x1, void* y0, void* y1, uint64_t n,
+               const bc_drelu_params* prm, const bc_seeds* seeds, uint64_t elem_base, void* rand, uint64_t rand_bytes,
+               void* capture, bc_msg_acct* acct, void* stream) {
+    if (op != BC_OP_DRELU && op != BC_OP_RELU) return fail(BC_ERR_ARG, "unknown op %u", op);
+    bc_drelu_params r;
+    int rc = check_params(prm, &r);
+    if (rc) return rc;
+    if (expand && !seeds) return fail(BC_ERR_NULL, "seeds is NULL");
+    if (elem_base > kMaxIndex || n > kMaxIndex - elem_base)
+        return fail(BC_ERR_ARG, "element indices must stay below 2^48");
+    if (acct) account(op, r, n, acct);
+    if (n == 0) return BC_OK;
+    const uint32_t w = width_of_ring(r.ell);
+    const bc::RandOffsets o = bc::rand_offsets(r.lx + 1, op == BC_OP_RELU, w, n);
+    if (!rand) return fail(BC_ERR_NULL, "randomness buffer is NULL");
+    if (!aligned(rand, 16)) return fail(BC_ERR_ALIGN, "randomness buffer must be 16-byte aligned");
+    if (rand_bytes < o.total) return fail(BC_ERR_WORKSPACE, "randomness buffer holds %llu of %llu bytes",
+                                          (unsigned long long)rand_bytes, (unsigned long long)o.total);
+    if (!expand) {
+        if (!x0 || !x1 || !y0 || !y1) return fail(BC_ERR_NULL, "share pointer is NULL");
+        if (!aligned(x0, w) || !aligned(x1, w) || !aligned(y0, w) || !aligned(y1, w))
+            return fail(BC_ERR_ALIGN, "share pointers must be %u-byte aligned", w);
+        if (capture && !aligned(capture, r.p < (1ull << 32) ? 4 : 8))
+            return fail(BC_ERR_ALIGN, "capture buffer misaligned");
+    }
+    bc::PreLaunch L;
+    L.x0 = x0;
+    L.x1 = x1;
+    L.y0 = y0;
+    L.y1 = y1;
+    L.cap = expand ? nullptr : capture;
+    L.rand = rand;
+    L.n = n;
+    L.elem_base = elem_base;
+    L.p = r.p;
+    L.ell = r.ell;
+    L.k_lo = r.k_lo;
+    L.npos = r.lx + 1;
+    L.relu = op == BC_OP_RELU;
+    L.expand = expand;
+    const bc_seeds zero{0, 0, 0, 0};
+    const bc_seeds& sd = seeds ? *seeds : zero;
+    L.s01 = stream_key(sd.seed01, sd.nonce);
+    L.s02 = stream_key(sd.seed02, sd.nonce);
+    L.s12 = stream_key(sd.seed12, sd.nonce);
+    const uint64_t grid = (n + 255) / 256, cap = (uint64_t)grid_cap(16);
+    L.grid = (int)(grid < cap ? grid : cap);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if (r.ell > 32) {
+        if (L.npos <= 12) e = bc::launch_pre_u64_lo(L, st);
+        else if (L.npos <= 24) e = bc::launch_pre_u64_mid(L, st);
+        else e = bc::launch_pre_u64_hi(L, st);
+    } else {
+        e = bc::launch_pre_u32(L, st);
+    }
+    return e == hipSuccess ? BC_OK : hip_fail(e, expand ? "expand launch" : "online launch");
+}
+
 }  // namespace
 
 namespace bc {
@@ -386,6 +445,31 @@ int bc_batch_plan(const bc_segment* segs, uint32_t nseg, const bc_drelu_params* 
 
 int bc_batch_run(const void* dev_plan, const void* host_plan, const bc_seeds* seeds, uint32_t grid, void* stream) {
     return batch_run(dev_plan, host_plan, seeds, grid, stream);
+}
+
+uint64_t bc_rand_bytes(uint32_t op, const bc_drelu_params* prm, uint64_t n) {
+    bc_drelu_params r;
+    if (op != BC_OP_DRELU && op != BC_OP_RELU) return 0;
+    if (check_params(prm, &r)) return 0;
+    return bc::rand_offsets(r.lx + 1, op == BC_OP_RELU, width_of_ring(r.ell), n).total;
+}
+
+int bc_rand_expand(void* rand, uint64_t rand_bytes, uint64_t n, uint32_t op, const bc_drelu_params* prm,
+                   const bc_seeds* seeds, uint64_t elem_base, void* stream) {
+    return pre_common(true, op, nullptr, nullptr, nullptr, nullptr, n, prm, seeds, elem_base, rand, rand_bytes, nullptr,
+                      nullptr, stream);
+}
+
+int bc_drelu_pre(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, const bc_drelu_params* prm,
+                 const void* rand, uint64_t rand_bytes, void* capture, bc_msg_acct* acct, void* stream) {
+    return pre_common(false, BC_OP_DRELU, x0, x1, y0, y1, n, prm, nullptr, 0, const_cast<void*>(rand), rand_bytes,
+                      capture, acct, stream);
+}
+
+int bc_relu_pre(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, const bc_drelu_params* prm,
+                const void* rand, uint64_t rand_bytes, void* capture, bc_msg_acct* acct, void* stream) {
+    return pre_common(false, BC_OP_RELU, x0, x1, y0, y1, n, prm, nullptr, 0, const_cast<void*>(rand), rand_bytes,
+                      capture, acct, stream);
 }
 
 int bc_relu(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, const bc_drelu_params* prm,

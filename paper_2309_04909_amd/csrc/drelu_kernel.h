@@ -50,6 +50,52 @@ struct BatchKArgs {
     uint32_t k01a, k01b, k02a, k02b, k12a, k12b;
 };
 
+// Steps 3-9 for one slot: the window position `pos` (sigma of the slot), the
+// slot's mask r and reshare z; returns both parties' messages and P2's test.
+template <typename T, int N, typename F>
+__device__ __forceinline__ bool slot_messages(T a0, T nb1, uint32_t pos, uint32_t k_lo, typename F::T r,
+                                              typename F::T z, const F& f, typename F::T& w0,
+                                              typename F::T& w1) {
+    using FT = typename F::T;
+    constexpr int LX = N - 1;
+    constexpr FT TWO_LX = (FT)1 << LX;                   // 2^l_x mod p = 2^l_x
+    constexpr FT WIN = TWO_LX - 1;                       // Z_{2^l_x}
+    constexpr FT WIN1 = (FT)((2ull << LX) - 1);          // l_x + 1 bits
+    const uint32_t s = k_lo + pos;
+    const bool last = pos == (uint32_t)LX;               // u_{l_x+1} := 0
+    const FT W0 = (FT)(a0 >> s) & WIN1;                  // bits [s, s + l_x]
+    const FT W1 = (FT)(nb1 >> s) & WIN1;
+    const FT u0n = last ? (FT)0 : (W0 >> 1);             // u_{i+1}
+    const FT u1n = last ? (FT)0 : (W1 >> 1);
+    const FT v0 = (W0 + u0n - 1) & WIN;                  // step 4: u_i + u_{i+1} - 1
+    const FT v1 = ((FT)0 - W1 - u1n) & WIN;              // P1: -cut_i - cut_{i+1}
+    const FT s0 = v0 ? v0 : TWO_LX;                      // step 5: Alg. 6
+    const FT s1 = v1 + (f.p - TWO_LX);
+    w0 = addmod(f.mul(s0, r), z, f);                     // steps 7-8: mask, reshare
+    w1 = addmod(f.mul(s1, r), (FT)(f.p - z), f);
+    return addmod(w0, w1, f) == 0;                       // step 9 (P2)
+}
+
+// Step 10-11 (DReLU): P2's fresh sharing (rho, D' - rho), then the unflip.
+template <typename T>
+__device__ __forceinline__ void drelu_finish(T dp, T rho, uint32_t t, T mask, T& y0, T& y1) {
+    const T d1 = (T)(dp - rho) & mask;
+    y0 = t ? (T)((T)1 - rho) & mask : rho;
+    y1 = t ? (T)((T)0 - d1) & mask : d1;
+}
+
+// Alg. 8 steps 3-5 with the triple ([a]_j, [b]_j, [c]_j) and the unflipped inputs.
+template <typename T>
+__device__ __forceinline__ void relu_finish(T dp, T in0, T in1, T ba0, T bb0, T bc0, T ba1, T bb1, T bc1, uint32_t t,
+                                            T mask, T& y0, T& y1) {
+    const T ee = (T)(dp - (T)(bb0 + bb1)) & mask;                 // P2: e = D' - b
+    const T dd = (T)((in0 - ba0) + (in1 - ba1)) & mask;           // P0, P1: d = x - a
+    const T m0 = (T)(dd * ee + dd * bb0 + ee * ba0 + bc0) & mask; // de + d[b] + e[a] + [c]
+    const T m1 = (T)(dd * bb1 + ee * ba1 + bc1) & mask;
+    y0 = t ? (T)(in0 - m0) & mask : m0;                            // t[x] + (1 - 2t)[x D']
+    y1 = t ? (T)(in1 - m1) & mask : m1;
+}
+
 // One element, all three parties.  N = l_x + 1 windows, fixed at compile
 // time: every loop over windows and slots is unrolled and all window masks
 // are constants.  Reads X0[e], X1[e], writes Y0[e], Y1[e]; the randomness
@@ -61,13 +107,8 @@ __device__ __forceinline__ void drelu_element(const T* __restrict__ X0, const T*
                                               uint32_t k_lo, const Stream& s01, const Stream& s02,
                                               const Stream& s12, const F& f) {
     using FT = typename F::T;
-    constexpr int LX = N - 1;
     constexpr bool WIDE = std::is_same<FT, uint64_t>::value;
-    constexpr FT TWO_LX = (FT)1 << LX;                   // 2^l_x mod p = 2^l_x
-    constexpr FT WIN = TWO_LX - 1;                       // Z_{2^l_x}
-    constexpr FT WIN1 = (FT)((2ull << LX) - 1);          // l_x + 1 bits
     static_assert(WIDE == (N == 33), "64-bit field elements exactly when l_x = 32");
-    const FT p_minus_two = f.p - TWO_LX;
 
     const T in0 = X0[e] & mask;
     const T in1 = X1[e] & mask;
@@ -106,40 +147,19 @@ __device__ __forceinline__ void drelu_element(const T* __restrict__ X0, const T*
             r = draw_r((j & 1) ? wm.w2 : wm.w0, f.p);
             z = draw_z((j & 1) ? wm.w3 : wm.w1, f.p);
         }
-        // Steps 3-4 for the position sigma(j) placed in slot j.
-        const uint32_t pos = key[j] & 63u;
-        const uint32_t s = k_lo + pos;
-        const bool last = pos == (uint32_t)LX;            // u_{l_x+1} := 0
-        const FT W0 = (FT)(a0 >> s) & WIN1;               // bits [s, s + l_x]
-        const FT W1 = (FT)(nb1 >> s) & WIN1;
-        const FT u0n = last ? (FT)0 : (W0 >> 1);          // u_{i+1}
-        const FT u1n = last ? (FT)0 : (W1 >> 1);
-        const FT v0 = (W0 + u0n - 1) & WIN;               // u_i + u_{i+1} - 1
-        const FT v1 = ((FT)0 - W1 - u1n) & WIN;           // P1: -cut_i - cut_{i+1}
-        // Step 5: Alg. 6.
-        const FT s0 = v0 ? v0 : TWO_LX;
-        const FT s1 = v1 + p_minus_two;
-        // Steps 7-8: mask and reshare.
-        const FT w0 = addmod(f.mul(s0, r), z, f);
-        const FT w1 = addmod(f.mul(s1, r), (FT)(f.p - z), f);
+        FT w0, w1;
+        zero |= slot_messages<T, N, F>(a0, nb1, key[j] & 63u, k_lo, r, z, f, w0, w1);
         if constexpr (CAP) {
             cap[e * N + j] = w0;
             cap[(ncap + e) * N + j] = w1;
         }
-        // Step 9 (P2): reconstruct and test for zero.
-        zero |= addmod(w0, w1, f) == 0;
     }
     const T dp = zero ? 1 : 0;
 
     T y0, y1;
     if constexpr (!RELU) {
-        // Step 10 (P2): fresh sharing (rho, D' - rho) with rho from seed_02.
-        const Words4 w = s02.block(g, TAG_RESP, 0);
-        const T rho = (T)join64(w.w0, w.w1) & mask;
-        const T d1 = (T)(dp - rho) & mask;
-        // Step 11: DReLU = t + (1 - 2t) D'.
-        y0 = t ? (T)((T)1 - rho) & mask : rho;
-        y1 = t ? (T)((T)0 - d1) & mask : d1;
+        const Words4 w = s02.block(g, TAG_RESP, 0);               // rho from seed_02
+        drelu_finish<T>(dp, (T)join64(w.w0, w.w1) & mask, t, mask, y0, y1);
     } else {
         // Alg. 8 preprocessing: [a]_0, [b]_0, [c]_0 from seed_02, [a]_1, [b]_1
         // from seed_12; P2 forms [c]_1 = (a0 + a1)(b0 + b1) - c0.
@@ -151,16 +171,8 @@ __device__ __forceinline__ void drelu_element(const T* __restrict__ X0, const T*
         const T bc0 = (T)join64(w1.w0, w1.w1) & mask;
         const T ba1 = (T)join64(w2.w0, w2.w1) & mask;
         const T bb1 = (T)join64(w2.w2, w2.w3) & mask;
-        const T bsum = (T)(bb0 + bb1);
-        const T bc1 = (T)((T)(ba0 + ba1) * bsum - bc0) & mask;
-        // Step 3 (P2): e = D' - b.  Step 4 (P0, P1): d = x - a, exchanged.
-        const T ee = (T)(dp - bsum) & mask;
-        const T dd = (T)((in0 - ba0) + (in1 - ba1)) & mask;
-        // Step 5: [x D'] = de + d[b] + e[a] + [c]; ReLU = t[x] + (1 - 2t)[x D'].
-        const T m0 = (T)(dd * ee + dd * bb0 + ee * ba0 + bc0) & mask;
-        const T m1 = (T)(dd * bb1 + ee * ba1 + bc1) & mask;
-        y0 = t ? (T)(in0 - m0) & mask : m0;
-        y1 = t ? (T)(in1 - m1) & mask : m1;
+        const T bc1 = (T)((T)(ba0 + ba1) * (T)(bb0 + bb1) - bc0) & mask;
+        relu_finish<T>(dp, in0, in1, ba0, bb0, bc0, ba1, bb1, bc1, t, mask, y0, y1);
     }
     Y0[e] = y0;
     Y1[e] = y1;

@@ -59,6 +59,46 @@ hipError_t launch_batch_u64_mid(const BatchLaunch& L, hipStream_t st);   // N 13
 hipError_t launch_batch_u64_hi(const BatchLaunch& L, hipStream_t st);    // N 25..33
 hipError_t launch_batch_u32(const BatchLaunch& L, hipStream_t st);       // N 2..17
 
+// Precomputed-randomness calls: the offline expansion (expand = true, writes
+// `rand`) or the online DReLU/ReLU (reads `rand`).
+struct PreLaunch {
+    const void* x0;
+    const void* x1;
+    void* y0;
+    void* y1;
+    void* cap;
+    void* rand;
+    uint64_t n, elem_base, p;
+    uint32_t ell, k_lo, npos;
+    bool relu, expand;
+    StreamKey s01, s02, s12;
+    int grid;
+};
+
+// Byte offsets of the sections of a randomness record on n elements
+// (each section starts at a 256-byte boundary).
+struct RandOffsets {
+    uint64_t perm, rz, tail, total;
+};
+
+inline uint64_t align256(uint64_t v) { return (v + 255) & ~255ull; }
+
+inline RandOffsets rand_offsets(uint32_t npos, bool relu, uint32_t ring_width, uint64_t n) {
+    RandOffsets o;
+    o.perm = 0;
+    const uint64_t perm_bytes = 4ull * ((npos + 3) / 4) * n;
+    o.rz = align256(perm_bytes);
+    const uint64_t rz_bytes = n * (npos <= 16 ? 4ull * npos : (npos <= 32 ? 8ull * npos : 16ull * npos));
+    o.tail = align256(o.rz + rz_bytes);
+    o.total = o.tail + (uint64_t)ring_width * n * (relu ? 6 : 1);
+    return o;
+}
+
+hipError_t launch_pre_u64_lo(const PreLaunch& L, hipStream_t st);    // N 2..12
+hipError_t launch_pre_u64_mid(const PreLaunch& L, hipStream_t st);   // N 13..24
+hipError_t launch_pre_u64_hi(const PreLaunch& L, hipStream_t st);    // N 25..33
+hipError_t launch_pre_u32(const PreLaunch& L, hipStream_t st);       // N 2..17
+
 // Kernel launchers, one per op, storage width and range of N = l_x + 1 (the
 // split only spreads compilation over several files).  Each returns
 // hipErrorInvalidValue when L.npos is outside its range.

@@ -1,0 +1,261 @@
+// Precomputed-randomness form of the DReLU (Alg. 7) and ReLU (Alg. 8) kernels.
+//
+// Everything the parties draw from their seeds is independent of the input,
+// so it can be expanded ahead of time (an offline phase) and kept resident:
+// P0/P1's flip t, shuffle and masks from seed_01, P2's response share from
+// seed_02, and the Beaver triple of Alg. 8's preprocessing including P2's
+// [c]_1.  The online kernel then streams the shares plus this record and does
+// steps 2-5 and 7-9 and the finish; it reuses the slot arithmetic of the fused
+// kernel, so both give bit-identical results and messages.
+//
+// Record of a call on n elements, structure of arrays (each array [.][n]):
+//   perm  uint32[ceil(N/4)][n]: byte q of word k is sigma(4k + q); bit 7 of
+//         byte 0 of word 0 is t
+//   rz    N <= 16: uint32[N][n], r_j | z_j << 16            (p < 2^16)
+//         N <= 32: uint32[2N][n], r_j at row 2j, z_j at 2j+1
+//         N == 33: uint64[2N][n], same rows
+//   tail  DReLU: T[n] rho.  ReLU: T[6][n] = [a]_0 [b]_0 [c]_0 [a]_1 [b]_1 [c]_1
+// Sections start at 256-byte boundaries.
+#pragma once
+
+#include "drelu_kernel.h"
+
+namespace bc {
+
+struct PreKArgs {
+    const void* x0;
+    const void* x1;
+    void* y0;
+    void* y1;
+    void* cap;
+    const uint32_t* perm;
+    const void* rz;
+    const void* tail;
+    uint64_t n;
+    uint64_t ring_mask;
+    uint32_t k_lo, pad;
+};
+
+struct ExpandKArgs {
+    uint32_t* perm;
+    void* rz;
+    void* tail;
+    uint64_t n;
+    uint64_t elem_base;
+    uint64_t ring_mask;
+    Stream s01, s02, s12;
+};
+
+template <int N>
+struct RzLayout {
+    static constexpr bool PACK16 = N <= 16;
+    static constexpr bool WIDE = N == 33;
+};
+
+// Offline: expand the seeds of n elements into the record.
+template <typename T, int N, typename F, bool RELU>
+__global__ __launch_bounds__(256) void k_expand(ExpandKArgs A, F f) {
+    const T mask = (T)A.ring_mask;
+    const uint64_t n = A.n;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        const uint64_t g = A.elem_base + e;
+        uint32_t key[N];
+        uint32_t t = 0;
+#pragma unroll
+        for (int b = 0; b < (N + 3) / 4; ++b) {
+            const Words4 w = A.s01.block(g, TAG_SHUFFLE, b);
+            if (b == 0) t = w.w0 & 1u;
+            const uint32_t ws[4] = {w.w0, w.w1, w.w2, w.w3};
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (4 * b + q < N) key[4 * b + q] = (ws[q] & ~63u) | (uint32_t)(4 * b + q);
+        }
+        sort_keys<N>(key);
+#pragma unroll
+        for (int k = 0; k < (N + 3) / 4; ++k) {
+            uint32_t word = (k == 0) ? (t << 7) : 0u;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (4 * k + q < N) word |= (key[4 * k + q] & 63u) << (8 * q);
+            A.perm[(uint64_t)k * n + e] = word;
+        }
+        Words4 wm = {0, 0, 0, 0};
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            if constexpr (RzLayout<N>::WIDE) {
+                const Words4 w = A.s01.block(g, TAG_MASK, (uint32_t)j);
+                uint64_t* rz = static_cast<uint64_t*>(A.rz);
+                rz[(uint64_t)(2 * j) * n + e] = 1 + __umul64hi(join64(w.w0, w.w1), f.p - 1);
+                rz[(uint64_t)(2 * j + 1) * n + e] = __umul64hi(join64(w.w2, w.w3), f.p);
+            } else {
+                if ((j & 1) == 0) wm = A.s01.block(g, TAG_MASK, (uint32_t)(j >> 1));
+                const uint32_t r = draw_r((j & 1) ? wm.w2 : wm.w0, (uint32_t)f.p);
+                const uint32_t z = draw_z((j & 1) ? wm.w3 : wm.w1, (uint32_t)f.p);
+                uint32_t* rz = static_cast<uint32_t*>(A.rz);
+                if constexpr (RzLayout<N>::PACK16) {
+                    rz[(uint64_t)j * n + e] = r | (z << 16);
+                } else {
+                    rz[(uint64_t)(2 * j) * n + e] = r;
+                    rz[(uint64_t)(2 * j + 1) * n + e] = z;
+                }
+            }
+        }
+        T* tail = static_cast<T*>(A.tail);
+        if constexpr (!RELU) {
+            const Words4 w = A.s02.block(g, TAG_RESP, 0);
+            tail[e] = (T)join64(w.w0, w.w1) & mask;
+        } else {
+            const Words4 w0 = A.s02.block(g, TAG_BEAVER, 0);
+            const Words4 w1 = A.s02.block(g, TAG_BEAVER, 1);
+            const Words4 w2 = A.s12.block(g, TAG_BEAVER, 0);
+            const T ba0 = (T)join64(w0.w0, w0.w1) & mask;
+            const T bb0 = (T)join64(w0.w2, w0.w3) & mask;
+            const T bc0 = (T)join64(w1.w0, w1.w1) & mask;
+            const T ba1 = (T)join64(w2.w0, w2.w1) & mask;
+            const T bb1 = (T)join64(w2.w2, w2.w3) & mask;
+            tail[e] = ba0;
+            tail[n + e] = bb0;
+            tail[2 * n + e] = bc0;
+            tail[3 * n + e] = ba1;
+            tail[4 * n + e] = bb1;
+            tail[5 * n + e] = (T)((T)(ba0 + ba1) * (T)(bb0 + bb1) - bc0) & mask;   // P2's [c]_1
+        }
+    }
+}
+
+// Online: Alg. 7 steps 2-5, 7-9 and the finish, reading the record.
+template <typename T, int N, typename F, bool RELU, bool CAP>
+__global__ __launch_bounds__(256) void k_drelu_pre(PreKArgs A, F f) {
+    using FT = typename F::T;
+    const T* __restrict__ X0 = static_cast<const T*>(A.x0);
+    const T* __restrict__ X1 = static_cast<const T*>(A.x1);
+    T* Y0 = static_cast<T*>(A.y0);
+    T* Y1 = static_cast<T*>(A.y1);
+    FT* cap = static_cast<FT*>(A.cap);
+    const T* __restrict__ tail = static_cast<const T*>(A.tail);
+    const T mask = (T)A.ring_mask;
+    const uint64_t n = A.n;
+    const uint32_t k_lo = A.k_lo;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        const T in0 = X0[e] & mask;
+        const T in1 = X1[e] & mask;
+        uint32_t perm[(N + 3) / 4];
+#pragma unroll
+        for (int k = 0; k < (N + 3) / 4; ++k) perm[k] = A.perm[(uint64_t)k * n + e];
+        const uint32_t t = (perm[0] >> 7) & 1u;
+        const T a0 = t ? (T)((T)0 - in0) & mask : in0;
+        const T a1 = t ? (T)((T)0 - in1) & mask : in1;
+        const T nb1 = (T)((T)0 - a1) & mask;
+        bool zero = false;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            FT r, z;
+            if constexpr (RzLayout<N>::WIDE) {
+                const uint64_t* rz = static_cast<const uint64_t*>(A.rz);
+                r = rz[(uint64_t)(2 * j) * n + e];
+                z = rz[(uint64_t)(2 * j + 1) * n + e];
+            } else if constexpr (RzLayout<N>::PACK16) {
+                const uint32_t v = static_cast<const uint32_t*>(A.rz)[(uint64_t)j * n + e];
+                r = v & 0xFFFFu;
+                z = v >> 16;
+            } else {
+                const uint32_t* rz = static_cast<const uint32_t*>(A.rz);
+                r = rz[(uint64_t)(2 * j) * n + e];
+                z = rz[(uint64_t)(2 * j + 1) * n + e];
+            }
+            const uint32_t pos = (perm[j >> 2] >> (8 * (j & 3))) & 63u;
+            FT w0, w1;
+            zero |= slot_messages<T, N, F>(a0, nb1, pos, k_lo, r, z, f, w0, w1);
+            if constexpr (CAP) {
+                cap[e * N + j] = w0;
+                cap[(n + e) * N + j] = w1;
+            }
+        }
+        const T dp = zero ? 1 : 0;
+        T y0, y1;
+        if constexpr (!RELU) {
+            drelu_finish<T>(dp, tail[e], t, mask, y0, y1);
+        } else {
+            relu_finish<T>(dp, in0, in1, tail[e], tail[n + e], tail[2 * n + e], tail[3 * n + e], tail[4 * n + e],
+                           tail[5 * n + e], t, mask, y0, y1);
+        }
+        Y0[e] = y0;
+        Y1[e] = y1;
+    }
+}
+
+template <typename T, int N, typename F>
+hipError_t launch_pre_field(const PreLaunch& L, const F& f, hipStream_t st) {
+    const uint64_t mask = L.ell >= 64 ? ~0ull : ((1ull << L.ell) - 1);
+    const RandOffsets o = rand_offsets(N, L.relu, sizeof(T), L.n);
+    uint8_t* base = static_cast<uint8_t*>(L.rand);
+    if (L.expand) {
+        ExpandKArgs A;
+        A.perm = reinterpret_cast<uint32_t*>(base + o.perm);
+        A.rz = base + o.rz;
+        A.tail = base + o.tail;
+        A.n = L.n;
+        A.elem_base = L.elem_base;
+        A.ring_mask = mask;
+        A.s01 = Stream{L.s01.k0, L.s01.k1, L.s01.n0, L.s01.n1};
+        A.s02 = Stream{L.s02.k0, L.s02.k1, L.s02.n0, L.s02.n1};
+        A.s12 = Stream{L.s12.k0, L.s12.k1, L.s12.n0, L.s12.n1};
+        if (L.relu)
+            hipLaunchKernelGGL((k_expand<T, N, F, true>), dim3(L.grid), dim3(256), 0, st, A, f);
+        else
+            hipLaunchKernelGGL((k_expand<T, N, F, false>), dim3(L.grid), dim3(256), 0, st, A, f);
+        return hipGetLastError();
+    }
+    PreKArgs A;
+    A.x0 = L.x0;
+    A.x1 = L.x1;
+    A.y0 = L.y0;
+    A.y1 = L.y1;
+    A.cap = L.cap;
+    A.perm = reinterpret_cast<const uint32_t*>(base + o.perm);
+    A.rz = base + o.rz;
+    A.tail = base + o.tail;
+    A.n = L.n;
+    A.ring_mask = mask;
+    A.k_lo = L.k_lo;
+    A.pad = 0;
+    if (L.relu) {
+        if (L.cap) hipLaunchKernelGGL((k_drelu_pre<T, N, F, true, true>), dim3(L.grid), dim3(256), 0, st, A, f);
+        else hipLaunchKernelGGL((k_drelu_pre<T, N, F, true, false>), dim3(L.grid), dim3(256), 0, st, A, f);
+    } else {
+        if (L.cap) hipLaunchKernelGGL((k_drelu_pre<T, N, F, false, true>), dim3(L.grid), dim3(256), 0, st, A, f);
+        else hipLaunchKernelGGL((k_drelu_pre<T, N, F, false, false>), dim3(L.grid), dim3(256), 0, st, A, f);
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int N>
+hipError_t launch_pre_exact(const PreLaunch& L, hipStream_t st) {
+    if constexpr (N <= 12) {
+        return launch_pre_field<T, N, FieldSmall>(L, make_field_small(L.p), st);
+    } else if constexpr (N <= 24) {
+        if constexpr (mersenne_exponent(N)) {
+            if (L.p == (1ull << N) - 1)
+                return launch_pre_field<T, N, FieldMersenne<N>>(L, FieldMersenne<N>{(uint32_t)L.p}, st);
+        }
+        return launch_pre_field<T, N, Field24>(L, make_field24(L.p), st);
+    } else if constexpr (N <= 32) {
+        return launch_pre_field<T, N, Field32>(L, make_field32(L.p), st);
+    } else {
+        return launch_pre_field<T, N, Field64>(L, make_field64(L.p), st);
+    }
+}
+
+template <typename T, int NLO, int NHI>
+hipError_t launch_pre_range(const PreLaunch& L, hipStream_t st) {
+    if constexpr (NLO > NHI) {
+        return hipErrorInvalidValue;
+    } else {
+        if (L.npos == (uint32_t)NLO) return launch_pre_exact<T, NLO>(L, st);
+        return launch_pre_range<T, NLO + 1, NHI>(L, st);
+    }
+}
+
+}  // namespace bc
