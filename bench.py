@@ -316,14 +316,35 @@ def run_serving(torch, B, count=600):
     return out
 
 
+def run_copy(torch, steps, warmup, mib=512):
+    """A plain device-to-device copy of known size: the reference for achievable
+    HBM bandwidth and for scaling rocprofv3's FETCH_SIZE / WRITE_SIZE counters."""
+    n = (mib << 20) // 8
+    src = torch.empty(n, dtype=torch.int64, device="cuda").fill_(3)
+    dst = torch.empty_like(src)
+    for _ in range(warmup):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    return {"bytes_per_copy": 2 * n * 8, "ms": round(ms, 4), "gbs": round(2 * n * 8 / ms / 1e6, 1),
+            "hbm_frac": round(2 * n * 8 / ms / 1e6 / HBM_PEAK_GBS, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--sections", default="cpu,batched,plain,serving",
-                    help="comma list of extra sections: cpu, batched, plain, serving")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 21)
+    ap.add_argument("--sections", default="cpu,batched,plain,serving,copy",
+                    help="comma list of extra sections: cpu, batched, plain, serving, copy")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 22)
     ap.add_argument("--cpu-workers", type=int, default=min(16, os.cpu_count() or 1))
     args = ap.parse_args()
 
@@ -377,6 +398,8 @@ def main():
         line["plain_drelu"] = run_plain_drelu(torch, B, args.steps, args.warmup)
     if "serving" in sections:
         line["serving"] = run_serving(torch, B)
+    if "copy" in sections:
+        line["copy_reference"] = run_copy(torch, args.steps, args.warmup)
     line.update(out)
     print(json.dumps(line), flush=True)
 

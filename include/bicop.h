@@ -124,6 +124,26 @@ int bc_msg_account(uint32_t op, const bc_drelu_params* prm, uint64_t n, bc_msg_a
 int bc_prg_blocks(uint32_t* out, uint64_t n, uint32_t nblocks, uint64_t seed,
                   uint64_t nonce, uint32_t tag, uint64_t elem_base, void* stream);
 
+/* ------------------------------------------------------------ schedules */
+
+/* Kernel kinds of the schedule table. */
+#define BC_SCHED_FUSED   0u   /* bc_drelu, bc_relu                       */
+#define BC_SCHED_STREAM  1u   /* bc_trunc_det, bc_trunc_prob, bc_mod_switch */
+#define BC_SCHED_PRE     2u   /* bc_drelu_pre, bc_relu_pre               */
+#define BC_SCHED_EXPAND  3u   /* bc_rand_expand                          */
+#define BC_SCHED_BATCH   4u   /* bc_batch_run with grid = 0              */
+
+/* Process-wide launch schedule: the grid of `kind` for window count npos
+ * (0..33; the streaming kernels use npos = 0) is capped at blocks_per_cu
+ * blocks of 256 threads per compute unit; each thread then handles
+ * n / (grid * 256) elements.  0 restores the built-in default.  Results do
+ * not depend on the schedule.  Set it before launching (the autotuner
+ * paper_2309_04909_amd/tune.py writes a table the binding applies). */
+int bc_set_schedule(uint32_t kind, uint32_t npos, uint32_t blocks_per_cu);
+
+/* The blocks per compute unit in effect for (kind, npos); 0 if invalid. */
+uint32_t bc_get_schedule(uint32_t kind, uint32_t npos);
+
 /* --------------------------------------------------------- truncation */
 
 /* Deterministic truncation, Alg. 4 (k2 = 0) and Alg. 5 (Sec. 5.1).

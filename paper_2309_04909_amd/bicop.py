@@ -78,6 +78,8 @@ _SIGS = {
                      ctypes.c_int),
     "bc_relu_pre": ([_P, _P, _P, _P, _U64, ctypes.POINTER(_Params), _P, _U64, _P, ctypes.POINTER(_Acct), _P],
                     ctypes.c_int),
+    "bc_set_schedule": ([_U32, _U32, _U32], ctypes.c_int),
+    "bc_get_schedule": ([_U32, _U32], _U32),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -96,6 +98,32 @@ def _load():
 
 
 lib = _load()
+
+SCHED_KINDS = {"fused": 0, "stream": 1, "pre": 2, "expand": 3, "batch": 4}
+SCHEDULES_PATH = os.path.join(_HERE, "schedules.json")
+
+
+def set_schedule(kind: str, npos: int, blocks_per_cu: int):
+    _check(lib.bc_set_schedule(SCHED_KINDS[kind], npos, blocks_per_cu), "set_schedule")
+
+
+def get_schedule(kind: str, npos: int) -> int:
+    return int(lib.bc_get_schedule(SCHED_KINDS[kind], npos))
+
+
+def load_schedules(path=SCHEDULES_PATH):
+    """Apply an autotuned schedule table (written by paper_2309_04909_amd.tune)."""
+    import json
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        table = json.load(f)
+    for e in table.get("grid", []):
+        set_schedule(e["kind"], int(e["npos"]), int(e["blocks_per_cu"]))
+    return table
+
+
+SCHEDULES = load_schedules()
 
 
 def _check(rc, where):

@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <atomic>
 #include <mutex>
 
 #include "internal.h"
@@ -128,6 +129,20 @@ constexpr uint64_t kMaxIndex = 1ull << 48;
 
 int grid_cap(int per_cu) { return bc::device_cus() * per_cu; }
 
+// Schedule table: blocks per compute unit of the grid, per kernel kind and
+// window count (0 = the built-in default).  Written by bc_set_schedule.
+constexpr int kKinds = 5;
+std::atomic<uint32_t> g_sched[kKinds][34];
+constexpr uint32_t kDefaultBpc[kKinds] = {16, 8, 16, 16, 8};
+
+uint64_t sched_grid(uint32_t kind, uint32_t npos, uint64_t work_blocks) {
+    uint32_t bpc = g_sched[kind][npos < 34 ? npos : 0].load(std::memory_order_relaxed);
+    if (!bpc) bpc = kDefaultBpc[kind];
+    const uint64_t cap = (uint64_t)grid_cap((int)bpc);
+    const uint64_t g = work_blocks < cap ? work_blocks : cap;
+    return g ? g : 1;
+}
+
 int drelu_common(uint32_t op, const void* x0, const void* x1, void* y0, void* y1, uint64_t n,
                  const bc_drelu_params* prm, const bc_seeds* seeds, uint64_t elem_base, void* capture,
                  bc_msg_acct* acct, void* stream) {
@@ -162,9 +177,7 @@ int drelu_common(uint32_t op, const void* x0, const void* x1, void* y0, void* y1
     L.s02 = stream_key(seeds->seed02, seeds->nonce);
     L.s12 = stream_key(seeds->seed12, seeds->nonce);
     L.block = 256;
-    uint64_t grid = (n + 255) / 256;
-    const uint64_t cap = (uint64_t)grid_cap(16);
-    L.grid = (int)(grid < cap ? grid : cap);
+    L.grid = (int)sched_grid(BC_SCHED_FUSED, L.npos, (n + 255) / 256);
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
     const bool relu = op == BC_OP_RELU;
@@ -246,7 +259,7 @@ int batch_run(const void* dev_plan, const void* host_plan, const bc_seeds* seeds
     L.s01 = stream_key(seeds->seed01, 0);
     L.s02 = stream_key(seeds->seed02, 0);
     L.s12 = stream_key(seeds->seed12, 0);
-    uint64_t g = grid ? grid : (uint64_t)grid_cap(8);
+    uint64_t g = grid ? grid : sched_grid(BC_SCHED_BATCH, L.npos, h->total_tiles);
     if (g > h->total_tiles) g = h->total_tiles;
     L.grid = (int)g;
     hipStream_t st = (hipStream_t)stream;
@@ -306,8 +319,7 @@ int pre_common(bool expand, uint32_t op, const void* x0, const void* x1, void* y
     L.s01 = stream_key(sd.seed01, sd.nonce);
     L.s02 = stream_key(sd.seed02, sd.nonce);
     L.s12 = stream_key(sd.seed12, sd.nonce);
-    const uint64_t grid = (n + 255) / 256, cap = (uint64_t)grid_cap(16);
-    L.grid = (int)(grid < cap ? grid : cap);
+    L.grid = (int)sched_grid(expand ? BC_SCHED_EXPAND : BC_SCHED_PRE, L.npos, (n + 255) / 256);
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
     if (r.ell > 32) {
@@ -363,6 +375,20 @@ const char* bc_last_error(void) { return g_err; }
 
 uint64_t bc_default_prime(uint32_t lx) { return default_prime(lx); }
 
+int bc_set_schedule(uint32_t kind, uint32_t npos, uint32_t blocks_per_cu) {
+    if (kind >= (uint32_t)kKinds) return fail(BC_ERR_ARG, "unknown schedule kind %u", kind);
+    if (npos > 33) return fail(BC_ERR_ARG, "npos = %u outside [0, 33]", npos);
+    if (blocks_per_cu > 1024) return fail(BC_ERR_ARG, "blocks_per_cu = %u above 1024", blocks_per_cu);
+    g_sched[kind][npos].store(blocks_per_cu, std::memory_order_relaxed);
+    return BC_OK;
+}
+
+uint32_t bc_get_schedule(uint32_t kind, uint32_t npos) {
+    if (kind >= (uint32_t)kKinds || npos > 33) return 0;
+    const uint32_t v = g_sched[kind][npos].load(std::memory_order_relaxed);
+    return v ? v : kDefaultBpc[kind];
+}
+
 int bc_check_params(const bc_drelu_params* prm, bc_drelu_params* resolved) { return check_params(prm, resolved); }
 
 int bc_msg_account(uint32_t op, const bc_drelu_params* prm, uint64_t n, bc_msg_acct* acct) {
@@ -396,7 +422,7 @@ int bc_trunc_det(const void* x0, const void* x1, void* y0, void* y1, uint64_t n,
     const uint32_t wi = width_of_ring(ell), wo = width_of_ring(ell - k1 - k2);
     if (!aligned(x0, wi) || !aligned(x1, wi) || !aligned(y0, wo) || !aligned(y1, wo))
         return fail(BC_ERR_ALIGN, "share pointers misaligned");
-    hipError_t e = bc::launch_trunc_det(x0, x1, y0, y1, n, ell, k1, k2, grid_cap(8), (hipStream_t)stream);
+    hipError_t e = bc::launch_trunc_det(x0, x1, y0, y1, n, ell, k1, k2, (int)sched_grid(BC_SCHED_STREAM, 0, ~0ull), (hipStream_t)stream);
     return e == hipSuccess ? BC_OK : hip_fail(e, "trunc_det launch");
 }
 
@@ -409,7 +435,7 @@ int bc_trunc_prob(const void* x0, const void* x1, void* y0, void* y1, uint64_t n
     const uint32_t w = width_of_ring(ell);
     if (!aligned(x0, w) || !aligned(x1, w) || !aligned(y0, w) || !aligned(y1, w))
         return fail(BC_ERR_ALIGN, "share pointers misaligned");
-    hipError_t e = bc::launch_trunc_prob(x0, x1, y0, y1, n, ell, k, grid_cap(8), (hipStream_t)stream);
+    hipError_t e = bc::launch_trunc_prob(x0, x1, y0, y1, n, ell, k, (int)sched_grid(BC_SCHED_STREAM, 0, ~0ull), (hipStream_t)stream);
     return e == hipSuccess ? BC_OK : hip_fail(e, "trunc_prob launch");
 }
 
@@ -425,7 +451,7 @@ int bc_mod_switch(const void* x0, const void* x1, void* y0, void* y1, uint64_t n
     const uint32_t wi = width_of_ring(ell_in), wo = p < (1ull << 32) ? 4u : 8u;
     if (!aligned(x0, wi) || !aligned(x1, wi) || !aligned(y0, wo) || !aligned(y1, wo))
         return fail(BC_ERR_ALIGN, "share pointers misaligned");
-    hipError_t e = bc::launch_mod_switch(x0, x1, y0, y1, n, ell_in, p, grid_cap(8), (hipStream_t)stream);
+    hipError_t e = bc::launch_mod_switch(x0, x1, y0, y1, n, ell_in, p, (int)sched_grid(BC_SCHED_STREAM, 0, ~0ull), (hipStream_t)stream);
     return e == hipSuccess ? BC_OK : hip_fail(e, "mod_switch launch");
 }
 

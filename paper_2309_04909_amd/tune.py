@@ -1,0 +1,156 @@
+"""Autotuner: picks launch schedules on the GPU and writes schedules.json.
+
+For each kernel kind and window count of the workloads it times a sweep of
+grid sizes (blocks of 256 threads per compute unit, so elements per thread
+= n / (grid * 256)); for the ragged batch it also sweeps the tile size.
+Results never depend on the schedule (checked here on every candidate);
+only speed does.  The binding applies schedules.json at import.
+
+    python -m paper_2309_04909_amd.tune [--quick]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import bicop as B
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+# (ell, lx, k_lo) of the workloads: key-bit DReLU, ResNet ReLU, matmul ReLU
+# (both rings), serving l = 32, plain DReLU (l_x = 31 and 32)
+SETTINGS = [(64, 18, 13), (64, 7, 11), (51, 11, 13), (24, 7, 10), (32, 8, 8), (64, 31, 0), (64, 32, 0)]
+BPC = [1, 2, 4, 8, 16, 32, 64]
+TILES = [256, 512, 1024, 2048, 4096, 8192]
+
+
+def _time(fn, reps=10, warm=2):
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def _shares(n, ell, seed):
+    rng = np.random.default_rng(seed)
+    dt = np.uint64 if ell > 32 else np.uint32
+    view = torch.int64 if ell > 32 else torch.int32
+    x0 = torch.from_numpy(rng.integers(0, 2 ** 62, size=n, dtype=np.int64).astype(dt).view(
+        np.int64 if ell > 32 else np.int32)).cuda().view(view)
+    x1 = torch.from_numpy(rng.integers(0, 2 ** 62, size=n, dtype=np.int64).astype(dt).view(
+        np.int64 if ell > 32 else np.int32)).cuda().view(view)
+    return x0, x1
+
+
+def tune_kind(kind, settings, n, reps):
+    out = []
+    for ell, lx, k_lo in settings:
+        prm = B.Params(ell, lx, k_lo)
+        npos = lx + 1
+        x0, x1 = _shares(n, ell, ell + lx)
+        y0, y1 = torch.empty_like(x0), torch.empty_like(x1)
+        sd = B.Seeds(1, 2, 3, 4)
+        rand = None
+        if kind in ("pre", "expand"):
+            rand = B.rand_expand(B.BC_OP_DRELU, prm, sd, n)
+        if kind == "fused":
+            fn = lambda: B.drelu(x0, x1, prm, sd, out=(y0, y1))  # noqa: E731
+        elif kind == "pre":
+            fn = lambda: B.drelu_pre(x0, x1, prm, rand, out=(y0, y1))  # noqa: E731
+        else:
+            fn = lambda: B.rand_expand(B.BC_OP_DRELU, prm, sd, n, out=rand)  # noqa: E731
+        ref = None
+        best = None
+        for bpc in BPC:
+            B.set_schedule(kind, npos, bpc)
+            ms = _time(fn, reps)
+            if kind != "expand":
+                got = (y0.clone(), y1.clone())
+                if ref is None:
+                    ref = got
+                assert torch.equal(ref[0].view(torch.int64), got[0].view(torch.int64)) and \
+                    torch.equal(ref[1].view(torch.int64), got[1].view(torch.int64)), "schedule changed a result"
+            if best is None or ms < best[1]:
+                best = (bpc, ms)
+            print(f"  {kind:6s} l={ell} lx={lx:2d} bpc={bpc:3d}: {ms:.3f} ms", flush=True)
+        B.set_schedule(kind, npos, best[0])
+        out.append({"kind": kind, "npos": npos, "blocks_per_cu": best[0], "ms": round(best[1], 4), "n": n,
+                    "setting": [ell, lx, k_lo]})
+    return out
+
+
+def tune_stream(n, reps):
+    x0, x1 = _shares(n, 64, 9)
+    y0, y1 = torch.empty_like(x0), torch.empty_like(x1)
+    best = None
+    for bpc in BPC:
+        B.set_schedule("stream", 0, bpc)
+        ms = _time(lambda: B.trunc_det(x0, x1, 64, 13, out=(y0, y1)), reps)
+        print(f"  stream bpc={bpc:3d}: {ms:.4f} ms ({32 * n / ms / 1e6:.0f} GB/s)", flush=True)
+        if best is None or ms < best[1]:
+            best = (bpc, ms)
+    B.set_schedule("stream", 0, best[0])
+    return [{"kind": "stream", "npos": 0, "blocks_per_cu": best[0], "ms": round(best[1], 4), "n": n}]
+
+
+def tune_batch(reps, batch=8):
+    """ResNet-18-shaped ragged batch (l = 64, l_x = 7): tile size x grid."""
+    from . import batch as BT
+    import workloads as W
+    prm = B.Params(64, 7, 11)
+    segs = []
+    for i, n in enumerate(W.resnet18_sizes(batch)):
+        x0, x1 = _shares(n, 64, 100 + i)
+        segs.append(BT.Segment(x0, x1, torch.empty_like(x0), torch.empty_like(x1), op=B.BC_OP_RELU, nonce=i))
+    best = None
+    for tile in TILES:
+        for bpc in (2, 4, 8, 16, 32):
+            B.set_schedule("batch", 8, bpc)
+            rb = BT.RaggedBatch(prm, B.Seeds(1, 2, 3), segs, tile_elems=tile)
+            ms = _time(rb.run, reps)
+            print(f"  batch tile={tile:5d} bpc={bpc:3d}: {ms:.3f} ms", flush=True)
+            if best is None or ms < best[2]:
+                best = (tile, bpc, ms)
+    B.set_schedule("batch", 8, best[1])
+    return [{"kind": "batch", "npos": 8, "blocks_per_cu": best[1], "ms": round(best[2], 4)}], best[0]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--quick", action="store_true")
+    ap.add_argument("--out", default=B.SCHEDULES_PATH)
+    a = ap.parse_args()
+    if not torch.cuda.is_available():
+        print("the autotuner needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    n = 1 << (21 if a.quick else 23)
+    reps = 5 if a.quick else 10
+    t0 = time.time()
+    grid = []
+    grid += tune_stream(n, reps)
+    grid += tune_kind("fused", SETTINGS, n, reps)
+    grid += tune_kind("pre", SETTINGS[:5], n, reps)
+    grid += tune_kind("expand", SETTINGS[:5], n, reps)
+    bgrid, tile = tune_batch(reps)
+    grid += bgrid
+    table = {"device": torch.cuda.get_device_name(0), "grid": grid, "batch_tile": tile,
+             "tuned_seconds": round(time.time() - t0, 1)}
+    with open(a.out, "w") as f:
+        json.dump(table, f, indent=1)
+    print(json.dumps(table))
+
+
+if __name__ == "__main__":
+    main()
