@@ -316,6 +316,45 @@ def run_serving(torch, B, count=600):
     return out
 
 
+def run_matmul_relu(torch, B, steps, warmup):
+    """ReLU after a fixed-point matmul: Z = A B (A 4096x4096, B 4096x1024, exact),
+    shared, truncated by f bits (Alg. 5), then ReLU on all 4,194,304 outputs.
+    Two-pass (trunc_det then relu) vs the fused bc_trunc_relu; l = 64 (f = 13)
+    and the l = 32 variant (f = 8)."""
+    out = {"workload": "ReLU after matmul [4096x4096].[4096x1024], 4,194,304 outputs"}
+    for ell, f, lx, k_lo in ((64, 13, 11, 13), (32, 8, 7, 10)):
+        _, (z0, z1) = W.matmul_relu(seed=3, ell=ell)
+        d0, d1 = to_dev(torch, z0), to_dev(torch, z1)
+        prm, sd = B.Params(ell - f, lx, k_lo), B.Seeds(*SEEDS, 21)
+        t0, t1 = torch.empty_like(d0), torch.empty_like(d1)
+        y0, y1 = torch.empty_like(d0), torch.empty_like(d1)
+
+        def two_pass():
+            B.trunc_det(d0, d1, ell, f, 0, out=(t0, t1))
+            B.relu(t0, t1, prm, sd, out=(y0, y1))
+
+        def fused():
+            B.trunc_relu(d0, d1, ell, f, prm, sd, out=(y0, y1))
+
+        res = {}
+        for name, fn in (("two_pass", two_pass), ("fused", fused)):
+            for _ in range(warmup):
+                fn()
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(steps):
+                fn()
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / steps
+            res[f"{name}_ms"] = round(ms, 4)
+            res[f"{name}_gelem_s"] = round(d0.numel() / ms / 1e6, 3)
+        out[f"l{ell}"] = dict(res, setting=f"trunc {f} -> Z_2^{ell - f}, k_lo={k_lo}, l_x={lx}")
+    return out
+
+
 def run_copy(torch, steps, warmup, mib=512):
     """A plain device-to-device copy of known size: the reference for achievable
     HBM bandwidth and for scaling rocprofv3's FETCH_SIZE / WRITE_SIZE counters."""
@@ -342,8 +381,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--sections", default="cpu,batched,plain,serving,copy",
-                    help="comma list of extra sections: cpu, batched, plain, serving, copy")
+    ap.add_argument("--sections", default="cpu,batched,plain,serving,copy,matmul",
+                    help="comma list of extra sections: cpu, batched, plain, serving, copy, matmul")
     ap.add_argument("--cpu-sample", type=int, default=1 << 22)
     ap.add_argument("--cpu-workers", type=int, default=min(16, os.cpu_count() or 1))
     args = ap.parse_args()
@@ -398,6 +437,8 @@ def main():
         line["plain_drelu"] = run_plain_drelu(torch, B, args.steps, args.warmup)
     if "serving" in sections:
         line["serving"] = run_serving(torch, B)
+    if "matmul" in sections:
+        line["matmul_relu"] = run_matmul_relu(torch, B, args.steps, args.warmup)
     if "copy" in sections:
         line["copy_reference"] = run_copy(torch, args.steps, args.warmup)
     line.update(out)

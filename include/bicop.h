@@ -206,6 +206,21 @@ int bc_relu(const void* x0, const void* x1, void* y0, void* y1, uint64_t n,
             const bc_drelu_params* prm, const bc_seeds* seeds, uint64_t elem_base,
             void* capture, bc_msg_acct* acct, void* stream);
 
+/* Truncate, then DReLU / ReLU, in one pass.  x0, x1 are shares of
+ * Z_{2^ell_in}; each party first applies the deterministic truncation of
+ * Alg. 5 by k1 low bits (P0: cut(x0, k1), P1: -cut(-x1, k1)), giving shares
+ * of Z_{2^(ell_in - k1)}, and the DReLU (Alg. 7) / ReLU (Alg. 8) of prm then
+ * runs in that ring (prm->ell must equal ell_in - k1; both rings must have
+ * the same storage width).  Outputs are shares of Z_{2^prm->ell}; the result
+ * is bit-identical to bc_trunc_det followed by bc_drelu / bc_relu, with one
+ * read and one write of the shares instead of two of each.  k1 > 0. */
+int bc_trunc_drelu(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, uint32_t ell_in, uint32_t k1,
+                   const bc_drelu_params* prm, const bc_seeds* seeds, uint64_t elem_base, void* capture,
+                   bc_msg_acct* acct, void* stream);
+int bc_trunc_relu(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, uint32_t ell_in, uint32_t k1,
+                  const bc_drelu_params* prm, const bc_seeds* seeds, uint64_t elem_base, void* capture,
+                  bc_msg_acct* acct, void* stream);
+
 /* ------------------------------------------ precomputed randomness */
 
 /* Everything the parties draw from their seeds is independent of the input

@@ -78,6 +78,10 @@ _SIGS = {
                      ctypes.c_int),
     "bc_relu_pre": ([_P, _P, _P, _P, _U64, ctypes.POINTER(_Params), _P, _U64, _P, ctypes.POINTER(_Acct), _P],
                     ctypes.c_int),
+    "bc_trunc_drelu": ([_P, _P, _P, _P, _U64, _U32, _U32, ctypes.POINTER(_Params), ctypes.POINTER(_Seeds), _U64, _P,
+                        ctypes.POINTER(_Acct), _P], ctypes.c_int),
+    "bc_trunc_relu": ([_P, _P, _P, _P, _U64, _U32, _U32, ctypes.POINTER(_Params), ctypes.POINTER(_Seeds), _U64, _P,
+                       ctypes.POINTER(_Acct), _P], ctypes.c_int),
     "bc_set_schedule": ([_U32, _U32, _U32], ctypes.c_int),
     "bc_get_schedule": ([_U32, _U32], _U32),
 }
@@ -284,6 +288,31 @@ def drelu(x0, x1, params: Params, seeds: Seeds, elem_base=0, capture=False, out=
 def relu(x0, x1, params: Params, seeds: Seeds, elem_base=0, capture=False, out=None, stream=None):
     """Alg. 8.  Returns (y0, y1) or (y0, y1, capture[2, n, lx+1])."""
     return _drelu_like(lib.bc_relu, "relu", x0, x1, params, seeds, elem_base, capture, out, stream)
+
+
+def _trunc_like(fn, name, x0, x1, ell_in, k1, params, seeds, elem_base, capture, out, stream):
+    _check_shares(x0, x1, ring_width(ell_in))
+    y0 = _out(x0, ring_width(params.ell), ring_dtype(params.ell), None if out is None else out[0])
+    y1 = _out(x1, ring_width(params.ell), ring_dtype(params.ell), None if out is None else out[1])
+    cap = None
+    if capture:
+        cap = torch.empty((2, x0.numel(), params.npos), dtype=field_dtype(params.resolved().p), device=x0.device)
+    _check(fn(x0.data_ptr(), x1.data_ptr(), y0.data_ptr(), y1.data_ptr(), x0.numel(), ell_in, k1,
+              ctypes.byref(params.c()), ctypes.byref(seeds.c()), elem_base, None if cap is None else cap.data_ptr(),
+              None, _stream(stream)), name)
+    return (y0, y1, cap) if capture else (y0, y1)
+
+
+def trunc_drelu(x0, x1, ell_in, k1, params: Params, seeds: Seeds, elem_base=0, capture=False, out=None, stream=None):
+    """Alg. 5 by k1 bits (Z_{2^ell_in} -> Z_{2^params.ell}) fused with Alg. 7."""
+    return _trunc_like(lib.bc_trunc_drelu, "trunc_drelu", x0, x1, ell_in, k1, params, seeds, elem_base, capture,
+                       out, stream)
+
+
+def trunc_relu(x0, x1, ell_in, k1, params: Params, seeds: Seeds, elem_base=0, capture=False, out=None, stream=None):
+    """Alg. 5 by k1 bits (Z_{2^ell_in} -> Z_{2^params.ell}) fused with Alg. 8."""
+    return _trunc_like(lib.bc_trunc_relu, "trunc_relu", x0, x1, ell_in, k1, params, seeds, elem_base, capture,
+                       out, stream)
 
 
 def prg_blocks(n, nblocks, seed, nonce, tag, elem_base=0, device="cuda", stream=None):

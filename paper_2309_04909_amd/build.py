@@ -38,34 +38,35 @@ def _run(cmd):
     return r.returncode, out
 
 
-def build(jobs: int | None = None, verbose: bool = False, asm: bool = False) -> str:
-    """Compile every HIP source and link libbicop.so.  Returns the library path."""
-    os.makedirs(BUILD, exist_ok=True)
+def build(jobs: int | None = None, verbose: bool = False, asm: bool = False, extra_flags=(), out: str = LIB,
+          build_dir: str = BUILD) -> str:
+    """Compile every HIP source and link libbicop.so (or `out`).  Returns the library path."""
+    os.makedirs(build_dir, exist_ok=True)
     srcs = sources()
     jobs = jobs or min(len(srcs), max(1, min(16, os.cpu_count() or 4)))
 
     def compile_one(src):
-        obj = os.path.join(BUILD, os.path.basename(src).replace(".hip", ".o"))
-        rc, out = _run([HIPCC, *FLAGS, "-c", src, "-o", obj])
+        obj = os.path.join(build_dir, os.path.basename(src).replace(".hip", ".o"))
+        rc, log = _run([HIPCC, *FLAGS, *extra_flags, "-c", src, "-o", obj])
         if rc == 0 and asm:
-            s = os.path.join(BUILD, os.path.basename(src).replace(".hip", ".s"))
-            _run([HIPCC, *FLAGS, "--cuda-device-only", "-S", src, "-o", s])
-        return src, obj, rc, out
+            s = os.path.join(build_dir, os.path.basename(src).replace(".hip", ".s"))
+            _run([HIPCC, *FLAGS, *extra_flags, "--cuda-device-only", "-S", src, "-o", s])
+        return src, obj, rc, log
 
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         results = list(ex.map(compile_one, srcs))
     errors = [(s, o) for s, _, rc, o in results if rc != 0]
-    for s, _, rc, out in results:
-        if out and (verbose or rc != 0):
-            print(f"--- {os.path.basename(s)}\n{out}", file=sys.stderr)
+    for s, _, rc, log in results:
+        if log and (verbose or rc != 0):
+            print(f"--- {os.path.basename(s)}\n{log}", file=sys.stderr)
     if errors:
         raise RuntimeError("hipcc failed for: " + ", ".join(os.path.basename(s) for s, _ in errors))
-    tmp = LIB + ".tmp"
-    rc, out = _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *[o for _, o, _, _ in results]])
+    tmp = out + ".tmp"
+    rc, log = _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *[o for _, o, _, _ in results]])
     if rc != 0:
-        raise RuntimeError("link failed:\n" + out)
-    os.replace(tmp, LIB)
-    return LIB
+        raise RuntimeError("link failed:\n" + log)
+    os.replace(tmp, out)
+    return out
 
 
 def clean():

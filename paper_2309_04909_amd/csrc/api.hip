@@ -145,10 +145,17 @@ uint64_t sched_grid(uint32_t kind, uint32_t npos, uint64_t work_blocks) {
 
 int drelu_common(uint32_t op, const void* x0, const void* x1, void* y0, void* y1, uint64_t n,
                  const bc_drelu_params* prm, const bc_seeds* seeds, uint64_t elem_base, void* capture,
-                 bc_msg_acct* acct, void* stream) {
+                 bc_msg_acct* acct, void* stream, uint32_t ell_in = 0, uint32_t k_in = 0) {
     bc_drelu_params r;
     int rc = check_params(prm, &r);
     if (rc) return rc;
+    if (k_in) {
+        if (ell_in < 2 || ell_in > 64 || (uint64_t)r.ell + k_in != ell_in)
+            return fail(BC_ERR_RING, "truncation must map Z_2^%u onto the ring of params (ell = %u, k1 = %u)", ell_in,
+                        r.ell, k_in);
+        if (width_of_ring(ell_in) != width_of_ring(r.ell))
+            return fail(BC_ERR_RING, "input ring %u and output ring %u must share a storage width", ell_in, r.ell);
+    }
     if (!seeds) return fail(BC_ERR_NULL, "seeds is NULL");
     if (elem_base > kMaxIndex || n > kMaxIndex - elem_base)
         return fail(BC_ERR_ARG, "element indices must stay below 2^48");
@@ -172,6 +179,7 @@ int drelu_common(uint32_t op, const void* x0, const void* x1, void* y0, void* y1
     L.lx = r.lx;
     L.k_lo = r.k_lo;
     L.npos = r.lx + 1;
+    L.k_in = k_in;
     L.p = r.p;
     L.s01 = stream_key(seeds->seed01, seeds->nonce);
     L.s02 = stream_key(seeds->seed02, seeds->nonce);
@@ -496,6 +504,20 @@ int bc_relu_pre(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, 
                 const void* rand, uint64_t rand_bytes, void* capture, bc_msg_acct* acct, void* stream) {
     return pre_common(false, BC_OP_RELU, x0, x1, y0, y1, n, prm, nullptr, 0, const_cast<void*>(rand), rand_bytes,
                       capture, acct, stream);
+}
+
+int bc_trunc_drelu(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, uint32_t ell_in, uint32_t k1,
+                   const bc_drelu_params* prm, const bc_seeds* seeds, uint64_t elem_base, void* capture,
+                   bc_msg_acct* acct, void* stream) {
+    if (k1 == 0) return fail(BC_ERR_RING, "k1 must be > 0 (use bc_drelu)");
+    return drelu_common(BC_OP_DRELU, x0, x1, y0, y1, n, prm, seeds, elem_base, capture, acct, stream, ell_in, k1);
+}
+
+int bc_trunc_relu(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, uint32_t ell_in, uint32_t k1,
+                  const bc_drelu_params* prm, const bc_seeds* seeds, uint64_t elem_base, void* capture,
+                  bc_msg_acct* acct, void* stream) {
+    if (k1 == 0) return fail(BC_ERR_RING, "k1 must be > 0 (use bc_relu)");
+    return drelu_common(BC_OP_RELU, x0, x1, y0, y1, n, prm, seeds, elem_base, capture, acct, stream, ell_in, k1);
 }
 
 int bc_relu(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, const bc_drelu_params* prm,

@@ -17,6 +17,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Launch attributes of the DReLU/ReLU kernels (256-thread blocks).  A build
+// may override them (e.g. with an amdgpu_waves_per_eu occupancy hint).
+#ifndef BC_KERNEL_ATTRS
+#define BC_KERNEL_ATTRS __launch_bounds__(256)
+#endif
+
 namespace bc {
 
 // ------------------------------------------------------------------ Philox

@@ -38,7 +38,8 @@ struct DreluKArgs {
     uint64_t n;
     uint64_t elem_base;
     uint64_t ring_mask;   // 2^l - 1
-    uint32_t k_lo, pad;
+    uint64_t in_mask;     // 2^l_in - 1 of the input ring (l_in = l + k_in)
+    uint32_t k_lo, k_in;  // k_in > 0: Alg. 5 truncation of the inputs by k_in bits first
     Stream s01, s02, s12;
 };
 
@@ -100,18 +101,23 @@ __device__ __forceinline__ void relu_finish(T dp, T in0, T in1, T ba0, T bb0, T 
 // time: every loop over windows and slots is unrolled and all window masks
 // are constants.  Reads X0[e], X1[e], writes Y0[e], Y1[e]; the randomness
 // belongs to global index g.  With CAP, the round-1 messages go to
-// cap[e * N + slot] (P0) and cap[(ncap + e) * N + slot] (P1).
+// cap[e * N + slot] (P0) and cap[(ncap + e) * N + slot] (P1).  With k_in > 0
+// the inputs are shares of Z_{2^(l + k_in)} (in_mask) and are first truncated
+// by k_in bits into Z_{2^l} (Alg. 5); with k_in = 0 and in_mask = mask the
+// same expressions are the plain load.
 template <typename T, int N, typename F, bool RELU, bool CAP>
 __device__ __forceinline__ void drelu_element(const T* __restrict__ X0, const T* __restrict__ X1, T* Y0, T* Y1,
                                               typename F::T* cap, uint64_t ncap, uint64_t e, uint64_t g, T mask,
-                                              uint32_t k_lo, const Stream& s01, const Stream& s02,
-                                              const Stream& s12, const F& f) {
+                                              T in_mask, uint32_t k_in, uint32_t k_lo, const Stream& s01,
+                                              const Stream& s02, const Stream& s12, const F& f) {
     using FT = typename F::T;
     constexpr bool WIDE = std::is_same<FT, uint64_t>::value;
     static_assert(WIDE == (N == 33), "64-bit field elements exactly when l_x = 32");
 
-    const T in0 = X0[e] & mask;
-    const T in1 = X1[e] & mask;
+    const T r0 = X0[e] & in_mask;
+    const T r1 = X1[e] & in_mask;
+    const T in0 = (T)(r0 >> k_in) & mask;                                           // P0: cut(x0, k_in)
+    const T in1 = (T)((T)0 - (T)((T)((T)0 - r1) & in_mask) >> k_in) & mask;        // P1: -cut(-x1, k_in)
 
     // Steps 1 and 6 (randomness): t and the shuffle keys from seed_01.
     uint32_t key[N];
@@ -180,7 +186,7 @@ __device__ __forceinline__ void drelu_element(const T* __restrict__ X0, const T*
 
 // One call: grid-stride over the n elements of one share pair.
 template <typename T, int N, typename F, bool RELU, bool CAP>
-__global__ __launch_bounds__(256) void k_drelu(DreluKArgs A, F f) {
+__global__ BC_KERNEL_ATTRS void k_drelu(DreluKArgs A, F f) {
     const T* X0 = static_cast<const T*>(A.x0);
     const T* X1 = static_cast<const T*>(A.x1);
     T* Y0 = static_cast<T*>(A.y0);
@@ -189,8 +195,8 @@ __global__ __launch_bounds__(256) void k_drelu(DreluKArgs A, F f) {
     const T mask = (T)A.ring_mask;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < A.n; e += stride)
-        drelu_element<T, N, F, RELU, CAP>(X0, X1, Y0, Y1, cap, A.n, e, A.elem_base + e, mask, A.k_lo, A.s01, A.s02,
-                                          A.s12, f);
+        drelu_element<T, N, F, RELU, CAP>(X0, X1, Y0, Y1, cap, A.n, e, A.elem_base + e, mask, (T)A.in_mask, A.k_in,
+                                          A.k_lo, A.s01, A.s02, A.s12, f);
 }
 
 // Ragged batch: a persistent grid walks the tiles of every segment.  Tile t
@@ -200,7 +206,7 @@ __global__ __launch_bounds__(256) void k_drelu(DreluKArgs A, F f) {
 // Each block takes tiles blockIdx.x, blockIdx.x + gridDim.x, ... until
 // total_tiles: every wave reaches the exit.
 template <typename T, int N, typename F>
-__global__ __launch_bounds__(256) void k_batch(const BatchPlanHeader* __restrict__ hdr,
+__global__ BC_KERNEL_ATTRS void k_batch(const BatchPlanHeader* __restrict__ hdr,
                                                const bc_segment* __restrict__ segs,
                                                const uint64_t* __restrict__ tile_begin, BatchKArgs A, F f) {
     const uint32_t nseg = A.nseg;
@@ -226,12 +232,12 @@ __global__ __launch_bounds__(256) void k_batch(const BatchPlanHeader* __restrict
         const uint64_t base = S.elem_base;
         if (S.op == BC_OP_RELU) {
             for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x)
-                drelu_element<T, N, F, true, false>(X0, X1, Y0, Y1, nullptr, 0, e, base + e, mask, A.k_lo, s01, s02,
-                                                    s12, f);
+                drelu_element<T, N, F, true, false>(X0, X1, Y0, Y1, nullptr, 0, e, base + e, mask, mask, 0, A.k_lo,
+                                                    s01, s02, s12, f);
         } else {
             for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x)
-                drelu_element<T, N, F, false, false>(X0, X1, Y0, Y1, nullptr, 0, e, base + e, mask, A.k_lo, s01, s02,
-                                                     s12, f);
+                drelu_element<T, N, F, false, false>(X0, X1, Y0, Y1, nullptr, 0, e, base + e, mask, mask, 0, A.k_lo,
+                                                     s01, s02, s12, f);
         }
     }
 }
@@ -252,8 +258,9 @@ inline DreluKArgs make_kargs(const DreluLaunch& L) {
     A.n = L.n;
     A.elem_base = L.elem_base;
     A.ring_mask = L.ell >= 64 ? ~0ull : ((1ull << L.ell) - 1);
+    A.in_mask = L.ell + L.k_in >= 64 ? ~0ull : ((1ull << (L.ell + L.k_in)) - 1);
     A.k_lo = L.k_lo;
-    A.pad = 0;
+    A.k_in = L.k_in;
     A.s01 = Stream{L.s01.k0, L.s01.k1, L.s01.n0, L.s01.n1};
     A.s02 = Stream{L.s02.k0, L.s02.k1, L.s02.n0, L.s02.n1};
     A.s12 = Stream{L.s12.k0, L.s12.k1, L.s12.n0, L.s12.n1};

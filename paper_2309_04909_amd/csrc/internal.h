@@ -23,6 +23,7 @@ struct DreluLaunch {
     uint64_t n;
     uint64_t elem_base;
     uint32_t ell, lx, k_lo, npos;
+    uint32_t k_in;        // > 0: inputs are shares of Z_{2^(ell + k_in)}, truncated first (Alg. 5)
     uint64_t p;
     StreamKey s01, s02, s12;
     int grid;

@@ -54,7 +54,7 @@ struct RzLayout {
 
 // Offline: expand the seeds of n elements into the record.
 template <typename T, int N, typename F, bool RELU>
-__global__ __launch_bounds__(256) void k_expand(ExpandKArgs A, F f) {
+__global__ BC_KERNEL_ATTRS void k_expand(ExpandKArgs A, F f) {
     const T mask = (T)A.ring_mask;
     const uint64_t n = A.n;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(256) void k_expand(ExpandKArgs A, F f) {
 
 // Online: Alg. 7 steps 2-5, 7-9 and the finish, reading the record.
 template <typename T, int N, typename F, bool RELU, bool CAP>
-__global__ __launch_bounds__(256) void k_drelu_pre(PreKArgs A, F f) {
+__global__ BC_KERNEL_ATTRS void k_drelu_pre(PreKArgs A, F f) {
     using FT = typename F::T;
     const T* __restrict__ X0 = static_cast<const T*>(A.x0);
     const T* __restrict__ X1 = static_cast<const T*>(A.x1);

@@ -221,3 +221,36 @@ def test_drelu_semantics_on_gpu(B):
     r0, r1 = B.relu(dev(x0), dev(x1), B.Params(ell, lx, k_lo), B.Seeds(1, 2, 3, 4))
     r = host(r0) + host(r1)
     assert np.array_equal(r, x * y)
+
+
+@pytest.mark.parametrize("op", ["drelu", "relu"])
+@pytest.mark.parametrize("ell_in,k1,lx,k_lo", [(64, 13, 11, 13), (64, 13, 18, 13), (32, 8, 7, 10), (64, 20, 7, 11)])
+def test_fused_trunc_then_drelu_relu(B, op, ell_in, k1, lx, k_lo):
+    """Alg. 5 by k1 bits fused with Alg. 7/8 equals trunc_det followed by the op, and the oracle."""
+    rng = np.random.default_rng(ell_in + k1 + lx)
+    ell = ell_in - k1
+    n = 5003
+    bound = 1 << (k_lo + lx - 1 + k1)
+    xs = rng.integers(-bound + 1, bound, size=n)
+    x = np.array([v % (1 << ell_in) for v in xs.tolist()], dtype=np.uint64)
+    x0, x1 = W.share(x, ell_in, rng)
+    seeds = (3, 1, 4)
+    prm, sd = B.Params(ell, lx, k_lo), B.Seeds(*seeds, 15)
+    fused = (B.trunc_relu if op == "relu" else B.trunc_drelu)(dev(x0), dev(x1), ell_in, k1, prm, sd, elem_base=9,
+                                                             capture=True)
+    t0, t1 = B.trunc_det(dev(x0), dev(x1), ell_in, k1)
+    two = (B.relu if op == "relu" else B.drelu)(t0, t1, prm, sd, elem_base=9, capture=True)
+    for a, b in zip(fused, two):
+        assert same(a, b)
+    e0, e1 = OPR.trunc_det(x0.astype(np.uint64), x1.astype(np.uint64), ell_in, k1)
+    o0, o1, w0, w1 = (OPR.relu if op == "relu" else OPR.drelu)(e0, e1, ell, lx, k_lo, default_prime(lx), seeds, 15,
+                                                               elem_base=9)
+    assert np.array_equal(host(fused[0]).astype(np.uint64), o0) and np.array_equal(host(fused[1]).astype(np.uint64), o1)
+
+
+def test_fused_trunc_rejects_mismatched_rings(B):
+    x = torch.zeros(10, dtype=torch.int64, device="cuda")
+    with pytest.raises(B.BicopError):
+        B.trunc_relu(x, x, 64, 13, B.Params(50, 11, 13), B.Seeds(1, 2, 3))        # 64 - 13 != 50
+    with pytest.raises(B.BicopError):
+        B.trunc_relu(x, x, 40, 10, B.Params(30, 7, 10), B.Seeds(1, 2, 3))         # 8-byte in, 4-byte out
