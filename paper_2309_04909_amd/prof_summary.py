@@ -1,0 +1,148 @@
+"""Summarise rocprofv3 runs of bench.py into profiles/.
+
+Inputs are the output directories of four runs of the same command:
+  --trace   rocprofv3 --kernel-trace --stats
+  --fetch   rocprofv3 --pmc FETCH_SIZE
+  --write   rocprofv3 --pmc WRITE_SIZE
+  --valu    rocprofv3 --pmc SQ_INSTS_VALU SQ_WAVES SQ_ACTIVE_INST_VALU GRBM_GUI_ACTIVE   (optional)
+FETCH_SIZE / WRITE_SIZE (KiB per dispatch) are scaled by what the same
+counters read for the plain device copy bench.py runs (copy_reference: a
+known number of bytes read and written), giving HBM bytes per launch.
+
+Writes profiles/<name>_kernel_stats.md, profiles/<name>_counters.md and
+profiles/traffic.json (bytes per launch per kernel, with the hash of the
+kernel sources they were measured on; bench.py reports null for a kernel
+whose sources changed since).
+
+    python -m paper_2309_04909_amd.prof_summary --trace D1 --fetch D2 --write D3 [--valu D4] \\
+        --name bench_keybit --cmd "<the profiled command>"
+"""
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+PROFILES = os.path.join(ROOT, "profiles")
+
+# kernel key -> (substring of the demangled name, sources the kernel is built from, algorithmic bytes per launch)
+N_KEYBIT = 1 << 24
+KERNELS = {
+    "drelu_keybit": ("k_drelu<unsigned long, 19, bc::FieldMersenne<19>, false, false>",
+                     ["bc_device.h", "drelu_kernel.h"], 32 * N_KEYBIT),
+    "trunc_det_keybit": ("OpTruncDet<unsigned long, unsigned long>", ["bc_device.h", "k_stream.hip"],
+                         32 * N_KEYBIT),
+}
+COPY_BYTES = 512 << 20          # bench.py copy_reference: 512 MiB read and 512 MiB written per copy
+
+
+def source_hash(names):
+    h = hashlib.sha256()
+    for nm in names:
+        with open(os.path.join(HERE, "csrc", nm), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _rows(d, suffix):
+    files = sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
+    out = []
+    for fn in files:
+        with open(fn, newline="") as f:
+            out.extend(csv.DictReader(f))
+    return out
+
+
+def kernel_stats(d):
+    return [r for r in _rows(d, "kernel_stats.csv")]
+
+
+def counters(d):
+    """{(kernel name, counter): [value per dispatch]}"""
+    acc = defaultdict(list)
+    for r in _rows(d, "counter_collection.csv"):
+        acc[(r["Kernel_Name"], r["Counter_Name"])].append(float(r["Counter_Value"]))
+    return acc
+
+
+def _match(name, key):
+    return key in name
+
+
+def _copy_name(names):
+    cands = [n for n in names if "copy" in n.lower()]
+    return cands[0] if cands else None
+
+
+def summarise(trace, fetch, write, valu, name, cmd):
+    os.makedirs(PROFILES, exist_ok=True)
+    stats = kernel_stats(trace)
+    lines = [f"# rocprofv3 kernel statistics: {name}", "", f"Command: `{cmd}`", "",
+             "| Kernel | Calls | Average (us) | Total (ms) | Share |", "|---|---|---|---|---|"]
+    for r in sorted(stats, key=lambda r: -float(r.get("TotalDurationNs", 0))):
+        lines.append(f"| `{r['Name'][:150]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.3f} | {float(r['Percentage']):.1f}% |")
+    with open(os.path.join(PROFILES, f"{name}_kernel_stats.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+    fc, wc = counters(fetch), counters(write)
+    names = sorted({k for k, _ in fc} | {k for k, _ in wc})
+    copy = _copy_name(names)
+    if copy is None:
+        raise SystemExit("no copy kernel found in the counter runs")
+    mean = lambda v: sum(v) / len(v)  # noqa: E731
+    scale_f = COPY_BYTES / (mean(fc[(copy, "FETCH_SIZE")]) * 1024)
+    scale_w = COPY_BYTES / (mean(wc[(copy, "WRITE_SIZE")]) * 1024)
+    vc = counters(valu) if valu else {}
+    tab = ["# HBM traffic and VALU instructions per launch: " + name, "", f"Command: `{cmd}`", "",
+           f"Counters scaled by the plain copy `{copy[:80]}` of {COPY_BYTES} B read + {COPY_BYTES} B written: "
+           f"FETCH_SIZE x {scale_f:.4f}, WRITE_SIZE x {scale_w:.4f}.", "",
+           "| Kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes (scaled) | Algorithmic bytes | Ratio | "
+           "VALU instr / wave |", "|---|---|---|---|---|---|---|"]
+    traffic = {}
+    path = os.path.join(PROFILES, "traffic.json")
+    if os.path.exists(path):
+        with open(path) as f:
+            traffic = json.load(f)
+    for key, (sub, srcs, alg) in KERNELS.items():
+        kn = [n for n in names if _match(n, sub)]
+        if not kn:
+            continue
+        k = kn[0]
+        fk, wk = mean(fc[(k, "FETCH_SIZE")]), mean(wc[(k, "WRITE_SIZE")])
+        hbm = fk * 1024 * scale_f + wk * 1024 * scale_w
+        vi = ""
+        if vc:
+            vk = [n for n in {a for a, _ in vc} if _match(n, sub)]
+            if vk and (vk[0], "SQ_INSTS_VALU") in vc and (vk[0], "SQ_WAVES") in vc:
+                vi = f"{mean(vc[(vk[0], 'SQ_INSTS_VALU')]) / mean(vc[(vk[0], 'SQ_WAVES')]):.0f}"
+        tab.append(f"| `{key}` | {fk:.0f} | {wk:.0f} | {hbm:.4g} | {alg:.4g} | {hbm / alg:.3f} | {vi} |")
+        traffic[key] = {"bytes_per_launch": round(hbm), "fetch_kib": fk, "write_kib": wk,
+                        "scale_fetch": scale_f, "scale_write": scale_w, "algorithmic_bytes": alg,
+                        "source_hash": source_hash(srcs), "command": cmd}
+    with open(os.path.join(PROFILES, f"{name}_counters.md"), "w") as f:
+        f.write("\n".join(tab) + "\n")
+    with open(path, "w") as f:
+        json.dump(traffic, f, indent=1)
+    return traffic
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--valu", default=None)
+    ap.add_argument("--name", default="bench_keybit")
+    ap.add_argument("--cmd", required=True)
+    a = ap.parse_args()
+    print(json.dumps(summarise(a.trace, a.fetch, a.write, a.valu, a.name, a.cmd), indent=1))
+
+
+if __name__ == "__main__":
+    main()
