@@ -355,6 +355,43 @@ def run_matmul_relu(torch, B, steps, warmup):
     return out
 
 
+# Tab. 6 / Tab. 7 (three P100 servers, LAN1): microseconds per DReLU / ReLU batch
+PAPER_LAN1_US = {"drelu": {1: 932.05, 1000: 997.36, 10000: 1375.86, 100000: 5698.69, 1000000: 58608.3},
+                 "relu": {1: 1519.43, 1000: 1608.76, 10000: 2275.01, 100000: 9958.73, 1000000: 90185.9}}
+
+
+def run_sweep(torch, B, steps, warmup):
+    """Batch sizes of the paper's unit experiments (1 ... 10^6) at l = 64, l_x = 7
+    (k_lo = 11): microseconds per call on one GPU, next to the paper's LAN1 times
+    (three networked P100 servers, where the network dominates: context only)."""
+    n_max = 10 ** 6
+    rng = np.random.default_rng(12)
+    x = W.encode(W.fixed_point(rng.standard_normal(n_max), 13), 64)
+    x0, x1 = W.share(x, 64, rng)
+    d0, d1 = to_dev(torch, x0), to_dev(torch, x1)
+    y0, y1 = torch.empty_like(d0), torch.empty_like(d1)
+    prm, sd = B.Params(64, 7, 11), B.Seeds(*SEEDS, 5)
+    out = {"workload": "DReLU / ReLU, l=64, k_lo=11, l_x=7, N(0,1) 2^13 values; paper = Tab. 6/7 LAN1 (context)"}
+    for op, fn in (("drelu", B.drelu), ("relu", B.relu)):
+        rows = {}
+        for n in (1, 1000, 10000, 100000, 1000000):
+            a0, a1, b0, b1 = d0[:n], d1[:n], y0[:n], y1[:n]
+            for _ in range(warmup):
+                fn(a0, a1, prm, sd, out=(b0, b1))
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(steps):
+                fn(a0, a1, prm, sd, out=(b0, b1))
+            b.record()
+            torch.cuda.synchronize()
+            us = a.elapsed_time(b) / steps * 1e3
+            rows[str(n)] = {"us": round(us, 2), "gelem_s": round(n / us / 1e3, 4), "paper_lan1_us": PAPER_LAN1_US[op][n]}
+        out[op] = rows
+    return out
+
+
 def run_copy(torch, steps, warmup, mib=512):
     """A plain device-to-device copy of known size: the reference for achievable
     HBM bandwidth and for scaling rocprofv3's FETCH_SIZE / WRITE_SIZE counters."""
@@ -381,8 +418,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--sections", default="cpu,batched,plain,serving,copy,matmul",
-                    help="comma list of extra sections: cpu, batched, plain, serving, copy, matmul")
+    ap.add_argument("--sections", default="cpu,batched,plain,serving,copy,matmul,sweep",
+                    help="comma list of extra sections: cpu, batched, plain, serving, copy, matmul, sweep")
     ap.add_argument("--cpu-sample", type=int, default=1 << 22)
     ap.add_argument("--cpu-workers", type=int, default=min(16, os.cpu_count() or 1))
     args = ap.parse_args()
@@ -439,6 +476,8 @@ def main():
         line["serving"] = run_serving(torch, B)
     if "matmul" in sections:
         line["matmul_relu"] = run_matmul_relu(torch, B, args.steps, args.warmup)
+    if "sweep" in sections:
+        line["batch_sweep"] = run_sweep(torch, B, args.steps, args.warmup)
     if "copy" in sections:
         line["copy_reference"] = run_copy(torch, args.steps, args.warmup)
     line.update(out)

@@ -117,7 +117,8 @@ __device__ __forceinline__ void drelu_element(const T* __restrict__ X0, const T*
     const T r0 = X0[e] & in_mask;
     const T r1 = X1[e] & in_mask;
     const T in0 = (T)(r0 >> k_in) & mask;                                           // P0: cut(x0, k_in)
-    const T in1 = (T)((T)0 - (T)((T)((T)0 - r1) & in_mask) >> k_in) & mask;        // P1: -cut(-x1, k_in)
+    const T nr1 = (T)((T)0 - r1) & in_mask;                                          // -x1 in the input ring
+    const T in1 = (T)((T)0 - (T)(nr1 >> k_in)) & mask;                              // P1: -cut(-x1, k_in)
 
     // Steps 1 and 6 (randomness): t and the shuffle keys from seed_01.
     uint32_t key[N];

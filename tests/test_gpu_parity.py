@@ -224,7 +224,8 @@ def test_drelu_semantics_on_gpu(B):
 
 
 @pytest.mark.parametrize("op", ["drelu", "relu"])
-@pytest.mark.parametrize("ell_in,k1,lx,k_lo", [(64, 13, 11, 13), (64, 13, 18, 13), (32, 8, 7, 10), (64, 20, 7, 11)])
+@pytest.mark.parametrize("ell_in,k1,lx,k_lo", [(64, 13, 11, 13), (64, 13, 18, 13), (32, 8, 7, 10), (64, 20, 7, 11),
+                                                  (64, 13, 11, 0), (32, 8, 12, 0)])
 def test_fused_trunc_then_drelu_relu(B, op, ell_in, k1, lx, k_lo):
     """Alg. 5 by k1 bits fused with Alg. 7/8 equals trunc_det followed by the op, and the oracle."""
     rng = np.random.default_rng(ell_in + k1 + lx)
