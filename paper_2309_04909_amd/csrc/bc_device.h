@@ -41,8 +41,15 @@ struct Words4 {
     uint32_t w0, w1, w2, w3;
 };
 
+// Three-input XOR in one gfx950 v_bitop3_b32 (truth table 0x96).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 // Ten rounds.  Round r uses key (k0 + r W0, k1 + r W1).  One round maps
 // (c0, c1, c2, c3) to (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0)).
+// In round 0, c2, c3 (the nonce) and the key are uniform, so the uniform
+// pairs are left to plain XORs (scalar unit); later rounds use xor3.
 __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                 uint32_t k0, uint32_t k1) {
 #pragma unroll
@@ -51,8 +58,8 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
         const uint64_t p1 = (uint64_t)PHILOX_M1 * c2;
         const uint32_t rk0 = k0 + (uint32_t)r * PHILOX_W0;
         const uint32_t rk1 = k1 + (uint32_t)r * PHILOX_W1;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ rk0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ rk1;
+        const uint32_t n0 = r == 0 ? ((uint32_t)(p1 >> 32) ^ rk0) ^ c1 : xor3((uint32_t)(p1 >> 32), c1, rk0);
+        const uint32_t n2 = r == 0 ? (c3 ^ rk1) ^ (uint32_t)(p0 >> 32) : xor3((uint32_t)(p0 >> 32), c3, rk1);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;

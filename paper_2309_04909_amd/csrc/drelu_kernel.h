@@ -51,21 +51,31 @@ struct BatchKArgs {
     uint32_t k01a, k01b, k02a, k02b, k12a, k12b;
 };
 
+// Bits [pos, pos + l_x] of a share already shifted down by k_lo (pos <= l_x).
+// With 64-bit shares and windows of at most 32 bits one v_alignbit_b32 of
+// the two halves does the variable shift.
+template <typename T, int N, typename FT>
+__device__ __forceinline__ FT window(T a, uint32_t pos) {
+    constexpr FT WIN1 = (FT)((2ull << (N - 1)) - 1);     // l_x + 1 bits
+    if constexpr (sizeof(T) == 8 && N <= 32)
+        return (FT)__builtin_amdgcn_alignbit((uint32_t)(a >> 32), (uint32_t)a, pos) & WIN1;
+    else
+        return (FT)(a >> pos) & WIN1;
+}
+
 // Steps 3-9 for one slot: the window position `pos` (sigma of the slot), the
 // slot's mask r and reshare z; returns both parties' messages and P2's test.
+// a0 and nb1 are P0's share and P1's negated share, both shifted down by k_lo.
 template <typename T, int N, typename F>
-__device__ __forceinline__ bool slot_messages(T a0, T nb1, uint32_t pos, uint32_t k_lo, typename F::T r,
-                                              typename F::T z, const F& f, typename F::T& w0,
-                                              typename F::T& w1) {
+__device__ __forceinline__ bool slot_messages(T a0, T nb1, uint32_t pos, typename F::T r, typename F::T z,
+                                              const F& f, typename F::T& w0, typename F::T& w1) {
     using FT = typename F::T;
     constexpr int LX = N - 1;
     constexpr FT TWO_LX = (FT)1 << LX;                   // 2^l_x mod p = 2^l_x
     constexpr FT WIN = TWO_LX - 1;                       // Z_{2^l_x}
-    constexpr FT WIN1 = (FT)((2ull << LX) - 1);          // l_x + 1 bits
-    const uint32_t s = k_lo + pos;
     const bool last = pos == (uint32_t)LX;               // u_{l_x+1} := 0
-    const FT W0 = (FT)(a0 >> s) & WIN1;                  // bits [s, s + l_x]
-    const FT W1 = (FT)(nb1 >> s) & WIN1;
+    const FT W0 = window<T, N, FT>(a0, pos);             // bits [k_lo + pos, k_lo + pos + l_x]
+    const FT W1 = window<T, N, FT>(nb1, pos);
     const FT u0n = last ? (FT)0 : (W0 >> 1);             // u_{i+1}
     const FT u1n = last ? (FT)0 : (W1 >> 1);
     const FT v0 = (W0 + u0n - 1) & WIN;                  // step 4: u_i + u_{i+1} - 1
@@ -138,6 +148,7 @@ __device__ __forceinline__ void drelu_element(const T* __restrict__ X0, const T*
     const T a0 = t ? (T)((T)0 - in0) & mask : in0;
     const T a1 = t ? (T)((T)0 - in1) & mask : in1;
     const T nb1 = (T)((T)0 - a1) & mask;                  // P1 cuts -[x]_1 mod 2^l
+    const T a0k = a0 >> k_lo, nb1k = nb1 >> k_lo;         // common low cut of every window
 
     bool zero = false;
     Words4 wm = {0, 0, 0, 0};
@@ -155,7 +166,7 @@ __device__ __forceinline__ void drelu_element(const T* __restrict__ X0, const T*
             z = draw_z((j & 1) ? wm.w3 : wm.w1, f.p);
         }
         FT w0, w1;
-        zero |= slot_messages<T, N, F>(a0, nb1, key[j] & 63u, k_lo, r, z, f, w0, w1);
+        zero |= slot_messages<T, N, F>(a0k, nb1k, key[j] & 63u, r, z, f, w0, w1);
         if constexpr (CAP) {
             cap[e * N + j] = w0;
             cap[(ncap + e) * N + j] = w1;

@@ -148,6 +148,7 @@ __global__ BC_KERNEL_ATTRS void k_drelu_pre(PreKArgs A, F f) {
         const T a0 = t ? (T)((T)0 - in0) & mask : in0;
         const T a1 = t ? (T)((T)0 - in1) & mask : in1;
         const T nb1 = (T)((T)0 - a1) & mask;
+        const T a0k = a0 >> k_lo, nb1k = nb1 >> k_lo;
         bool zero = false;
 #pragma unroll
         for (int j = 0; j < N; ++j) {
@@ -167,7 +168,7 @@ __global__ BC_KERNEL_ATTRS void k_drelu_pre(PreKArgs A, F f) {
             }
             const uint32_t pos = (perm[j >> 2] >> (8 * (j & 3))) & 63u;
             FT w0, w1;
-            zero |= slot_messages<T, N, F>(a0, nb1, pos, k_lo, r, z, f, w0, w1);
+            zero |= slot_messages<T, N, F>(a0k, nb1k, pos, r, z, f, w0, w1);
             if constexpr (CAP) {
                 cap[e * N + j] = w0;
                 cap[(n + e) * N + j] = w1;
