@@ -46,14 +46,16 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
 }
 
-// Ten rounds.  Round r uses key (k0 + r W0, k1 + r W1).  One round maps
-// (c0, c1, c2, c3) to (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0)).
+// Rounds R0..9 of Philox4x32-10.  Round r uses key (k0 + r W0, k1 + r W1) and
+// maps (c0, c1, c2, c3) to
+//   (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0)).
 // In round 0, c2, c3 (the nonce) and the key are uniform, so the uniform
 // pairs are left to plain XORs (scalar unit); later rounds use xor3.
-__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                                uint32_t k0, uint32_t k1) {
+template <int R0>
+__device__ __forceinline__ Words4 philox_rounds(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                                uint32_t k1) {
 #pragma unroll
-    for (int r = 0; r < 10; ++r) {
+    for (int r = R0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)PHILOX_M0 * c0;
         const uint64_t p1 = (uint64_t)PHILOX_M1 * c2;
         const uint32_t rk0 = k0 + (uint32_t)r * PHILOX_W0;
@@ -68,19 +70,70 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
     return {c0, c1, c2, c3};
 }
 
+__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                uint32_t k0, uint32_t k1) {
+    return philox_rounds<0>(c0, c1, c2, c3, k0, k1);
+}
+
+// The key is uniform.  Passing it through an empty asm stops the compiler
+// from hoisting all round keys of every seed out of the element loop, and the
+// scheduling barrier stops it from computing the round keys of later blocks
+// ahead of time; either exhausts the SGPRs.  Each block recomputes its round
+// keys with scalar adds.
+__device__ __forceinline__ void launder_key(uint32_t& a, uint32_t& c) {
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("" : "+s"(a), "+s"(c));
+}
+
+// Blocks of one stream at one element index g.  The counters of all its
+// blocks, (lo g, hi16(g) | tag << 16 | b << 24, nonce), differ only in word 1,
+// which round 0 folds into word 0 alone.  So hi/lo(M0 lo g) of round 0,
+// M1 c2 of round 1 and M0 c0 of round 2 are the same for every block; they
+// are computed once here, and each block runs 16 multiplies instead of 20.
+struct StreamAt {
+    uint32_t k0, k1;    // key
+    uint32_t ghi;       // hi16(g)
+    uint32_t u0;        // hi(M1 n0) ^ k0: round-0 word 0 without the block's word 1
+    uint32_t c3a;       // round-0 output word 3, lo(M0 lo g)
+    uint32_t c0b, c1b;  // round-1 output words 0 and 1
+    uint32_t h2, l2;    // hi / lo(M0 c0b) of round 2
+
+    __device__ __forceinline__ Words4 block(uint32_t tag, uint32_t b) const {
+        uint32_t a = k0, c = k1;
+        launder_key(a, c);
+        const uint32_t x0 = u0 ^ (ghi | (tag << 16) | (b << 24));              // round 0, word 0
+        const uint64_t p0 = (uint64_t)PHILOX_M0 * x0;                          // round 1
+        const uint32_t y2 = xor3((uint32_t)(p0 >> 32), c3a, c + PHILOX_W1);
+        const uint32_t y3 = (uint32_t)p0;
+        const uint64_t p1 = (uint64_t)PHILOX_M1 * y2;                          // round 2
+        const uint32_t z0 = xor3((uint32_t)(p1 >> 32), c1b, a + 2u * PHILOX_W0);
+        const uint32_t z2 = xor3(h2, y3, c + 2u * PHILOX_W1);
+        return philox_rounds<3>(z0, (uint32_t)p1, z2, l2, a, c);
+    }
+};
+
 // Counter of block b of stream `tag` for global element index g.
 struct Stream {
     uint32_t k0, k1;   // key = seed
     uint32_t n0, n1;   // (c2, c3) = nonce
     __device__ __forceinline__ Words4 block(uint64_t g, uint32_t tag, uint32_t b) const {
         const uint32_t c1 = ((uint32_t)(g >> 32) & 0xFFFFu) | (tag << 16) | (b << 24);
-        // The key is uniform.  Passing it through an empty asm stops the
-        // compiler from hoisting all round keys of every seed out of the
-        // element loop (which exhausts SGPRs); each block recomputes its round
-        // keys with scalar adds instead.
         uint32_t a = k0, c = k1;
-        asm volatile("" : "+s"(a), "+s"(c));
+        launder_key(a, c);
         return philox4x32_10((uint32_t)g, c1, n0, n1, a, c);
+    }
+    // The shared rounds of every block at element g (same words as block()).
+    __device__ __forceinline__ StreamAt at(uint64_t g) const {
+        uint32_t a = k0, c = k1;
+        launder_key(a, c);
+        const uint64_t P0 = (uint64_t)PHILOX_M0 * (uint32_t)g;                // round 0
+        const uint64_t P1 = (uint64_t)PHILOX_M1 * n0;
+        const uint32_t e2 = (uint32_t)(P0 >> 32) ^ (n1 ^ c);
+        const uint64_t Q1 = (uint64_t)PHILOX_M1 * e2;                         // round 1
+        const uint32_t c0b = (uint32_t)(Q1 >> 32) ^ ((uint32_t)P1 ^ (a + PHILOX_W0));
+        const uint64_t Q2 = (uint64_t)PHILOX_M0 * c0b;                        // round 2
+        return StreamAt{k0, k1, (uint32_t)(g >> 32) & 0xFFFFu, (uint32_t)(P1 >> 32) ^ a, (uint32_t)P0, c0b,
+                        (uint32_t)Q1, (uint32_t)(Q2 >> 32), (uint32_t)Q2};
     }
 };
 
@@ -99,10 +152,9 @@ struct FieldSmall {
     float pinv;
     __device__ __forceinline__ uint32_t reduce24(uint32_t x) const {   // x < 2^24
         const uint32_t q = (uint32_t)((float)x * pinv);
-        int32_t r = (int32_t)(x - __umul24(q, p));
-        r = r < 0 ? r + (int32_t)p : r;
-        r = r >= (int32_t)p ? r - (int32_t)p : r;
-        return (uint32_t)r;
+        uint32_t r = x - __umul24(q, p);   // in (-p, 2p), mod 2^32
+        r = min(r, r + p);                 // negative: the wrapped r + p is the small one
+        return min(r, r - p);              // >= p: r - p; else r - p wraps and r stays
     }
     __device__ __forceinline__ uint32_t mul(uint32_t a, uint32_t b) const { return reduce24(__umul24(a, b)); }
 };
@@ -118,7 +170,7 @@ struct FieldMersenne {
     __device__ __forceinline__ uint32_t mul(uint32_t a, uint32_t b) const {
         const uint64_t x = (uint64_t)a * b;
         const uint32_t s = ((uint32_t)x & p) + (uint32_t)(x >> K);
-        return s >= p ? s - p : s;
+        return min(s, s - p);             // s < p: s - p wraps above s
     }
 };
 
@@ -180,9 +232,21 @@ struct Field64 {
 // sum is >= 2^32 > p, so it also takes the subtraction (exact mod 2^32).
 template <typename F>
 __device__ __forceinline__ typename F::T addmod(typename F::T a, typename F::T b, const F& f) {
-    const typename F::T s = a + b;
+    using FT = typename F::T;
+    const FT s = a + b;
     if constexpr (F::kWrap) return (s < a || s >= f.p) ? s - f.p : s;
-    return s >= f.p ? s - f.p : s;
+    return min(s, (FT)(s - f.p));         // s < p: s - p wraps above s
+}
+
+// a, b < p: (a - b) mod p.  Without wrap (2p <= 2^bits) the wrapped
+// difference plus p is the answer exactly when a < b, and it is then the
+// smaller of the two: one subtraction, one addition and one min.
+template <typename F>
+__device__ __forceinline__ typename F::T submod(typename F::T a, typename F::T b, const F& f) {
+    using FT = typename F::T;
+    const FT d = a - b;
+    if constexpr (F::kWrap) return a < b ? d + f.p : d;
+    return min(d, (FT)(d + f.p));
 }
 
 // r_s in Z_p^* and z_s in Z_p by multiply-shift of uniform 32-bit words

@@ -64,27 +64,31 @@ __device__ __forceinline__ FT window(T a, uint32_t pos) {
 }
 
 // Steps 3-9 for one slot: the window position `pos` (sigma of the slot), the
-// slot's mask r and reshare z; returns both parties' messages and P2's test.
+// slot's mask r and reshare z; returns both parties' messages and P2's
+// reconstruction w0 + w1 mod p (the slot is zero when it is 0).
 // a0 and nb1 are P0's share and P1's negated share, both shifted down by k_lo.
+// Every select is written as masks and adds so that it stays on the
+// full-rate VOP2 forms (no compare / cndmask pairs).
 template <typename T, int N, typename F>
-__device__ __forceinline__ bool slot_messages(T a0, T nb1, uint32_t pos, typename F::T r, typename F::T z,
-                                              const F& f, typename F::T& w0, typename F::T& w1) {
+__device__ __forceinline__ typename F::T slot_messages(T a0, T nb1, uint32_t pos, typename F::T r, typename F::T z,
+                                                       const F& f, typename F::T& w0, typename F::T& w1) {
     using FT = typename F::T;
     constexpr int LX = N - 1;
     constexpr FT TWO_LX = (FT)1 << LX;                   // 2^l_x mod p = 2^l_x
     constexpr FT WIN = TWO_LX - 1;                       // Z_{2^l_x}
-    const bool last = pos == (uint32_t)LX;               // u_{l_x+1} := 0
     const FT W0 = window<T, N, FT>(a0, pos);             // bits [k_lo + pos, k_lo + pos + l_x]
     const FT W1 = window<T, N, FT>(nb1, pos);
-    const FT u0n = last ? (FT)0 : (W0 >> 1);             // u_{i+1}
-    const FT u1n = last ? (FT)0 : (W1 >> 1);
-    const FT v0 = (W0 + u0n - 1) & WIN;                  // step 4: u_i + u_{i+1} - 1
+    const FT more = (FT)(int64_t)((int32_t)(pos - (uint32_t)LX) >> 31);   // all ones unless pos = l_x
+    const FT u0n = (W0 >> 1) & more;                     // u_{i+1}, and u_{l_x+1} := 0
+    const FT u1n = (W1 >> 1) & more;
+    // step 4 and step 5 (Alg. 6) for P0: v0 = u_i + u_{i+1} - 1 in Z_{2^l_x},
+    // s0 = v0, or 2^l_x when v0 = 0, which is ((v0 - 1) mod 2^l_x) + 1.
+    const FT s0 = ((W0 + u0n - 2) & WIN) + 1;
     const FT v1 = ((FT)0 - W1 - u1n) & WIN;              // P1: -cut_i - cut_{i+1}
-    const FT s0 = v0 ? v0 : TWO_LX;                      // step 5: Alg. 6
     const FT s1 = v1 + (f.p - TWO_LX);
     w0 = addmod(f.mul(s0, r), z, f);                     // steps 7-8: mask, reshare
-    w1 = addmod(f.mul(s1, r), (FT)(f.p - z), f);
-    return addmod(w0, w1, f) == 0;                       // step 9 (P2)
+    w1 = submod(f.mul(s1, r), z, f);
+    return addmod(w0, w1, f);                            // step 9 (P2)
 }
 
 // Step 10-11 (DReLU): P2's fresh sharing (rho, D' - rho), then the unflip.
@@ -131,11 +135,12 @@ __device__ __forceinline__ void drelu_element(const T* __restrict__ X0, const T*
     const T in1 = (T)((T)0 - (T)(nr1 >> k_in)) & mask;                              // P1: -cut(-x1, k_in)
 
     // Steps 1 and 6 (randomness): t and the shuffle keys from seed_01.
+    const StreamAt r01 = s01.at(g);
     uint32_t key[N];
     uint32_t t = 0;
 #pragma unroll
     for (int b = 0; b < (N + 3) / 4; ++b) {
-        const Words4 w = s01.block(g, TAG_SHUFFLE, b);
+        const Words4 w = r01.block(TAG_SHUFFLE, b);
         if (b == 0) t = w.w0 & 1u;
         const uint32_t ws[4] = {w.w0, w.w1, w.w2, w.w3};
 #pragma unroll
@@ -150,29 +155,30 @@ __device__ __forceinline__ void drelu_element(const T* __restrict__ X0, const T*
     const T nb1 = (T)((T)0 - a1) & mask;                  // P1 cuts -[x]_1 mod 2^l
     const T a0k = a0 >> k_lo, nb1k = nb1 >> k_lo;         // common low cut of every window
 
-    bool zero = false;
+    FT least = f.p;                                        // P2: min over slots of w0 + w1 mod p
     Words4 wm = {0, 0, 0, 0};
 #pragma unroll
     for (int j = 0; j < N; ++j) {
         // Steps 7-8 randomness of slot j.
         FT r, z;
         if constexpr (WIDE) {
-            const Words4 w = s01.block(g, TAG_MASK, (uint32_t)j);
+            const Words4 w = r01.block(TAG_MASK, (uint32_t)j);
             r = 1 + __umul64hi(join64(w.w0, w.w1), f.p - 1);
             z = __umul64hi(join64(w.w2, w.w3), f.p);
         } else {
-            if ((j & 1) == 0) wm = s01.block(g, TAG_MASK, (uint32_t)(j >> 1));
+            if ((j & 1) == 0) wm = r01.block(TAG_MASK, (uint32_t)(j >> 1));
             r = draw_r((j & 1) ? wm.w2 : wm.w0, f.p);
             z = draw_z((j & 1) ? wm.w3 : wm.w1, f.p);
         }
         FT w0, w1;
-        zero |= slot_messages<T, N, F>(a0k, nb1k, key[j] & 63u, r, z, f, w0, w1);
+        const FT w = slot_messages<T, N, F>(a0k, nb1k, key[j] & 63u, r, z, f, w0, w1);
+        least = w < least ? w : least;
         if constexpr (CAP) {
             cap[e * N + j] = w0;
             cap[(ncap + e) * N + j] = w1;
         }
     }
-    const T dp = zero ? 1 : 0;
+    const T dp = least == 0 ? 1 : 0;                       // D' = [some slot is 0]
 
     T y0, y1;
     if constexpr (!RELU) {
@@ -181,8 +187,9 @@ __device__ __forceinline__ void drelu_element(const T* __restrict__ X0, const T*
     } else {
         // Alg. 8 preprocessing: [a]_0, [b]_0, [c]_0 from seed_02, [a]_1, [b]_1
         // from seed_12; P2 forms [c]_1 = (a0 + a1)(b0 + b1) - c0.
-        const Words4 w0 = s02.block(g, TAG_BEAVER, 0);
-        const Words4 w1 = s02.block(g, TAG_BEAVER, 1);
+        const StreamAt r02 = s02.at(g);
+        const Words4 w0 = r02.block(TAG_BEAVER, 0);
+        const Words4 w1 = r02.block(TAG_BEAVER, 1);
         const Words4 w2 = s12.block(g, TAG_BEAVER, 0);
         const T ba0 = (T)join64(w0.w0, w0.w1) & mask;
         const T bb0 = (T)join64(w0.w2, w0.w3) & mask;

@@ -60,11 +60,12 @@ __global__ BC_KERNEL_ATTRS void k_expand(ExpandKArgs A, F f) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
         const uint64_t g = A.elem_base + e;
+        const StreamAt r01 = A.s01.at(g);
         uint32_t key[N];
         uint32_t t = 0;
 #pragma unroll
         for (int b = 0; b < (N + 3) / 4; ++b) {
-            const Words4 w = A.s01.block(g, TAG_SHUFFLE, b);
+            const Words4 w = r01.block(TAG_SHUFFLE, b);
             if (b == 0) t = w.w0 & 1u;
             const uint32_t ws[4] = {w.w0, w.w1, w.w2, w.w3};
 #pragma unroll
@@ -84,12 +85,12 @@ __global__ BC_KERNEL_ATTRS void k_expand(ExpandKArgs A, F f) {
 #pragma unroll
         for (int j = 0; j < N; ++j) {
             if constexpr (RzLayout<N>::WIDE) {
-                const Words4 w = A.s01.block(g, TAG_MASK, (uint32_t)j);
+                const Words4 w = r01.block(TAG_MASK, (uint32_t)j);
                 uint64_t* rz = static_cast<uint64_t*>(A.rz);
                 rz[(uint64_t)(2 * j) * n + e] = 1 + __umul64hi(join64(w.w0, w.w1), f.p - 1);
                 rz[(uint64_t)(2 * j + 1) * n + e] = __umul64hi(join64(w.w2, w.w3), f.p);
             } else {
-                if ((j & 1) == 0) wm = A.s01.block(g, TAG_MASK, (uint32_t)(j >> 1));
+                if ((j & 1) == 0) wm = r01.block(TAG_MASK, (uint32_t)(j >> 1));
                 const uint32_t r = draw_r((j & 1) ? wm.w2 : wm.w0, (uint32_t)f.p);
                 const uint32_t z = draw_z((j & 1) ? wm.w3 : wm.w1, (uint32_t)f.p);
                 uint32_t* rz = static_cast<uint32_t*>(A.rz);
@@ -106,8 +107,9 @@ __global__ BC_KERNEL_ATTRS void k_expand(ExpandKArgs A, F f) {
             const Words4 w = A.s02.block(g, TAG_RESP, 0);
             tail[e] = (T)join64(w.w0, w.w1) & mask;
         } else {
-            const Words4 w0 = A.s02.block(g, TAG_BEAVER, 0);
-            const Words4 w1 = A.s02.block(g, TAG_BEAVER, 1);
+            const StreamAt r02 = A.s02.at(g);
+            const Words4 w0 = r02.block(TAG_BEAVER, 0);
+            const Words4 w1 = r02.block(TAG_BEAVER, 1);
             const Words4 w2 = A.s12.block(g, TAG_BEAVER, 0);
             const T ba0 = (T)join64(w0.w0, w0.w1) & mask;
             const T bb0 = (T)join64(w0.w2, w0.w3) & mask;
@@ -149,7 +151,7 @@ __global__ BC_KERNEL_ATTRS void k_drelu_pre(PreKArgs A, F f) {
         const T a1 = t ? (T)((T)0 - in1) & mask : in1;
         const T nb1 = (T)((T)0 - a1) & mask;
         const T a0k = a0 >> k_lo, nb1k = nb1 >> k_lo;
-        bool zero = false;
+        FT least = f.p;
 #pragma unroll
         for (int j = 0; j < N; ++j) {
             FT r, z;
@@ -168,13 +170,14 @@ __global__ BC_KERNEL_ATTRS void k_drelu_pre(PreKArgs A, F f) {
             }
             const uint32_t pos = (perm[j >> 2] >> (8 * (j & 3))) & 63u;
             FT w0, w1;
-            zero |= slot_messages<T, N, F>(a0k, nb1k, pos, r, z, f, w0, w1);
+            const FT w = slot_messages<T, N, F>(a0k, nb1k, pos, r, z, f, w0, w1);
+            least = w < least ? w : least;
             if constexpr (CAP) {
                 cap[e * N + j] = w0;
                 cap[(n + e) * N + j] = w1;
             }
         }
-        const T dp = zero ? 1 : 0;
+        const T dp = least == 0 ? 1 : 0;
         T y0, y1;
         if constexpr (!RELU) {
             drelu_finish<T>(dp, tail[e], t, mask, y0, y1);
