@@ -143,6 +143,15 @@ __device__ __forceinline__ uint64_t join64(uint32_t lo, uint32_t hi) {
 
 // ------------------------------------------------------------ Z_p arithmetic
 
+// a * b + c in one v_mad_u64_u32.  Written out because, with operands the
+// compiler knows to be narrow, it otherwise splits the product into 24-bit
+// multiplies and 64-bit shift-adds.
+__device__ __forceinline__ uint64_t mad_u64_u32(uint32_t a, uint32_t b, uint64_t c) {
+    uint64_t d, carry;
+    asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(d), "=s"(carry) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+
 // p < 2^12.  a, b < p, so a*b < 2^24 is exact in one v_mul_u32_u24 and in
 // fp32.  The fp32 quotient is within one of floor(x / p); two corrections.
 struct FieldSmall {
@@ -157,6 +166,10 @@ struct FieldSmall {
         return min(r, r - p);              // >= p: r - p; else r - p wraps and r stays
     }
     __device__ __forceinline__ uint32_t mul(uint32_t a, uint32_t b) const { return reduce24(__umul24(a, b)); }
+    // a, b, c < p: a*b + c <= p^2 - p < 2^24 as well.
+    __device__ __forceinline__ uint32_t mul_add(uint32_t a, uint32_t b, uint32_t c) const {
+        return reduce24(__umul24(a, b) + c);
+    }
 };
 
 // p < 2^24, p = 2^K - 1 (Mersenne).  a*b < 2^48 from one 64-bit multiply;
@@ -172,6 +185,13 @@ struct FieldMersenne {
         const uint32_t s = ((uint32_t)x & p) + (uint32_t)(x >> K);
         return min(s, s - p);             // s < p: s - p wraps above s
     }
+    // a, b, c < p: x = a*b + c <= p^2 - p, so x >> K <= p - 2 and the fold is
+    // still below 2p; the addend rides in the multiply.
+    __device__ __forceinline__ uint32_t mul_add(uint32_t a, uint32_t b, uint32_t c) const {
+        const uint64_t x = mad_u64_u32(a, b, c);
+        const uint32_t s = ((uint32_t)x & p) + (uint32_t)(x >> K);
+        return min(s, s - p);
+    }
 };
 
 // p < 2^24, any prime.  a*b < 2^48 is exact in fp64; an fp64 quotient is
@@ -182,7 +202,13 @@ struct Field24 {
     uint32_t p;
     double pd, pinv;
     __device__ __forceinline__ uint32_t mul(uint32_t a, uint32_t b) const {
-        const double xd = (double)a * (double)b;
+        return reduce((double)a * (double)b);
+    }
+    // a, b, c < p: a*b + c < 2^48 is exact in one fp64 fma.
+    __device__ __forceinline__ uint32_t mul_add(uint32_t a, uint32_t b, uint32_t c) const {
+        return reduce(__builtin_fma((double)a, (double)b, (double)c));
+    }
+    __device__ __forceinline__ uint32_t reduce(double xd) const {   // integer xd < 2^48
         const double q = __builtin_floor(xd * pinv);
         double r = __builtin_fma(-q, pd, xd);
         r = r < 0.0 ? r + pd : r;
@@ -199,7 +225,13 @@ struct Field32 {
     uint32_t p;
     uint64_t mu;
     __device__ __forceinline__ uint32_t mul(uint32_t a, uint32_t b) const {
-        const uint64_t x = (uint64_t)a * b;
+        return reduce((uint64_t)a * b);
+    }
+    // a, b, c < p < 2^32: a*b + c < 2^64, and the Barrett bound holds for any x < 2^64.
+    __device__ __forceinline__ uint32_t mul_add(uint32_t a, uint32_t b, uint32_t c) const {
+        return reduce((uint64_t)a * b + c);
+    }
+    __device__ __forceinline__ uint32_t reduce(uint64_t x) const {
         const uint64_t q = __umul64hi(x, mu);
         uint64_t r = x - q * p;
         r = r >= p ? r - p : r;
@@ -225,6 +257,11 @@ struct Field64 {
         r = r < 0 ? r + (int64_t)p : r;
         r = r >= (int64_t)p ? r - (int64_t)p : r;
         return (uint64_t)r;
+    }
+    __device__ __forceinline__ uint64_t mul_add(uint64_t a, uint64_t b, uint64_t c) const {
+        const uint64_t m = mul(a, b);
+        const uint64_t s = m + c;          // < 2p < 2^35
+        return s >= p ? s - p : s;
     }
 };
 

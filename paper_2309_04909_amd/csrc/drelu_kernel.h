@@ -52,12 +52,15 @@ struct BatchKArgs {
 };
 
 // Bits [pos, pos + l_x] of a share already shifted down by k_lo (pos <= l_x).
-// With 64-bit shares and windows of at most 32 bits one v_alignbit_b32 of
-// the two halves does the variable shift.
+// With 64-bit shares: when bits [0, 2 l_x] fit in 32 bits a 32-bit shift of
+// the low word, else (windows of at most 32 bits) one v_alignbit_b32 of the
+// two halves does the variable shift.
 template <typename T, int N, typename FT>
 __device__ __forceinline__ FT window(T a, uint32_t pos) {
     constexpr FT WIN1 = (FT)((2ull << (N - 1)) - 1);     // l_x + 1 bits
-    if constexpr (sizeof(T) == 8 && N <= 32)
+    if constexpr (sizeof(T) == 8 && 2 * N - 1 <= 32)     // bits [0, 2 l_x] fit in the low word
+        return (FT)((uint32_t)a >> pos) & WIN1;
+    else if constexpr (sizeof(T) == 8 && N <= 32)
         return (FT)__builtin_amdgcn_alignbit((uint32_t)(a >> 32), (uint32_t)a, pos) & WIN1;
     else
         return (FT)(a >> pos) & WIN1;
@@ -86,8 +89,8 @@ __device__ __forceinline__ typename F::T slot_messages(T a0, T nb1, uint32_t pos
     const FT s0 = ((W0 + u0n - 2) & WIN) + 1;
     const FT v1 = ((FT)0 - W1 - u1n) & WIN;              // P1: -cut_i - cut_{i+1}
     const FT s1 = v1 + (f.p - TWO_LX);
-    w0 = addmod(f.mul(s0, r), z, f);                     // steps 7-8: mask, reshare
-    w1 = submod(f.mul(s1, r), z, f);
+    w0 = f.mul_add(s0, r, z);                            // steps 7-8: mask, reshare
+    w1 = f.mul_add(s1, r, (FT)(f.p - z));                // P1: s1 r - z
     return addmod(w0, w1, f);                            // step 9 (P2)
 }
 
