@@ -413,6 +413,10 @@ def run_copy(torch, steps, warmup, mib=512):
             "hbm_frac": round(2 * n * 8 / ms / 1e6 / HBM_PEAK_GBS, 4)}
 
 
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -436,7 +440,9 @@ def main():
 
     out = {}
     if "cpu" in sections:
+        t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(inputs, min(args.cpu_sample, c["n"]), max(1, args.cpu_workers))
+        progress(f"cpu baseline done in {time.perf_counter() - t0:.1f} s")
 
     import torch
     from paper_2309_04909_amd import bicop as B
@@ -468,18 +474,18 @@ def main():
                     "drelu_gelem_s": round(c["n"] / kern["drelu"] / 1e6, 3),
                     "trunc_det_gbs": round(td_gbs, 1), "trunc_det_hbm_frac": round(td_gbs / HBM_PEAK_GBS, 4)},
     }
-    if "batched" in sections:
-        line["batched_vs_plain"] = run_batched_vs_plain(torch, B, max(3, args.steps // 5), 2)
-    if "plain" in sections:
-        line["plain_drelu"] = run_plain_drelu(torch, B, args.steps, args.warmup)
-    if "serving" in sections:
-        line["serving"] = run_serving(torch, B)
-    if "matmul" in sections:
-        line["matmul_relu"] = run_matmul_relu(torch, B, args.steps, args.warmup)
-    if "sweep" in sections:
-        line["batch_sweep"] = run_sweep(torch, B, args.steps, args.warmup)
-    if "copy" in sections:
-        line["copy_reference"] = run_copy(torch, args.steps, args.warmup)
+    progress(f"headline: {value:.3f} Gelem/s, {ms_step:.4f} ms per step")
+    runs = [("batched", "batched_vs_plain", lambda: run_batched_vs_plain(torch, B, max(3, args.steps // 5), 2)),
+            ("plain", "plain_drelu", lambda: run_plain_drelu(torch, B, args.steps, args.warmup)),
+            ("serving", "serving", lambda: run_serving(torch, B)),
+            ("matmul", "matmul_relu", lambda: run_matmul_relu(torch, B, args.steps, args.warmup)),
+            ("sweep", "batch_sweep", lambda: run_sweep(torch, B, args.steps, args.warmup)),
+            ("copy", "copy_reference", lambda: run_copy(torch, args.steps, args.warmup))]
+    for sec, key, fn in runs:
+        if sec in sections:
+            t0 = time.perf_counter()
+            line[key] = fn()
+            progress(f"section {sec} done in {time.perf_counter() - t0:.1f} s")
     line.update(out)
     print(json.dumps(line), flush=True)
 

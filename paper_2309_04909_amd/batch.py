@@ -32,6 +32,8 @@ class RaggedBatch:
         self.params = params
         self.seeds = seeds
         self.segments = list(segments)
+        if tile_elems == 0:                          # autotuned tile size, else the library default
+            tile_elems = int(B.SCHEDULES.get("batch_tile", 0))
         self.grid = grid
         width = B.ring_width(params.ell)
         nseg = len(self.segments)

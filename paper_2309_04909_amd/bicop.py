@@ -127,8 +127,6 @@ def load_schedules(path=SCHEDULES_PATH):
     return table
 
 
-SCHEDULES = load_schedules()
-
 
 def _check(rc, where):
     if rc != 0:
@@ -363,3 +361,7 @@ def drelu_pre(x0, x1, params: Params, rand, capture=False, out=None, stream=None
 def relu_pre(x0, x1, params: Params, rand, capture=False, out=None, stream=None):
     """Online Alg. 8 from a record made by rand_expand(BC_OP_RELU, ...)."""
     return _pre_like(lib.bc_relu_pre, "relu_pre", x0, x1, params, rand, capture, out, stream)
+
+
+# The autotuned schedule table, applied once the whole binding is defined.
+SCHEDULES = load_schedules()

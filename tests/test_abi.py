@@ -148,3 +148,26 @@ def test_batch_plan_validation_on_host():
     junk = (ctypes.c_uint8 * nbytes)()
     sd = B.Seeds(1, 2, 3).c()
     assert L.bc_batch_run(ctypes.addressof(junk), junk, ctypes.byref(sd), 0, None) == -8
+
+
+def test_schedule_table_round_trip(tmp_path):
+    """An autotuned schedules.json is applied by load_schedules (host-side table only)."""
+    import json
+    from paper_2309_04909_amd import bicop as B
+    before = {(k, n): B.get_schedule(k, n) for k, n in (("fused", 19), ("stream", 0), ("batch", 8))}
+    table = {"grid": [{"kind": "fused", "npos": 19, "blocks_per_cu": 7},
+                      {"kind": "stream", "npos": 0, "blocks_per_cu": 3},
+                      {"kind": "batch", "npos": 8, "blocks_per_cu": 5}], "batch_tile": 2048}
+    path = tmp_path / "schedules.json"
+    path.write_text(json.dumps(table))
+    try:
+        got = B.load_schedules(str(path))
+        assert got["batch_tile"] == 2048
+        assert B.get_schedule("fused", 19) == 7
+        assert B.get_schedule("stream", 0) == 3
+        assert B.get_schedule("batch", 8) == 5
+        with pytest.raises(B.BicopError):
+            B.set_schedule("fused", 19, 2000)          # above the 1024 limit
+    finally:
+        for (k, n), v in before.items():
+            B.set_schedule(k, n, v)
