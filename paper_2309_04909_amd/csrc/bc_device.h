@@ -143,6 +143,23 @@ __device__ __forceinline__ uint64_t join64(uint32_t lo, uint32_t hi) {
 
 // ------------------------------------------------------------ Z_p arithmetic
 
+// A uniform value copied into a VGPR.  On gfx950 the VOP2 forms issue at about
+// twice the rate with VGPR or literal operands as with an SGPR operand, so
+// the runtime prime of the smaller fields is kept in VGPRs by the kernels.
+__device__ __forceinline__ uint32_t in_vgpr(uint32_t x) {
+    uint32_t v;
+    asm("v_mov_b32 %0, %1" : "=v"(v) : "s"(x));
+    return v;
+}
+__device__ __forceinline__ uint64_t in_vgpr(uint64_t x) {
+    return (uint64_t)in_vgpr((uint32_t)x) | ((uint64_t)in_vgpr((uint32_t)(x >> 32)) << 32);
+}
+__device__ __forceinline__ float in_vgpr(float x) {
+    float v;
+    asm("v_mov_b32 %0, %1" : "=v"(v) : "s"(x));
+    return v;
+}
+
 // a * b + c in one v_mad_u64_u32.  Written out because, with operands the
 // compiler knows to be narrow, it otherwise splits the product into 24-bit
 // multiplies and 64-bit shift-adds.
@@ -165,6 +182,7 @@ struct FieldSmall {
         r = min(r, r + p);                 // negative: the wrapped r + p is the small one
         return min(r, r - p);              // >= p: r - p; else r - p wraps and r stays
     }
+    __device__ __forceinline__ FieldSmall vgpr() const { return FieldSmall{in_vgpr(p), in_vgpr(pinv)}; }
     __device__ __forceinline__ uint32_t mul(uint32_t a, uint32_t b) const { return reduce24(__umul24(a, b)); }
     // a, b, c < p: a*b + c <= p^2 - p < 2^24 as well.
     __device__ __forceinline__ uint32_t mul_add(uint32_t a, uint32_t b, uint32_t c) const {
@@ -179,7 +197,11 @@ template <int K>
 struct FieldMersenne {
     using T = uint32_t;
     static constexpr bool kWrap = false;
-    uint32_t p;   // 2^K - 1
+    // A compile-time p becomes a literal operand: on gfx950 the VOP2 forms
+    // issue at about twice the rate with literal or VGPR operands as with an
+    // SGPR operand.
+    static constexpr uint32_t p = (1u << K) - 1;
+    __device__ __forceinline__ FieldMersenne vgpr() const { return *this; }
     __device__ __forceinline__ uint32_t mul(uint32_t a, uint32_t b) const {
         const uint64_t x = (uint64_t)a * b;
         const uint32_t s = ((uint32_t)x & p) + (uint32_t)(x >> K);
@@ -201,6 +223,7 @@ struct Field24 {
     static constexpr bool kWrap = false;
     uint32_t p;
     double pd, pinv;
+    __device__ __forceinline__ Field24 vgpr() const { return Field24{in_vgpr(p), pd, pinv}; }
     __device__ __forceinline__ uint32_t mul(uint32_t a, uint32_t b) const {
         return reduce((double)a * (double)b);
     }
@@ -224,6 +247,7 @@ struct Field32 {
     static constexpr bool kWrap = true;   // p may exceed 2^31: a + b can wrap
     uint32_t p;
     uint64_t mu;
+    __device__ __forceinline__ Field32 vgpr() const { return Field32{in_vgpr(p), mu}; }
     __device__ __forceinline__ uint32_t mul(uint32_t a, uint32_t b) const {
         return reduce((uint64_t)a * b);
     }
@@ -247,6 +271,7 @@ struct Field64 {
     static constexpr bool kWrap = false;
     uint64_t p;
     double pd, pinv;
+    __device__ __forceinline__ Field64 vgpr() const { return *this; }
     __device__ __forceinline__ uint64_t mul(uint64_t a, uint64_t b) const {
         const uint64_t lo = a * b;
         const uint64_t hi = __umul64hi(a, b);

@@ -208,13 +208,14 @@ __device__ __forceinline__ void drelu_element(const T* __restrict__ X0, const T*
 
 // One call: grid-stride over the n elements of one share pair.
 template <typename T, int N, typename F, bool RELU, bool CAP>
-__global__ BC_KERNEL_ATTRS void k_drelu(DreluKArgs A, F f) {
+__global__ BC_KERNEL_ATTRS void k_drelu(DreluKArgs A, F f_arg) {
+    const F f = f_arg.vgpr();
     const T* X0 = static_cast<const T*>(A.x0);
     const T* X1 = static_cast<const T*>(A.x1);
     T* Y0 = static_cast<T*>(A.y0);
     T* Y1 = static_cast<T*>(A.y1);
     typename F::T* cap = static_cast<typename F::T*>(A.cap);
-    const T mask = (T)A.ring_mask;
+    const T mask = in_vgpr((T)A.ring_mask);
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < A.n; e += stride)
         drelu_element<T, N, F, RELU, CAP>(X0, X1, Y0, Y1, cap, A.n, e, A.elem_base + e, mask, (T)A.in_mask, A.k_in,
@@ -230,11 +231,12 @@ __global__ BC_KERNEL_ATTRS void k_drelu(DreluKArgs A, F f) {
 template <typename T, int N, typename F>
 __global__ BC_KERNEL_ATTRS void k_batch(const BatchPlanHeader* __restrict__ hdr,
                                                const bc_segment* __restrict__ segs,
-                                               const uint64_t* __restrict__ tile_begin, BatchKArgs A, F f) {
+                                               const uint64_t* __restrict__ tile_begin, BatchKArgs A, F f_arg) {
+    const F f = f_arg.vgpr();
     const uint32_t nseg = A.nseg;
     const uint64_t total = A.total_tiles;
     const uint64_t tile = A.tile_elems;
-    const T mask = (T)A.ring_mask;
+    const T mask = in_vgpr((T)A.ring_mask);
     for (uint64_t t = blockIdx.x; t < total; t += gridDim.x) {
         // segment of tile t: largest s with tile_begin[s] <= t (uniform search)
         uint32_t lo = 0, hi = nseg;
@@ -310,7 +312,7 @@ hipError_t launch_exact(const DreluLaunch& L, hipStream_t st) {
     } else if constexpr (N <= 24) {
         if constexpr (mersenne_exponent(N)) {
             if (L.p == (1ull << N) - 1)
-                return launch_field<T, N, FieldMersenne<N>, RELU>(L, FieldMersenne<N>{(uint32_t)L.p}, st);
+                return launch_field<T, N, FieldMersenne<N>, RELU>(L, FieldMersenne<N>{}, st);
         }
         return launch_field<T, N, Field24, RELU>(L, make_field24(L.p), st);
     } else if constexpr (N <= 32) {
@@ -345,7 +347,7 @@ hipError_t launch_batch_exact(const BatchLaunch& L, hipStream_t st) {
     } else if constexpr (N <= 24) {
         if constexpr (mersenne_exponent(N)) {
             if (L.p == (1ull << N) - 1)
-                return launch_batch_field<T, N, FieldMersenne<N>>(L, FieldMersenne<N>{(uint32_t)L.p}, st);
+                return launch_batch_field<T, N, FieldMersenne<N>>(L, FieldMersenne<N>{}, st);
         }
         return launch_batch_field<T, N, Field24>(L, make_field24(L.p), st);
     } else if constexpr (N <= 32) {

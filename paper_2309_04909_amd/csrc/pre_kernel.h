@@ -128,7 +128,8 @@ __global__ BC_KERNEL_ATTRS void k_expand(ExpandKArgs A, F f) {
 
 // Online: Alg. 7 steps 2-5, 7-9 and the finish, reading the record.
 template <typename T, int N, typename F, bool RELU, bool CAP>
-__global__ BC_KERNEL_ATTRS void k_drelu_pre(PreKArgs A, F f) {
+__global__ BC_KERNEL_ATTRS void k_drelu_pre(PreKArgs A, F f_arg) {
+    const F f = f_arg.vgpr();
     using FT = typename F::T;
     const T* __restrict__ X0 = static_cast<const T*>(A.x0);
     const T* __restrict__ X1 = static_cast<const T*>(A.x1);
@@ -136,7 +137,7 @@ __global__ BC_KERNEL_ATTRS void k_drelu_pre(PreKArgs A, F f) {
     T* Y1 = static_cast<T*>(A.y1);
     FT* cap = static_cast<FT*>(A.cap);
     const T* __restrict__ tail = static_cast<const T*>(A.tail);
-    const T mask = (T)A.ring_mask;
+    const T mask = in_vgpr((T)A.ring_mask);
     const uint64_t n = A.n;
     const uint32_t k_lo = A.k_lo;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -242,7 +243,7 @@ hipError_t launch_pre_exact(const PreLaunch& L, hipStream_t st) {
     } else if constexpr (N <= 24) {
         if constexpr (mersenne_exponent(N)) {
             if (L.p == (1ull << N) - 1)
-                return launch_pre_field<T, N, FieldMersenne<N>>(L, FieldMersenne<N>{(uint32_t)L.p}, st);
+                return launch_pre_field<T, N, FieldMersenne<N>>(L, FieldMersenne<N>{}, st);
         }
         return launch_pre_field<T, N, Field24>(L, make_field24(L.p), st);
     } else if constexpr (N <= 32) {
