@@ -108,6 +108,22 @@ uint64_t bc_default_prime(uint32_t lx);
  * compute calls would return.  Host only. */
 int bc_check_params(const bc_drelu_params* prm, bc_drelu_params* resolved);
 
+/* Key-bit window of Sec. 6.1 (Tab. 5's "integer + fractional" notation)
+ * for fixed-point values with f fractional bits: the DReLU keeps int_bits
+ * integer bits (counting any guard bit) and frac_bits fractional bits, so
+ * it drops the low k_lo = f - frac_bits bits and tests l_x = int_bits +
+ * frac_bits bits above them.  Fills *out with (ell, l_x, k_lo, default p)
+ * and validates it like bc_check_params; frac_bits > f is BC_ERR_WINDOW.
+ * Host only. */
+int bc_keybit_params(uint32_t ell, uint32_t f, uint32_t int_bits, uint32_t frac_bits, bc_drelu_params* out);
+
+/* Integer bits of the key-bit window, guard bit included, for values with
+ * |x| < bound at f fractional bits: the smallest i >= 1 with
+ * bound <= 2^(f + i - 1), so that |x| < 2^(k_lo + l_x - 1) holds for any
+ * frac_bits (the guard-bit domain on which the sign is exact outside
+ * |x| < 2^k_lo).  Host only. */
+uint32_t bc_keybit_int_bits(uint64_t bound, uint32_t f);
+
 /* Message accounting for one call of `op` (BC_OP_DRELU / BC_OP_RELU) on n
  * elements.  Round 1: each of P0, P1 sends l_x + 1 values of Z_p, i.e.
  * (l_x+1)^2 bits per element (Tab. 1, Sec. 5.4 step 8).  DReLU round 2: one

@@ -60,6 +60,8 @@ _SIGS = {
     "bc_default_prime": ([_U32], _U64),
     "bc_check_params": ([ctypes.POINTER(_Params), ctypes.POINTER(_Params)], ctypes.c_int),
     "bc_msg_account": ([_U32, ctypes.POINTER(_Params), _U64, ctypes.POINTER(_Acct)], ctypes.c_int),
+    "bc_keybit_params": ([_U32, _U32, _U32, _U32, ctypes.POINTER(_Params)], ctypes.c_int),
+    "bc_keybit_int_bits": ([_U64, _U32], _U32),
     "bc_prg_blocks": ([_P, _U64, _U32, _U64, _U64, _U32, _U64, _P], ctypes.c_int),
     "bc_trunc_det": ([_P, _P, _P, _P, _U64, _U32, _U32, _U32, _P], ctypes.c_int),
     "bc_trunc_prob": ([_P, _P, _P, _P, _U64, _U32, _U32, _P], ctypes.c_int),
@@ -183,6 +185,18 @@ def msg_account(op, params: Params, n):
     _check(lib.bc_msg_account(op, ctypes.byref(params.c()), n, ctypes.byref(a)), "msg_account")
     return {"bits": dict(zip(LINKS, list(a.bits))), "stored_bytes": dict(zip(LINKS, list(a.stored_bytes))),
             "rounds": a.rounds}
+
+
+def keybit_params(ell, f, int_bits, frac_bits) -> "Params":
+    """Key-bit window (Sec. 6.1): k_lo = f - frac_bits, l_x = int_bits + frac_bits, default p."""
+    out = _Params()
+    _check(lib.bc_keybit_params(ell, f, int_bits, frac_bits, ctypes.byref(out)), "keybit_params")
+    return Params(out.ell, out.lx, out.k_lo, out.p)
+
+
+def keybit_int_bits(bound, f) -> int:
+    """Integer bits (guard bit included) of the key-bit window for |x| < bound at f fractional bits."""
+    return int(lib.bc_keybit_int_bits(bound, f))
 
 
 # ------------------------------------------------------------------- helpers

@@ -399,6 +399,25 @@ uint32_t bc_get_schedule(uint32_t kind, uint32_t npos) {
 
 int bc_check_params(const bc_drelu_params* prm, bc_drelu_params* resolved) { return check_params(prm, resolved); }
 
+int bc_keybit_params(uint32_t ell, uint32_t f, uint32_t int_bits, uint32_t frac_bits, bc_drelu_params* out) {
+    if (!out) return fail(BC_ERR_NULL, "out is NULL");
+    if (frac_bits > f) return fail(BC_ERR_WINDOW, "frac_bits = %u exceeds f = %u", frac_bits, f);
+    if (int_bits > 64 || frac_bits > 64) return fail(BC_ERR_WINDOW, "window bits above 64");
+    bc_drelu_params q{};
+    q.ell = ell;
+    q.lx = int_bits + frac_bits;
+    q.k_lo = f - frac_bits;
+    return check_params(&q, out);
+}
+
+uint32_t bc_keybit_int_bits(uint64_t bound, uint32_t f) {
+    uint32_t c = 0;                                   // ceil(log2(bound)): smallest c with bound <= 2^c
+    while (c < 64 && (bound > (1ull << c))) ++c;
+    if (bound > (1ull << 63)) c = 64;
+    const int64_t i = (int64_t)c - (int64_t)f + 1;
+    return i < 1 ? 1u : (uint32_t)i;
+}
+
 int bc_msg_account(uint32_t op, const bc_drelu_params* prm, uint64_t n, bc_msg_acct* acct) {
     if (!acct) return fail(BC_ERR_NULL, "acct is NULL");
     if (op != BC_OP_DRELU && op != BC_OP_RELU) return fail(BC_ERR_ARG, "unknown op %u", op);

@@ -171,3 +171,49 @@ def test_schedule_table_round_trip(tmp_path):
     finally:
         for (k, n), v in before.items():
             B.set_schedule(k, n, v)
+
+
+@pytest.mark.parametrize("ell,f", [(64, 13), (64, 16), (32, 8), (51, 13)])
+def test_keybit_params_match_oracle(ell, f):
+    """bc_keybit_params is the oracle's key-bit window (Sec. 6.1) plus its validation and default prime."""
+    from paper_2309_04909_amd import bicop as B
+    for ib in range(0, 34):
+        for fb in range(0, min(f, 4) + 1):
+            k_lo, lx = OP.keybit_window(f, ib, fb)
+            try:
+                OP.check_drelu(ell, lx, k_lo, OP.default_prime(lx) if 1 <= lx <= 32 else 0)
+                ok = True
+            except ValueError:
+                ok = False
+            if ok:
+                got = B.keybit_params(ell, f, ib, fb)
+                assert (got.ell, got.lx, got.k_lo, got.p) == (ell, lx, k_lo, OP.default_prime(lx))
+            else:
+                with pytest.raises(B.BicopError):
+                    B.keybit_params(ell, f, ib, fb)
+    with pytest.raises(B.BicopError):
+        B.keybit_params(ell, f, 5, f + 1)                # more fractional bits than f
+
+
+def test_keybit_settings_of_the_workloads():
+    """Tab. 5's "5 + 2" at f = 13 and the 2^30-bounded key-bit setting."""
+    from paper_2309_04909_amd import bicop as B
+    r = B.keybit_params(64, 13, 5, 2)
+    assert (r.k_lo, r.lx, r.p) == (11, 7, 251)
+    ib = B.keybit_int_bits(1 << 30, 13)
+    assert ib == 18
+    r = B.keybit_params(64, 13, ib, 0)
+    assert (r.k_lo, r.lx, r.p) == (13, 18, (1 << 19) - 1)
+
+
+@pytest.mark.parametrize("f", [0, 8, 13])
+def test_keybit_int_bits_is_the_smallest_guarded_window(f):
+    from paper_2309_04909_amd import bicop as B
+    for bound in [1, 2, 3, 255, 256, 257, 1 << 20, (1 << 30) - 1, 1 << 30, (1 << 30) + 1, (1 << 62) + 5]:
+        i = B.keybit_int_bits(bound, f)
+        assert i >= 1
+        for fb in range(0, f + 1):
+            k_lo, lx = OP.keybit_window(f, i, fb)
+            assert OP.guard_bound(k_lo, lx) >= bound                 # |x| < bound is inside the guard domain
+            if i > 1:
+                assert OP.guard_bound(*OP.keybit_window(f, i - 1, fb)) < bound   # and one bit fewer is not
