@@ -134,9 +134,32 @@ def cpu_baseline(inputs, sample: int, workers: int):
     with ctx.Pool(workers) as pool:
         done = sum(pool.map(_oracle_chunk, jobs))
     dt = time.perf_counter() - t0
+    # the same oracle in this one process on the first chunks (about 2^20 elements)
+    single = []
+    for j in jobs:
+        single.append(j)
+        if sum(len(c[4]) for c in single) >= (1 << 20):
+            break
+    t1 = time.perf_counter()
+    done1 = sum(_oracle_chunk(j) for j in single)
+    dt1 = time.perf_counter() - t1
     return {"value": done / dt / 1e9, "unit": "Gelem/s", "cores": workers, "kind": "oracle",
             "sample": f"first {done} elements of the step (13-bit trunc_det of z and key-bit DReLU of x), "
-                      f"{workers} processes, {dt:.1f} s wall"}
+                      f"{workers} processes, {dt:.1f} s wall",
+            "single_process": {"value": done1 / dt1 / 1e9, "unit": "Gelem/s", "elements": done1,
+                               "seconds": round(dt1, 2)},
+            "cpu_model": _cpu_model(), "os_cpu_count": os.cpu_count()}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 # ------------------------------------------------------------------- GPU parts
@@ -392,6 +415,53 @@ def run_sweep(torch, B, steps, warmup):
     return out
 
 
+def _event_ms(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def run_precomputed(torch, B, inputs, steps, warmup):
+    """Precomputed-randomness mode, labelled separately: the offline expansion of the
+    seeds into the resident record (bc_rand_expand), the online call that streams
+    shares plus record (bc_drelu_pre / bc_relu_pre), and the fused call beside them,
+    on the key-bit inputs (2^24 elements, l = 64)."""
+    x0, x1 = to_dev(torch, inputs[0]), to_dev(torch, inputs[1])
+    n = x0.numel()
+    out = {"workload": f"{n} key-bit inputs, l=64; offline = seed expansion into the record, online = "
+                       "shares + record streamed, fused = in-kernel PRG"}
+    sd = B.Seeds(*SEEDS, 21)
+    for name, op, prm in (("drelu_lx18", B.BC_OP_DRELU, B.Params(64, 18, 13)),
+                          ("relu_lx7", B.BC_OP_RELU, B.Params(64, 7, 11))):
+        online = B.drelu_pre if op == B.BC_OP_DRELU else B.relu_pre
+        fused = B.drelu if op == B.BC_OP_DRELU else B.relu
+        rand = B.rand_expand(op, prm, sd, n)
+        y0, y1 = torch.empty_like(x0), torch.empty_like(x1)
+        f0, f1 = torch.empty_like(x0), torch.empty_like(x1)
+        ms_off = _event_ms(torch, lambda: B.rand_expand(op, prm, sd, n, out=rand), steps, warmup)
+        ms_on = _event_ms(torch, lambda: online(x0, x1, prm, rand, out=(y0, y1)), steps, warmup)
+        ms_fu = _event_ms(torch, lambda: fused(x0, x1, prm, sd, out=(f0, f1)), steps, warmup)
+        same = bool(torch.equal(y0, f0) and torch.equal(y1, f1))
+        rb = B.rand_bytes(op, prm, n)
+        byt = 32 * n + rb
+        out[name] = {"record_bytes_per_elem": round(rb / n, 1), "offline_ms": round(ms_off, 4),
+                     "online_ms": round(ms_on, 4), "fused_ms": round(ms_fu, 4),
+                     "online_gelem_s": round(n / ms_on / 1e6, 3), "fused_gelem_s": round(n / ms_fu / 1e6, 3),
+                     "online_gbs": round(byt / ms_on / 1e6, 1),
+                     "online_hbm_frac": round(byt / ms_on / 1e6 / HBM_PEAK_GBS, 4),
+                     "identical_to_fused": same}
+        del rand
+    return out
+
+
 def run_copy(torch, steps, warmup, mib=512):
     """A plain device-to-device copy of known size: the reference for achievable
     HBM bandwidth and for scaling rocprofv3's FETCH_SIZE / WRITE_SIZE counters."""
@@ -422,9 +492,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--sections", default="cpu,batched,plain,serving,copy,matmul,sweep",
-                    help="comma list of extra sections: cpu, batched, plain, serving, copy, matmul, sweep")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 22)
+    ap.add_argument("--sections", default="cpu,batched,precomputed,plain,serving,copy,matmul,sweep",
+                    help="comma list of extra sections: cpu, batched, precomputed, plain, serving, copy, matmul, "
+                         "sweep")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 24)
     ap.add_argument("--cpu-workers", type=int, default=min(16, os.cpu_count() or 1))
     args = ap.parse_args()
 
@@ -476,6 +547,7 @@ def main():
     }
     progress(f"headline: {value:.3f} Gelem/s, {ms_step:.4f} ms per step")
     runs = [("batched", "batched_vs_plain", lambda: run_batched_vs_plain(torch, B, max(3, args.steps // 5), 2)),
+            ("precomputed", "precomputed_randomness", lambda: run_precomputed(torch, B, inputs, 10, 2)),
             ("plain", "plain_drelu", lambda: run_plain_drelu(torch, B, args.steps, args.warmup)),
             ("serving", "serving", lambda: run_serving(torch, B)),
             ("matmul", "matmul_relu", lambda: run_matmul_relu(torch, B, args.steps, args.warmup)),
