@@ -148,6 +148,9 @@ int bc_prg_blocks(uint32_t* out, uint64_t n, uint32_t nblocks, uint64_t seed,
 #define BC_SCHED_PRE     2u   /* bc_drelu_pre, bc_relu_pre               */
 #define BC_SCHED_EXPAND  3u   /* bc_rand_expand                          */
 #define BC_SCHED_BATCH   4u   /* bc_batch_run with grid = 0              */
+#define BC_SCHED_GROUP   5u   /* bc_drelu, bc_relu on small n: the value is
+                                 the largest number of lanes per element
+                                 (1 = off, 4, 8; default 8)                */
 
 /* Process-wide launch schedule: the grid of `kind` for window count npos
  * (0..33; the streaming kernels use npos = 0) is capped at blocks_per_cu

@@ -58,7 +58,7 @@ class RaggedBatch:
     def run(self, stream=None):
         """Enqueue the one persistent launch on `stream` (default: current)."""
         B._check(B.lib.bc_batch_run(self.dev_plan.data_ptr(), ctypes.addressof(self.host_plan),
-                                    ctypes.byref(self._c_seeds), self.grid, B._stream(stream)), "batch_run")
+                                    ctypes.byref(self._c_seeds), self.grid, B._stream(stream, self.dev_plan)), "batch_run")
 
     def capture(self):
         """Capture run() into a CUDA/HIP graph; returns the torch.cuda.CUDAGraph."""

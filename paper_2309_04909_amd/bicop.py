@@ -105,7 +105,7 @@ def _load():
 
 lib = _load()
 
-SCHED_KINDS = {"fused": 0, "stream": 1, "pre": 2, "expand": 3, "batch": 4}
+SCHED_KINDS = {"fused": 0, "stream": 1, "pre": 2, "expand": 3, "batch": 4, "group": 5}
 SCHEDULES_PATH = os.path.join(_HERE, "schedules.json")
 
 
@@ -148,7 +148,11 @@ class Params:
     p: int = 0
 
     def c(self):
-        return _Params(self.ell, self.lx, self.k_lo, 0, self.p)
+        # the ctypes struct is built once per (immutable) setting
+        s = self.__dict__.get("_c")
+        if s is None:
+            s = self.__dict__["_c"] = _Params(self.ell, self.lx, self.k_lo, 0, self.p)
+        return s
 
     @property
     def npos(self):
@@ -168,8 +172,11 @@ class Seeds:
     nonce: int = 0
 
     def c(self):
-        m = (1 << 64) - 1
-        return _Seeds(self.seed01 & m, self.seed02 & m, self.seed12 & m, self.nonce & m)
+        s = self.__dict__.get("_c")
+        if s is None:
+            m = (1 << 64) - 1
+            s = self.__dict__["_c"] = _Seeds(self.seed01 & m, self.seed02 & m, self.seed12 & m, self.nonce & m)
+        return s
 
 
 def version():
@@ -214,10 +221,18 @@ def field_dtype(p):
     return torch.uint32 if p < (1 << 32) else torch.uint64
 
 
-def _stream(stream):
-    if stream is None:
-        stream = torch.cuda.current_stream()
-    return ctypes.c_void_p(stream.cuda_stream)
+_raw_stream = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+
+
+def _stream(stream, like=None):
+    """The HIP stream handle to enqueue on: `stream`, else torch's current
+    stream of the device of `like` (or of the current device)."""
+    if stream is not None:
+        return stream.cuda_stream
+    dev = like.get_device() if like is not None else torch.cuda.current_device()
+    if _raw_stream is not None:
+        return _raw_stream(dev)
+    return torch.cuda.current_stream(dev).cuda_stream
 
 
 def _check_shares(x0, x1, width, what="shares"):
@@ -250,7 +265,7 @@ def trunc_det(x0, x1, ell, k1, k2=0, out=None, stream=None):
     y0 = _out(x0, ring_width(m), ring_dtype(m), None if out is None else out[0])
     y1 = _out(x1, ring_width(m), ring_dtype(m), None if out is None else out[1])
     _check(lib.bc_trunc_det(x0.data_ptr(), x1.data_ptr(), y0.data_ptr(), y1.data_ptr(), x0.numel(), ell, k1, k2,
-                            _stream(stream)), "trunc_det")
+                            _stream(stream, x0)), "trunc_det")
     return y0, y1
 
 
@@ -260,7 +275,7 @@ def trunc_prob(x0, x1, ell, k, out=None, stream=None):
     y0 = _out(x0, ring_width(ell), ring_dtype(ell), None if out is None else out[0])
     y1 = _out(x1, ring_width(ell), ring_dtype(ell), None if out is None else out[1])
     _check(lib.bc_trunc_prob(x0.data_ptr(), x1.data_ptr(), y0.data_ptr(), y1.data_ptr(), x0.numel(), ell, k,
-                             _stream(stream)), "trunc_prob")
+                             _stream(stream, x0)), "trunc_prob")
     return y0, y1
 
 
@@ -271,7 +286,7 @@ def mod_switch(x0, x1, ell_in, p, out=None, stream=None):
     y0 = _out(x0, w, field_dtype(p), None if out is None else out[0])
     y1 = _out(x1, w, field_dtype(p), None if out is None else out[1])
     _check(lib.bc_mod_switch(x0.data_ptr(), x1.data_ptr(), y0.data_ptr(), y1.data_ptr(), x0.numel(), ell_in, p,
-                             _stream(stream)), "mod_switch")
+                             _stream(stream, x0)), "mod_switch")
     return y0, y1
 
 
@@ -283,10 +298,9 @@ def _drelu_like(fn, name, x0, x1, params, seeds, elem_base, capture, out, stream
     if capture:
         p = params.resolved().p
         cap = torch.empty((2, x0.numel(), params.npos), dtype=field_dtype(p), device=x0.device)
-    acct = _Acct()
     _check(fn(x0.data_ptr(), x1.data_ptr(), y0.data_ptr(), y1.data_ptr(), x0.numel(), ctypes.byref(params.c()),
-              ctypes.byref(seeds.c()), elem_base, None if cap is None else cap.data_ptr(), ctypes.byref(acct),
-              _stream(stream)), name)
+              ctypes.byref(seeds.c()), elem_base, None if cap is None else cap.data_ptr(), None,
+              _stream(stream, x0)), name)
     if capture:
         return y0, y1, cap
     return y0, y1
@@ -311,7 +325,7 @@ def _trunc_like(fn, name, x0, x1, ell_in, k1, params, seeds, elem_base, capture,
         cap = torch.empty((2, x0.numel(), params.npos), dtype=field_dtype(params.resolved().p), device=x0.device)
     _check(fn(x0.data_ptr(), x1.data_ptr(), y0.data_ptr(), y1.data_ptr(), x0.numel(), ell_in, k1,
               ctypes.byref(params.c()), ctypes.byref(seeds.c()), elem_base, None if cap is None else cap.data_ptr(),
-              None, _stream(stream)), name)
+              None, _stream(stream, x0)), name)
     return (y0, y1, cap) if capture else (y0, y1)
 
 
@@ -350,7 +364,7 @@ def rand_expand(op, params: Params, seeds: Seeds, n, elem_base=0, out=None, devi
         _check(lib.bc_check_params(ctypes.byref(params.c()), None), "rand_expand")
     buf = out if out is not None else torch.empty(max(nb, 1), dtype=torch.uint8, device=device)
     _check(lib.bc_rand_expand(buf.data_ptr(), buf.numel(), n, op, ctypes.byref(params.c()), ctypes.byref(seeds.c()),
-                              elem_base, _stream(stream)), "rand_expand")
+                              elem_base, _stream(stream, buf)), "rand_expand")
     return buf
 
 
@@ -363,7 +377,7 @@ def _pre_like(fn, name, x0, x1, params, rand, capture, out, stream):
         cap = torch.empty((2, x0.numel(), params.npos), dtype=field_dtype(params.resolved().p), device=x0.device)
     _check(fn(x0.data_ptr(), x1.data_ptr(), y0.data_ptr(), y1.data_ptr(), x0.numel(), ctypes.byref(params.c()),
               rand.data_ptr(), rand.numel() * rand.element_size(), None if cap is None else cap.data_ptr(), None,
-              _stream(stream)), name)
+              _stream(stream, x0)), name)
     return (y0, y1, cap) if capture else (y0, y1)
 
 

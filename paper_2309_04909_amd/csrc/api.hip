@@ -69,11 +69,26 @@ bool is_prime64(uint64_t n) {
     return true;
 }
 
+// Computed once per l_x (Miller-Rabin on every call would dominate the host
+// cost of a small DReLU call).
 uint64_t default_prime(uint32_t lx) {
     if (lx < 1 || lx > 32) return 0;
-    uint64_t c = (1ull << (lx + 1)) - 1;
+    static std::atomic<uint64_t> cache[33];
+    uint64_t c = cache[lx].load(std::memory_order_relaxed);
+    if (c) return c;
+    c = (1ull << (lx + 1)) - 1;
     while (!is_prime64(c)) --c;
+    cache[lx].store(c, std::memory_order_relaxed);
     return c;
+}
+
+// is_prime64 with a one-entry memo of the last explicit prime that passed.
+bool is_prime_cached(uint64_t p) {
+    static std::atomic<uint64_t> last{0};
+    if (p != 0 && last.load(std::memory_order_relaxed) == p) return true;
+    if (!is_prime64(p)) return false;
+    last.store(p, std::memory_order_relaxed);
+    return true;
 }
 
 // ------------------------------------------------------------ validation
@@ -89,9 +104,10 @@ int check_params(const bc_drelu_params* prm, bc_drelu_params* out) {
     if (prm->lx < 1 || prm->lx > 32) return fail(BC_ERR_WINDOW, "lx = %u outside [1, 32]", prm->lx);
     if ((uint64_t)prm->k_lo + 2ull * prm->lx > prm->ell)
         return fail(BC_ERR_WINDOW, "k_lo + 2 lx = %u exceeds ell = %u", prm->k_lo + 2 * prm->lx, prm->ell);
-    uint64_t p = prm->p ? prm->p : default_prime(prm->lx);
+    const uint64_t dp = default_prime(prm->lx);
+    uint64_t p = prm->p ? prm->p : dp;
     const uint64_t lo = 1ull << prm->lx, hi = 1ull << (prm->lx + 1);
-    if (!(lo < p && p < hi) || !is_prime64(p))
+    if (!(lo < p && p < hi) || (p != dp && !is_prime_cached(p)))
         return fail(BC_ERR_PRIME, "p = %llu is not a prime in (2^%u, 2^%u)", (unsigned long long)p, prm->lx, prm->lx + 1);
     if (out) {
         *out = *prm;
@@ -131,9 +147,26 @@ int grid_cap(int per_cu) { return bc::device_cus() * per_cu; }
 
 // Schedule table: blocks per compute unit of the grid, per kernel kind and
 // window count (0 = the built-in default).  Written by bc_set_schedule.
-constexpr int kKinds = 5;
+constexpr int kKinds = 6;
 std::atomic<uint32_t> g_sched[kKinds][34];
-constexpr uint32_t kDefaultBpc[kKinds] = {16, 8, 16, 16, 8};
+// blocks per CU of each kind; for BC_SCHED_GROUP the largest lanes per element
+constexpr uint32_t kDefaultBpc[kKinds] = {16, 8, 16, 16, 8, 8};
+
+// Lanes per element of a DReLU/ReLU call: calls too small to give every SIMD
+// one wave at one lane per element spread each element over 8 or 4 lanes (up
+// to the group schedule's limit) while the grid stays within one wave per
+// SIMD; beyond that the lanes' repeated shuffle and sort cost more than the
+// latency they hide (measured on MI355X for l_x = 7, 18, 31, 32).  Capturing
+// calls keep one lane per element.
+int lanes_per_element(uint32_t npos, uint64_t n, bool capture) {
+    if (capture) return 1;
+    uint32_t gmax = g_sched[BC_SCHED_GROUP][npos < 34 ? npos : 0].load(std::memory_order_relaxed);
+    if (!gmax) gmax = kDefaultBpc[BC_SCHED_GROUP];
+    const uint64_t target = (uint64_t)bc::device_cus() * 4 * 64;   // one wave on each of 4 SIMDs per CU
+    if (gmax >= 8 && n * 8 <= target) return 8;
+    if (gmax >= 4 && n * 4 <= target) return 4;
+    return 1;
+}
 
 uint64_t sched_grid(uint32_t kind, uint32_t npos, uint64_t work_blocks) {
     uint32_t bpc = g_sched[kind][npos < 34 ? npos : 0].load(std::memory_order_relaxed);
@@ -185,7 +218,8 @@ int drelu_common(uint32_t op, const void* x0, const void* x1, void* y0, void* y1
     L.s02 = stream_key(seeds->seed02, seeds->nonce);
     L.s12 = stream_key(seeds->seed12, seeds->nonce);
     L.block = 256;
-    L.grid = (int)sched_grid(BC_SCHED_FUSED, L.npos, (n + 255) / 256);
+    L.group = lanes_per_element(L.npos, n, capture != nullptr);
+    L.grid = (int)sched_grid(BC_SCHED_FUSED, L.npos, (n * (uint64_t)L.group + 255) / 256);
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
     const bool relu = op == BC_OP_RELU;
@@ -471,7 +505,7 @@ int bc_mod_switch(const void* x0, const void* x1, void* y0, void* y1, uint64_t n
     if (ell_in < 1 || ell_in > 63) return fail(BC_ERR_RING, "ell_in = %u outside [1, 63]", ell_in);
     const uint64_t lo = 1ull << ell_in;
     const uint64_t hi = ell_in == 63 ? ~0ull : (1ull << (ell_in + 1));
-    if (!(lo < p && (p < hi || (ell_in == 63))) || !is_prime64(p))
+    if (!(lo < p && (p < hi || (ell_in == 63))) || !is_prime_cached(p))
         return fail(BC_ERR_PRIME, "p = %llu is not a prime in (2^%u, 2^%u)", (unsigned long long)p, ell_in, ell_in + 1);
     if (n == 0) return BC_OK;
     if (!x0 || !x1 || !y0 || !y1) return fail(BC_ERR_NULL, "share pointer is NULL");

@@ -222,6 +222,132 @@ __global__ BC_KERNEL_ATTRS void k_drelu(DreluKArgs A, F f_arg) {
                                           A.k_lo, A.s01, A.s02, A.s12, f);
 }
 
+// Lane groups for small calls: G consecutive lanes share one element, so a
+// call of n elements still runs n * G threads.  Every lane of the group draws
+// and sorts the shuffle keys (cheap next to the slots), lane l takes mask
+// block kG + l in round k (its two slots, or one slot when l_x = 32), and the
+// group's P2 minimum is combined by lane shuffles; lane 0 finishes and writes.
+// Results are those of drelu_element: same draws, same slots, same messages.
+template <typename T, int N, typename F, bool RELU, int G>
+__device__ __forceinline__ void drelu_element_group(const T* __restrict__ X0, const T* __restrict__ X1, T* Y0, T* Y1,
+                                                    uint64_t e, uint64_t g, uint32_t lane, T mask, T in_mask,
+                                                    uint32_t k_in, uint32_t k_lo, const Stream& s01,
+                                                    const Stream& s02, const Stream& s12, const F& f) {
+    using FT = typename F::T;
+    constexpr bool WIDE = std::is_same<FT, uint64_t>::value;
+    constexpr int SPB = WIDE ? 1 : 2;                       // slots per mask block
+    constexpr int NB = (N + SPB - 1) / SPB;                 // mask blocks
+    constexpr int ROUNDS = (NB + G - 1) / G;
+
+    const T r0 = X0[e] & in_mask;
+    const T r1 = X1[e] & in_mask;
+    const T in0 = (T)(r0 >> k_in) & mask;
+    const T nr1 = (T)((T)0 - r1) & in_mask;
+    const T in1 = (T)((T)0 - (T)(nr1 >> k_in)) & mask;
+
+    const StreamAt r01 = s01.at(g);
+    uint32_t key[N];
+    uint32_t t = 0;
+#pragma unroll
+    for (int b = 0; b < (N + 3) / 4; ++b) {
+        const Words4 w = r01.block(TAG_SHUFFLE, b);
+        if (b == 0) t = w.w0 & 1u;
+        const uint32_t ws[4] = {w.w0, w.w1, w.w2, w.w3};
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (4 * b + q < N) key[4 * b + q] = (ws[q] & ~63u) | (uint32_t)(4 * b + q);
+    }
+    sort_keys<N>(key);
+
+    const T a0 = t ? (T)((T)0 - in0) & mask : in0;
+    const T a1 = t ? (T)((T)0 - in1) & mask : in1;
+    const T nb1 = (T)((T)0 - a1) & mask;
+    const T a0k = a0 >> k_lo, nb1k = nb1 >> k_lo;
+
+    FT least = f.p;
+#pragma unroll
+    for (int k = 0; k < ROUNDS; ++k) {
+        const uint32_t blk = (uint32_t)(k * G) + lane;      // this lane's mask block
+        const Words4 w = r01.block(TAG_MASK, blk);
+#pragma unroll
+        for (int h = 0; h < SPB; ++h) {
+            // slot j = SPB * blk + h; its sorted key, chosen among the G lanes' candidates
+            uint32_t kj = key[SPB * k * G + h < N ? SPB * k * G + h : N - 1];
+#pragma unroll
+            for (int q = 1; q < G; ++q)
+                if (SPB * (k * G + q) + h < N) kj = lane == (uint32_t)q ? key[SPB * (k * G + q) + h] : kj;
+            FT r, z;
+            if constexpr (WIDE) {
+                r = 1 + __umul64hi(join64(w.w0, w.w1), f.p - 1);
+                z = __umul64hi(join64(w.w2, w.w3), f.p);
+            } else {
+                r = draw_r(h ? w.w2 : w.w0, f.p);
+                z = draw_z(h ? w.w3 : w.w1, f.p);
+            }
+            FT w0, w1;
+            const FT v = slot_messages<T, N, F>(a0k, nb1k, kj & 63u, r, z, f, w0, w1);
+            const bool valid = SPB * blk + h < (uint32_t)N;
+            least = (valid && v < least) ? v : least;
+        }
+    }
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) {
+        if constexpr (WIDE) {
+            const uint32_t lo = __shfl_xor((uint32_t)least, o, G), hi = __shfl_xor((uint32_t)(least >> 32), o, G);
+            const FT other = join64(lo, hi);
+            least = other < least ? other : least;
+        } else {
+            const FT other = (FT)__shfl_xor((uint32_t)least, o, G);
+            least = other < least ? other : least;
+        }
+    }
+    const T dp = least == 0 ? 1 : 0;
+
+    T y0, y1;
+    if constexpr (!RELU) {
+        const Words4 w = s02.block(g, TAG_RESP, 0);
+        drelu_finish<T>(dp, (T)join64(w.w0, w.w1) & mask, t, mask, y0, y1);
+    } else {
+        const StreamAt r02 = s02.at(g);
+        const Words4 w0 = r02.block(TAG_BEAVER, 0);
+        const Words4 w1 = r02.block(TAG_BEAVER, 1);
+        const Words4 w2 = s12.block(g, TAG_BEAVER, 0);
+        const T ba0 = (T)join64(w0.w0, w0.w1) & mask;
+        const T bb0 = (T)join64(w0.w2, w0.w3) & mask;
+        const T bc0 = (T)join64(w1.w0, w1.w1) & mask;
+        const T ba1 = (T)join64(w2.w0, w2.w1) & mask;
+        const T bb1 = (T)join64(w2.w2, w2.w3) & mask;
+        const T bc1 = (T)((T)(ba0 + ba1) * (T)(bb0 + bb1) - bc0) & mask;
+        relu_finish<T>(dp, in0, in1, ba0, bb0, bc0, ba1, bb1, bc1, t, mask, y0, y1);
+    }
+    if (lane == 0) {
+        Y0[e] = y0;
+        Y1[e] = y1;
+    }
+}
+
+// Lane-group launch: thread t serves element t / G as lane t % G.  Every lane
+// of a group is active or inactive together (the loop bound is per element),
+// so the shuffles only read lanes that take part.
+template <typename T, int N, typename F, bool RELU, int G>
+__global__ BC_KERNEL_ATTRS void k_drelu_group(DreluKArgs A, F f_arg) {
+    static_assert(G >= 2 && (G & (G - 1)) == 0 && 256 % G == 0, "G: a power of two dividing the block");
+    const F f = f_arg.vgpr();
+    const T* X0 = static_cast<const T*>(A.x0);
+    const T* X1 = static_cast<const T*>(A.x1);
+    T* Y0 = static_cast<T*>(A.y0);
+    T* Y1 = static_cast<T*>(A.y1);
+    const T mask = in_vgpr((T)A.ring_mask);
+    const uint32_t lane = threadIdx.x & (G - 1);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t total = A.n * G;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+        const uint64_t e = t / G;
+        drelu_element_group<T, N, F, RELU, G>(X0, X1, Y0, Y1, e, A.elem_base + e, lane, mask, (T)A.in_mask, A.k_in,
+                                              A.k_lo, A.s01, A.s02, A.s12, f);
+    }
+}
+
 // Ragged batch: a persistent grid walks the tiles of every segment.  Tile t
 // belongs to the segment s with tile_begin[s] <= t < tile_begin[s + 1]; each
 // segment has its own op, nonce and global element offset, so every element
@@ -294,7 +420,11 @@ inline DreluKArgs make_kargs(const DreluLaunch& L) {
 template <typename T, int N, typename F, bool RELU>
 hipError_t launch_field(const DreluLaunch& L, const F& f, hipStream_t st) {
     const DreluKArgs A = make_kargs(L);
-    if (L.cap)
+    if (L.group == 8)
+        hipLaunchKernelGGL((k_drelu_group<T, N, F, RELU, 8>), dim3(L.grid), dim3(L.block), 0, st, A, f);
+    else if (L.group == 4)
+        hipLaunchKernelGGL((k_drelu_group<T, N, F, RELU, 4>), dim3(L.grid), dim3(L.block), 0, st, A, f);
+    else if (L.cap)
         hipLaunchKernelGGL((k_drelu<T, N, F, RELU, true>), dim3(L.grid), dim3(L.block), 0, st, A, f);
     else
         hipLaunchKernelGGL((k_drelu<T, N, F, RELU, false>), dim3(L.grid), dim3(L.block), 0, st, A, f);

@@ -28,6 +28,7 @@ struct DreluLaunch {
     StreamKey s01, s02, s12;
     int grid;
     int block;
+    int group;            // lanes per element: 1, or 4 / 8 (lane-group kernel, no capture)
 };
 
 // Device plan of a ragged batch: this header, then nseg bc_segment records,

@@ -255,3 +255,42 @@ def test_fused_trunc_rejects_mismatched_rings(B):
         B.trunc_relu(x, x, 64, 13, B.Params(50, 11, 13), B.Seeds(1, 2, 3))        # 64 - 13 != 50
     with pytest.raises(B.BicopError):
         B.trunc_relu(x, x, 40, 10, B.Params(30, 7, 10), B.Seeds(1, 2, 3))         # 8-byte in, 4-byte out
+
+
+@pytest.mark.parametrize("ell,lx,k_lo", [(64, 18, 13), (64, 32, 0), (64, 31, 0), (64, 7, 11), (51, 11, 13),
+                                         (32, 8, 8), (24, 7, 10), (64, 2, 5)])
+def test_lane_groups_agree_with_one_lane(B, ell, lx, k_lo):
+    """Small calls spread each element over 4 or 8 lanes (mask blocks split
+    among the lanes, P2's minimum combined by lane shuffles).  Forcing each
+    group size through the schedule table gives identical outputs, also for
+    fused truncation and element indices across 2^32."""
+    rng = np.random.default_rng(ell + 100 * lx + k_lo)
+    prm = B.Params(ell, lx, k_lo)
+    before = B.get_schedule("group", lx + 1)
+    try:
+        for n, elem_base in [(1, 0), (5, 7), (999, (1 << 32) - 400), (12000, 12345)]:
+            x0, x1 = _inputs(rng, n, ell, lx, k_lo)
+            sd = B.Seeds(11, 22, 33, n)
+            for fn in (B.drelu, B.relu):
+                outs = []
+                for gmax in (1, 4, 8):
+                    B.set_schedule("group", lx + 1, gmax)
+                    outs.append(fn(dev(x0), dev(x1), prm, sd, elem_base=elem_base))
+                for o in outs[1:]:
+                    assert same(o[0], outs[0][0]) and same(o[1], outs[0][1]), (fn.__name__, n)
+    finally:
+        B.set_schedule("group", lx + 1, before)
+
+
+def test_lane_groups_fused_truncation(B):
+    """bc_trunc_relu on small calls (lane groups) equals the two passes."""
+    rng = np.random.default_rng(91)
+    prm = B.Params(51, 11, 13)
+    for n in (3, 700, 30000):
+        x0 = rand_ring(rng, n, 64)
+        x1 = rand_ring(rng, n, 64)
+        sd = B.Seeds(5, 6, 7, n)
+        f0, f1 = B.trunc_relu(dev(x0), dev(x1), 64, 13, prm, sd)
+        t0, t1 = B.trunc_det(dev(x0), dev(x1), 64, 13)
+        r0, r1 = B.relu(t0, t1, prm, sd)
+        assert same(f0, r0) and same(f1, r1)
