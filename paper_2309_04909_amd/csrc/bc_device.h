@@ -216,6 +216,65 @@ struct FieldMersenne {
     }
 };
 
+// p = 2^K - c with c < 64 (pseudo-Mersenne), K <= 32.  Every default prime
+// (the largest prime below 2^K) has this form.  x = a*b + d (a, b, d < p)
+// is below 2^(2K); with 2^K = c mod p, x = H 2^K + L folds to L + c H
+// < (c + 1) 2^K, a second fold to L' + c H' < 2^K + c^2 < 2p, and one
+// conditional subtraction ends it.  p is a literal, and both folds are
+// multiply-adds.
+template <int K, uint32_t CC>
+struct FieldPM {
+    static_assert(K >= 14 && K <= 32 && CC >= 1 && CC < 64, "pseudo-Mersenne 2^K - c");
+    using T = uint32_t;
+    static constexpr bool kWrap = K == 32;   // p > 2^31: 32-bit sums can wrap
+    static constexpr uint32_t p = (uint32_t)((1ull << K) - CC);
+    static constexpr uint32_t LOW = (uint32_t)((1ull << K) - 1);
+    __device__ __forceinline__ FieldPM vgpr() const { return *this; }
+    __device__ __forceinline__ uint32_t mul(uint32_t a, uint32_t b) const { return mul_add(a, b, 0); }
+    __device__ __forceinline__ uint32_t mul_add(uint32_t a, uint32_t b, uint32_t d) const {
+        const uint64_t x = mad_u64_u32(a, b, d);
+        uint32_t H, L;
+        if constexpr (K == 32) {
+            H = (uint32_t)(x >> 32);
+            L = (uint32_t)x;
+        } else {
+            H = __builtin_amdgcn_alignbit((uint32_t)(x >> 32), (uint32_t)x, K);   // x >> K < 2^K <= 2^32
+            L = (uint32_t)x & LOW;
+        }
+        uint32_t H2, L2;
+        if constexpr (K <= 24) {
+            const uint32_t t = __umul24(H, CC) + L;                // < 2^(K + 6) <= 2^30
+            H2 = t >> K;
+            L2 = t & LOW;
+        } else {
+            const uint64_t t = mad_u64_u32(H, CC, L);               // < 2^(K + 6)
+            if constexpr (K == 32) {
+                H2 = (uint32_t)(t >> 32);
+                L2 = (uint32_t)t;
+            } else {
+                H2 = __builtin_amdgcn_alignbit((uint32_t)(t >> 32), (uint32_t)t, K);
+                L2 = (uint32_t)t & LOW;
+            }
+        }
+        if constexpr (K == 32) {
+            // S = L2 + c H2 < 2^32 + c^2 may exceed 32 bits; S >= p exactly when
+            // S + c reaches 2^32, and then S - p = (S + c) mod 2^32.
+            const uint64_t S = (uint64_t)L2 + __umul24(H2, CC);
+            const uint64_t R = S + CC;
+            return (R >> 32) ? (uint32_t)R : (uint32_t)S;
+        } else {
+            const uint32_t S = L2 + __umul24(H2, CC);              // < 2^K + c^2 < 2p
+            return min(S, S - p);
+        }
+    }
+};
+
+// 2^K minus the largest prime below 2^K, for K = lx + 1 in 12..33 (the
+// default primes; 0 where unused).  Checked against an independent
+// primality search on the host.
+constexpr uint32_t kPrimeDelta[34] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 3, 1, 3, 19, 15, 1,
+                                      5, 1, 3, 9, 3, 15, 3, 39, 5, 39, 57, 3, 35, 1, 5, 9};
+
 // p < 2^24, any prime.  a*b < 2^48 is exact in fp64; an fp64 quotient is
 // within one of floor(x / p), and the remainder from an fma is exact.
 struct Field24 {

@@ -433,23 +433,36 @@ hipError_t launch_field(const DreluLaunch& L, const F& f, hipStream_t st) {
 
 constexpr bool mersenne_exponent(int k) { return k == 13 || k == 17 || k == 19; }   // 2^k - 1 prime, 12 < k <= 24
 
+// Calls fn(field) with the Z_p arithmetic for N = l_x + 1 (p has N bits):
+// fp32-quotient 24-bit products for p < 2^12; for the default primes the
+// Mersenne fold (2^13 - 1, 2^17 - 1, 2^19 - 1) or the pseudo-Mersenne folds
+// (every other default prime up to 2^32); for any other prime an fp64
+// quotient (p < 2^24) or Barrett (p < 2^32); and the 128-bit product with an
+// fp64 quotient for l_x = 32.
+template <int N, typename Fn>
+hipError_t with_field(uint64_t p, Fn&& fn) {
+    if constexpr (N <= 12) {
+        return fn(make_field_small(p));
+    } else if constexpr (N <= 32) {
+        if constexpr (mersenne_exponent(N)) {
+            if (p == (1ull << N) - 1) return fn(FieldMersenne<N>{});
+        } else {
+            if (p == (1ull << N) - kPrimeDelta[N]) return fn(FieldPM<N, kPrimeDelta[N]>{});
+        }
+        if constexpr (N <= 24)
+            return fn(make_field24(p));
+        else
+            return fn(make_field32(p));
+    } else {
+        return fn(make_field64(p));
+    }
+}
+
 // The field type follows from N = l_x + 1 (p has N bits), and from p itself
 // when p is a Mersenne prime.
 template <typename T, int N, bool RELU>
 hipError_t launch_exact(const DreluLaunch& L, hipStream_t st) {
-    if constexpr (N <= 12) {
-        return launch_field<T, N, FieldSmall, RELU>(L, make_field_small(L.p), st);
-    } else if constexpr (N <= 24) {
-        if constexpr (mersenne_exponent(N)) {
-            if (L.p == (1ull << N) - 1)
-                return launch_field<T, N, FieldMersenne<N>, RELU>(L, FieldMersenne<N>{}, st);
-        }
-        return launch_field<T, N, Field24, RELU>(L, make_field24(L.p), st);
-    } else if constexpr (N <= 32) {
-        return launch_field<T, N, Field32, RELU>(L, make_field32(L.p), st);
-    } else {
-        return launch_field<T, N, Field64, RELU>(L, make_field64(L.p), st);
-    }
+    return with_field<N>(L.p, [&](auto f) { return launch_field<T, N, decltype(f), RELU>(L, f, st); });
 }
 
 template <typename T, int N, typename F>
@@ -472,19 +485,7 @@ hipError_t launch_batch_field(const BatchLaunch& L, const F& f, hipStream_t st) 
 
 template <typename T, int N>
 hipError_t launch_batch_exact(const BatchLaunch& L, hipStream_t st) {
-    if constexpr (N <= 12) {
-        return launch_batch_field<T, N, FieldSmall>(L, make_field_small(L.p), st);
-    } else if constexpr (N <= 24) {
-        if constexpr (mersenne_exponent(N)) {
-            if (L.p == (1ull << N) - 1)
-                return launch_batch_field<T, N, FieldMersenne<N>>(L, FieldMersenne<N>{}, st);
-        }
-        return launch_batch_field<T, N, Field24>(L, make_field24(L.p), st);
-    } else if constexpr (N <= 32) {
-        return launch_batch_field<T, N, Field32>(L, make_field32(L.p), st);
-    } else {
-        return launch_batch_field<T, N, Field64>(L, make_field64(L.p), st);
-    }
+    return with_field<N>(L.p, [&](auto f) { return launch_batch_field<T, N, decltype(f)>(L, f, st); });
 }
 
 template <typename T, int NLO, int NHI>

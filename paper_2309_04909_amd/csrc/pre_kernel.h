@@ -238,19 +238,7 @@ hipError_t launch_pre_field(const PreLaunch& L, const F& f, hipStream_t st) {
 
 template <typename T, int N>
 hipError_t launch_pre_exact(const PreLaunch& L, hipStream_t st) {
-    if constexpr (N <= 12) {
-        return launch_pre_field<T, N, FieldSmall>(L, make_field_small(L.p), st);
-    } else if constexpr (N <= 24) {
-        if constexpr (mersenne_exponent(N)) {
-            if (L.p == (1ull << N) - 1)
-                return launch_pre_field<T, N, FieldMersenne<N>>(L, FieldMersenne<N>{}, st);
-        }
-        return launch_pre_field<T, N, Field24>(L, make_field24(L.p), st);
-    } else if constexpr (N <= 32) {
-        return launch_pre_field<T, N, Field32>(L, make_field32(L.p), st);
-    } else {
-        return launch_pre_field<T, N, Field64>(L, make_field64(L.p), st);
-    }
+    return with_field<N>(L.p, [&](auto f) { return launch_pre_field<T, N, decltype(f)>(L, f, st); });
 }
 
 template <typename T, int NLO, int NHI>

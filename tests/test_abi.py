@@ -217,3 +217,14 @@ def test_keybit_int_bits_is_the_smallest_guarded_window(f):
             assert OP.guard_bound(k_lo, lx) >= bound                 # |x| < bound is inside the guard domain
             if i > 1:
                 assert OP.guard_bound(*OP.keybit_window(f, i - 1, fb)) < bound   # and one bit fewer is not
+
+
+def test_pseudo_mersenne_table_is_the_default_primes():
+    """The kernels' table of 2^K - p (bc_device.h) against the oracle's own
+    largest-prime-below-2^K search, for every K = l_x + 1 it covers."""
+    src = open(os.path.join(ROOT, "paper_2309_04909_amd", "csrc", "bc_device.h")).read()
+    m = re.search(r"kPrimeDelta\[34\]\s*=\s*\{([^}]*)\}", src)
+    table = [int(v) for v in m.group(1).replace("\n", " ").split(",")]
+    assert len(table) == 34
+    for K in range(12, 34):
+        assert table[K] == (1 << K) - OP.default_prime(K - 1), K
