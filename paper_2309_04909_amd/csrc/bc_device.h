@@ -269,6 +269,33 @@ struct FieldPM {
     }
 };
 
+// p = 2^33 - 9, the default prime of l_x = 32 (64-bit field elements).
+// For a, b, d < p: split each at bit 32 (the high parts are single bits);
+// then a*b + d = (a0 b0 + d0) + 2^32 (a1 b0 + a0 b1 + d1) + 2^64 a1 b1, and
+// with 2^33 = 9 and 2^64 = 9 * 2^31 (mod p) each part folds below 2^36; their
+// sum (< 2^37) folds once more below 2^33 + 144 < 2p.  Three 32x32 multiply-
+// adds, no fp64 and no 64x64 product.
+struct FieldPM33 {
+    using T = uint64_t;
+    static constexpr bool kWrap = false;
+    static constexpr uint64_t p = (1ull << 33) - 9;
+    static constexpr uint64_t LOW33 = (1ull << 33) - 1;
+    __device__ __forceinline__ FieldPM33 vgpr() const { return *this; }
+    __device__ __forceinline__ uint64_t mul(uint64_t a, uint64_t b) const { return mul_add(a, b, 0); }
+    __device__ __forceinline__ uint64_t mul_add(uint64_t a, uint64_t b, uint64_t d) const {
+        const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+        const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+        const uint32_t d0 = (uint32_t)d, d1 = (uint32_t)(d >> 32);
+        const uint64_t t0 = mad_u64_u32(a0, b0, d0);                                   // < 2^64
+        const uint64_t A = mad_u64_u32((uint32_t)(t0 >> 33), 9u, t0 & LOW33);          // < 2^35
+        const uint64_t C = (uint64_t)(a1 ? b0 : 0u) + (b1 ? a0 : 0u) + d1;             // < 2^33 - 18
+        const uint64_t Cm = mad_u64_u32((uint32_t)(C >> 1), 9u, (C & 1) << 32);        // C 2^32 mod-folded
+        const uint64_t U = A + Cm + ((a1 & b1) ? (9ull << 31) : 0ull);                 // < 2^37
+        const uint64_t R = (U & LOW33) + 9u * (uint32_t)(U >> 33);                      // < 2p
+        return R >= p ? R - p : R;
+    }
+};
+
 // 2^K minus the largest prime below 2^K, for K = lx + 1 in 12..33 (the
 // default primes; 0 where unused).  Checked against an independent
 // primality search on the host.

@@ -436,9 +436,9 @@ constexpr bool mersenne_exponent(int k) { return k == 13 || k == 17 || k == 19; 
 // Calls fn(field) with the Z_p arithmetic for N = l_x + 1 (p has N bits):
 // fp32-quotient 24-bit products for p < 2^12; for the default primes the
 // Mersenne fold (2^13 - 1, 2^17 - 1, 2^19 - 1) or the pseudo-Mersenne folds
-// (every other default prime up to 2^32); for any other prime an fp64
-// quotient (p < 2^24) or Barrett (p < 2^32); and the 128-bit product with an
-// fp64 quotient for l_x = 32.
+// (every other default prime up to 2^33); for any other prime an fp64
+// quotient (p < 2^24), Barrett (p < 2^32), or the 128-bit product with an
+// fp64 quotient (l_x = 32).
 template <int N, typename Fn>
 hipError_t with_field(uint64_t p, Fn&& fn) {
     if constexpr (N <= 12) {
@@ -454,6 +454,7 @@ hipError_t with_field(uint64_t p, Fn&& fn) {
         else
             return fn(make_field32(p));
     } else {
+        if (p == (1ull << 33) - kPrimeDelta[33]) return fn(FieldPM33{});
         return fn(make_field64(p));
     }
 }
