@@ -2,11 +2,13 @@
 """Benchmark of the Bicoptor 2.0 DReLU/ReLU hot path on one MI355X.
 
 One step is one pass of the key-bit workload: the 13-bit deterministic
-truncation (Alg. 5) of 2^24 shared products z = x1 * x2 in Z_{2^64}, followed
-by the key-bit DReLU (Alg. 7, l = 64, k_lo = 13, l_x = 18, p = 2^19 - 1) of
-2^24 shared fixed-point values x (f = 13, |x| < 2^30).  Inputs are seeded
-synthetic data, resident in HBM before timing starts.  `value` is DReLU
-elements per second of the whole step.
+truncation (Alg. 5) of 2^24 shared products z = x1 * x2 in Z_{2^64} and the
+key-bit DReLU (Alg. 7, l = 64, k_lo = 13, l_x = 18, p = 2^19 - 1) of 2^24
+shared fixed-point values x (f = 13, |x| < 2^30).  The two are independent:
+the HBM-bound truncation runs on a second stream beside the ALU-bound DReLU,
+and a step ends when both have.  Inputs are seeded synthetic data, resident
+in HBM before timing starts.  `value` is DReLU elements per second of the
+whole step.
 
 Printed as one JSON line (rank 0), with extra sections:
   kernels           per-kernel average durations (HIP events on the launch stream)
@@ -166,20 +168,20 @@ def _cpu_model():
 
 
 class Timer:
-    """HIP events on the stream the kernels are launched on (torch's current stream)."""
+    """HIP events on the stream a kernel is launched on (default: torch's current stream)."""
 
     def __init__(self, torch):
         self.torch = torch
         self.pairs = {}
 
-    def start(self):
+    def start(self, stream=None):
         e = self.torch.cuda.Event(enable_timing=True)
-        e.record()
+        e.record(stream)
         return e
 
-    def stop(self, name, s):
+    def stop(self, name, s, stream=None):
         e = self.torch.cuda.Event(enable_timing=True)
-        e.record()
+        e.record(stream)
         self.pairs.setdefault(name, []).append((s, e))
 
     def avg_ms(self, name):
@@ -200,15 +202,20 @@ def run_keybit(torch, B, inputs, steps, warmup):
     y0, y1 = torch.empty_like(x0), torch.empty_like(x1)
     t0, t1 = torch.empty_like(z0), torch.empty_like(z1)
 
+    main = torch.cuda.current_stream()
+    side = torch.cuda.Stream()                     # default priority
+
     def step(timer=None):
-        s = timer.start() if timer else None
-        B.trunc_det(z0, z1, c["ell"], c["trunc_k"], 0, out=(t0, t1))
+        side.wait_stream(main)                      # the step starts on both streams together
+        s = timer.start(side) if timer else None
+        B.trunc_det(z0, z1, c["ell"], c["trunc_k"], 0, out=(t0, t1), stream=side)
         if timer:
-            timer.stop("trunc_det", s)
-            s = timer.start()
+            timer.stop("trunc_det", s, side)
+        s = timer.start() if timer else None
         B.drelu(x0, x1, prm, sd, out=(y0, y1))
         if timer:
             timer.stop("drelu", s)
+        main.wait_stream(side)                      # and ends when both are done
 
     for _ in range(warmup):
         step()
