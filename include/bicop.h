@@ -140,6 +140,17 @@ int bc_msg_account(uint32_t op, const bc_drelu_params* prm, uint64_t n, bc_msg_a
 int bc_prg_blocks(uint32_t* out, uint64_t n, uint32_t nblocks, uint64_t seed,
                   uint64_t nonce, uint32_t tag, uint64_t elem_base, void* stream);
 
+/* The Z_p multiply-add of the DReLU/ReLU kernels, elementwise, for checking
+ * the field arithmetic (Alg. 7 steps 7-8: the masked and reshared
+ * messages v r + z).  For a setting (lx, p) as in bc_drelu_params (p = 0:
+ * the default prime) it writes out[i] = (a[i] b[i] + d[i]) mod p using the
+ * same field code as the kernels: fp32-quotient products, Mersenne or
+ * pseudo-Mersenne folds, fp64 quotient, Barrett or the 128-bit product.
+ * Requires a[i], b[i] < p and d[i] <= p (other values give unspecified
+ * results).  Device arrays of n uint64, 8-byte aligned. */
+int bc_zp_mul_add(const uint64_t* a, const uint64_t* b, const uint64_t* d, uint64_t* out, uint64_t n,
+                  uint32_t lx, uint64_t p, void* stream);
+
 /* ------------------------------------------------------------ schedules */
 
 /* Kernel kinds of the schedule table. */

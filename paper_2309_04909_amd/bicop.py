@@ -61,6 +61,7 @@ _SIGS = {
     "bc_check_params": ([ctypes.POINTER(_Params), ctypes.POINTER(_Params)], ctypes.c_int),
     "bc_msg_account": ([_U32, ctypes.POINTER(_Params), _U64, ctypes.POINTER(_Acct)], ctypes.c_int),
     "bc_keybit_params": ([_U32, _U32, _U32, _U32, ctypes.POINTER(_Params)], ctypes.c_int),
+    "bc_zp_mul_add": ([_P, _P, _P, _P, _U64, _U32, _U64, _P], ctypes.c_int),
     "bc_keybit_int_bits": ([_U64, _U32], _U32),
     "bc_prg_blocks": ([_P, _U64, _U32, _U64, _U64, _U32, _U64, _P], ctypes.c_int),
     "bc_trunc_det": ([_P, _P, _P, _P, _U64, _U32, _U32, _U32, _P], ctypes.c_int),
@@ -351,6 +352,19 @@ def prg_blocks(n, nblocks, seed, nonce, tag, elem_base=0, device="cuda", stream=
 
 
 # ------------------------------------------------- precomputed randomness
+
+
+def zp_mul_add(a, b, d, lx, p=0, out=None, stream=None):
+    """(a b + d) mod p elementwise with the kernels' field arithmetic (int64 CUDA tensors)."""
+    for t in (a, b, d):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.element_size() != 8 or not t.is_contiguous():
+            raise TypeError("a, b, d must be contiguous 8-byte CUDA tensors")
+    if not (a.numel() == b.numel() == d.numel()):
+        raise ValueError("a, b, d differ in length")
+    out = _out(a, 8, torch.int64, out)
+    _check(lib.bc_zp_mul_add(a.data_ptr(), b.data_ptr(), d.data_ptr(), out.data_ptr(), a.numel(), lx, p,
+                             _stream(stream, a)), "zp_mul_add")
+    return out
 
 
 def rand_bytes(op, params: Params, n):

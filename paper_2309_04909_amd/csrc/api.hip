@@ -474,6 +474,22 @@ int bc_prg_blocks(uint32_t* out, uint64_t n, uint32_t nblocks, uint64_t seed, ui
     return e == hipSuccess ? BC_OK : hip_fail(e, "prg launch");
 }
 
+int bc_zp_mul_add(const uint64_t* a, const uint64_t* b, const uint64_t* d, uint64_t* out, uint64_t n, uint32_t lx,
+                  uint64_t p, void* stream) {
+    bc_drelu_params q{64, lx, 0, 0, p};
+    bc_drelu_params r;
+    int rc = check_params(&q, &r);
+    if (rc) return rc;
+    if (n > kMaxIndex) return fail(BC_ERR_ARG, "n must stay below 2^48");
+    if (n == 0) return BC_OK;
+    if (!a || !b || !d || !out) return fail(BC_ERR_NULL, "array pointer is NULL");
+    if (!aligned(a, 8) || !aligned(b, 8) || !aligned(d, 8) || !aligned(out, 8))
+        return fail(BC_ERR_ALIGN, "arrays must be 8-byte aligned");
+    bc::ZpLaunch L{a, b, d, out, n, r.p, r.lx + 1, (int)sched_grid(BC_SCHED_STREAM, 0, (n + 255) / 256)};
+    hipError_t e = bc::launch_zp_mul_add(L, (hipStream_t)stream);
+    return e == hipSuccess ? BC_OK : hip_fail(e, "zp_mul_add launch");
+}
+
 int bc_trunc_det(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, uint32_t ell, uint32_t k1, uint32_t k2,
                  void* stream) {
     if (ell < 1 || ell > 64) return fail(BC_ERR_RING, "ell = %u outside [1, 64]", ell);

@@ -96,6 +96,19 @@ inline RandOffsets rand_offsets(uint32_t npos, bool relu, uint32_t ring_width, u
     return o;
 }
 
+// Elementwise Z_p multiply-add with the kernels' field arithmetic (diagnostic).
+struct ZpLaunch {
+    const uint64_t* a;
+    const uint64_t* b;
+    const uint64_t* d;
+    uint64_t* out;
+    uint64_t n;
+    uint64_t p;
+    uint32_t npos;
+    int grid;
+};
+hipError_t launch_zp_mul_add(const ZpLaunch& L, hipStream_t st);
+
 hipError_t launch_pre_u64_lo(const PreLaunch& L, hipStream_t st);    // N 2..12
 hipError_t launch_pre_u64_mid(const PreLaunch& L, hipStream_t st);   // N 13..24
 hipError_t launch_pre_u64_hi(const PreLaunch& L, hipStream_t st);    // N 25..33
