@@ -331,6 +331,7 @@ def run_serving(torch, B, count=600):
     seeds = B.Seeds(*SEEDS)
     budget = 64 << 30
     srv = S.Server(pools, params, seeds, hbm_budget=budget, max_slots=256, nstreams=4)
+    srv.warmup()
     srv.run(serving_jobs(S, 7, None, 50, pool_n))                         # warm-up
     sat = S.summarize(srv.run(serving_jobs(S, 8, None, count, pool_n)))
     mean_n = (2.0 ** 24 - 2.0 ** 10) / (14 * np.log(2.0))
