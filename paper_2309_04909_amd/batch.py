@@ -47,17 +47,20 @@ class RaggedBatch:
             recs[i] = B._Segment(s.x0.data_ptr(), s.x1.data_ptr(), s.y0.data_ptr(), s.y1.data_ptr(), s.x0.numel(),
                                  s.elem_base, s.nonce & m, s.op, 0)
         nbytes = int(B.lib.bc_batch_plan_bytes(nseg))
-        self.host_plan = (ctypes.c_uint8 * nbytes)()
-        B._check(B.lib.bc_batch_plan(recs, nseg, ctypes.byref(params.c()), tile_elems, self.host_plan, nbytes),
-                 "batch_plan")
+        # The plan is built in pinned host memory and uploaded asynchronously
+        # on the current stream (runs on that stream, or on streams ordered
+        # after it, see it); the host copy stays alive with this object.
+        self.host_plan = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+        B._check(B.lib.bc_batch_plan(recs, nseg, ctypes.byref(params.c()), tile_elems, self.host_plan.data_ptr(),
+                                     nbytes), "batch_plan")
         dev = self.segments[0].x0.device
-        self.dev_plan = torch.frombuffer(bytearray(self.host_plan), dtype=torch.uint8).to(dev)
+        self.dev_plan = self.host_plan.to(dev, non_blocking=True)
         self._c_seeds = seeds.c()
         self.elements = sum(s.x0.numel() for s in self.segments)
 
     def run(self, stream=None):
         """Enqueue the one persistent launch on `stream` (default: current)."""
-        B._check(B.lib.bc_batch_run(self.dev_plan.data_ptr(), ctypes.addressof(self.host_plan),
+        B._check(B.lib.bc_batch_run(self.dev_plan.data_ptr(), self.host_plan.data_ptr(),
                                     ctypes.byref(self._c_seeds), self.grid, B._stream(stream, self.dev_plan)), "batch_run")
 
     def capture(self):
