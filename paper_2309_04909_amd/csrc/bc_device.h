@@ -90,25 +90,33 @@ __device__ __forceinline__ void launder_key(uint32_t& a, uint32_t& c) {
 // which round 0 folds into word 0 alone.  So hi/lo(M0 lo g) of round 0,
 // M1 c2 of round 1 and M0 c0 of round 2 are the same for every block; they
 // are computed once here, and each block runs 16 multiplies instead of 20.
+// The shared words that meet a round key in rounds 1-3 are stored already
+// XORed with it, so those XORs take two VGPR operands (a full-rate VOP2)
+// instead of three.
 struct StreamAt {
     uint32_t k0, k1;    // key
     uint32_t ghi;       // hi16(g)
     uint32_t u0;        // hi(M1 n0) ^ k0: round-0 word 0 without the block's word 1
-    uint32_t c3a;       // round-0 output word 3, lo(M0 lo g)
-    uint32_t c0b, c1b;  // round-1 output words 0 and 1
-    uint32_t h2, l2;    // hi / lo(M0 c0b) of round 2
+    uint32_t c3k;       // round-0 output word 3 ^ round-1 key 1
+    uint32_t c1k;       // round-1 output word 1 ^ round-2 key 0
+    uint32_t h2k;       // hi(M0 c0) of round 2 ^ round-2 key 1
+    uint32_t l2k;       // lo(M0 c0) of round 2 (round-3 word 3) ^ round-3 key 1
 
     __device__ __forceinline__ Words4 block(uint32_t tag, uint32_t b) const {
         uint32_t a = k0, c = k1;
         launder_key(a, c);
         const uint32_t x0 = u0 ^ (ghi | (tag << 16) | (b << 24));              // round 0, word 0
         const uint64_t p0 = (uint64_t)PHILOX_M0 * x0;                          // round 1
-        const uint32_t y2 = xor3((uint32_t)(p0 >> 32), c3a, c + PHILOX_W1);
+        const uint32_t y2 = (uint32_t)(p0 >> 32) ^ c3k;
         const uint32_t y3 = (uint32_t)p0;
         const uint64_t p1 = (uint64_t)PHILOX_M1 * y2;                          // round 2
-        const uint32_t z0 = xor3((uint32_t)(p1 >> 32), c1b, a + 2u * PHILOX_W0);
-        const uint32_t z2 = xor3(h2, y3, c + 2u * PHILOX_W1);
-        return philox_rounds<3>(z0, (uint32_t)p1, z2, l2, a, c);
+        const uint32_t z0 = (uint32_t)(p1 >> 32) ^ c1k;
+        const uint32_t z2 = y3 ^ h2k;
+        const uint64_t q0 = (uint64_t)PHILOX_M0 * z0;                          // round 3
+        const uint64_t q1 = (uint64_t)PHILOX_M1 * z2;
+        const uint32_t n0 = xor3((uint32_t)(q1 >> 32), (uint32_t)p1, a + 3u * PHILOX_W0);
+        const uint32_t n2 = (uint32_t)(q0 >> 32) ^ l2k;
+        return philox_rounds<4>(n0, (uint32_t)q1, n2, (uint32_t)q0, a, c);
     }
 };
 
@@ -132,8 +140,14 @@ struct Stream {
         const uint64_t Q1 = (uint64_t)PHILOX_M1 * e2;                         // round 1
         const uint32_t c0b = (uint32_t)(Q1 >> 32) ^ ((uint32_t)P1 ^ (a + PHILOX_W0));
         const uint64_t Q2 = (uint64_t)PHILOX_M0 * c0b;                        // round 2
-        return StreamAt{k0, k1, (uint32_t)(g >> 32) & 0xFFFFu, (uint32_t)(P1 >> 32) ^ a, (uint32_t)P0, c0b,
-                        (uint32_t)Q1, (uint32_t)(Q2 >> 32), (uint32_t)Q2};
+        return StreamAt{k0,
+                        k1,
+                        (uint32_t)(g >> 32) & 0xFFFFu,
+                        (uint32_t)(P1 >> 32) ^ a,
+                        (uint32_t)P0 ^ (c + PHILOX_W1),
+                        (uint32_t)Q1 ^ (a + 2u * PHILOX_W0),
+                        (uint32_t)(Q2 >> 32) ^ (c + 2u * PHILOX_W1),
+                        (uint32_t)Q2 ^ (c + 3u * PHILOX_W1)};
     }
 };
 
