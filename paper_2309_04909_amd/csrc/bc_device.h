@@ -230,15 +230,16 @@ struct FieldMersenne {
     }
 };
 
-// p = 2^K - c with c < 64 (pseudo-Mersenne), K <= 32.  Every default prime
-// (the largest prime below 2^K) has this form.  x = a*b + d (a, b, d < p)
+// p = 2^K - c with c < 64 and c^2 < p (pseudo-Mersenne), K <= 32.  Every
+// default prime (the largest prime below 2^K) has this form.  x = a*b + d (a, b, d < p)
 // is below 2^(2K); with 2^K = c mod p, x = H 2^K + L folds to L + c H
 // < (c + 1) 2^K, a second fold to L' + c H' < 2^K + c^2 < 2p, and one
 // conditional subtraction ends it.  p is a literal, and both folds are
 // multiply-adds.
 template <int K, uint32_t CC>
 struct FieldPM {
-    static_assert(K >= 14 && K <= 32 && CC >= 1 && CC < 64, "pseudo-Mersenne 2^K - c");
+    static_assert(K >= 2 && K <= 32 && CC >= 1 && CC < 64 && (uint64_t)CC * CC < (1ull << K) - CC,
+                  "pseudo-Mersenne 2^K - c with c^2 < p");
     using T = uint32_t;
     static constexpr bool kWrap = K == 32;   // p > 2^31: 32-bit sums can wrap
     static constexpr uint32_t p = (uint32_t)((1ull << K) - CC);
@@ -246,6 +247,13 @@ struct FieldPM {
     __device__ __forceinline__ FieldPM vgpr() const { return *this; }
     __device__ __forceinline__ uint32_t mul(uint32_t a, uint32_t b) const { return mul_add(a, b, 0); }
     __device__ __forceinline__ uint32_t mul_add(uint32_t a, uint32_t b, uint32_t d) const {
+        if constexpr (K <= 12) {
+            // x < p^2 < 2^24: every step in 32 bits with 24-bit multiply-adds
+            const uint32_t x = __umul24(a, b) + d;
+            const uint32_t t = __umul24(x >> K, CC) + (x & LOW);    // < (c + 1) 2^K
+            const uint32_t S = __umul24(t >> K, CC) + (t & LOW);    // < 2^K + c^2 < 2p
+            return min(S, S - p);
+        }
         const uint64_t x = mad_u64_u32(a, b, d);
         uint32_t H, L;
         if constexpr (K == 32) {
@@ -310,10 +318,10 @@ struct FieldPM33 {
     }
 };
 
-// 2^K minus the largest prime below 2^K, for K = lx + 1 in 12..33 (the
+// 2^K minus the largest prime below 2^K, for K = lx + 1 in 2..33 (the
 // default primes; 0 where unused).  Checked against an independent
 // primality search on the host.
-constexpr uint32_t kPrimeDelta[34] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 3, 1, 3, 19, 15, 1,
+constexpr uint32_t kPrimeDelta[34] = {0, 0, 1, 1, 3, 1, 3, 1, 5, 3, 3, 9, 3, 1, 3, 19, 15, 1,
                                       5, 1, 3, 9, 3, 15, 3, 39, 5, 39, 57, 3, 35, 1, 5, 9};
 
 // p < 2^24, any prime.  a*b < 2^48 is exact in fp64; an fp64 quotient is

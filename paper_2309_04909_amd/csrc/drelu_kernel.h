@@ -445,14 +445,15 @@ hipError_t launch_field(const DreluLaunch& L, const F& f, hipStream_t st) {
 constexpr bool mersenne_exponent(int k) { return k == 13 || k == 17 || k == 19; }   // 2^k - 1 prime, 12 < k <= 24
 
 // Calls fn(field) with the Z_p arithmetic for N = l_x + 1 (p has N bits):
-// fp32-quotient 24-bit products for p < 2^12; for the default primes the
-// Mersenne fold (2^13 - 1, 2^17 - 1, 2^19 - 1) or the pseudo-Mersenne folds
-// (every other default prime up to 2^33); for any other prime an fp64
+// for the default primes the Mersenne fold (2^13 - 1, 2^17 - 1, 2^19 - 1)
+// or the pseudo-Mersenne folds (every other default prime up to 2^33); for
+// any other prime fp32-quotient 24-bit products (p < 2^12), an fp64
 // quotient (p < 2^24), Barrett (p < 2^32), or the 128-bit product with an
 // fp64 quotient (l_x = 32).
 template <int N, typename Fn>
 hipError_t with_field(uint64_t p, Fn&& fn) {
     if constexpr (N <= 12) {
+        if (p == (1ull << N) - kPrimeDelta[N]) return fn(FieldPM<N, kPrimeDelta[N]>{});
         return fn(make_field_small(p));
     } else if constexpr (N <= 32) {
         if constexpr (mersenne_exponent(N)) {
