@@ -112,6 +112,13 @@ def test_error_paths_without_gpu():
     bad = B.Params(64, 7, 0, 0).c()
     bad.reserved = 1
     assert L.bc_drelu(None, None, None, None, 1, ctypes.byref(bad), ctypes.byref(sd), 0, None, None, None) == -8
+    # the diagnostic field multiply-add validates its setting like the protocol calls
+    assert L.bc_zp_mul_add(None, None, None, None, 10, 0, 0, None) == -3            # l_x = 0
+    assert L.bc_zp_mul_add(None, None, None, None, 10, 33, 0, None) == -3           # l_x > 32
+    assert L.bc_zp_mul_add(None, None, None, None, 10, 7, 255, None) == -4          # not prime
+    assert L.bc_zp_mul_add(None, None, None, None, 10, 7, 0, None) == -1            # NULL arrays
+    assert L.bc_zp_mul_add(None, None, None, None, 0, 7, 0, None) == 0              # n = 0
+    assert L.bc_zp_mul_add(None, None, None, None, 1 << 48, 7, 0, None) == -8       # n too large
 
 
 def test_batch_plan_validation_on_host():
