@@ -118,7 +118,7 @@ def test_error_paths_without_gpu():
     assert L.bc_zp_mul_add(None, None, None, None, 10, 7, 255, None) == -4          # not prime
     assert L.bc_zp_mul_add(None, None, None, None, 10, 7, 0, None) == -1            # NULL arrays
     assert L.bc_zp_mul_add(None, None, None, None, 0, 7, 0, None) == 0              # n = 0
-    assert L.bc_zp_mul_add(None, None, None, None, 1 << 48, 7, 0, None) == -8       # n too large
+    assert L.bc_zp_mul_add(None, None, None, None, (1 << 48) + 1, 7, 0, None) == -8  # n above 2^48
 
 
 def test_batch_plan_validation_on_host():
