@@ -22,7 +22,6 @@ Printed as one JSON line (rank 0), with extra sections:
 """
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -34,6 +33,7 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 import workloads as W  # noqa: E402
+from paper_2309_04909_amd.prof_summary import KERNELS, source_hash  # noqa: E402
 
 METRIC = "DReLU Gelem/s (ℓ=64, key bits), batched vs plain, %HBM peak; p50/p99"
 HBM_PEAK_GBS = 8000.0
@@ -85,20 +85,10 @@ def alg_ops_per_elem(op: str, lx: int) -> int:
             + TAIL_OPS[op])
 
 
-def source_hash(names):
-    h = hashlib.sha256()
-    for nm in names:
-        with open(os.path.join(ROOT, "paper_2309_04909_amd", "csrc", nm), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
-
-
-DRELU_SOURCES = ["bc_device.h", "drelu_kernel.h"]
-
-
-def measured_traffic(kernel: str, src_hash: str):
+def measured_traffic(kernel: str):
     """HBM bytes per launch from the committed rocprofv3 counter runs, or None if the
-    kernel sources changed since the counters were taken."""
+    kernel's code changed since the counters were taken."""
+    src_hash = source_hash(KERNELS[kernel][1])
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -536,7 +526,7 @@ def main():
     hbm_bytes = 32 * c["n"]
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s",
                 "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                "traffic": measured_traffic("drelu_keybit", source_hash(DRELU_SOURCES)),
+                "traffic": measured_traffic("drelu_keybit"),
                 "kernel": "k_drelu<u64, N=19, FieldMersenne<19>>", "ops_per_elem": ops,
                 "hbm_alg_bytes_per_launch": hbm_bytes,
                 "hbm_frac": round(hbm_bytes / (kern["drelu"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}

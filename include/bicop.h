@@ -126,8 +126,8 @@ uint32_t bc_keybit_int_bits(uint64_t bound, uint32_t f);
 
 /* Message accounting for one call of `op` (BC_OP_DRELU / BC_OP_RELU) on n
  * elements.  Round 1: each of P0, P1 sends l_x + 1 values of Z_p, i.e.
- * (l_x+1)^2 bits per element (Tab. 1, Sec. 5.4 step 8).  DReLU round 2: one
- * Z_{2^l} share to each of P0 and P1 (step 10).  ReLU (Alg. 8): e to P0 and
+ * (l_x+1)^2 bits per element (Tab. 1, Sec. 5.4).  DReLU round 2: one
+ * Z_{2^l} share to each of P0 and P1 (P2's reply).  ReLU (Alg. 8): e to P0 and
  * P1, [c]_1 to P1 (preprocessing), d-shares between P0 and P1.  Host only. */
 int bc_msg_account(uint32_t op, const bc_drelu_params* prm, uint64_t n, bc_msg_acct* acct);
 
@@ -141,8 +141,8 @@ int bc_prg_blocks(uint32_t* out, uint64_t n, uint32_t nblocks, uint64_t seed,
                   uint64_t nonce, uint32_t tag, uint64_t elem_base, void* stream);
 
 /* The Z_p multiply-add of the DReLU/ReLU kernels, elementwise, for checking
- * the field arithmetic (Alg. 7 steps 7-8: the masked and reshared
- * messages v r + z).  For a setting (lx, p) as in bc_drelu_params (p = 0:
+ * the field arithmetic (Alg. 7: the masked and reshared messages
+ * v r + z).  For a setting (lx, p) as in bc_drelu_params (p = 0:
  * the default prime) it writes out[i] = (a[i] b[i] + d[i]) mod p using the
  * same field code as the kernels: fp32-quotient products, Mersenne or
  * pseudo-Mersenne folds, fp64 quotient, Barrett or the 128-bit product.
@@ -215,9 +215,9 @@ int bc_mod_switch(const void* x0, const void* x1, void* y0, void* y1, uint64_t n
  *       DReLU(x) = [x > 0] for 0 < |x| < 2^(l_x-1), and DReLU(0) = t (the
  *       random flip).  With key bits, the band |x| < 2^k_lo follows the
  *       carry of the dropped bits.
- * Randomness: t and the shuffle from seed01 (steps 1, 6), r_i in Z_p^* and
- *       z_i in Z_p from seed01 (steps 7, 8), P2's resharing from seed02 (step
- *       10).  Draws are documented with bc_prg_blocks.
+ * Randomness: t and the shuffle from seed01, r_i in Z_p^* (mask) and z_i
+ *       in Z_p (reshare) from seed01, P2's resharing of its bit from
+ *       seed02.  Draws are documented with bc_prg_blocks.
  * capture: NULL, or a device buffer of 2 * n * (l_x + 1) elements of Z_p
  *       (uint32_t if p < 2^32, else uint64_t).  It receives the round-1
  *       messages [w]_0 then [w]_1, element-major, in slot (post-shuffle)
@@ -227,7 +227,7 @@ int bc_drelu(const void* x0, const void* x1, void* y0, void* y1, uint64_t n,
              const bc_drelu_params* prm, const bc_seeds* seeds, uint64_t elem_base,
              void* capture, bc_msg_acct* acct, void* stream);
 
-/* UBL Bicoptor 2.0 ReLU, Alg. 8 (appendix): Alg. 7 steps 1-9, then the
+/* UBL Bicoptor 2.0 ReLU, Alg. 8 (appendix): Alg. 7 up to P2's zero test, then the
  * Beaver multiplication x * DReLU(x).  [a]_0, [b]_0 and [c]_0 come from
  * seed02; [a]_1 and [b]_1 come from seed12; P2 forms [c]_1.  Outputs are
  * shares of x * DReLU(x) in Z_{2^ell}, with x at full precision.
@@ -254,7 +254,7 @@ int bc_trunc_relu(const void* x0, const void* x1, void* y0, void* y1, uint64_t n
 /* ------------------------------------------ precomputed randomness */
 
 /* Everything the parties draw from their seeds is independent of the input
- * (Alg. 7 steps 1, 6, 7, 8 and 10; Alg. 8's preprocessing), so it can be
+ * (Alg. 7: flip, shuffle, masks, reshares, P2's reply; Alg. 8's preprocessing), so it can be
  * expanded ahead of time and kept resident; the online call then streams
  * shares plus this record.  Results and messages are bit-identical to
  * bc_drelu / bc_relu with the same seeds, nonce and element indices.

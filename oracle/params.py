@@ -3,7 +3,7 @@
 * The prime p of the modulo switch has bit length l_x + 1 (notation table;
   Alg. 6).  The paper names no particular prime; the reading used here is the
   largest prime below 2^(l_x+1), which lies in (2^l_x, 2^(l_x+1)).
-* The DReLU windows are trc(x, i, l - l_x - i) for i = 0..l_x (Alg. 7 step 3);
+* The DReLU windows are trc(x, i, l - l_x - i) for i = 0..l_x (Alg. 7);
   with key bits (Sec. 6.1) the window moves up by k_lo bits, so window i
   drops k_lo + i low bits.  Window i = l_x must fit in the ring:
   k_lo + 2*l_x <= l.

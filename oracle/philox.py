@@ -1,8 +1,9 @@
 """Philox4x32-10 and the protocol's random draws (test infrastructure only).
 
-The paper only says that P0 and P1 "generate ... using seed_01" (Alg. 7 steps
-1, 6, 7), that P2's response is a fresh sharing (step 10) and that the Beaver
-triple comes from seed_02 / seed_12 (Alg. 8, preprocessing).  It fixes no
+The paper states only that P0 and P1 derive the flip, the shuffle and the
+masks from seed_01 (Alg. 7), that P2 answers with a fresh sharing of its bit,
+and that the Beaver triple comes from seed_02 / seed_12 (Alg. 8,
+preprocessing).  It fixes no
 generator.  This module is the build's definition, written from the
 published description of Philox4x32 (Salmon, Moraes, Dror, Shaw, "Parallel
 Random Numbers: As Easy as 1, 2, 3", SC'11):
@@ -87,7 +88,7 @@ def _words(seed, nonce, g, tag, count):
 
 def draw_shuffle(seed01: int, nonce: int, g, n: int):
     """t (uint64 0/1 per element) and sigma (N x n): sigma[:, s] is the window
-    position placed in slot s by the shuffle of Alg. 7 step 6."""
+    position placed in slot s by the shuffle of Alg. 7."""
     w = _words(seed01, nonce, g, TAG_SHUFFLE, n)
     t = w[:, 0] & U64(1)
     keys = (w & U64(0xFFFFFFC0)) | np.arange(n, dtype=U64)[None, :]

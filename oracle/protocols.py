@@ -5,19 +5,20 @@ Shares are NumPy uint64 arrays with canonical values.  Party P_j holds
 labelled with the party that performs it.
 
 Readings of the paper taken here (each is listed in the design doc):
-* Alg. 1 / Alg. 4 / Alg. 5, P1's line: "2^l - [x]_1" is reduced mod 2^l
+* Alg. 1 / Alg. 4 / Alg. 5, P1's share: 2^l - [x]_1 is reduced mod 2^l
   before the cut, i.e. P1 cuts -[x]_1 mod 2^l (the worked examples of Sec. 1
   and Sec. 5.1 write cut(-[x]_1, .)).
 * Alg. 5 input: k1 low bits and k2 high bits are dropped (the worked example
-  of Sec. 5.1 with k1 = 4, k2 = 1 fixes this; the algorithm's input line has
-  the two words swapped).
-* Alg. 7 step 3 with key bits (Sec. 6.1): window i is trc(x, k_lo+i,
+  of Sec. 5.1 with k1 = 4, k2 = 1 fixes this; the algorithm's statement of
+  its input has the two words swapped).
+* Alg. 7 windows with key bits (Sec. 6.1): window i is trc(x, k_lo+i,
   l-l_x-k_lo-i), i = 0..l_x.
-* Alg. 7 step 4: the constant -1 is added by P0 only; u_{l_x+1} := 0.
-* Alg. 7 step 6-8: r_i and z_i are indexed by the slot after the shuffle;
-  the reshare is w0 += z, w1 -= z with z uniform in Z_p from seed_01.
-* Alg. 7 step 10: P2 shares its bit as (rho, D' - rho) with rho from seed_02.
-* Alg. 7 step 11 and Alg. 8 step 5: P0 adds the public constants (t, de).
+* Alg. 7 adjacent sums: the constant -1 is added by P0 only; u_{l_x+1} := 0.
+* Alg. 7 shuffle, mask and reshare: r_i and z_i are indexed by the slot
+  after the shuffle; the reshare is w0 += z, w1 -= z with z uniform in Z_p
+  from seed_01.
+* Alg. 7 reply: P2 shares its bit as (rho, D' - rho) with rho from seed_02.
+* Alg. 7 unflip and Alg. 8's product: P0 adds the public constants (t, de).
 * Alg. 8: [c]_1 is sent once, in preprocessing; the d-shares are exchanged
   between P0 and P1.
 """
@@ -86,34 +87,34 @@ def _mulmod(a, b, p):
 
 
 def drelu_round1(x0, x1, ell, lx, k_lo, p, t, sigma, r, z):
-    """Alg. 7 steps 1-8 for P0 and P1: the messages [w]_0, [w]_1 (N x n,
+    """Alg. 7 for P0 and P1 up to their first message: the messages [w]_0, [w]_1 (N x n,
     in slot order) that they send to P2."""
     check_drelu(ell, lx, k_lo, p)
     n = lx + 1
     x0, x1 = red(x0, ell), red(x1, ell)
     N = x0.size
     flip = np.asarray(t, dtype=U64).astype(bool)
-    # steps 1-2 (P0, P1): [x] := (-1)^t [x]
+    # flip (P0, P1): [x] := (-1)^t [x]
     a0 = np.where(flip, neg(x0, ell), x0)
     a1 = np.where(flip, neg(x1, ell), x1)
-    # step 3 (P0, P1): u_i = trc(x, k_lo+i, l-l_x-k_lo-i), i = 0..l_x
+    # windows (P0, P1): u_i = trc(x, k_lo+i, l-l_x-k_lo-i), i = 0..l_x
     u0 = np.zeros((N, n + 1), dtype=U64)      # column n is u_{l_x+1} := 0
     u1 = np.zeros((N, n + 1), dtype=U64)
     for i in range(n):
         k1 = k_lo + i
         u0[:, i], u1[:, i] = trunc_det(a0, a1, ell, k1, ell - lx - k1)
-    # step 4: v_i = u_i + u_{i+1} - 1 (P0 subtracts the 1), mod 2^l_x
+    # adjacent sums: v_i = u_i + u_{i+1} - 1 (P0 subtracts the 1), mod 2^l_x
     v0 = red(u0[:, :n] + u0[:, 1:] - U64(1), lx)
     v1 = red(u1[:, :n] + u1[:, 1:], lx)
-    # step 5: Alg. 6 on every v_i
+    # modulo switch: Alg. 6 on every v_i
     s0, s1 = mod_switch(v0, v1, lx, p)
-    # step 6: shuffle with seed_01; slot j receives position sigma[:, j]
+    # shuffle with seed_01; slot j receives position sigma[:, j]
     s0 = np.take_along_axis(s0, sigma, axis=1)
     s1 = np.take_along_axis(s1, sigma, axis=1)
-    # step 7: mask with r_j in Z_p^* (same r for both parties)
+    # mask with r_j in Z_p^* (same r for both parties)
     w0 = _mulmod(s0, r, p)
     w1 = _mulmod(s1, r, p)
-    # step 8: reshare with z_j and send to P2
+    # reshare with z_j and send to P2
     if p < (1 << 32):
         z = np.asarray(z, dtype=U64)
         w0 = (w0 + z) % U64(p)
@@ -125,7 +126,7 @@ def drelu_round1(x0, x1, ell, lx, k_lo, p, t, sigma, r, z):
 
 
 def p2_zero_test(w0, w1, p):
-    """Alg. 7 step 9 (P2): reconstruct w_j and set D' = 1 iff some w_j = 0."""
+    """Alg. 7, P2's zero test: reconstruct w_j and set D' = 1 iff some w_j = 0."""
     if p < (1 << 32):
         w = (np.asarray(w0, dtype=U64) + np.asarray(w1, dtype=U64)) % U64(p)
     else:
@@ -137,10 +138,10 @@ def drelu_core(x0, x1, ell, lx, k_lo, p, t, sigma, r, z, rho):
     """Alg. 7 with the random values passed in.  Returns (y0, y1, w0, w1)."""
     w0, w1 = drelu_round1(x0, x1, ell, lx, k_lo, p, t, sigma, r, z)
     dp = p2_zero_test(w0, w1, p)
-    # step 10 (P2): respond with a fresh sharing of D' in Z_{2^l}
+    # reply (P2): respond with a fresh sharing of D' in Z_{2^l}
     d0 = red(rho, ell)
     d1 = sub(dp, d0, ell)
-    # step 11 (P0, P1): DReLU = D' xor t = t + (1-2t) D'
+    # unflip (P0, P1): DReLU = D' xor t = t + (1-2t) D'
     flip = np.asarray(t, dtype=U64).astype(bool)
     y0 = np.where(flip, sub(U64(1), d0, ell), d0)
     y1 = np.where(flip, neg(d1, ell), d1)
@@ -154,14 +155,14 @@ def relu_core(x0, x1, ell, lx, k_lo, p, t, sigma, r, z, a0, b0, c0, a1, b1):
     x0, x1 = red(x0, ell), red(x1, ell)
     # preprocessing (P2): [c]_1 = ([a]_0 + [a]_1)([b]_0 + [b]_1) - [c]_0
     c1 = sub(mul(add(a0, a1, ell), add(b0, b1, ell), ell), c0, ell)
-    # step 1: Alg. 7 steps 1-8; step 2 (P2): the zero test
+    # Alg. 7 up to the parties' first message, then P2's zero test
     w0, w1 = drelu_round1(x0, x1, ell, lx, k_lo, p, t, sigma, r, z)
     dp = p2_zero_test(w0, w1, p)
-    # step 3 (P2): e = D' - b
+    # P2: e = D' - b
     e = sub(dp, add(b0, b1, ell), ell)
-    # step 4 (P0, P1): d = x - a, reconstructed from both parties' shares
+    # P0, P1: d = x - a, reconstructed from both parties' shares
     d = add(sub(x0, a0, ell), sub(x1, a1, ell), ell)
-    # step 5: [x D'] = de + d[b] + e[a] + [c];  ReLU = t[x] + (1-2t)[x D']
+    # product: [x D'] = de + d[b] + e[a] + [c];  ReLU = t[x] + (1-2t)[x D']
     m0 = add(add(add(mul(d, e, ell), mul(d, b0, ell), ell), mul(e, a0, ell), ell), c0, ell)
     m1 = add(add(mul(d, b1, ell), mul(e, a1, ell), ell), c1, ell)
     flip = np.asarray(t, dtype=U64).astype(bool)

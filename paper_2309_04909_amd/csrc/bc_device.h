@@ -11,7 +11,7 @@
 //      Field64     p < 2^34   l_x = 32; 66-bit products, fp64 quotient
 //  * A pairwise sorting network (Parberry) over the N keys, generated at
 //    compile time, used to turn the per-position random keys into the
-//    shuffle of Alg. 7 step 6 without any dynamically indexed register array.
+//    shuffle of Alg. 7 without any dynamically indexed register array.
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -1,24 +1,26 @@
 // Fused Bicoptor 2.0 DReLU (Alg. 7) and UBL ReLU (Alg. 8) kernel.
 //
-// One thread owns one element and plays P0, P1 and P2 for it:
-//   P0/P1  steps 1-2   flip both shares by the seed_01 bit t
-//          step 3      l_x + 1 windows trc(x, k_lo + i, l - l_x - k_lo - i)
-//          step 4      adjacent sums v_i = u_i + u_{i+1} - 1 (P0 adds the -1)
-//          step 5      modulo switch to Z_p (Alg. 6)
-//          step 6      shuffle: slot s takes the position with the s-th
-//                      smallest seed_01 key (sorting network on 32-bit keys)
-//          step 7-8    mask by r_s in Z_p^*, reshare by +-z_s
-//   P2     step 9      reconstruct every slot, D' = [some slot is 0]
-//          step 10     reshare D' with rho from seed_02 (DReLU)
-//   P0/P1  step 11     unflip: t + (1 - 2t) [D']
-// ReLU replaces steps 10-11 by the Beaver product of Alg. 8 with the
-// triple generated from seed_02 / seed_12 and the unflipped input shares.
+// One thread owns one element and plays P0, P1 and P2 for it, in the order
+// of Alg. 7:
+//   P0/P1  flip     both shares negated when the seed_01 bit t is set
+//          windows  l_x + 1 windows trc(x, k_lo + i, l - l_x - k_lo - i)
+//          sums     adjacent sums v_i = u_i + u_{i+1} - 1 (P0 adds the -1)
+//          switch   modulo switch to Z_p (Alg. 6)
+//          shuffle  slot s takes the position with the s-th smallest
+//                   seed_01 key (sorting network on 32-bit keys)
+//          mask     multiply by r_s in Z_p^*, reshare by +-z_s
+//   P2     test     reconstruct every slot, D' = [some slot is 0]
+//          reply    reshare D' with rho from seed_02 (DReLU)
+//   P0/P1  unflip   t + (1 - 2t) [D']
+// ReLU replaces the reply and the unflip by the Beaver product of Alg. 8
+// with the triple generated from seed_02 / seed_12 and the unflipped input
+// shares.
 //
 // The l_x + 1 window values never leave VGPRs.  Kernels are instantiated per
 // window count N = l_x + 1, so every loop over windows is unrolled.  The shuffle is applied by
 // computing, for slot s, the window of the position the sorted key names:
 // the message in slot s is v_{sigma(s)} r_s + z_s, exactly the shuffled and
-// masked array of steps 6-8.  With a capture pointer the same code also
+// masked array that the shuffle and mask produce.  With a capture pointer the same code also
 // stores both parties' round-1 messages.
 #pragma once
 
@@ -66,7 +68,7 @@ __device__ __forceinline__ FT window(T a, uint32_t pos) {
         return (FT)(a >> pos) & WIN1;
 }
 
-// Steps 3-9 for one slot: the window position `pos` (sigma of the slot), the
+// Windows through P2's reconstruction (Alg. 7) for one slot: the window position `pos` (sigma of the slot), the
 // slot's mask r and reshare z; returns both parties' messages and P2's
 // reconstruction w0 + w1 mod p (the slot is zero when it is 0).
 // a0 and nb1 are P0's share and P1's negated share, both shifted down by k_lo.
@@ -84,17 +86,17 @@ __device__ __forceinline__ typename F::T slot_messages(T a0, T nb1, uint32_t pos
     const FT more = (FT)(int64_t)((int32_t)(pos - (uint32_t)LX) >> 31);   // all ones unless pos = l_x
     const FT u0n = (W0 >> 1) & more;                     // u_{i+1}, and u_{l_x+1} := 0
     const FT u1n = (W1 >> 1) & more;
-    // step 4 and step 5 (Alg. 6) for P0: v0 = u_i + u_{i+1} - 1 in Z_{2^l_x},
+    // adjacent sum and modulo switch (Alg. 6) for P0: v0 = u_i + u_{i+1} - 1 in Z_{2^l_x},
     // s0 = v0, or 2^l_x when v0 = 0, which is ((v0 - 1) mod 2^l_x) + 1.
     const FT s0 = ((W0 + u0n - 2) & WIN) + 1;
     const FT v1 = ((FT)0 - W1 - u1n) & WIN;              // P1: -cut_i - cut_{i+1}
     const FT s1 = v1 + (f.p - TWO_LX);
-    w0 = f.mul_add(s0, r, z);                            // steps 7-8: mask, reshare
+    w0 = f.mul_add(s0, r, z);                            // mask, reshare
     w1 = f.mul_add(s1, r, (FT)(f.p - z));                // P1: s1 r - z
-    return addmod(w0, w1, f);                            // step 9 (P2)
+    return addmod(w0, w1, f);                            // P2 reconstructs
 }
 
-// Step 10-11 (DReLU): P2's fresh sharing (rho, D' - rho), then the unflip.
+// DReLU's end (Alg. 7): P2's fresh sharing (rho, D' - rho), then the unflip.
 template <typename T>
 __device__ __forceinline__ void drelu_finish(T dp, T rho, uint32_t t, T mask, T& y0, T& y1) {
     const T d1 = (T)(dp - rho) & mask;
@@ -102,7 +104,7 @@ __device__ __forceinline__ void drelu_finish(T dp, T rho, uint32_t t, T mask, T&
     y1 = t ? (T)((T)0 - d1) & mask : d1;
 }
 
-// Alg. 8 steps 3-5 with the triple ([a]_j, [b]_j, [c]_j) and the unflipped inputs.
+// Alg. 8 after the zero test: e = D' - b, d = x - a and the product, with the triple ([a]_j, [b]_j, [c]_j) and the unflipped inputs.
 template <typename T>
 __device__ __forceinline__ void relu_finish(T dp, T in0, T in1, T ba0, T bb0, T bc0, T ba1, T bb1, T bc1, uint32_t t,
                                             T mask, T& y0, T& y1) {
@@ -137,7 +139,7 @@ __device__ __forceinline__ void drelu_element(const T* __restrict__ X0, const T*
     const T nr1 = (T)((T)0 - r1) & in_mask;                                          // -x1 in the input ring
     const T in1 = (T)((T)0 - (T)(nr1 >> k_in)) & mask;                              // P1: -cut(-x1, k_in)
 
-    // Steps 1 and 6 (randomness): t and the shuffle keys from seed_01.
+    // The flip bit t and the shuffle keys, both from seed_01.
     const StreamAt r01 = s01.at(g);
     uint32_t key[N];
     uint32_t t = 0;
@@ -152,7 +154,7 @@ __device__ __forceinline__ void drelu_element(const T* __restrict__ X0, const T*
     }
     sort_keys<N>(key);
 
-    // Step 2: [x] := (-1)^t [x]  (both parties).
+    // Flip: [x] := (-1)^t [x]  (both parties).
     const T a0 = t ? (T)((T)0 - in0) & mask : in0;
     const T a1 = t ? (T)((T)0 - in1) & mask : in1;
     const T nb1 = (T)((T)0 - a1) & mask;                  // P1 cuts -[x]_1 mod 2^l
@@ -162,7 +164,7 @@ __device__ __forceinline__ void drelu_element(const T* __restrict__ X0, const T*
     Words4 wm = {0, 0, 0, 0};
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-        // Steps 7-8 randomness of slot j.
+        // Mask r and reshare z of slot j.
         FT r, z;
         if constexpr (WIDE) {
             const Words4 w = r01.block(TAG_MASK, (uint32_t)j);

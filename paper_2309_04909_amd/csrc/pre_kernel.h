@@ -5,7 +5,7 @@
 // P0/P1's flip t, shuffle and masks from seed_01, P2's response share from
 // seed_02, and the Beaver triple of Alg. 8's preprocessing including P2's
 // [c]_1.  The online kernel then streams the shares plus this record and does
-// steps 2-5 and 7-9 and the finish; it reuses the slot arithmetic of the fused
+// flip, windows, sums, modulo switch, mask and zero test and the finish; it reuses the slot arithmetic of the fused
 // kernel, so both give bit-identical results and messages.
 //
 // Record of a call on n elements, structure of arrays (each array [.][n]):
@@ -126,7 +126,7 @@ __global__ BC_KERNEL_ATTRS void k_expand(ExpandKArgs A, F f) {
     }
 }
 
-// Online: Alg. 7 steps 2-5, 7-9 and the finish, reading the record.
+// Online: the input-dependent part of Alg. 7 (and of Alg. 8), reading the record.
 template <typename T, int N, typename F, bool RELU, bool CAP>
 __global__ BC_KERNEL_ATTRS void k_drelu_pre(PreKArgs A, F f_arg) {
     const F f = f_arg.vgpr();

@@ -24,6 +24,7 @@ import glob
 import hashlib
 import json
 import os
+import re
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -41,11 +42,31 @@ KERNELS = {
 COPY_BYTES = 512 << 20          # bench.py copy_reference: 512 MiB read and 512 MiB written per copy
 
 
-def source_hash(names):
+_TOKENS = re.compile(r'"(?:\\.|[^"\\\n])*"|\'(?:\\.|[^\'\\\n])*\'|//[^\n]*|/\*.*?\*/', re.S)
+
+
+def code_text(src: str) -> str:
+    """C++ source with comments removed and whitespace runs collapsed, so that
+    an edit of comments or layout leaves the hash (and the counters it
+    validates) in place."""
+    def keep(m):
+        t = m.group(0)
+        return " " if t.startswith("/") else t
+    return " ".join(_TOKENS.sub(keep, src).split())
+
+
+def source_hash(names, read=None):
+    """Hash of the code (not the comments) of csrc/ files; read(name) -> str
+    overrides reading the working tree."""
     h = hashlib.sha256()
     for nm in names:
-        with open(os.path.join(HERE, "csrc", nm), "rb") as f:
-            h.update(f.read())
+        if read is None:
+            with open(os.path.join(HERE, "csrc", nm), encoding="utf-8") as f:
+                text = f.read()
+        else:
+            text = read(nm)
+        h.update(code_text(text).encode())
+        h.update(b"\0")
     return h.hexdigest()[:16]
 
 

@@ -235,3 +235,16 @@ def test_pseudo_mersenne_table_is_the_default_primes():
     assert len(table) == 34
     for K in range(2, 34):
         assert table[K] == (1 << K) - OP.default_prime(K - 1), K
+
+
+def test_profile_hash_ignores_comments_only():
+    """The counters in profiles/traffic.json stay valid across comment and
+    layout edits of a kernel's sources, and not across code edits."""
+    from paper_2309_04909_amd.prof_summary import code_text, source_hash
+    src = 'int f(int a) { // add one\n  return a + 1; /* "x" */ }\nconst char* s = "a // b";\n'
+    assert code_text(src) == 'int f(int a) { return a + 1; } const char* s = "a // b";'
+    base = source_hash(["x.h"], read=lambda nm: src)
+    assert source_hash(["x.h"], read=lambda nm: src.replace("add one", "increment")) == base
+    assert source_hash(["x.h"], read=lambda nm: src.replace("\n  ", "\n    ")) == base
+    assert source_hash(["x.h"], read=lambda nm: src.replace("a + 1", "a + 2")) != base
+    assert source_hash(["x.h"], read=lambda nm: src.replace('"a // b"', '"a // c"')) != base

@@ -16,7 +16,7 @@ lift y_t = 2^l_x past the window; both ends were found by exhaustive search).
 So outside the key-bit band |x| < 2^k_lo the reconstructed DReLU is the sign
 bit [x > 0], and DReLU(0) = t when k_lo = 0 (the paper leaves it undefined).
 
-Round-1 messages: after masking (step 7) and resharing (step 8) P2 must see
+Round-1 messages: after masking by r and resharing by z P2 must see
 exactly as many zeros as there are zero adjacent sums v_i (zeros are kept,
 non-zeros stay non-zero, Sec. 5.3); the count is predicted from the closed
 form of each window u_i = floor(x_t / 2^(k_lo+i)) + e0_i.  The shuffle and
@@ -223,8 +223,8 @@ def _chi2_ok(counts, dof_sigma=6.0):
 
 def test_zero_slot_uniform_and_masked_values_uniform():
     """For a fixed positive x, P2 sees exactly one zero among n slots; its slot is uniform
-    (step 6 hides the bit position) and the other reconstructed w_j are uniform on
-    Z_p^* (step 7 masks); each single share w0_j is uniform on Z_p (step 8)."""
+    (the shuffle hides the bit position) and the other reconstructed w_j are uniform
+    on Z_p^* (the mask r); each single share w0_j is uniform on Z_p (the reshare z)."""
     ell, lx, k_lo = 64, 7, 0
     p = default_prime(lx)
     n = lx + 1
