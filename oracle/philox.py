@@ -33,6 +33,14 @@ for p > 2^32):
   TAG_RESP (seed_02): rho = (w0 | w1 << 32) mod 2^l of block 0.
   TAG_BEAVER: seed_02 block 0 -> [a]_0 = w0|w1<<32, [b]_0 = w2|w3<<32;
     seed_02 block 1 -> [c]_0 = w0|w1<<32;  seed_12 block 0 -> [a]_1, [b]_1.
+  TAG_RSS (replicated sharing, Alg. drelu2 in the appendix): the 64-bit
+    values V_k = w_{2k} | w_{2k+1} << 32 of the seed_012 stream (word 2k of
+    the stream is word 2k % 4 of block 2k // 4), each reduced mod 2^l:
+      V_0, V_1, V_2 = alpha_0, alpha_1, alpha_2 (the sharing of t),
+      V_3 = [s]_1,
+      V_4, V_5, V_6 = alpha'_0..2 (zero sharing of the product [s][t]),
+      V_7, V_8, V_9 = alpha''_0..2 (zero sharing of the ReLU product);
+    seed_12 block 0: [s]_2 = w0 | w1 << 32;  seed_2 block 0: s = w0 & 1.
 """
 
 import numpy as np
@@ -48,6 +56,7 @@ TAG_SHUFFLE = 1
 TAG_MASK = 2
 TAG_RESP = 3
 TAG_BEAVER = 4
+TAG_RSS = 5
 
 _M32 = U64(0xFFFFFFFF)
 
@@ -136,3 +145,20 @@ def draw_beaver(seed02: int, seed12: int, nonce: int, g, ell: int):
     a1 = red(_u64_pair(b2[0], b2[1]), ell)
     bb1 = red(_u64_pair(b2[2], b2[3]), ell)
     return a0, bb0, c0, a1, bb1
+
+
+def draw_rss(seed012: int, seed12: int, seed2: int, nonce: int, g, ell: int, relu: bool):
+    """The replicated-sharing draws of Alg. drelu2's preprocessing (and of
+    the ReLU's product): a dict with alpha (3 arrays), s1, s2, s (0/1),
+    alpha_st (3) and, for the ReLU, alpha_relu (3)."""
+    g = np.asarray(g, dtype=U64)
+    nv = 10 if relu else 7
+    w = _words(seed012, nonce, g, TAG_RSS, 2 * nv)
+    v = [red(_u64_pair(w[:, 2 * k], w[:, 2 * k + 1]), ell) for k in range(nv)]
+    b12 = block(seed12, nonce, g, TAG_RSS, 0)
+    b2 = block(seed2, nonce, g, TAG_RSS, 0)
+    out = {"alpha": v[0:3], "s1": v[3], "s2": red(_u64_pair(b12[0], b12[1]), ell), "s": b2[0] & U64(1),
+           "alpha_st": v[4:7]}
+    if relu:
+        out["alpha_relu"] = v[7:10]
+    return out

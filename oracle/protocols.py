@@ -21,6 +21,16 @@ Readings of the paper taken here (each is listed in the design doc):
 * Alg. 7 unflip and Alg. 8's product: P0 adds the public constants (t, de).
 * Alg. 8: [c]_1 is sent once, in preprocessing; the d-shares are exchanged
   between P0 and P1.
+* Alg. drelu2 (replicated sharing, appendix): x = [x]_0 + [x]_1 + [x]_2 and
+  P_j holds ([x]_j, [x]_{j+1}), indices mod 3 (the shares each party forms in
+  the preprocessing say so).  Every party draws all three alpha_j from
+  seed_012.  The products [s][t] and, for the ReLU, [x][DReLU(x)] use the
+  replicated-sharing multiplication: P_j forms
+  z_j = u_j v_j + u_j v_{j+1} + u_{j+1} v_j + gamma_j with a zero sharing
+  gamma_j = alpha'_j - alpha'_{j-1} (fresh alphas from seed_012, built like
+  the sharing of t) and sends z_j to P_{j-1}; the product's shares are z_j.
+  The public bit D'' is added to share 0 (held by P0 and P2), and is counted
+  as an l-bit value, as the algorithm reduces it mod 2^l.
 """
 
 import numpy as np
@@ -202,6 +212,104 @@ def relu(x0, x1, ell, lx, k_lo, p, seeds, nonce, elem_base=0, g=None):
     return relu_core(x0, x1, ell, lx, k_lo, p, t, sigma, r, z, a0, b0, c0, a1, b1)
 
 
+# ----------------------------------- replicated secret sharing (Alg. drelu2)
+
+
+def rss_reconstruct(sh, ell):
+    """x = [x]_0 + [x]_1 + [x]_2 mod 2^l."""
+    return add(add(sh[0], sh[1], ell), sh[2], ell)
+
+
+def zero_sharing(alpha, ell):
+    """beta_j = alpha_j - alpha_{j-1} (indices mod 3): three shares of 0, as
+    the preprocessing of Alg. drelu2 builds them from seed_012."""
+    return [sub(alpha[j], alpha[j - 1], ell) for j in range(3)]
+
+
+def rss_mul(u, v, gamma, ell):
+    """[u v] from replicated shares: P_j holds (u_j, u_{j+1}), (v_j, v_{j+1})
+    and forms z_j = u_j v_j + u_j v_{j+1} + u_{j+1} v_j + gamma_j; the nine
+    cross terms u_a v_b each appear once over j = 0, 1, 2, and the gamma_j
+    sum to 0.  P_j sends z_j to P_{j-1}, so that P_j holds (z_j, z_{j+1})."""
+    z = []
+    for j in range(3):
+        k = (j + 1) % 3
+        zj = add(add(mul(u[j], v[j], ell), mul(u[j], v[k], ell), ell), mul(u[k], v[j], ell), ell)
+        z.append(add(zj, gamma[j], ell))
+    return z
+
+
+def rss_preprocess(t, d, ell):
+    """Alg. drelu2 preprocessing, from t (seed_01) and the draws d of
+    ``philox.draw_rss``.  Returns ([t], [s], [s xor t]), each a list of
+    three share arrays."""
+    t = np.asarray(t, dtype=U64)
+    # [t] := (beta_0, beta_1 + t, beta_2) with beta_j = alpha_j - alpha_{j-1}
+    beta = zero_sharing(d["alpha"], ell)
+    ts = [beta[0], add(beta[1], t, ell), beta[2]]
+    # [s]_1 from seed_012, [s]_2 from seed_12; P2 draws the bit s from seed_2
+    # and sends [s]_0 = s - [s]_1 - [s]_2 to P0
+    s0 = sub(sub(red(d["s"], ell), d["s1"], ell), d["s2"], ell)
+    ss = [s0, d["s1"], d["s2"]]
+    # [s xor t] = [s] + [t] - 2 [s][t]
+    st = rss_mul(ss, ts, zero_sharing(d["alpha_st"], ell), ell)
+    sxt = [sub(add(ss[j], ts[j], ell), mul(U64(2), st[j], ell), ell) for j in range(3)]
+    return ts, ss, sxt
+
+
+def rss_drelu_core(x, ell, lx, k_lo, p, t, sigma, r, z, d):
+    """Alg. drelu2 with the random values passed in (t, sigma, r, z as for
+    Alg. 7; d from ``philox.draw_rss``).  x = three share arrays.  Returns
+    (y, w0, w1): y the three shares of DReLU(x), w0, w1 the round-1
+    messages."""
+    x = [red(xi, ell) for xi in x]
+    _, _, sxt = rss_preprocess(t, d, ell)
+    # P0 enters [x]_0 + [x]_1, P1 enters [x]_2; both run Alg. 7 up to their
+    # messages to P2
+    w0, w1 = drelu_round1(add(x[0], x[1], ell), x[2], ell, lx, k_lo, p, t, sigma, r, z)
+    dp = p2_zero_test(w0, w1, p)
+    # P2: D'' = s xor D', sent to P0 and P1
+    dpp = dp ^ np.asarray(d["s"], dtype=U64)
+    # everyone: [DReLU(x)] = D'' + [s xor t] - 2 D'' [s xor t]; the public
+    # D'' goes to share 0
+    y = [sub(sxt[j], mul(U64(2) * dpp, sxt[j], ell), ell) for j in range(3)]
+    y[0] = add(y[0], dpp, ell)
+    return y, w0, w1
+
+
+def rss_relu_core(x, ell, lx, k_lo, p, t, sigma, r, z, d):
+    """RSS ReLU (appendix): Alg. drelu2, then the replicated-sharing product
+    [x][DReLU(x)] with the full-precision x.  Returns (y, w0, w1)."""
+    x = [red(xi, ell) for xi in x]
+    dr, w0, w1 = rss_drelu_core(x, ell, lx, k_lo, p, t, sigma, r, z, d)
+    y = rss_mul(x, dr, zero_sharing(d["alpha_relu"], ell), ell)
+    return y, w0, w1
+
+
+def _rss(x0, x1, x2, ell, lx, k_lo, p, seeds, nonce, elem_base, g, relu):
+    seed01, _, seed12, seed012, seed2 = seeds
+    g = _indices(np.asarray(x0).size, elem_base, g)
+    n = lx + 1
+    t, sigma = philox.draw_shuffle(seed01, nonce, g, n)
+    r, z = philox.draw_masks(seed01, nonce, g, n, p)
+    d = philox.draw_rss(seed012, seed12, seed2, nonce, g, ell, relu)
+    core = rss_relu_core if relu else rss_drelu_core
+    return core((x0, x1, x2), ell, lx, k_lo, p, t, sigma, r, z, d)
+
+
+def rss_drelu(x0, x1, x2, ell, lx, k_lo, p, seeds, nonce, elem_base=0, g=None):
+    """Alg. drelu2 with randomness drawn from the seeds.
+
+    seeds = (seed_01, seed_02, seed_12, seed_012, seed_2) (seed_02 is not
+    drawn from).  Returns (y, w0, w1) with y = [y_0, y_1, y_2]."""
+    return _rss(x0, x1, x2, ell, lx, k_lo, p, seeds, nonce, elem_base, g, False)
+
+
+def rss_relu(x0, x1, x2, ell, lx, k_lo, p, seeds, nonce, elem_base=0, g=None):
+    """RSS ReLU with randomness drawn from the seeds.  Returns (y, w0, w1)."""
+    return _rss(x0, x1, x2, ell, lx, k_lo, p, seeds, nonce, elem_base, g, True)
+
+
 # ------------------------------------------------------ message accounting
 
 LINKS = ("P0->P2", "P1->P2", "P2->P0", "P2->P1", "P0->P1", "P1->P0")
@@ -221,4 +329,11 @@ def msg_bits(op: str, ell: int, lx: int, p: int):
         return [wbits, wbits, ell, ell, 0, 0], 2
     if op == "relu":
         return [wbits, wbits, ell, 2 * ell, ell, ell], 2
+    # Alg. drelu2: preprocessing sends [s]_0 (P2->P0) and the reshared z_j of
+    # [s][t] (P0->P2, P1->P0, P2->P1); online, round 1 as Alg. 7 and D'' from
+    # P2 to P0 and P1.  The RSS ReLU adds one more product: a third round.
+    if op == "rss_drelu":
+        return [wbits + ell, wbits, 2 * ell, 2 * ell, 0, ell], 2
+    if op == "rss_relu":
+        return [wbits + 2 * ell, wbits, 2 * ell, 3 * ell, 0, 2 * ell], 3
     raise ValueError(op)
