@@ -49,8 +49,10 @@ extern "C" {
 #define BC_ERR_WORKSPACE  -7  /* workspace / plan buffer too small               */
 #define BC_ERR_ARG        -8  /* other invalid argument (op, n, index range)     */
 
-#define BC_OP_DRELU 0u
-#define BC_OP_RELU  1u
+#define BC_OP_DRELU     0u
+#define BC_OP_RELU      1u
+#define BC_OP_RSS_DRELU 2u   /* replicated sharing, Alg. drelu2 */
+#define BC_OP_RSS_RELU  3u
 
 /* DReLU/ReLU setting (Alg. 7 "Setting" plus the key-bit window of Sec. 6.1).
  *   ell  : ring bit length l, shares in Z_{2^l}, 1..64
@@ -77,6 +79,18 @@ typedef struct {
     uint64_t seed12;
     uint64_t nonce;
 } bc_seeds;
+
+/* Seeds of the replicated-sharing calls (the Setting of Alg. drelu2): the
+ * fields of bc_seeds, then seed012 of all three parties and seed2 of P2
+ * alone.  seed02 is not drawn from by these calls. */
+typedef struct {
+    uint64_t seed01;
+    uint64_t seed02;
+    uint64_t seed12;
+    uint64_t nonce;
+    uint64_t seed012;
+    uint64_t seed2;
+} bc_rss_seeds;
 
 /* Links, in this order: P0->P2, P1->P2, P2->P0, P2->P1, P0->P1, P1->P0. */
 #define BC_NLINKS 6
@@ -124,11 +138,14 @@ int bc_keybit_params(uint32_t ell, uint32_t f, uint32_t int_bits, uint32_t frac_
  * |x| < 2^k_lo).  Host only. */
 uint32_t bc_keybit_int_bits(uint64_t bound, uint32_t f);
 
-/* Message accounting for one call of `op` (BC_OP_DRELU / BC_OP_RELU) on n
- * elements.  Round 1: each of P0, P1 sends l_x + 1 values of Z_p, i.e.
- * (l_x+1)^2 bits per element (Tab. 1, Sec. 5.4).  DReLU round 2: one
- * Z_{2^l} share to each of P0 and P1 (P2's reply).  ReLU (Alg. 8): e to P0 and
- * P1, [c]_1 to P1 (preprocessing), d-shares between P0 and P1.  Host only. */
+/* Message accounting for one call of `op` (BC_OP_*) on n elements.
+ * Round 1: each of P0, P1 sends l_x + 1 values of Z_p, i.e. (l_x+1)^2 bits
+ * per element (Tab. 1, Sec. 5.4).  DReLU round 2: one Z_{2^l} share to each
+ * of P0 and P1 (P2's reply).  ReLU (Alg. 8): e to P0 and P1, [c]_1 to P1
+ * (preprocessing), d-shares between P0 and P1.  RSS DReLU (Alg. drelu2):
+ * round 1 as above; D'' (l bits) to P0 and P1; preprocessing [s]_0 to P0 and
+ * the reshare of [s][t] on P0->P2, P1->P0, P2->P1.  RSS ReLU: one more such
+ * reshare, in a third round.  Host only. */
 int bc_msg_account(uint32_t op, const bc_drelu_params* prm, uint64_t n, bc_msg_acct* acct);
 
 /* Raw Philox4x32-10 blocks, for checking the generator.  Writes
@@ -250,6 +267,38 @@ int bc_trunc_drelu(const void* x0, const void* x1, void* y0, void* y1, uint64_t 
 int bc_trunc_relu(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, uint32_t ell_in, uint32_t k1,
                   const bc_drelu_params* prm, const bc_seeds* seeds, uint64_t elem_base, void* capture,
                   bc_msg_acct* acct, void* stream);
+
+/* ------------------------------------------- replicated sharing (RSS) */
+
+/* Bicoptor 2.0 DReLU over replicated shares, Alg. drelu2 (appendix), all
+ * three parties in one kernel.
+ * In  : x0, x1, x2 -- the shares [x]_0, [x]_1, [x]_2 of x in Z_{2^ell}
+ *       (x = x0 + x1 + x2); P_j holds ([x]_j, [x]_{j+1}), indices mod 3.
+ * Out : y0, y1, y2 -- the three shares of DReLU(x) in Z_{2^ell}.  The bit is
+ *       the one bc_drelu gives for the 2-of-2 input ([x]_0 + [x]_1, [x]_2)
+ *       with the same seed01 and nonce (P0 enters [x]_0 + [x]_1, P1 enters
+ *       [x]_2); P2 replies with D'' = s xor D', and the shares are those of
+ *       D'' xor s xor t, with D'' added to share 0.
+ * Randomness: t, the shuffle, r_i and z_i from seed01 exactly as bc_drelu;
+ *       from seed012 the alphas of [t] = (a0 - a2, a1 - a0 + t, a2 - a1),
+ *       [s]_1 and the zero sharing of the product [s][t]; [s]_2 from seed12;
+ *       P2's bit s from seed2 (tag 5 of the counter layout of bc_prg_blocks).
+ * capture: NULL, or the round-1 messages of P0 and P1, laid out as for
+ *       bc_drelu.
+ * acct: NULL, or receives bc_msg_account(BC_OP_RSS_DRELU, prm, n).
+ * y_j may equal x_j.  Other conventions as bc_drelu. */
+int bc_rss_drelu(const void* x0, const void* x1, const void* x2, void* y0, void* y1, void* y2, uint64_t n,
+                 const bc_drelu_params* prm, const bc_rss_seeds* seeds, uint64_t elem_base, void* capture,
+                 bc_msg_acct* acct, void* stream);
+
+/* ReLU over replicated shares (appendix): bc_rss_drelu, then the
+ * replicated-sharing product of [x] (full precision) and [DReLU(x)]: P_j
+ * forms u_j v_j + u_j v_{j+1} + u_{j+1} v_j plus a zero share from seed012.
+ * Outputs are the three shares of x DReLU(x).  Arguments as bc_rss_drelu;
+ * acct receives bc_msg_account(BC_OP_RSS_RELU, prm, n). */
+int bc_rss_relu(const void* x0, const void* x1, const void* x2, void* y0, void* y1, void* y2, uint64_t n,
+                const bc_drelu_params* prm, const bc_rss_seeds* seeds, uint64_t elem_base, void* capture,
+                bc_msg_acct* acct, void* stream);
 
 /* ------------------------------------------ precomputed randomness */
 

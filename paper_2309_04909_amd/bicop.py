@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libbicop.so")
 
 BC_OP_DRELU = 0
 BC_OP_RELU = 1
+BC_OP_RSS_DRELU = 2
+BC_OP_RSS_RELU = 3
 LINKS = ("P0->P2", "P1->P2", "P2->P0", "P2->P1", "P0->P1", "P1->P0")
 
 
@@ -36,6 +38,11 @@ class _Params(ctypes.Structure):
 class _Seeds(ctypes.Structure):
     _fields_ = [("seed01", ctypes.c_uint64), ("seed02", ctypes.c_uint64), ("seed12", ctypes.c_uint64),
                 ("nonce", ctypes.c_uint64)]
+
+
+class _RssSeeds(ctypes.Structure):
+    _fields_ = [("seed01", ctypes.c_uint64), ("seed02", ctypes.c_uint64), ("seed12", ctypes.c_uint64),
+                ("nonce", ctypes.c_uint64), ("seed012", ctypes.c_uint64), ("seed2", ctypes.c_uint64)]
 
 
 class _Acct(ctypes.Structure):
@@ -71,6 +78,10 @@ _SIGS = {
                   ctypes.POINTER(_Acct), _P], ctypes.c_int),
     "bc_relu": ([_P, _P, _P, _P, _U64, ctypes.POINTER(_Params), ctypes.POINTER(_Seeds), _U64, _P,
                  ctypes.POINTER(_Acct), _P], ctypes.c_int),
+    "bc_rss_drelu": ([_P, _P, _P, _P, _P, _P, _U64, ctypes.POINTER(_Params), ctypes.POINTER(_RssSeeds), _U64, _P,
+                      ctypes.POINTER(_Acct), _P], ctypes.c_int),
+    "bc_rss_relu": ([_P, _P, _P, _P, _P, _P, _U64, ctypes.POINTER(_Params), ctypes.POINTER(_RssSeeds), _U64, _P,
+                     ctypes.POINTER(_Acct), _P], ctypes.c_int),
     "bc_batch_plan_bytes": ([_U32], _U64),
     "bc_batch_plan": ([ctypes.POINTER(_Segment), _U32, ctypes.POINTER(_Params), _U32, _P, _U64], ctypes.c_int),
     "bc_batch_run": ([_P, _P, ctypes.POINTER(_Seeds), _U32, _P], ctypes.c_int),
@@ -177,6 +188,26 @@ class Seeds:
         if s is None:
             m = (1 << 64) - 1
             s = self.__dict__["_c"] = _Seeds(self.seed01 & m, self.seed02 & m, self.seed12 & m, self.nonce & m)
+        return s
+
+
+@dataclass(frozen=True)
+class RssSeeds:
+    """Seeds of the replicated-sharing calls: those of Seeds, plus seed012
+    (all three parties) and seed2 (P2 alone)."""
+    seed01: int
+    seed02: int
+    seed12: int
+    seed012: int
+    seed2: int
+    nonce: int = 0
+
+    def c(self):
+        s = self.__dict__.get("_c")
+        if s is None:
+            m = (1 << 64) - 1
+            s = self.__dict__["_c"] = _RssSeeds(self.seed01 & m, self.seed02 & m, self.seed12 & m, self.nonce & m,
+                                                self.seed012 & m, self.seed2 & m)
         return s
 
 
@@ -315,6 +346,33 @@ def drelu(x0, x1, params: Params, seeds: Seeds, elem_base=0, capture=False, out=
 def relu(x0, x1, params: Params, seeds: Seeds, elem_base=0, capture=False, out=None, stream=None):
     """Alg. 8.  Returns (y0, y1) or (y0, y1, capture[2, n, lx+1])."""
     return _drelu_like(lib.bc_relu, "relu", x0, x1, params, seeds, elem_base, capture, out, stream)
+
+
+def _rss_like(fn, name, x, params, seeds, elem_base, capture, out, stream):
+    if len(x) != 3:
+        raise ValueError("replicated sharing takes three share arrays")
+    w = ring_width(params.ell)
+    _check_shares(x[0], x[1], w)
+    _check_shares(x[1], x[2], w)
+    y = [_out(x[j], w, ring_dtype(params.ell), None if out is None else out[j]) for j in range(3)]
+    cap = None
+    if capture:
+        cap = torch.empty((2, x[0].numel(), params.npos), dtype=field_dtype(params.resolved().p), device=x[0].device)
+    _check(fn(x[0].data_ptr(), x[1].data_ptr(), x[2].data_ptr(), y[0].data_ptr(), y[1].data_ptr(), y[2].data_ptr(),
+              x[0].numel(), ctypes.byref(params.c()), ctypes.byref(seeds.c()), elem_base,
+              None if cap is None else cap.data_ptr(), None, _stream(stream, x[0])), name)
+    return (tuple(y), cap) if capture else tuple(y)
+
+
+def rss_drelu(x, params: Params, seeds: RssSeeds, elem_base=0, capture=False, out=None, stream=None):
+    """Alg. drelu2 on replicated shares x = (x0, x1, x2).  Returns (y0, y1, y2),
+    or ((y0, y1, y2), capture[2, n, lx+1])."""
+    return _rss_like(lib.bc_rss_drelu, "rss_drelu", x, params, seeds, elem_base, capture, out, stream)
+
+
+def rss_relu(x, params: Params, seeds: RssSeeds, elem_base=0, capture=False, out=None, stream=None):
+    """RSS ReLU (appendix) on replicated shares x = (x0, x1, x2)."""
+    return _rss_like(lib.bc_rss_relu, "rss_relu", x, params, seeds, elem_base, capture, out, stream)
 
 
 def _trunc_like(fn, name, x0, x1, ell_in, k1, params, seeds, elem_base, capture, out, stream):

@@ -134,6 +134,19 @@ int account(uint32_t op, const bc_drelu_params& r, uint64_t n, bc_msg_acct* a) {
         a->stored_bytes[4] = a->stored_bytes[5] = rbytes * n;
     }
     a->rounds = 2;
+    if (op == BC_OP_RSS_DRELU || op == BC_OP_RSS_RELU) {
+        // links 2, 3 already carry D''; P2 also sends [s]_0 to P0.  Every
+        // product of replicated shares ([s][t], and the ReLU's) reshares z_j
+        // from P_j to P_{j-1}: P0->P2, P1->P0, P2->P1.
+        const uint64_t prods = op == BC_OP_RSS_RELU ? 2 : 1;
+        a->bits[2] += (uint64_t)r.ell * n;
+        a->stored_bytes[2] += rbytes * n;
+        for (int l : {0, 5, 3}) {
+            a->bits[l] += prods * r.ell * n;
+            a->stored_bytes[l] += prods * rbytes * n;
+        }
+        if (op == BC_OP_RSS_RELU) a->rounds = 3;
+    }
     return BC_OK;
 }
 
@@ -234,6 +247,56 @@ int drelu_common(uint32_t op, const void* x0, const void* x1, void* y0, void* y1
         e = relu ? bc::launch_relu_u32(L, st) : bc::launch_drelu_u32(L, st);
     }
     if (e != hipSuccess) return hip_fail(e, op == BC_OP_RELU ? "relu launch" : "drelu launch");
+    return BC_OK;
+}
+
+int rss_common(bool relu, const void* x0, const void* x1, const void* x2, void* y0, void* y1, void* y2, uint64_t n,
+               const bc_drelu_params* prm, const bc_rss_seeds* seeds, uint64_t elem_base, void* capture,
+               bc_msg_acct* acct, void* stream) {
+    bc_drelu_params r;
+    int rc = check_params(prm, &r);
+    if (rc) return rc;
+    if (!seeds) return fail(BC_ERR_NULL, "seeds is NULL");
+    if (elem_base > kMaxIndex || n > kMaxIndex - elem_base)
+        return fail(BC_ERR_ARG, "element indices must stay below 2^48");
+    if (acct) account(relu ? BC_OP_RSS_RELU : BC_OP_RSS_DRELU, r, n, acct);
+    if (n == 0) return BC_OK;
+    if (!x0 || !x1 || !x2 || !y0 || !y1 || !y2) return fail(BC_ERR_NULL, "share pointer is NULL");
+    const uint32_t w = width_of_ring(r.ell);
+    if (!aligned(x0, w) || !aligned(x1, w) || !aligned(x2, w) || !aligned(y0, w) || !aligned(y1, w) ||
+        !aligned(y2, w))
+        return fail(BC_ERR_ALIGN, "share pointers must be %u-byte aligned", w);
+    if (capture && !aligned(capture, r.p < (1ull << 32) ? 4 : 8))
+        return fail(BC_ERR_ALIGN, "capture buffer misaligned");
+    bc::RssLaunch L;
+    L.x0 = x0;
+    L.x1 = x1;
+    L.x2 = x2;
+    L.y0 = y0;
+    L.y1 = y1;
+    L.y2 = y2;
+    L.cap = capture;
+    L.n = n;
+    L.elem_base = elem_base;
+    L.p = r.p;
+    L.ell = r.ell;
+    L.lx = r.lx;
+    L.k_lo = r.k_lo;
+    L.npos = r.lx + 1;
+    L.relu = relu;
+    L.s01 = stream_key(seeds->seed01, seeds->nonce);
+    L.s12 = stream_key(seeds->seed12, seeds->nonce);
+    L.s012 = stream_key(seeds->seed012, seeds->nonce);
+    L.s2 = stream_key(seeds->seed2, seeds->nonce);
+    L.grid = (int)sched_grid(BC_SCHED_FUSED, L.npos, (n + 255) / 256);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if (r.ell > 32)
+        e = L.npos <= 12 ? bc::launch_rss_u64_lo(L, st)
+                         : (L.npos <= 24 ? bc::launch_rss_u64_mid(L, st) : bc::launch_rss_u64_hi(L, st));
+    else
+        e = bc::launch_rss_u32(L, st);
+    if (e != hipSuccess) return hip_fail(e, relu ? "rss relu launch" : "rss drelu launch");
     return BC_OK;
 }
 
@@ -454,7 +517,7 @@ uint32_t bc_keybit_int_bits(uint64_t bound, uint32_t f) {
 
 int bc_msg_account(uint32_t op, const bc_drelu_params* prm, uint64_t n, bc_msg_acct* acct) {
     if (!acct) return fail(BC_ERR_NULL, "acct is NULL");
-    if (op != BC_OP_DRELU && op != BC_OP_RELU) return fail(BC_ERR_ARG, "unknown op %u", op);
+    if (op > BC_OP_RSS_RELU) return fail(BC_ERR_ARG, "unknown op %u", op);
     bc_drelu_params r;
     int rc = check_params(prm, &r);
     if (rc) return rc;
@@ -587,6 +650,18 @@ int bc_trunc_relu(const void* x0, const void* x1, void* y0, void* y1, uint64_t n
                   bc_msg_acct* acct, void* stream) {
     if (k1 == 0) return fail(BC_ERR_RING, "k1 must be > 0 (use bc_relu)");
     return drelu_common(BC_OP_RELU, x0, x1, y0, y1, n, prm, seeds, elem_base, capture, acct, stream, ell_in, k1);
+}
+
+int bc_rss_drelu(const void* x0, const void* x1, const void* x2, void* y0, void* y1, void* y2, uint64_t n,
+                 const bc_drelu_params* prm, const bc_rss_seeds* seeds, uint64_t elem_base, void* capture,
+                 bc_msg_acct* acct, void* stream) {
+    return rss_common(false, x0, x1, x2, y0, y1, y2, n, prm, seeds, elem_base, capture, acct, stream);
+}
+
+int bc_rss_relu(const void* x0, const void* x1, const void* x2, void* y0, void* y1, void* y2, uint64_t n,
+                const bc_drelu_params* prm, const bc_rss_seeds* seeds, uint64_t elem_base, void* capture,
+                bc_msg_acct* acct, void* stream) {
+    return rss_common(true, x0, x1, x2, y0, y1, y2, n, prm, seeds, elem_base, capture, acct, stream);
 }
 
 int bc_relu(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, const bc_drelu_params* prm,

@@ -116,28 +116,18 @@ __device__ __forceinline__ void relu_finish(T dp, T in0, T in1, T ba0, T bb0, T 
     y1 = t ? (T)(in1 - m1) & mask : m1;
 }
 
-// One element, all three parties.  N = l_x + 1 windows, fixed at compile
-// time: every loop over windows and slots is unrolled and all window masks
-// are constants.  Reads X0[e], X1[e], writes Y0[e], Y1[e]; the randomness
-// belongs to global index g.  With CAP, the round-1 messages go to
-// cap[e * N + slot] (P0) and cap[(ncap + e) * N + slot] (P1).  With k_in > 0
-// the inputs are shares of Z_{2^(l + k_in)} (in_mask) and are first truncated
-// by k_in bits into Z_{2^l} (Alg. 5); with k_in = 0 and in_mask = mask the
-// same expressions are the plain load.
-template <typename T, int N, typename F, bool RELU, bool CAP>
-__device__ __forceinline__ void drelu_element(const T* __restrict__ X0, const T* __restrict__ X1, T* Y0, T* Y1,
-                                              typename F::T* cap, uint64_t ncap, uint64_t e, uint64_t g, T mask,
-                                              T in_mask, uint32_t k_in, uint32_t k_lo, const Stream& s01,
-                                              const Stream& s02, const Stream& s12, const F& f) {
+// Alg. 7 from the flip through P2's zero test for one element: the 2-of-2
+// input (in0, in1) of Z_{2^l}, randomness of global index g.  Returns D'
+// (1 when some slot reconstructs to 0) and the flip bit t.  With CAP the
+// round-1 messages go to cap[e * N + slot] (P0) and cap[(ncap + e) * N +
+// slot] (P1).
+template <typename T, int N, typename F, bool CAP>
+__device__ __forceinline__ T drelu_round1(T in0, T in1, uint64_t g, T mask, uint32_t k_lo, const Stream& s01,
+                                          typename F::T* cap, uint64_t ncap, uint64_t e, const F& f,
+                                          uint32_t& t_out) {
     using FT = typename F::T;
     constexpr bool WIDE = std::is_same<FT, uint64_t>::value;
     static_assert(WIDE == (N == 33), "64-bit field elements exactly when l_x = 32");
-
-    const T r0 = X0[e] & in_mask;
-    const T r1 = X1[e] & in_mask;
-    const T in0 = (T)(r0 >> k_in) & mask;                                           // P0: cut(x0, k_in)
-    const T nr1 = (T)((T)0 - r1) & in_mask;                                          // -x1 in the input ring
-    const T in1 = (T)((T)0 - (T)(nr1 >> k_in)) & mask;                              // P1: -cut(-x1, k_in)
 
     // The flip bit t and the shuffle keys, both from seed_01.
     const StreamAt r01 = s01.at(g);
@@ -183,7 +173,30 @@ __device__ __forceinline__ void drelu_element(const T* __restrict__ X0, const T*
             cap[(ncap + e) * N + j] = w1;
         }
     }
-    const T dp = least == 0 ? 1 : 0;                       // D' = [some slot is 0]
+    t_out = t;
+    return least == 0 ? 1 : 0;                             // D' = [some slot is 0]
+}
+
+// One element, all three parties.  N = l_x + 1 windows, fixed at compile
+// time: every loop over windows and slots is unrolled and all window masks
+// are constants.  Reads X0[e], X1[e], writes Y0[e], Y1[e]; the randomness
+// belongs to global index g.  With CAP, the round-1 messages are captured
+// (drelu_round1).  With k_in > 0 the inputs are shares of Z_{2^(l + k_in)}
+// (in_mask) and are first truncated by k_in bits into Z_{2^l} (Alg. 5); with
+// k_in = 0 and in_mask = mask the same expressions are the plain load.
+template <typename T, int N, typename F, bool RELU, bool CAP>
+__device__ __forceinline__ void drelu_element(const T* __restrict__ X0, const T* __restrict__ X1, T* Y0, T* Y1,
+                                              typename F::T* cap, uint64_t ncap, uint64_t e, uint64_t g, T mask,
+                                              T in_mask, uint32_t k_in, uint32_t k_lo, const Stream& s01,
+                                              const Stream& s02, const Stream& s12, const F& f) {
+    const T r0 = X0[e] & in_mask;
+    const T r1 = X1[e] & in_mask;
+    const T in0 = (T)(r0 >> k_in) & mask;                                           // P0: cut(x0, k_in)
+    const T nr1 = (T)((T)0 - r1) & in_mask;                                          // -x1 in the input ring
+    const T in1 = (T)((T)0 - (T)(nr1 >> k_in)) & mask;                              // P1: -cut(-x1, k_in)
+
+    uint32_t t;
+    const T dp = drelu_round1<T, N, F, CAP>(in0, in1, g, mask, k_lo, s01, cap, ncap, e, f, t);
 
     T y0, y1;
     if constexpr (!RELU) {

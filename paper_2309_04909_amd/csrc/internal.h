@@ -96,6 +96,27 @@ inline RandOffsets rand_offsets(uint32_t npos, bool relu, uint32_t ring_width, u
     return o;
 }
 
+// Fully validated replicated-sharing DReLU/ReLU launch (Alg. drelu2).
+struct RssLaunch {
+    const void* x0;
+    const void* x1;
+    const void* x2;
+    void* y0;
+    void* y1;
+    void* y2;
+    void* cap;
+    uint64_t n, elem_base, p;
+    uint32_t ell, lx, k_lo, npos;
+    bool relu;
+    StreamKey s01, s12, s012, s2;
+    int grid;
+};
+
+hipError_t launch_rss_u64_lo(const RssLaunch& L, hipStream_t st);    // N 2..12
+hipError_t launch_rss_u64_mid(const RssLaunch& L, hipStream_t st);   // N 13..24
+hipError_t launch_rss_u64_hi(const RssLaunch& L, hipStream_t st);    // N 25..33
+hipError_t launch_rss_u32(const RssLaunch& L, hipStream_t st);       // N 2..17
+
 // Elementwise Z_p multiply-add with the kernels' field arithmetic (diagnostic).
 struct ZpLaunch {
     const uint64_t* a;

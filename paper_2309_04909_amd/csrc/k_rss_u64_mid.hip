@@ -1,0 +1,12 @@
+// Instantiations of the replicated-sharing DReLU / ReLU kernel (Alg. drelu2)
+// for 64-bit share storage, one kernel per window count N = l_x + 1 in
+// [13, 24].
+#include "rss_kernel.h"
+
+namespace bc {
+
+hipError_t launch_rss_u64_mid(const RssLaunch& L, hipStream_t st) {
+    return launch_rss_range<uint64_t, 13, 24>(L, st);
+}
+
+}  // namespace bc

@@ -66,17 +66,22 @@ def test_check_params_rejects_like_oracle():
             OP.check_drelu(ell, lx, k, p or (OP.default_prime(lx) if 1 <= lx <= 32 else 3))
 
 
-@pytest.mark.parametrize("op", ["drelu", "relu"])
+@pytest.mark.parametrize("op", ["drelu", "relu", "rss_drelu", "rss_relu"])
 @pytest.mark.parametrize("ell,lx,k", [(64, 7, 11), (64, 18, 13), (64, 31, 0), (64, 32, 0), (24, 7, 10)])
 def test_msg_account_matches_oracle(op, ell, lx, k):
     from paper_2309_04909_amd import bicop as B
     n = 1000
-    a = B.msg_account(B.BC_OP_DRELU if op == "drelu" else B.BC_OP_RELU, B.Params(ell, lx, k), n)
+    code = {"drelu": B.BC_OP_DRELU, "relu": B.BC_OP_RELU, "rss_drelu": B.BC_OP_RSS_DRELU,
+            "rss_relu": B.BC_OP_RSS_RELU}[op]
+    a = B.msg_account(code, B.Params(ell, lx, k), n)
     bits, rounds = OPR.msg_bits(op, ell, lx, OP.default_prime(lx))
     assert [a["bits"][l] for l in B.LINKS] == [b * n for b in bits]
     assert a["rounds"] == rounds
     wbytes = 4 if OP.default_prime(lx) < (1 << 32) else 8
-    assert a["stored_bytes"]["P0->P2"] == (lx + 1) * wbytes * n
+    assert a["stored_bytes"]["P1->P2"] == (lx + 1) * wbytes * n
+    rbytes = 4 if ell <= 32 else 8
+    for link in B.LINKS[2:]:
+        assert a["stored_bytes"][link] * ell == a["bits"][link] * rbytes
 
 
 def test_tab1_row_through_the_abi():
@@ -248,3 +253,24 @@ def test_profile_hash_ignores_comments_only():
     assert source_hash(["x.h"], read=lambda nm: src.replace("\n  ", "\n    ")) == base
     assert source_hash(["x.h"], read=lambda nm: src.replace("a + 1", "a + 2")) != base
     assert source_hash(["x.h"], read=lambda nm: src.replace('"a // b"', '"a // c"')) != base
+
+
+def test_rss_error_paths_without_gpu():
+    """The replicated-sharing calls validate on the host like bc_drelu: every
+    call below fails validation (or has n = 0), so nothing is launched."""
+    from paper_2309_04909_amd import bicop as B
+    L = B.lib
+    prm, sd = B.Params(64, 7, 11).c(), B.RssSeeds(1, 2, 3, 4, 5, 6).c()
+    for fn in (L.bc_rss_drelu, L.bc_rss_relu):
+        args = lambda n, prm=prm, sd=sd, base=0: (None, None, None, None, None, None, n, ctypes.byref(prm),
+                                                   sd if sd is None else ctypes.byref(sd), base, None, None, None)
+        assert fn(*args(10)) == -1                                   # NULL shares
+        assert fn(*args(0)) == 0                                      # n = 0
+        assert fn(*args(10, sd=None)) == -1                           # NULL seeds
+        assert fn(*args(10, prm=B.Params(64, 40, 0).c())) == -3       # window too wide
+        assert fn(*args(10, prm=B.Params(64, 7, 0, 255).c())) == -4   # not prime
+        assert fn(*args(10, base=(1 << 48) - 5)) == -8                # indices past 2^48
+        acct = B._Acct()
+        assert fn(None, None, None, None, None, None, 0, ctypes.byref(prm), ctypes.byref(sd), 0, None,
+                  ctypes.byref(acct), None) == 0
+    assert L.bc_msg_account(4, ctypes.byref(prm), 1, ctypes.byref(B._Acct())) == -8

@@ -63,6 +63,20 @@ def share(x, ell: int, rng: np.random.Generator):
     return x0.astype(dt), x1.astype(dt)
 
 
+def share3(x, ell: int, rng: np.random.Generator):
+    """Replicated (2-of-3) sharing: x = x0 + x1 + x2 mod 2^l with x0, x1
+    uniform.  Returns (x0, x1, x2) in the storage dtype of the ring."""
+    x = np.asarray(x, dtype=U64)
+    a = rng.bit_generator.random_raw(x.size).astype(U64).reshape(x.shape)
+    b = rng.bit_generator.random_raw(x.size).astype(U64).reshape(x.shape)
+    c = x - a - b
+    if ell < 64:
+        m = U64((1 << ell) - 1)
+        a, b, c = a & m, b & m, c & m
+    dt = storage_dtype(ell)
+    return a.astype(dt), b.astype(dt), c.astype(dt)
+
+
 def signed_values(x, ell: int) -> np.ndarray:
     """Signed int64 view of canonical ring elements (ell <= 64)."""
     x = np.asarray(x, dtype=U64)
