@@ -15,8 +15,13 @@ Printed as one JSON line (rank 0), with extra sections:
   roofline          the dominant kernel (the fused DReLU) against its ALU roofline
   cpu_baseline      the CPU oracle timed on a bounded sample of the same workload
   batched_vs_plain  ResNet-18 ragged ReLU: one persistent graph launch vs 17 launches
-  serving           continuous-batching request loop: p50/p99 latency and Gelem/s
+  precomputed_randomness  offline seed expansion, online call on shares + record
+  replicated_sharing      RSS DReLU / ReLU (Alg. drelu2) beside the 2-of-2 calls
   plain_drelu       l = 64 without key bits (l_x = 32), 65,536 elements: us per call
+  serving           continuous-batching request loop: p50/p99 latency and Gelem/s
+  matmul_relu       truncate-then-ReLU of a 4096 x 4096 . 4096 x 1024 product
+  batch_sweep       latency floor to throughput plateau over batch sizes
+  copy_reference    a plain copy: achievable HBM bandwidth, counter scaling
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--sections ...]
 """
@@ -73,14 +78,19 @@ PHILOX_OPS = 60          # 10 rounds x (two 32x32->64 multiplies + four XORs)
 SLOT_OPS = 40            # per slot: two windows, adjacent sums, mod switch, two draws,
                          # two masked products with reshare, P2's sum and zero test
 SLOT_OPS_WIDE = 64       # same with 64-bit field elements (l_x = 32)
-TAIL_OPS = {"drelu": 12, "relu": 40}
+TAIL_OPS = {"drelu": 12, "relu": 40,
+            # replicated sharing at l = 64: [t], [s], the zero sharing, the product [s][t]
+            # (two 64-bit multiplies per share), [s xor t], the finish; the ReLU adds a product
+            "rss_drelu": 100, "rss_relu": 160}
+# Philox blocks per element beyond the shuffle keys and the masks
+TAIL_BLOCKS = {"drelu": 1, "relu": 3, "rss_drelu": 6, "rss_relu": 7}
 
 
 def alg_ops_per_elem(op: str, lx: int) -> int:
     """32-bit integer operations per element of the fused kernel (the model in the design doc)."""
     n = lx + 1
     wide = lx == 32
-    blocks = (n + 3) // 4 + (n if wide else (n + 1) // 2) + (1 if op == "drelu" else 3)
+    blocks = (n + 3) // 4 + (n if wide else (n + 1) // 2) + TAIL_BLOCKS[op]
     return (blocks * PHILOX_OPS + n * (SLOT_OPS_WIDE if wide else SLOT_OPS) + 2 * batcher_comparators(n)
             + TAIL_OPS[op])
 
@@ -460,6 +470,36 @@ def run_precomputed(torch, B, inputs, steps, warmup):
     return out
 
 
+def run_rss(torch, B, inputs, steps, warmup):
+    """Replicated-sharing DReLU / ReLU (Alg. drelu2) on the 2^24 key-bit values,
+    shared as ([x]_0 - a, a, [x]_1) with a uniform, at the key-bit setting
+    (l_x = 18) and at l_x = 7; the 2-of-2 call on the same values beside it."""
+    x0, x1 = inputs[0], inputs[1]
+    n = x0.size
+    a = np.random.default_rng(31).integers(0, 1 << 63, size=n, dtype=np.uint64) * np.uint64(2)
+    xs = tuple(to_dev(torch, v) for v in (x0 - a, a, x1))
+    u0, u1 = to_dev(torch, x0), to_dev(torch, x1)
+    out = {"workload": f"{n} key-bit values in Z_2^64 as replicated shares; 48 B/elem algorithmic "
+                       "(three shares in, three out)"}
+    sd, sd2 = B.RssSeeds(*SEEDS, 0x5EED012, 0x5EED2, 41), B.Seeds(*SEEDS, 41)
+    ys = tuple(torch.empty_like(v) for v in xs)
+    y0, y1 = torch.empty_like(u0), torch.empty_like(u1)
+    for name, prm in (("lx18", B.Params(64, 18, 13)), ("lx7", B.Params(64, 7, 11))):
+        for op in ("drelu", "relu"):
+            rss = B.rss_drelu if op == "drelu" else B.rss_relu
+            ubl = B.drelu if op == "drelu" else B.relu
+            ms = _event_ms(torch, lambda: rss(xs, prm, sd, out=ys), steps, warmup)
+            ms_ubl = _event_ms(torch, lambda: ubl(u0, u1, prm, sd2, out=(y0, y1)), steps, warmup)
+            ops = alg_ops_per_elem("rss_" + op, prm.lx)
+            tops = ops * n / (ms * 1e-3) / 1e12
+            out[f"{op}_{name}"] = {"ms": round(ms, 4), "gelem_s": round(n / ms / 1e6, 3),
+                                   "gbs": round(48 * n / ms / 1e6, 1),
+                                   "hbm_frac": round(48 * n / ms / 1e6 / HBM_PEAK_GBS, 4),
+                                   "ops_per_elem": ops, "alu_frac": round(tops / VALU_PEAK_TOPS, 4),
+                                   "two_of_two_ms": round(ms_ubl, 4)}
+    return out
+
+
 def run_copy(torch, steps, warmup, mib=512):
     """A plain device-to-device copy of known size: the reference for achievable
     HBM bandwidth and for scaling rocprofv3's FETCH_SIZE / WRITE_SIZE counters."""
@@ -490,9 +530,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--sections", default="cpu,batched,precomputed,plain,serving,copy,matmul,sweep",
-                    help="comma list of extra sections: cpu, batched, precomputed, plain, serving, copy, matmul, "
-                         "sweep")
+    ap.add_argument("--sections", default="cpu,batched,precomputed,rss,plain,serving,copy,matmul,sweep",
+                    help="comma list of extra sections: cpu, batched, precomputed, rss, plain, serving, copy, "
+                         "matmul, sweep")
     ap.add_argument("--cpu-sample", type=int, default=1 << 24)
     ap.add_argument("--cpu-workers", type=int, default=min(16, os.cpu_count() or 1))
     args = ap.parse_args()
@@ -546,6 +586,7 @@ def main():
     progress(f"headline: {value:.3f} Gelem/s, {ms_step:.4f} ms per step")
     runs = [("batched", "batched_vs_plain", lambda: run_batched_vs_plain(torch, B, max(3, args.steps // 5), 2)),
             ("precomputed", "precomputed_randomness", lambda: run_precomputed(torch, B, inputs, 10, 2)),
+            ("rss", "replicated_sharing", lambda: run_rss(torch, B, inputs, 20, 5)),
             ("plain", "plain_drelu", lambda: run_plain_drelu(torch, B, args.steps, args.warmup)),
             ("serving", "serving", lambda: run_serving(torch, B)),
             ("matmul", "matmul_relu", lambda: run_matmul_relu(torch, B, args.steps, args.warmup)),

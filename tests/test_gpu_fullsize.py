@@ -157,3 +157,32 @@ def test_resnet18_ragged_batch_73859072(B):
         idx = sample_indices(x.size, rng, k=300)
         o0, o1, _, _ = OPR.relu(x0[idx], x1[idx], 64, 7, 11, 251, SEEDS, 100 + i, g=idx.astype(U64))
         assert np.array_equal(y0[idx], o0) and np.array_equal(y1[idx], o1), f"segment {i}"
+
+
+@pytest.mark.parametrize("lx,k_lo", [(18, 13), (7, 11)])
+def test_rss_keybit_2p24(B, lx, k_lo):
+    """Replicated-sharing DReLU / ReLU on the 2^24 key-bit values, shared as
+    bench.py shares them: the DReLU property on every element, the ReLU
+    identity x DReLU(x) on every element, the oracle on samples."""
+    x, (x0, x1), _, _ = W.keybit_drelu(seed=2, n=1 << 24)
+    n = x.size
+    a = np.random.default_rng(31).integers(0, 1 << 63, size=n, dtype=np.uint64) * U64(2)
+    xs = (x0 - a, a, x1)
+    d = tuple(dev(v) for v in xs)
+    seeds5 = SEEDS + (0x5EED012, 0x5EED2)
+    prm, sd = B.Params(64, lx, k_lo), B.RssSeeds(*seeds5, 41)
+    yd = [host(t) for t in B.rss_drelu(d, prm, sd)]
+    yr = [host(t) for t in B.rss_relu(d, prm, sd)]
+    del d
+    xi = signed(x, 64)
+    dr = yd[0] + yd[1] + yd[2]
+    if lx == 18:
+        check_drelu_property(dr, xi, k_lo)
+    else:
+        # |x| < 2^30 exceeds this window's guard domain: only the bit property is fixed
+        assert np.all((dr == 0) | (dr == 1))
+    assert np.array_equal(yr[0] + yr[1] + yr[2], x * dr)
+    idx = sample_indices(n, np.random.default_rng(9), k=1500)
+    e, _, _ = OPR.rss_relu(*(v[idx] for v in xs), 64, lx, k_lo, default_prime(lx), seeds5, 41, g=idx.astype(U64))
+    for j in range(3):
+        assert np.array_equal(yr[j][idx], e[j])
