@@ -41,6 +41,8 @@ for p > 2^32):
       V_4, V_5, V_6 = alpha'_0..2 (zero sharing of the product [s][t]),
       V_7, V_8, V_9 = alpha''_0..2 (zero sharing of the ReLU product);
     seed_12 block 0: [s]_2 = w0 | w1 << 32;  seed_2 block 0: s = w0 & 1.
+  TAG_MUL (the Beaver triple of an elementwise product, Alg. linear): the
+    layout of TAG_BEAVER under its own tag.
 """
 
 import numpy as np
@@ -57,6 +59,7 @@ TAG_MASK = 2
 TAG_RESP = 3
 TAG_BEAVER = 4
 TAG_RSS = 5
+TAG_MUL = 6
 
 _M32 = U64(0xFFFFFFFF)
 
@@ -134,11 +137,11 @@ def draw_rho(seed02: int, nonce: int, g, ell: int):
     return red(_u64_pair(b[0], b[1]), ell)
 
 
-def draw_beaver(seed02: int, seed12: int, nonce: int, g, ell: int):
+def draw_beaver(seed02: int, seed12: int, nonce: int, g, ell: int, tag: int = TAG_BEAVER):
     """([a]_0, [b]_0, [c]_0) from seed_02 and ([a]_1, [b]_1) from seed_12."""
-    b0 = block(seed02, nonce, g, TAG_BEAVER, 0)
-    b1 = block(seed02, nonce, g, TAG_BEAVER, 1)
-    b2 = block(seed12, nonce, g, TAG_BEAVER, 0)
+    b0 = block(seed02, nonce, g, tag, 0)
+    b1 = block(seed02, nonce, g, tag, 1)
+    b2 = block(seed12, nonce, g, tag, 0)
     a0 = red(_u64_pair(b0[0], b0[1]), ell)
     bb0 = red(_u64_pair(b0[2], b0[3]), ell)
     c0 = red(_u64_pair(b1[0], b1[1]), ell)

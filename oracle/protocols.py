@@ -21,6 +21,11 @@ Readings of the paper taken here (each is listed in the design doc):
 * Alg. 7 unflip and Alg. 8's product: P0 adds the public constants (t, de).
 * Alg. 8: [c]_1 is sent once, in preprocessing; the d-shares are exchanged
   between P0 and P1.
+* Alg. linear (truncate-then-multiply): the truncation is Alg. 1; with an
+  odd f the first factor drops floor(f/2) bits and the second ceil(f/2).
+  The product is a Beaver multiplication with the triple dealt as in
+  Alg. 8's preprocessing ([a]_0, [b]_0, [c]_0 from seed_02, [a]_1, [b]_1
+  from seed_12, [c]_1 formed by P2), under its own stream tag.
 * Alg. drelu2 (replicated sharing, appendix): x = [x]_0 + [x]_1 + [x]_2 and
   P_j holds ([x]_j, [x]_{j+1}), indices mod 3 (the shares each party forms in
   the preprocessing say so).  Every party draws all three alpha_j from
@@ -210,6 +215,47 @@ def relu(x0, x1, ell, lx, k_lo, p, seeds, nonce, elem_base=0, g=None):
     r, z = philox.draw_masks(seed01, nonce, g, n, p)
     a0, b0, c0, a1, b1 = philox.draw_beaver(seed02, seed12, nonce, g, ell)
     return relu_core(x0, x1, ell, lx, k_lo, p, t, sigma, r, z, a0, b0, c0, a1, b1)
+
+
+# -------------------------------------- truncate-then-multiply (Alg. linear)
+
+TRUNC_NONE, TRUNC_AFTER, TRUNC_BEFORE = 0, 1, 2
+
+
+def beaver_mul(x0, x1, y0, y1, ell, a0, b0, c0, a1, b1):
+    """[x y] from 2-of-2 shares and a Beaver triple.  P2 forms
+    [c]_1 = (a0 + a1)(b0 + b1) - c0 and sends it to P1; P0 and P1 open
+    d = x - a and e = y - b; [xy]_0 = de + d[b]_0 + e[a]_0 + [c]_0 and
+    [xy]_1 = d[b]_1 + e[a]_1 + [c]_1."""
+    c1 = sub(mul(add(a0, a1, ell), add(b0, b1, ell), ell), c0, ell)
+    d = add(sub(x0, a0, ell), sub(x1, a1, ell), ell)
+    e = add(sub(y0, b0, ell), sub(y1, b1, ell), ell)
+    z0 = add(add(add(mul(d, e, ell), mul(d, b0, ell), ell), mul(e, a0, ell), ell), c0, ell)
+    z1 = add(add(mul(d, b1, ell), mul(e, a1, ell), ell), c1, ell)
+    return z0, z1
+
+
+def mul_trunc_core(x0, x1, y0, y1, ell, f, order, a0, b0, c0, a1, b1):
+    """The product of two shared values with f fractional bits dropped:
+    order TRUNC_BEFORE is Alg. linear (Alg. 1 on x by floor(f/2) bits and on
+    y by ceil(f/2), then the product); TRUNC_AFTER multiplies, then applies
+    Alg. 1 by f; TRUNC_NONE (f = 0) is the plain product."""
+    x0, x1, y0, y1 = (red(v, ell) for v in (x0, x1, y0, y1))
+    if order == TRUNC_BEFORE:
+        x0, x1 = trunc_prob(x0, x1, ell, f // 2)
+        y0, y1 = trunc_prob(y0, y1, ell, f - f // 2)
+    z0, z1 = beaver_mul(x0, x1, y0, y1, ell, a0, b0, c0, a1, b1)
+    if order == TRUNC_AFTER:
+        z0, z1 = trunc_prob(z0, z1, ell, f)
+    return z0, z1
+
+
+def mul_trunc(x0, x1, y0, y1, ell, f, order, seeds, nonce, elem_base=0, g=None):
+    """``mul_trunc_core`` with the triple drawn from the seeds (seed_02,
+    seed_12 of seeds = (seed_01, seed_02, seed_12, ...))."""
+    g = _indices(np.asarray(x0).size, elem_base, g)
+    a0, b0, c0, a1, b1 = philox.draw_beaver(seeds[1], seeds[2], nonce, g, ell, tag=philox.TAG_MUL)
+    return mul_trunc_core(x0, x1, y0, y1, ell, f, order, a0, b0, c0, a1, b1)
 
 
 # ----------------------------------- replicated secret sharing (Alg. drelu2)

@@ -59,3 +59,18 @@ def expected_zero_count(x, Rp, t, ell, lx, k_lo):
         u.append(0)
         out.append(sum(1 for i in range(lx + 1) if (u[i] + u[i + 1] - 1) % m == 0))
     return np.array(out)
+
+
+def expected_trunc_prob(x, R, ell, k):
+    """Reconstruction of Alg. 1 (SecureML) on x shared as (x + R, -R): the
+    exact form floor(sgn(x) / 2^k) + e0 + 2^(l-k) ([x < 0] - [x + R >= 2^l])
+    mod 2^l, with e0 = [(x mod 2^k) + (R mod 2^k) >= 2^k] and x, R canonical.
+    The last term is e1.  Python ints, per element."""
+    out = []
+    for xv, rv in zip(x.tolist(), R.tolist()):
+        xs = xv - (1 << ell) if xv >> (ell - 1) else xv
+        lo = (1 << k) - 1
+        e0 = ((xv & lo) + (rv & lo)) >> k
+        wrap = (xv + rv) >> ell
+        out.append(((xs >> k) + e0 + (1 << (ell - k)) * ((xv >> (ell - 1)) - wrap)) % (1 << ell))
+    return np.array(out, dtype=object)
