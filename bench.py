@@ -17,6 +17,7 @@ Printed as one JSON line (rank 0), with extra sections:
   batched_vs_plain  ResNet-18 ragged ReLU: one persistent graph launch vs 17 launches
   precomputed_randomness  offline seed expansion, online call on shares + record
   replicated_sharing      RSS DReLU / ReLU (Alg. drelu2) beside the 2-of-2 calls
+  truncate_then_multiply  Alg. linear vs multiply-then-truncate: time and e1 counts
   plain_drelu       l = 64 without key bits (l_x = 32), 65,536 elements: us per call
   serving           continuous-batching request loop: p50/p99 latency and Gelem/s
   matmul_relu       truncate-then-ReLU of a 4096 x 4096 . 4096 x 1024 product
@@ -500,6 +501,39 @@ def run_rss(torch, B, inputs, steps, warmup):
     return out
 
 
+def run_linear(torch, B, steps, warmup):
+    """Alg. linear against multiply-then-truncate: the elementwise secure product
+    of 2^24 pairs of 31-bit fixed-point values (5 + 26 bits, the l = 64 setting
+    of Sec. 4) in Z_2^64, truncated by f = 26.  Times each order (48 B/elem
+    algorithmic: four input shares, two output shares) and counts the elements
+    whose result is off by more than 2^32 from floor(x y / 2^26): the e1 failures
+    (an e1 adds about 2^(64-26); e0 and the truncate-first order's lost precision
+    stay below 2^20)."""
+    (x, (x0, x1)), (y, (y0, y1)) = W.linear_factors(seed=5)
+    n = x.size
+    d = [to_dev(torch, v) for v in (x0, x1, y0, y1)]
+    z0, z1 = torch.empty_like(d[0]), torch.empty_like(d[1])
+    sd = B.Seeds(*SEEDS, 77)
+    xs, ys = W.signed_values(x, 64).astype(np.int64), W.signed_values(y, 64).astype(np.int64)
+    exact = (xs * ys) >> 26
+    rate = float(np.mean(np.abs(xs.astype(np.float64) * ys.astype(np.float64)))) / 2.0 ** 64
+    out = {"workload": f"{n} products of 31-bit fixed-point factors (f = 26) in Z_2^64; 48 B/elem algorithmic",
+           "expected_e1_rate_after": round(rate, 5)}
+    for name, order, f in (("none", B.BC_TRUNC_NONE, 0), ("after", B.BC_TRUNC_AFTER, 26),
+                           ("before", B.BC_TRUNC_BEFORE, 26)):
+        ms = _event_ms(torch, lambda: B.mul_trunc(*d, 64, f, order, sd, out=(z0, z1)), steps, warmup)
+        r = {"ms": round(ms, 4), "gelem_s": round(n / ms / 1e6, 2), "gbs": round(48 * n / ms / 1e6, 1),
+             "hbm_frac": round(48 * n / ms / 1e6 / HBM_PEAK_GBS, 4)}
+        if f:
+            got = (z0.cpu().numpy().view(np.uint64) + z1.cpu().numpy().view(np.uint64)).view(np.int64)
+            err = np.abs(got - exact)
+            e1 = err > (1 << 32)
+            r["e1_failures"] = int(np.count_nonzero(e1))
+            r["max_error_without_e1"] = int(err[~e1].max())
+        out[name] = r
+    return out
+
+
 def run_copy(torch, steps, warmup, mib=512):
     """A plain device-to-device copy of known size: the reference for achievable
     HBM bandwidth and for scaling rocprofv3's FETCH_SIZE / WRITE_SIZE counters."""
@@ -530,9 +564,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--sections", default="cpu,batched,precomputed,rss,plain,serving,copy,matmul,sweep",
-                    help="comma list of extra sections: cpu, batched, precomputed, rss, plain, serving, copy, "
-                         "matmul, sweep")
+    ap.add_argument("--sections", default="cpu,batched,precomputed,rss,linear,plain,serving,copy,matmul,sweep",
+                    help="comma list of extra sections: cpu, batched, precomputed, rss, linear, plain, serving, "
+                         "copy, matmul, sweep")
     ap.add_argument("--cpu-sample", type=int, default=1 << 24)
     ap.add_argument("--cpu-workers", type=int, default=min(16, os.cpu_count() or 1))
     args = ap.parse_args()
@@ -587,6 +621,7 @@ def main():
     runs = [("batched", "batched_vs_plain", lambda: run_batched_vs_plain(torch, B, max(3, args.steps // 5), 2)),
             ("precomputed", "precomputed_randomness", lambda: run_precomputed(torch, B, inputs, 10, 2)),
             ("rss", "replicated_sharing", lambda: run_rss(torch, B, inputs, 20, 5)),
+            ("linear", "truncate_then_multiply", lambda: run_linear(torch, B, 20, 5)),
             ("plain", "plain_drelu", lambda: run_plain_drelu(torch, B, args.steps, args.warmup)),
             ("serving", "serving", lambda: run_serving(torch, B)),
             ("matmul", "matmul_relu", lambda: run_matmul_relu(torch, B, args.steps, args.warmup)),

@@ -268,6 +268,30 @@ int bc_trunc_relu(const void* x0, const void* x1, void* y0, void* y1, uint64_t n
                   const bc_drelu_params* prm, const bc_seeds* seeds, uint64_t elem_base, void* capture,
                   bc_msg_acct* acct, void* stream);
 
+/* ------------------------------------------------ multiply and truncate */
+
+#define BC_TRUNC_NONE   0u   /* the plain product (f must be 0)                  */
+#define BC_TRUNC_AFTER  1u   /* multiply, then Alg. 1 on the product by f bits   */
+#define BC_TRUNC_BEFORE 2u   /* Alg. linear: Alg. 1 on x by floor(f/2) bits and
+                                on y by ceil(f/2) bits, then multiply            */
+
+/* Elementwise product of 2-of-2 shares with the SecureML truncation (Alg. 1)
+ * before the product (truncate-then-multiply, Alg. linear, Sec. 4) or after
+ * it (multiply-then-truncate), all three parties in one kernel.
+ * In  : x0, x1, y0, y1 -- n shares of x and of y in Z_{2^ell}.
+ * Out : z0, z1 -- n shares in Z_{2^ell} of trc(x, f/2) trc(y, f/2)
+ *       (BEFORE), trc(x y, f) (AFTER) or x y (NONE), each truncation with
+ *       the e0 and e1 of Alg. 1 for its shares.
+ * The multiplication uses a Beaver triple: [a]_0, [b]_0, [c]_0 from seed02,
+ * [a]_1, [b]_1 from seed12 (tag 6, the block layout of bc_relu's triple),
+ * [c]_1 = (a0 + a1)(b0 + b1) - c0 formed by P2; d = x - a and e = y - b are
+ * opened between P0 and P1.
+ * ell in [1, 64]; f < ell (AFTER), ceil(f/2) < ell (BEFORE), f = 0 (NONE).
+ * z may equal x or y (in place).  Other conventions as bc_drelu; seed01 is
+ * not drawn from. */
+int bc_mul_trunc(const void* x0, const void* x1, const void* y0, const void* y1, void* z0, void* z1, uint64_t n,
+                 uint32_t ell, uint32_t f, uint32_t order, const bc_seeds* seeds, uint64_t elem_base, void* stream);
+
 /* ------------------------------------------- replicated sharing (RSS) */
 
 /* Bicoptor 2.0 DReLU over replicated shares, Alg. drelu2 (appendix), all

@@ -21,6 +21,7 @@ BC_OP_DRELU = 0
 BC_OP_RELU = 1
 BC_OP_RSS_DRELU = 2
 BC_OP_RSS_RELU = 3
+BC_TRUNC_NONE, BC_TRUNC_AFTER, BC_TRUNC_BEFORE = 0, 1, 2
 LINKS = ("P0->P2", "P1->P2", "P2->P0", "P2->P1", "P0->P1", "P1->P0")
 
 
@@ -78,6 +79,7 @@ _SIGS = {
                   ctypes.POINTER(_Acct), _P], ctypes.c_int),
     "bc_relu": ([_P, _P, _P, _P, _U64, ctypes.POINTER(_Params), ctypes.POINTER(_Seeds), _U64, _P,
                  ctypes.POINTER(_Acct), _P], ctypes.c_int),
+    "bc_mul_trunc": ([_P, _P, _P, _P, _P, _P, _U64, _U32, _U32, _U32, ctypes.POINTER(_Seeds), _U64, _P], ctypes.c_int),
     "bc_rss_drelu": ([_P, _P, _P, _P, _P, _P, _U64, ctypes.POINTER(_Params), ctypes.POINTER(_RssSeeds), _U64, _P,
                       ctypes.POINTER(_Acct), _P], ctypes.c_int),
     "bc_rss_relu": ([_P, _P, _P, _P, _P, _P, _U64, ctypes.POINTER(_Params), ctypes.POINTER(_RssSeeds), _U64, _P,
@@ -346,6 +348,24 @@ def drelu(x0, x1, params: Params, seeds: Seeds, elem_base=0, capture=False, out=
 def relu(x0, x1, params: Params, seeds: Seeds, elem_base=0, capture=False, out=None, stream=None):
     """Alg. 8.  Returns (y0, y1) or (y0, y1, capture[2, n, lx+1])."""
     return _drelu_like(lib.bc_relu, "relu", x0, x1, params, seeds, elem_base, capture, out, stream)
+
+
+def mul_trunc(x0, x1, y0, y1, ell, f, order, seeds: Seeds, elem_base=0, out=None, stream=None):
+    """Elementwise product of shares with Alg. 1 truncation: order BC_TRUNC_BEFORE
+    is Alg. linear (factors by floor(f/2) and ceil(f/2) bits first),
+    BC_TRUNC_AFTER truncates the product by f, BC_TRUNC_NONE (f = 0) is the
+    plain product.  Returns (z0, z1) in Z_{2^ell}."""
+    w = ring_width(ell)
+    _check_shares(x0, x1, w)
+    _check_shares(y0, y1, w)
+    if y0.numel() != x0.numel():
+        raise ValueError("x and y differ in length")
+    z0 = _out(x0, w, ring_dtype(ell), None if out is None else out[0])
+    z1 = _out(x1, w, ring_dtype(ell), None if out is None else out[1])
+    _check(lib.bc_mul_trunc(x0.data_ptr(), x1.data_ptr(), y0.data_ptr(), y1.data_ptr(), z0.data_ptr(), z1.data_ptr(),
+                            x0.numel(), ell, f, order, ctypes.byref(seeds.c()), elem_base, _stream(stream, x0)),
+           "mul_trunc")
+    return z0, z1
 
 
 def _rss_like(fn, name, x, params, seeds, elem_base, capture, out, stream):

@@ -652,6 +652,48 @@ int bc_trunc_relu(const void* x0, const void* x1, void* y0, void* y1, uint64_t n
     return drelu_common(BC_OP_RELU, x0, x1, y0, y1, n, prm, seeds, elem_base, capture, acct, stream, ell_in, k1);
 }
 
+int bc_mul_trunc(const void* x0, const void* x1, const void* y0, const void* y1, void* z0, void* z1, uint64_t n,
+                 uint32_t ell, uint32_t f, uint32_t order, const bc_seeds* seeds, uint64_t elem_base, void* stream) {
+    if (ell < 1 || ell > 64) return fail(BC_ERR_RING, "ell = %u outside [1, 64]", ell);
+    bc::MulLaunch L;
+    L.kx = L.ky = L.kz = 0;
+    if (order == BC_TRUNC_NONE) {
+        if (f) return fail(BC_ERR_ARG, "f must be 0 without truncation");
+    } else if (order == BC_TRUNC_AFTER) {
+        if (f >= ell) return fail(BC_ERR_RING, "f = %u must be below ell = %u", f, ell);
+        L.kz = f;
+    } else if (order == BC_TRUNC_BEFORE) {
+        if (f - f / 2 >= ell) return fail(BC_ERR_RING, "ceil(f/2) = %u must be below ell = %u", f - f / 2, ell);
+        L.kx = f / 2;
+        L.ky = f - f / 2;
+    } else {
+        return fail(BC_ERR_ARG, "unknown truncation order %u", order);
+    }
+    if (!seeds) return fail(BC_ERR_NULL, "seeds is NULL");
+    if (elem_base > kMaxIndex || n > kMaxIndex - elem_base)
+        return fail(BC_ERR_ARG, "element indices must stay below 2^48");
+    if (n == 0) return BC_OK;
+    if (!x0 || !x1 || !y0 || !y1 || !z0 || !z1) return fail(BC_ERR_NULL, "share pointer is NULL");
+    const uint32_t w = width_of_ring(ell);
+    if (!aligned(x0, w) || !aligned(x1, w) || !aligned(y0, w) || !aligned(y1, w) || !aligned(z0, w) ||
+        !aligned(z1, w))
+        return fail(BC_ERR_ALIGN, "share pointers must be %u-byte aligned", w);
+    L.x0 = x0;
+    L.x1 = x1;
+    L.y0 = y0;
+    L.y1 = y1;
+    L.z0 = z0;
+    L.z1 = z1;
+    L.n = n;
+    L.elem_base = elem_base;
+    L.ell = ell;
+    L.s02 = stream_key(seeds->seed02, seeds->nonce);
+    L.s12 = stream_key(seeds->seed12, seeds->nonce);
+    L.grid_cap = (int)sched_grid(BC_SCHED_STREAM, 0, ~0ull);
+    hipError_t e = bc::launch_mul(L, (hipStream_t)stream);
+    return e == hipSuccess ? BC_OK : hip_fail(e, "mul launch");
+}
+
 int bc_rss_drelu(const void* x0, const void* x1, const void* x2, void* y0, void* y1, void* y2, uint64_t n,
                  const bc_drelu_params* prm, const bc_rss_seeds* seeds, uint64_t elem_base, void* capture,
                  bc_msg_acct* acct, void* stream) {

@@ -37,6 +37,7 @@ constexpr uint32_t TAG_MASK = 2;
 constexpr uint32_t TAG_RESP = 3;
 constexpr uint32_t TAG_BEAVER = 4;
 constexpr uint32_t TAG_RSS = 5;      // replicated-sharing preprocessing (Alg. drelu2)
+constexpr uint32_t TAG_MUL = 6;      // Beaver triple of the elementwise product (Alg. linear)
 
 struct Words4 {
     uint32_t w0, w1, w2, w3;

@@ -117,6 +117,22 @@ hipError_t launch_rss_u64_mid(const RssLaunch& L, hipStream_t st);   // N 13..24
 hipError_t launch_rss_u64_hi(const RssLaunch& L, hipStream_t st);    // N 25..33
 hipError_t launch_rss_u32(const RssLaunch& L, hipStream_t st);       // N 2..17
 
+// Validated elementwise product with truncation (Alg. linear / multiply-then-truncate).
+struct MulLaunch {
+    const void* x0;
+    const void* x1;
+    const void* y0;
+    const void* y1;
+    void* z0;
+    void* z1;
+    uint64_t n, elem_base;
+    uint32_t ell, kx, ky, kz;   // Alg. 1 shifts of the factors (kx, ky) and of the product (kz)
+    StreamKey s02, s12;
+    int grid_cap;
+};
+
+hipError_t launch_mul(const MulLaunch& L, hipStream_t st);
+
 // Elementwise Z_p multiply-add with the kernels' field arithmetic (diagnostic).
 struct ZpLaunch {
     const uint64_t* a;

@@ -274,3 +274,27 @@ def test_rss_error_paths_without_gpu():
         assert fn(None, None, None, None, None, None, 0, ctypes.byref(prm), ctypes.byref(sd), 0, None,
                   ctypes.byref(acct), None) == 0
     assert L.bc_msg_account(4, ctypes.byref(prm), 1, ctypes.byref(B._Acct())) == -8
+
+
+def test_mul_trunc_error_paths_without_gpu():
+    """bc_mul_trunc validates ring, order, f, seeds and indices on the host."""
+    from paper_2309_04909_amd import bicop as B
+    L = B.lib
+    sd = B.Seeds(1, 2, 3, 4).c()
+    N = None
+
+    def call(n=10, ell=64, f=26, order=B.BC_TRUNC_BEFORE, seeds=sd, base=0):
+        return L.bc_mul_trunc(N, N, N, N, N, N, n, ell, f, order, None if seeds is None else ctypes.byref(seeds),
+                              base, N)
+    assert call() == -1                                  # NULL shares
+    assert call(n=0) == 0
+    assert call(ell=0) == -2 and call(ell=65) == -2
+    assert call(order=B.BC_TRUNC_NONE) == -8             # f must be 0 without truncation
+    assert call(order=B.BC_TRUNC_NONE, f=0) == -1
+    assert call(order=B.BC_TRUNC_AFTER, f=64) == -2      # f >= ell
+    assert call(order=B.BC_TRUNC_AFTER, ell=8, f=7) == -1
+    assert call(order=B.BC_TRUNC_BEFORE, ell=8, f=15) == -2   # ceil(15/2) = 8 >= ell
+    assert call(order=B.BC_TRUNC_BEFORE, ell=8, f=14) == -1
+    assert call(order=3) == -8
+    assert call(seeds=None) == -1
+    assert call(base=(1 << 48) - 5) == -8

@@ -147,6 +147,20 @@ RESNET18_SHAPES = (
 )
 
 
+def linear_factors(seed: int = 5, n: int = 1 << 24, f: int = 26, int_bits: int = 5, ell: int = 64):
+    """Two tensors of fixed-point factors for one secure multiplication:
+    values uniform over the whole domain of int_bits integer and f fractional
+    bits (|x| < 2^(int_bits + f), 31 bits at the defaults, the l = 64 setting
+    of Sec. 4), each shared 2-of-2.  Returns ((x, (x0, x1)), (y, (y0, y1)))."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(2):
+        v = rng.integers(-(1 << (int_bits + f)) + 1, 1 << (int_bits + f), size=n)
+        x = encode(v, ell)
+        out.append((x, share(x, ell, rng)))
+    return tuple(out)
+
+
 def resnet18_sizes(batch: int = 32):
     return [batch * c * h * w for (c, h, w) in RESNET18_SHAPES]
 
