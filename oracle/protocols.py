@@ -217,6 +217,78 @@ def relu(x0, x1, ell, lx, k_lo, p, seeds, nonce, elem_base=0, g=None):
     return relu_core(x0, x1, ell, lx, k_lo, p, t, sigma, r, z, a0, b0, c0, a1, b1)
 
 
+# ------------------------------- parties apart: packed round-1 messages (Alg. 7)
+
+
+def msg_words(npos: int) -> int:
+    """32-bit words per element of one party's packed round-1 message: npos
+    slots of npos bits each (p has npos = l_x + 1 bits), rounded up."""
+    return (npos * npos + 31) // 32
+
+
+def pack_messages(w, npos: int):
+    """Bit-pack one party's messages (N x npos values < 2^npos, slot order):
+    bit b of slot s is bit s * npos + b of the element's bit string, and word
+    k holds its bits 32k .. 32k + 31.  Returns uint32 words, word-major:
+    out[k, i] is word k of element i."""
+    w = np.asarray(w, dtype=object)
+    N = w.shape[0]
+    out = np.zeros((msg_words(npos), N), dtype=object)
+    for s in range(npos):
+        for b in range(npos):
+            pos = s * npos + b
+            out[pos // 32] += ((w[:, s] >> b) & 1) << (pos % 32)
+    return out.astype(np.uint32)
+
+
+def unpack_messages(words, npos: int):
+    """Inverse of ``pack_messages``: N x npos slot values (Python ints)."""
+    words = np.asarray(words, dtype=np.uint32).astype(object)
+    N = words.shape[1]
+    w = np.zeros((N, npos), dtype=object)
+    for s in range(npos):
+        for b in range(npos):
+            pos = s * npos + b
+            w[:, s] += ((words[pos // 32] >> (pos % 32)) & 1) << b
+    return w
+
+
+def drelu_send(party, xj, ell, lx, k_lo, p, seeds, nonce, elem_base=0, g=None):
+    """P0's or P1's part of Alg. 7's first round with its own share only: the
+    packed message it sends to P2.  Every step before P2 is share-local, so
+    the other party's share does not enter; it is passed to drelu_round1 as
+    zero and that party's output is dropped."""
+    xj = np.asarray(xj, dtype=U64)
+    g = _indices(xj.size, elem_base, g)
+    n = lx + 1
+    t, sigma = philox.draw_shuffle(seeds[0], nonce, g, n)
+    r, z = philox.draw_masks(seeds[0], nonce, g, n, p)
+    zero = np.zeros_like(xj)
+    w0, w1 = drelu_round1(xj if party == 0 else zero, xj if party == 1 else zero, ell, lx, k_lo, p, t, sigma, r, z)
+    return pack_messages(w0 if party == 0 else w1, n)
+
+
+def drelu_reply(words0, words1, ell, lx, p, seeds, nonce, elem_base=0, g=None):
+    """P2: unpack both messages, D' = [some slot reconstructs to 0], and the
+    reply shares (rho, D' - rho) of Z_{2^l} for P0 and P1."""
+    w0, w1 = unpack_messages(words0, lx + 1), unpack_messages(words1, lx + 1)
+    g = _indices(w0.shape[0], elem_base, g)
+    dp = p2_zero_test(w0, w1, p)
+    rho = philox.draw_rho(seeds[1], nonce, g, ell)
+    return rho, sub(dp, rho, ell)
+
+
+def drelu_finish(party, dj, ell, lx, seeds, nonce, elem_base=0, g=None):
+    """P0 or P1 unflips its reply share: P0 t + (1 - 2t) d0, P1 (1 - 2t) d1."""
+    dj = np.asarray(dj, dtype=U64)
+    g = _indices(dj.size, elem_base, g)
+    t, _ = philox.draw_shuffle(seeds[0], nonce, g, lx + 1)
+    flip = t.astype(bool)
+    if party == 0:
+        return np.where(flip, sub(U64(1), dj, ell), red(dj, ell))
+    return np.where(flip, neg(dj, ell), red(dj, ell))
+
+
 # -------------------------------------- truncate-then-multiply (Alg. linear)
 
 TRUNC_NONE, TRUNC_AFTER, TRUNC_BEFORE = 0, 1, 2
