@@ -18,6 +18,7 @@ Printed as one JSON line (rank 0), with extra sections:
   precomputed_randomness  offline seed expansion, online call on shares + record
   replicated_sharing      RSS DReLU / ReLU (Alg. drelu2) beside the 2-of-2 calls
   truncate_then_multiply  Alg. linear vs multiply-then-truncate: time and e1 counts
+  parties_apart     the DReLU as one kernel per party with packed messages in HBM
   plain_drelu       l = 64 without key bits (l_x = 32), 65,536 elements: us per call
   serving           continuous-batching request loop: p50/p99 latency and Gelem/s
   matmul_relu       truncate-then-ReLU of a 4096 x 4096 . 4096 x 1024 product
@@ -534,6 +535,40 @@ def run_linear(torch, B, steps, warmup):
     return out
 
 
+def run_split(torch, B, inputs, steps, warmup):
+    """The DReLU with the parties apart (each party's kernel on its own, the
+    round-1 messages bit-packed in HBM as they would cross a link) on the 2^24
+    key-bit values, beside the fused call.  Per kernel: time and HBM bytes
+    (send: own share in, packed message out; reply: both messages in, two
+    reply shares out; finish: reply share in, output share out)."""
+    x0, x1 = to_dev(torch, inputs[0]), to_dev(torch, inputs[1])
+    n = x0.numel()
+    out = {"workload": f"{n} key-bit values, l = 64; messages word-major, ceil(N^2 / 32) words per element"}
+    sd = B.Seeds(*SEEDS, 61)
+    for name, prm in (("lx18", B.Params(64, 18, 13)), ("lx7", B.Params(64, 7, 11))):
+        words = B.msg_words(prm.npos)
+        m0 = torch.empty((words, n), dtype=torch.int32, device="cuda")
+        m1 = torch.empty_like(m0)
+        r0, r1, y0, y1 = (torch.empty_like(x0) for _ in range(4))
+        ms = {
+            "send_p0": _event_ms(torch, lambda: B.drelu_send(0, x0, prm, sd, out=m0), steps, warmup),
+            "send_p1": _event_ms(torch, lambda: B.drelu_send(1, x1, prm, sd, out=m1), steps, warmup),
+            "reply_p2": _event_ms(torch, lambda: B.drelu_reply(m0, m1, prm, sd, out=(r0, r1)), steps, warmup),
+            "finish_p0": _event_ms(torch, lambda: B.drelu_finish(0, r0, prm, sd, out=y0), steps, warmup),
+            "finish_p1": _event_ms(torch, lambda: B.drelu_finish(1, r1, prm, sd, out=y1), steps, warmup),
+            "fused": _event_ms(torch, lambda: B.drelu(x0, x1, prm, sd), steps, warmup),
+        }
+        byt = {"send_p0": 8 + 4 * words, "send_p1": 8 + 4 * words, "reply_p2": 8 * words + 16, "finish_p0": 16,
+               "finish_p1": 16}
+        r = {k: round(v, 4) for k, v in ms.items()}
+        r["parties_sum_ms"] = round(sum(v for k, v in ms.items() if k != "fused"), 4)
+        r["message_bytes_per_elem"] = 4 * words
+        r["message_bits_theoretical"] = prm.npos * prm.npos
+        r["gbs"] = {k: round(b * n / ms[k] / 1e6, 1) for k, b in byt.items()}
+        out[name] = r
+    return out
+
+
 def run_copy(torch, steps, warmup, mib=512):
     """A plain device-to-device copy of known size: the reference for achievable
     HBM bandwidth and for scaling rocprofv3's FETCH_SIZE / WRITE_SIZE counters."""
@@ -564,9 +599,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--sections", default="cpu,batched,precomputed,rss,linear,plain,serving,copy,matmul,sweep",
-                    help="comma list of extra sections: cpu, batched, precomputed, rss, linear, plain, serving, "
-                         "copy, matmul, sweep")
+    ap.add_argument("--sections",
+                    default="cpu,batched,precomputed,rss,linear,split,plain,serving,copy,matmul,sweep",
+                    help="comma list of extra sections: cpu, batched, precomputed, rss, linear, split, plain, "
+                         "serving, copy, matmul, sweep")
     ap.add_argument("--cpu-sample", type=int, default=1 << 24)
     ap.add_argument("--cpu-workers", type=int, default=min(16, os.cpu_count() or 1))
     args = ap.parse_args()
@@ -622,6 +658,7 @@ def main():
             ("precomputed", "precomputed_randomness", lambda: run_precomputed(torch, B, inputs, 10, 2)),
             ("rss", "replicated_sharing", lambda: run_rss(torch, B, inputs, 20, 5)),
             ("linear", "truncate_then_multiply", lambda: run_linear(torch, B, 20, 5)),
+            ("split", "parties_apart", lambda: run_split(torch, B, inputs, 20, 5)),
             ("plain", "plain_drelu", lambda: run_plain_drelu(torch, B, args.steps, args.warmup)),
             ("serving", "serving", lambda: run_serving(torch, B)),
             ("matmul", "matmul_relu", lambda: run_matmul_relu(torch, B, args.steps, args.warmup)),

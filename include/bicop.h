@@ -268,6 +268,36 @@ int bc_trunc_relu(const void* x0, const void* x1, void* y0, void* y1, uint64_t n
                   const bc_drelu_params* prm, const bc_seeds* seeds, uint64_t elem_base, void* capture,
                   bc_msg_acct* acct, void* stream);
 
+/* -------------------------------------------- DReLU with the parties apart */
+
+/* 32-bit words per element of one party's packed round-1 message for
+ * npos = l_x + 1 windows: ceil(npos^2 / 32); 0 if npos is outside [2, 33].
+ * Host only. */
+uint32_t bc_msg_words(uint32_t npos);
+
+/* P0's (party 0) or P1's (party 1) part of Alg. 7's first round, alone: from
+ * its own share x (n elements of Z_{2^ell}) the message it sends to P2, with
+ * the same draws and values as bc_drelu's capture.  The N = l_x + 1 slot
+ * values (each below p < 2^N) are bit-packed: bit b of slot s is bit s N + b
+ * of the element's string, word k holds bits 32k .. 32k + 31, and word k of
+ * element i is msg[k * n + i] (word-major); the spare high bits are 0.  msg
+ * holds bc_msg_words(N) * n uint32_t, 4-byte aligned. */
+int bc_drelu_send(uint32_t party, const void* x, uint32_t* msg, uint64_t n, const bc_drelu_params* prm,
+                  const bc_seeds* seeds, uint64_t elem_base, void* stream);
+
+/* P2's part: unpacks both parties' messages (as bc_drelu_send writes them),
+ * sets D' = 1 when some slot reconstructs to 0 mod p, and writes its reply,
+ * a fresh sharing of D' in Z_{2^ell}: d0 = rho (to P0, rho from seed02) and
+ * d1 = D' - rho (to P1). */
+int bc_drelu_reply(const uint32_t* msg0, const uint32_t* msg1, void* d0, void* d1, uint64_t n,
+                   const bc_drelu_params* prm, const bc_seeds* seeds, uint64_t elem_base, void* stream);
+
+/* P0's or P1's unflip of its reply share d with the flip bit t of seed01:
+ * P0 y = t + (1 - 2t) d, P1 y = (1 - 2t) d, in Z_{2^ell}.  send, reply and
+ * finish with the same arguments give bc_drelu's outputs.  y may equal d. */
+int bc_drelu_finish(uint32_t party, const void* d, void* y, uint64_t n, const bc_drelu_params* prm,
+                    const bc_seeds* seeds, uint64_t elem_base, void* stream);
+
 /* ------------------------------------------------ multiply and truncate */
 
 #define BC_TRUNC_NONE   0u   /* the plain product (f must be 0)                  */

@@ -79,6 +79,12 @@ _SIGS = {
                   ctypes.POINTER(_Acct), _P], ctypes.c_int),
     "bc_relu": ([_P, _P, _P, _P, _U64, ctypes.POINTER(_Params), ctypes.POINTER(_Seeds), _U64, _P,
                  ctypes.POINTER(_Acct), _P], ctypes.c_int),
+    "bc_msg_words": ([_U32], _U32),
+    "bc_drelu_send": ([_U32, _P, _P, _U64, ctypes.POINTER(_Params), ctypes.POINTER(_Seeds), _U64, _P], ctypes.c_int),
+    "bc_drelu_reply": ([_P, _P, _P, _P, _U64, ctypes.POINTER(_Params), ctypes.POINTER(_Seeds), _U64, _P],
+                       ctypes.c_int),
+    "bc_drelu_finish": ([_U32, _P, _P, _U64, ctypes.POINTER(_Params), ctypes.POINTER(_Seeds), _U64, _P],
+                        ctypes.c_int),
     "bc_mul_trunc": ([_P, _P, _P, _P, _P, _P, _U64, _U32, _U32, _U32, ctypes.POINTER(_Seeds), _U64, _P], ctypes.c_int),
     "bc_rss_drelu": ([_P, _P, _P, _P, _P, _P, _U64, ctypes.POINTER(_Params), ctypes.POINTER(_RssSeeds), _U64, _P,
                       ctypes.POINTER(_Acct), _P], ctypes.c_int),
@@ -348,6 +354,55 @@ def drelu(x0, x1, params: Params, seeds: Seeds, elem_base=0, capture=False, out=
 def relu(x0, x1, params: Params, seeds: Seeds, elem_base=0, capture=False, out=None, stream=None):
     """Alg. 8.  Returns (y0, y1) or (y0, y1, capture[2, n, lx+1])."""
     return _drelu_like(lib.bc_relu, "relu", x0, x1, params, seeds, elem_base, capture, out, stream)
+
+
+def msg_words(npos):
+    """32-bit words per element of one party's packed round-1 message."""
+    return int(lib.bc_msg_words(npos))
+
+
+def _check_one(t, width, what):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a CUDA tensor")
+    if t.element_size() != width or not t.is_contiguous():
+        raise TypeError(f"{what}: expected contiguous {width}-byte elements")
+
+
+def drelu_send(party, x, params: Params, seeds: Seeds, elem_base=0, out=None, stream=None):
+    """P0's (party 0) or P1's (party 1) round-1 message, from its own share x,
+    bit-packed: an int32 tensor [msg_words(lx + 1), n], word-major."""
+    _check_one(x, ring_width(params.ell), "share")
+    shape = (msg_words(params.npos), x.numel())
+    msg = out if out is not None else torch.empty(shape, dtype=torch.int32, device=x.device)
+    if tuple(msg.shape) != shape or msg.element_size() != 4 or not msg.is_contiguous():
+        raise ValueError("bad message tensor")
+    _check(lib.bc_drelu_send(party, x.data_ptr(), msg.data_ptr(), x.numel(), ctypes.byref(params.c()),
+                             ctypes.byref(seeds.c()), elem_base, _stream(stream, x)), "drelu_send")
+    return msg
+
+
+def drelu_reply(msg0, msg1, params: Params, seeds: Seeds, elem_base=0, out=None, stream=None):
+    """P2: the zero test on both packed messages; returns its reply shares (d0, d1)."""
+    n = msg0.shape[1]
+    if msg0.shape != msg1.shape or msg0.shape[0] != msg_words(params.npos):
+        raise ValueError("message tensors do not match the setting")
+    _check_one(msg0, 4, "message")
+    _check_one(msg1, 4, "message")
+    d0 = _out(msg0[0], ring_width(params.ell), ring_dtype(params.ell), None if out is None else out[0])
+    d1 = _out(msg0[0], ring_width(params.ell), ring_dtype(params.ell), None if out is None else out[1])
+    _check(lib.bc_drelu_reply(msg0.data_ptr(), msg1.data_ptr(), d0.data_ptr(), d1.data_ptr(), n,
+                              ctypes.byref(params.c()), ctypes.byref(seeds.c()), elem_base, _stream(stream, msg0)),
+           "drelu_reply")
+    return d0, d1
+
+
+def drelu_finish(party, d, params: Params, seeds: Seeds, elem_base=0, out=None, stream=None):
+    """P0's or P1's unflip of its reply share."""
+    _check_one(d, ring_width(params.ell), "reply share")
+    y = _out(d, ring_width(params.ell), ring_dtype(params.ell), out)
+    _check(lib.bc_drelu_finish(party, d.data_ptr(), y.data_ptr(), d.numel(), ctypes.byref(params.c()),
+                               ctypes.byref(seeds.c()), elem_base, _stream(stream, d)), "drelu_finish")
+    return y
 
 
 def mul_trunc(x0, x1, y0, y1, ell, f, order, seeds: Seeds, elem_base=0, out=None, stream=None):

@@ -300,6 +300,53 @@ int rss_common(bool relu, const void* x0, const void* x1, const void* x2, void* 
     return BC_OK;
 }
 
+int split_common(bc::SplitLaunch::Kind kind, uint32_t party, const void* in0, const void* in1, void* out0, void* out1,
+                 uint64_t n, const bc_drelu_params* prm, const bc_seeds* seeds, uint64_t elem_base, void* stream) {
+    bc_drelu_params r;
+    int rc = check_params(prm, &r);
+    if (rc) return rc;
+    if (!seeds) return fail(BC_ERR_NULL, "seeds is NULL");
+    if (elem_base > kMaxIndex || n > kMaxIndex - elem_base)
+        return fail(BC_ERR_ARG, "element indices must stay below 2^48");
+    if (n == 0) return BC_OK;
+    const bool reply = kind == bc::SplitLaunch::REPLY;
+    if (!in0 || !out0 || (reply && (!in1 || !out1))) return fail(BC_ERR_NULL, "array pointer is NULL");
+    const uint32_t w = width_of_ring(r.ell);
+    // send reads a share and writes words; reply reads words and writes shares; finish shares to shares
+    const uint32_t win = kind == bc::SplitLaunch::REPLY ? 4 : w;
+    const uint32_t wout = kind == bc::SplitLaunch::SEND ? 4 : w;
+    if (!aligned(in0, win) || (in1 && !aligned(in1, win)) || !aligned(out0, wout) || (out1 && !aligned(out1, wout)))
+        return fail(BC_ERR_ALIGN, "arrays must be aligned to their element size");
+    bc::SplitLaunch L;
+    L.kind = kind;
+    L.party = party;
+    L.in0 = in0;
+    L.in1 = in1;
+    L.out0 = out0;
+    L.out1 = out1;
+    L.n = n;
+    L.elem_base = elem_base;
+    L.p = r.p;
+    L.ell = r.ell;
+    L.lx = r.lx;
+    L.k_lo = r.k_lo;
+    L.npos = r.lx + 1;
+    L.s01 = stream_key(seeds->seed01, seeds->nonce);
+    L.s02 = stream_key(seeds->seed02, seeds->nonce);
+    L.grid = (int)sched_grid(kind == bc::SplitLaunch::FINISH ? BC_SCHED_STREAM : BC_SCHED_FUSED,
+                             kind == bc::SplitLaunch::FINISH ? 0 : L.npos, (n + 255) / 256);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if (kind == bc::SplitLaunch::FINISH)
+        e = bc::launch_split_finish(L, st);
+    else if (r.ell > 32)
+        e = L.npos <= 17 ? bc::launch_split_u64_lo(L, st) : bc::launch_split_u64_hi(L, st);
+    else
+        e = bc::launch_split_u32(L, st);
+    if (e != hipSuccess) return hip_fail(e, "split drelu launch");
+    return BC_OK;
+}
+
 int batch_plan(const bc_segment* segs, uint32_t nseg, const bc_drelu_params* prm, uint32_t tile_elems, void* plan,
                uint64_t plan_bytes) {
     if (!segs || !plan) return fail(BC_ERR_NULL, "segments or plan is NULL");
@@ -650,6 +697,25 @@ int bc_trunc_relu(const void* x0, const void* x1, void* y0, void* y1, uint64_t n
                   bc_msg_acct* acct, void* stream) {
     if (k1 == 0) return fail(BC_ERR_RING, "k1 must be > 0 (use bc_relu)");
     return drelu_common(BC_OP_RELU, x0, x1, y0, y1, n, prm, seeds, elem_base, capture, acct, stream, ell_in, k1);
+}
+
+uint32_t bc_msg_words(uint32_t npos) { return npos >= 2 && npos <= 33 ? (npos * npos + 31) / 32 : 0; }
+
+int bc_drelu_send(uint32_t party, const void* x, uint32_t* msg, uint64_t n, const bc_drelu_params* prm,
+                  const bc_seeds* seeds, uint64_t elem_base, void* stream) {
+    if (party > 1) return fail(BC_ERR_ARG, "party = %u: the senders are 0 and 1", party);
+    return split_common(bc::SplitLaunch::SEND, party, x, nullptr, msg, nullptr, n, prm, seeds, elem_base, stream);
+}
+
+int bc_drelu_reply(const uint32_t* msg0, const uint32_t* msg1, void* d0, void* d1, uint64_t n,
+                   const bc_drelu_params* prm, const bc_seeds* seeds, uint64_t elem_base, void* stream) {
+    return split_common(bc::SplitLaunch::REPLY, 0, msg0, msg1, d0, d1, n, prm, seeds, elem_base, stream);
+}
+
+int bc_drelu_finish(uint32_t party, const void* d, void* y, uint64_t n, const bc_drelu_params* prm,
+                    const bc_seeds* seeds, uint64_t elem_base, void* stream) {
+    if (party > 1) return fail(BC_ERR_ARG, "party = %u: the finishers are 0 and 1", party);
+    return split_common(bc::SplitLaunch::FINISH, party, d, nullptr, y, nullptr, n, prm, seeds, elem_base, stream);
 }
 
 int bc_mul_trunc(const void* x0, const void* x1, const void* y0, const void* y1, void* z0, void* z1, uint64_t n,

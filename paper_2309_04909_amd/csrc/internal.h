@@ -117,6 +117,26 @@ hipError_t launch_rss_u64_mid(const RssLaunch& L, hipStream_t st);   // N 13..24
 hipError_t launch_rss_u64_hi(const RssLaunch& L, hipStream_t st);    // N 25..33
 hipError_t launch_rss_u32(const RssLaunch& L, hipStream_t st);       // N 2..17
 
+// Validated launch of one party's part of the DReLU with the parties apart.
+struct SplitLaunch {
+    enum Kind { SEND, REPLY, FINISH };
+    Kind kind;
+    uint32_t party;       // SEND, FINISH: 0 (P0) or 1 (P1)
+    const void* in0;
+    const void* in1;
+    void* out0;
+    void* out1;
+    uint64_t n, elem_base, p;
+    uint32_t ell, lx, k_lo, npos;
+    StreamKey s01, s02;
+    int grid;
+};
+
+hipError_t launch_split_u64_lo(const SplitLaunch& L, hipStream_t st);   // SEND / REPLY, N 2..17
+hipError_t launch_split_u64_hi(const SplitLaunch& L, hipStream_t st);   // SEND / REPLY, N 18..33
+hipError_t launch_split_u32(const SplitLaunch& L, hipStream_t st);      // SEND / REPLY, N 2..17
+hipError_t launch_split_finish(const SplitLaunch& L, hipStream_t st);   // FINISH, any ring
+
 // Validated elementwise product with truncation (Alg. linear / multiply-then-truncate).
 struct MulLaunch {
     const void* x0;

@@ -298,3 +298,22 @@ def test_mul_trunc_error_paths_without_gpu():
     assert call(order=3) == -8
     assert call(seeds=None) == -1
     assert call(base=(1 << 48) - 5) == -8
+
+
+def test_split_drelu_host_side():
+    """Message size per setting matches the oracle's packing, and the
+    parties-apart calls validate on the host."""
+    from paper_2309_04909_amd import bicop as B
+    L = B.lib
+    assert [L.bc_msg_words(n) for n in range(2, 34)] == [OPR.msg_words(n) for n in range(2, 34)]
+    assert L.bc_msg_words(1) == 0 and L.bc_msg_words(34) == 0
+    prm, sd = B.Params(64, 18, 13).c(), B.Seeds(1, 2, 3, 4).c()
+    P_, S_ = ctypes.byref(prm), ctypes.byref(sd)
+    assert L.bc_drelu_send(2, None, None, 10, P_, S_, 0, None) == -8          # party
+    assert L.bc_drelu_send(0, None, None, 10, P_, S_, 0, None) == -1          # NULL
+    assert L.bc_drelu_send(1, None, None, 0, P_, S_, 0, None) == 0            # n = 0
+    assert L.bc_drelu_send(0, None, None, 10, P_, None, 0, None) == -1        # seeds
+    assert L.bc_drelu_reply(None, None, None, None, 10, P_, S_, 0, None) == -1
+    assert L.bc_drelu_reply(None, None, None, None, 10, P_, S_, (1 << 48) - 1, None) == -8
+    assert L.bc_drelu_finish(3, None, None, 10, P_, S_, 0, None) == -8
+    assert L.bc_drelu_finish(1, None, None, 10, ctypes.byref(B.Params(64, 40, 0).c()), S_, 0, None) == -3
