@@ -15,6 +15,7 @@ Printed as one JSON line (rank 0), with extra sections:
   roofline          the dominant kernel (the fused DReLU) against its ALU roofline
   cpu_baseline      the CPU oracle timed on a bounded sample of the same workload
   batched_vs_plain  ResNet-18 ragged ReLU: one persistent graph launch vs 17 launches
+  layer_chain       truncate-then-ReLU of every ResNet-18 layer in one batch launch
   precomputed_randomness  offline seed expansion, online call on shares + record
   replicated_sharing      RSS DReLU / ReLU (Alg. drelu2) beside the 2-of-2 calls
   truncate_then_multiply  Alg. linear vs multiply-then-truncate: time and e1 counts
@@ -277,6 +278,55 @@ def run_batched_vs_plain(torch, B, steps, warmup, batch=32):
             "speedup": round(ms_plain / ms_batch, 4), "identical_outputs": bool(same),
             "batched": "one persistent launch (bc_batch_run) replayed from a HIP graph",
             "plain": "17 bc_relu launches"}
+
+
+def run_chain(torch, B, steps, warmup, batch=32):
+    """Truncate-then-ReLU over a whole layer chain: the 17 ResNet-18 ReLU
+    tensors (batch 32) arrive as products with 26 fractional bits in Z_2^64;
+    each is truncated by 13 bits (Alg. 5) into Z_2^51 and ReLU'd (k_lo = 11,
+    l_x = 7).  One graph-replayed batch launch with per-segment truncation
+    against 17 fused calls and against 34 two-pass calls (trunc_det, relu)."""
+    from paper_2309_04909_amd import batch as BT
+    prm = B.Params(51, 7, 11)
+    data = W.resnet18_relu(seed=4, batch=batch, f=26)
+    segs = []
+    for i, (_, (x0, x1)) in enumerate(data):
+        d0, d1 = to_dev(torch, x0), to_dev(torch, x1)
+        segs.append(BT.Segment(d0, d1, torch.empty_like(d0), torch.empty_like(d1), op=B.BC_OP_RELU, nonce=200 + i,
+                               k_in=13))
+    del data
+    total = sum(s.x0.numel() for s in segs)
+    rb = BT.RaggedBatch(prm, B.Seeds(*SEEDS), segs)
+    graph = rb.capture()
+    tmp = [(torch.empty_like(s.x0), torch.empty_like(s.x1)) for s in segs]
+    outs = [(torch.empty_like(s.x0), torch.empty_like(s.x1)) for s in segs]
+
+    def fused():
+        for s, o in zip(segs, outs):
+            B.trunc_relu(s.x0, s.x1, 64, 13, prm, B.Seeds(*SEEDS, s.nonce), out=o)
+
+    def two_pass():
+        for s, t, o in zip(segs, tmp, outs):
+            B.trunc_det(s.x0, s.x1, 64, 13, 0, out=t)
+            B.relu(t[0], t[1], prm, B.Seeds(*SEEDS, s.nonce), out=o)
+
+    # the three variants interleaved over three rounds, best of each (the first
+    # timings after the host-side setup run on a GPU that is still clocking up)
+    ms_batch = ms_fused = ms_two = float("inf")
+    same_fused = same_two = True
+    for _ in range(3):
+        ms_batch = min(ms_batch, _event_ms(torch, graph.replay, steps, warmup))
+        ms_fused = min(ms_fused, _event_ms(torch, fused, steps, warmup))
+        same_fused &= all(torch.equal(o[0], s.y0) and torch.equal(o[1], s.y1) for s, o in zip(segs, outs))
+        ms_two = min(ms_two, _event_ms(torch, two_pass, steps, warmup))
+        same_two &= all(torch.equal(o[0], s.y0) and torch.equal(o[1], s.y1) for s, o in zip(segs, outs))
+    return {"workload": f"ResNet-18 ReLU inputs as products (f = 26) in Z_2^64, batch {batch}: 17 tensors, {total} "
+                        "elements; trunc_det by 13 into Z_2^51, then ReLU (k_lo = 11, l_x = 7, p = 251)",
+            "elements": total, "batched_ms": round(ms_batch, 4), "fused_calls_ms": round(ms_fused, 4),
+            "two_pass_ms": round(ms_two, 4), "batched_gelem_s": round(total / ms_batch / 1e6, 3),
+            "identical_outputs": bool(same_fused and same_two),
+            "batched": "one persistent launch with per-segment truncation, replayed from a HIP graph",
+            "fused_calls": "17 bc_trunc_relu launches", "two_pass": "17 x (bc_trunc_det + bc_relu)"}
 
 
 def run_plain_drelu(torch, B, steps, warmup):
@@ -600,9 +650,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--sections",
-                    default="cpu,batched,precomputed,rss,linear,split,plain,serving,copy,matmul,sweep",
-                    help="comma list of extra sections: cpu, batched, precomputed, rss, linear, split, plain, "
-                         "serving, copy, matmul, sweep")
+                    default="cpu,batched,chain,precomputed,rss,linear,split,plain,serving,copy,matmul,sweep",
+                    help="comma list of extra sections: cpu, batched, chain, precomputed, rss, linear, split, "
+                         "plain, serving, copy, matmul, sweep")
     ap.add_argument("--cpu-sample", type=int, default=1 << 24)
     ap.add_argument("--cpu-workers", type=int, default=min(16, os.cpu_count() or 1))
     args = ap.parse_args()
@@ -655,6 +705,7 @@ def main():
     }
     progress(f"headline: {value:.3f} Gelem/s, {ms_step:.4f} ms per step")
     runs = [("batched", "batched_vs_plain", lambda: run_batched_vs_plain(torch, B, max(3, args.steps // 5), 2)),
+            ("chain", "layer_chain", lambda: run_chain(torch, B, 10, 2)),
             ("precomputed", "precomputed_randomness", lambda: run_precomputed(torch, B, inputs, 10, 2)),
             ("rss", "replicated_sharing", lambda: run_rss(torch, B, inputs, 20, 5)),
             ("linear", "truncate_then_multiply", lambda: run_linear(torch, B, 20, 5)),

@@ -386,9 +386,10 @@ int bc_relu_pre(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, 
 
 /* ------------------------------------------------------ ragged batching */
 
-/* One segment of a ragged batch: a share pair of its own length, op, nonce
- * and global element offset.  Every element of a segment gets exactly the
- * result of bc_drelu / bc_relu on that segment with seeds->nonce = nonce and
+/* One segment of a ragged batch: a share pair of its own length, op, nonce,
+ * global element offset and input truncation.  Every element of a segment
+ * gets exactly the result of bc_drelu / bc_relu (k_in = 0) or bc_trunc_drelu /
+ * bc_trunc_relu with k1 = k_in on that segment, with seeds->nonce = nonce and
  * the same elem_base.  Outputs of one segment must not overlap inputs or
  * outputs of another. */
 typedef struct {
@@ -400,7 +401,10 @@ typedef struct {
     uint64_t elem_base;  /* global index of element 0 (n + base <= 2^48) */
     uint64_t nonce;      /* per-segment nonce                          */
     uint32_t op;         /* BC_OP_DRELU or BC_OP_RELU                   */
-    uint32_t reserved;   /* must be 0                                  */
+    uint32_t k_in;       /* low bits each party first truncates from its
+                            input share (Alg. 5); the inputs are then
+                            shares of Z_{2^(ell + k_in)}, of the storage
+                            width of ell.  0 = none                      */
 } bc_segment;
 
 /* Bytes of the plan buffer for nseg segments: a 64-byte header, the segment

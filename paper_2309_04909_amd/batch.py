@@ -1,8 +1,10 @@
 """Ragged batches: many DReLU/ReLU share pairs in one persistent launch.
 
 A batch shares one setting (ring, window, prime) and the three seeds; each
-segment has its own length, op, nonce and global element offset, and gets
-exactly the result of a single bc_drelu / bc_relu call on it.  The plan is
+segment has its own length, op, nonce, global element offset and input
+truncation k_in, and gets exactly the result of a single bc_drelu / bc_relu
+(or, with k_in > 0, bc_trunc_drelu / bc_trunc_relu) call on it: the
+truncate-then-ReLU of a whole layer chain is one launch.  The plan is
 built on the host by the C ABI (bc_batch_plan), copied to device memory once,
 and every run is a single kernel launch (bc_batch_run) that a HIP graph can
 capture.
@@ -25,6 +27,7 @@ class Segment:
     op: int = B.BC_OP_RELU
     nonce: int = 0
     elem_base: int = 0
+    k_in: int = 0          # truncate the inputs by k_in bits first (Alg. 5): shares of Z_2^(ell + k_in)
 
 
 class RaggedBatch:
@@ -45,7 +48,7 @@ class RaggedBatch:
                 raise ValueError("segment input and output lengths differ")
             m = (1 << 64) - 1
             recs[i] = B._Segment(s.x0.data_ptr(), s.x1.data_ptr(), s.y0.data_ptr(), s.y1.data_ptr(), s.x0.numel(),
-                                 s.elem_base, s.nonce & m, s.op, 0)
+                                 s.elem_base, s.nonce & m, s.op, s.k_in)
         nbytes = int(B.lib.bc_batch_plan_bytes(nseg))
         # The plan is built in pinned host memory and uploaded asynchronously
         # on the current stream (runs on that stream, or on streams ordered
@@ -64,7 +67,10 @@ class RaggedBatch:
                                     ctypes.byref(self._c_seeds), self.grid, B._stream(stream, self.dev_plan)), "batch_run")
 
     def capture(self):
-        """Capture run() into a CUDA/HIP graph; returns the torch.cuda.CUDAGraph."""
+        """Capture run() into a CUDA/HIP graph; returns the torch.cuda.CUDAGraph.
+
+        The graph's kernel reads this batch's device plan, so the graph keeps
+        the batch (and with it the plan) alive for as long as it exists."""
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):
@@ -74,4 +80,5 @@ class RaggedBatch:
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
             self.run()
+        g.ragged_batch = self
         return g

@@ -54,7 +54,7 @@ class _Acct(ctypes.Structure):
 class _Segment(ctypes.Structure):
     _fields_ = [("x0", ctypes.c_void_p), ("x1", ctypes.c_void_p), ("y0", ctypes.c_void_p), ("y1", ctypes.c_void_p),
                 ("n", ctypes.c_uint64), ("elem_base", ctypes.c_uint64), ("nonce", ctypes.c_uint64),
-                ("op", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("op", ctypes.c_uint32), ("k_in", ctypes.c_uint32)]
 
 
 _P = ctypes.c_void_p

@@ -365,7 +365,9 @@ int batch_plan(const bc_segment* segs, uint32_t nseg, const bc_drelu_params* prm
     for (uint32_t i = 0; i < nseg; ++i) {
         const bc_segment& s = segs[i];
         if (s.op != BC_OP_DRELU && s.op != BC_OP_RELU) return fail(BC_ERR_ARG, "segment %u: unknown op %u", i, s.op);
-        if (s.reserved) return fail(BC_ERR_ARG, "segment %u: reserved must be 0", i);
+        if (s.k_in && (r.ell + s.k_in > 64 || width_of_ring(r.ell + s.k_in) != w))
+            return fail(BC_ERR_RING, "segment %u: input ring %u + %u must share the storage width of %u", i, r.ell,
+                        s.k_in, r.ell);
         if (s.elem_base > kMaxIndex || s.n > kMaxIndex - s.elem_base)
             return fail(BC_ERR_ARG, "segment %u: element indices must stay below 2^48", i);
         if (s.n && (!s.x0 || !s.x1 || !s.y0 || !s.y1)) return fail(BC_ERR_NULL, "segment %u: NULL share pointer", i);

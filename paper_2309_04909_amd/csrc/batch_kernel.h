@@ -1,0 +1,101 @@
+// Ragged batch of DReLU / ReLU segments (one setting, one persistent launch).
+#pragma once
+
+#include "drelu_kernel.h"
+
+namespace bc {
+
+struct BatchKArgs {
+    uint64_t total_tiles;
+    uint64_t tile_elems;
+    uint64_t ring_mask;
+    uint32_t nseg, k_lo, ell;
+    uint32_t k01a, k01b, k02a, k02b, k12a, k12b;
+};
+
+// Ragged batch: a persistent grid walks the tiles of every segment.  Tile t
+// belongs to the segment s with tile_begin[s] <= t < tile_begin[s + 1]; each
+// segment has its own op, nonce and global element offset, so every element
+// gets exactly the randomness (and result) of a single call on its segment.
+// Each block takes tiles blockIdx.x, blockIdx.x + gridDim.x, ... until
+// total_tiles: every wave reaches the exit.
+template <typename T, int N, typename F>
+__global__ BC_KERNEL_ATTRS void k_batch(const BatchPlanHeader* __restrict__ hdr,
+                                               const bc_segment* __restrict__ segs,
+                                               const uint64_t* __restrict__ tile_begin, BatchKArgs A, F f_arg) {
+    // The device plan must still be the one this launch was built from: a
+    // plan whose memory was freed and reused fails these checks, and then no
+    // block walks it.
+    if (hdr->magic != kBatchMagic || hdr->nseg != A.nseg || hdr->total_tiles != A.total_tiles) return;
+    const F f = f_arg.vgpr();
+    const uint32_t nseg = A.nseg;
+    const uint64_t total = A.total_tiles;
+    const uint64_t tile = A.tile_elems;
+    const T mask = in_vgpr((T)A.ring_mask);
+    for (uint64_t t = blockIdx.x; t < total; t += gridDim.x) {
+        // segment of tile t: largest s with tile_begin[s] <= t (uniform search)
+        uint32_t lo = 0, hi = nseg;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (tile_begin[mid] <= t) lo = mid; else hi = mid;
+        }
+        const bc_segment& S = segs[lo];
+        const T* X0 = static_cast<const T*>(S.x0);
+        const T* X1 = static_cast<const T*>(S.x1);
+        T* Y0 = static_cast<T*>(S.y0);
+        T* Y1 = static_cast<T*>(S.y1);
+        const uint64_t e0 = (t - tile_begin[lo]) * tile;
+        const uint64_t e1 = e0 + tile < S.n ? e0 + tile : S.n;
+        const uint32_t n0 = (uint32_t)S.nonce, n1 = (uint32_t)(S.nonce >> 32);
+        const Stream s01{A.k01a, A.k01b, n0, n1}, s02{A.k02a, A.k02b, n0, n1}, s12{A.k12a, A.k12b, n0, n1};
+        const uint64_t base = S.elem_base;
+        // the segment's input ring l + k_in (Alg. 5 by k_in first; 0 = the plain load)
+        const uint32_t k_in = S.k_in, lin = A.ell + k_in;
+        const T in_mask = lin >= 8 * sizeof(T) ? (T)~(T)0 : (T)(((T)1 << lin) - 1);
+        if (S.op == BC_OP_RELU) {
+            for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x)
+                drelu_element<T, N, F, true, false>(X0, X1, Y0, Y1, nullptr, 0, e, base + e, mask, in_mask, k_in,
+                                                    A.k_lo, s01, s02, s12, f);
+        } else {
+            for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x)
+                drelu_element<T, N, F, false, false>(X0, X1, Y0, Y1, nullptr, 0, e, base + e, mask, in_mask, k_in,
+                                                     A.k_lo, s01, s02, s12, f);
+        }
+    }
+}
+
+template <typename T, int N, typename F>
+hipError_t launch_batch_field(const BatchLaunch& L, const F& f, hipStream_t st) {
+    BatchKArgs A;
+    A.total_tiles = L.total_tiles;
+    A.tile_elems = L.tile_elems;
+    A.ring_mask = L.ell >= 64 ? ~0ull : ((1ull << L.ell) - 1);
+    A.nseg = L.nseg;
+    A.k_lo = L.k_lo;
+    A.ell = L.ell;
+    A.k01a = L.s01.k0;
+    A.k01b = L.s01.k1;
+    A.k02a = L.s02.k0;
+    A.k02b = L.s02.k1;
+    A.k12a = L.s12.k0;
+    A.k12b = L.s12.k1;
+    hipLaunchKernelGGL((k_batch<T, N, F>), dim3(L.grid), dim3(256), 0, st, L.hdr, L.segs, L.tile_begin, A, f);
+    return hipGetLastError();
+}
+
+template <typename T, int N>
+hipError_t launch_batch_exact(const BatchLaunch& L, hipStream_t st) {
+    return with_field<N>(L.p, [&](auto f) { return launch_batch_field<T, N, decltype(f)>(L, f, st); });
+}
+
+template <typename T, int NLO, int NHI>
+hipError_t launch_batch_range(const BatchLaunch& L, hipStream_t st) {
+    if constexpr (NLO > NHI) {
+        return hipErrorInvalidValue;
+    } else {
+        if (L.npos == (uint32_t)NLO) return launch_batch_exact<T, NLO>(L, st);
+        return launch_batch_range<T, NLO + 1, NHI>(L, st);
+    }
+}
+
+}  // namespace bc

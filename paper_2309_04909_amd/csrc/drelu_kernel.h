@@ -16,12 +16,12 @@
 // with the triple generated from seed_02 / seed_12 and the unflipped input
 // shares.
 //
-// The l_x + 1 window values never leave VGPRs.  Kernels are instantiated per
-// window count N = l_x + 1, so every loop over windows is unrolled.  The shuffle is applied by
-// computing, for slot s, the window of the position the sorted key names:
-// the message in slot s is v_{sigma(s)} r_s + z_s, exactly the shuffled and
-// masked array that the shuffle and mask produce.  With a capture pointer the same code also
-// stores both parties' round-1 messages.
+// The l_x + 1 window values never leave VGPRs.  Kernels are instantiated
+// per window count N = l_x + 1, so every loop over windows is unrolled.  The
+// shuffle is applied by computing, for slot s, the window of the position
+// the sorted key names: the message in slot s is v_{sigma(s)} r_s + z_s,
+// exactly the array that the shuffle and mask produce.  With a capture
+// pointer the same code also stores both parties' round-1 messages.
 #pragma once
 
 #include <type_traits>
@@ -45,14 +45,6 @@ struct DreluKArgs {
     Stream s01, s02, s12;
 };
 
-struct BatchKArgs {
-    uint64_t total_tiles;
-    uint64_t tile_elems;
-    uint64_t ring_mask;
-    uint32_t nseg, k_lo;
-    uint32_t k01a, k01b, k02a, k02b, k12a, k12b;
-};
-
 // Bits [pos, pos + l_x] of a share already shifted down by k_lo (pos <= l_x).
 // With 64-bit shares: when bits [0, 2 l_x] fit in 32 bits a 32-bit shift of
 // the low word, else (windows of at most 32 bits) one v_alignbit_b32 of the
@@ -68,9 +60,10 @@ __device__ __forceinline__ FT window(T a, uint32_t pos) {
         return (FT)(a >> pos) & WIN1;
 }
 
-// Windows through P2's reconstruction (Alg. 7) for one slot: the window position `pos` (sigma of the slot), the
-// slot's mask r and reshare z; returns both parties' messages and P2's
-// reconstruction w0 + w1 mod p (the slot is zero when it is 0).
+// Windows through P2's reconstruction (Alg. 7) for one slot: the window
+// position `pos` (sigma of the slot), the slot's mask r and reshare z;
+// returns both parties' messages and P2's reconstruction w0 + w1 mod p (the
+// slot is zero when it is 0).
 // a0 and nb1 are P0's share and P1's negated share, both shifted down by k_lo.
 // Every select is written as masks and adds so that it stays on the
 // full-rate VOP2 forms (no compare / cndmask pairs).
@@ -104,7 +97,8 @@ __device__ __forceinline__ void drelu_finish(T dp, T rho, uint32_t t, T mask, T&
     y1 = t ? (T)((T)0 - d1) & mask : d1;
 }
 
-// Alg. 8 after the zero test: e = D' - b, d = x - a and the product, with the triple ([a]_j, [b]_j, [c]_j) and the unflipped inputs.
+// Alg. 8 after the zero test: e = D' - b, d = x - a and the product, with
+// the triple ([a]_j, [b]_j, [c]_j) and the unflipped inputs.
 template <typename T>
 __device__ __forceinline__ void relu_finish(T dp, T in0, T in1, T ba0, T bb0, T bc0, T ba1, T bb1, T bc1, uint32_t t,
                                             T mask, T& y0, T& y1) {
@@ -374,50 +368,6 @@ __global__ BC_KERNEL_ATTRS void k_drelu_group(DreluKArgs A, F f_arg) {
     }
 }
 
-// Ragged batch: a persistent grid walks the tiles of every segment.  Tile t
-// belongs to the segment s with tile_begin[s] <= t < tile_begin[s + 1]; each
-// segment has its own op, nonce and global element offset, so every element
-// gets exactly the randomness (and result) of a single call on its segment.
-// Each block takes tiles blockIdx.x, blockIdx.x + gridDim.x, ... until
-// total_tiles: every wave reaches the exit.
-template <typename T, int N, typename F>
-__global__ BC_KERNEL_ATTRS void k_batch(const BatchPlanHeader* __restrict__ hdr,
-                                               const bc_segment* __restrict__ segs,
-                                               const uint64_t* __restrict__ tile_begin, BatchKArgs A, F f_arg) {
-    const F f = f_arg.vgpr();
-    const uint32_t nseg = A.nseg;
-    const uint64_t total = A.total_tiles;
-    const uint64_t tile = A.tile_elems;
-    const T mask = in_vgpr((T)A.ring_mask);
-    for (uint64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        // segment of tile t: largest s with tile_begin[s] <= t (uniform search)
-        uint32_t lo = 0, hi = nseg;
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (tile_begin[mid] <= t) lo = mid; else hi = mid;
-        }
-        const bc_segment& S = segs[lo];
-        const T* X0 = static_cast<const T*>(S.x0);
-        const T* X1 = static_cast<const T*>(S.x1);
-        T* Y0 = static_cast<T*>(S.y0);
-        T* Y1 = static_cast<T*>(S.y1);
-        const uint64_t e0 = (t - tile_begin[lo]) * tile;
-        const uint64_t e1 = e0 + tile < S.n ? e0 + tile : S.n;
-        const uint32_t n0 = (uint32_t)S.nonce, n1 = (uint32_t)(S.nonce >> 32);
-        const Stream s01{A.k01a, A.k01b, n0, n1}, s02{A.k02a, A.k02b, n0, n1}, s12{A.k12a, A.k12b, n0, n1};
-        const uint64_t base = S.elem_base;
-        if (S.op == BC_OP_RELU) {
-            for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x)
-                drelu_element<T, N, F, true, false>(X0, X1, Y0, Y1, nullptr, 0, e, base + e, mask, mask, 0, A.k_lo,
-                                                    s01, s02, s12, f);
-        } else {
-            for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x)
-                drelu_element<T, N, F, false, false>(X0, X1, Y0, Y1, nullptr, 0, e, base + e, mask, mask, 0, A.k_lo,
-                                                     s01, s02, s12, f);
-        }
-    }
-}
-
 // Host helpers: field parameters for each prime size.
 inline FieldSmall make_field_small(uint64_t p) { return FieldSmall{(uint32_t)p, 1.0f / (float)p}; }
 inline Field24 make_field24(uint64_t p) { return Field24{(uint32_t)p, (double)p, 1.0 / (double)p}; }
@@ -491,39 +441,6 @@ hipError_t with_field(uint64_t p, Fn&& fn) {
 template <typename T, int N, bool RELU>
 hipError_t launch_exact(const DreluLaunch& L, hipStream_t st) {
     return with_field<N>(L.p, [&](auto f) { return launch_field<T, N, decltype(f), RELU>(L, f, st); });
-}
-
-template <typename T, int N, typename F>
-hipError_t launch_batch_field(const BatchLaunch& L, const F& f, hipStream_t st) {
-    BatchKArgs A;
-    A.total_tiles = L.total_tiles;
-    A.tile_elems = L.tile_elems;
-    A.ring_mask = L.ell >= 64 ? ~0ull : ((1ull << L.ell) - 1);
-    A.nseg = L.nseg;
-    A.k_lo = L.k_lo;
-    A.k01a = L.s01.k0;
-    A.k01b = L.s01.k1;
-    A.k02a = L.s02.k0;
-    A.k02b = L.s02.k1;
-    A.k12a = L.s12.k0;
-    A.k12b = L.s12.k1;
-    hipLaunchKernelGGL((k_batch<T, N, F>), dim3(L.grid), dim3(256), 0, st, L.hdr, L.segs, L.tile_begin, A, f);
-    return hipGetLastError();
-}
-
-template <typename T, int N>
-hipError_t launch_batch_exact(const BatchLaunch& L, hipStream_t st) {
-    return with_field<N>(L.p, [&](auto f) { return launch_batch_field<T, N, decltype(f)>(L, f, st); });
-}
-
-template <typename T, int NLO, int NHI>
-hipError_t launch_batch_range(const BatchLaunch& L, hipStream_t st) {
-    if constexpr (NLO > NHI) {
-        return hipErrorInvalidValue;
-    } else {
-        if (L.npos == (uint32_t)NLO) return launch_batch_exact<T, NLO>(L, st);
-        return launch_batch_range<T, NLO + 1, NHI>(L, st);
-    }
 }
 
 template <typename T, bool RELU, int NLO, int NHI>

@@ -1,6 +1,6 @@
 // Persistent ragged-batch kernels for 64-bit share storage, one per
 // window count N = l_x + 1 in [13, 24].
-#include "drelu_kernel.h"
+#include "batch_kernel.h"
 
 namespace bc {
 

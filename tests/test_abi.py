@@ -156,6 +156,16 @@ def test_batch_plan_validation_on_host():
     bad = B.Params(64, 7, 0, 257).c()
     seg[0].elem_base = 0
     assert L.bc_batch_plan(seg, 2, ctypes.byref(bad), 1024, buf, nbytes) == -4
+    # per-segment input truncation: the input ring must keep the storage width
+    seg[1].k_in = 1
+    assert L.bc_batch_plan(seg, 2, ctypes.byref(prm), 1024, buf, nbytes) == -2      # 64 + 1 bits
+    r51 = B.Params(51, 11, 13).c()
+    seg[1].k_in = 13
+    assert L.bc_batch_plan(seg, 2, ctypes.byref(r51), 1024, buf, nbytes) == 0       # Z_2^64 -> Z_2^51
+    r24 = B.Params(24, 7, 10).c()
+    seg[1].k_in = 9                                                                  # 33 bits: another width
+    assert L.bc_batch_plan(seg, 2, ctypes.byref(r24), 1024, buf, nbytes) == -2
+    seg[1].k_in = 0
     # bc_batch_run refuses a buffer that is not a plan (checked before any launch)
     junk = (ctypes.c_uint8 * nbytes)()
     sd = B.Seeds(1, 2, 3).c()

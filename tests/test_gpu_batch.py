@@ -121,3 +121,71 @@ def test_batch_graph_replays(M):
         assert float(junk) == float(junk)
         for (a0, a1), s in zip(eager, segs):
             assert same(a0, s.y0) and same(a1, s.y1), rep
+
+
+def test_graph_keeps_its_plan_alive(M):
+    """A graph captured from a batch that the caller does not keep still
+    replays correctly after the allocator has handed out (and overwritten)
+    fresh memory: the graph holds the batch, and with it the device plan."""
+    import gc
+    B, bt = M
+    rng = np.random.default_rng(12)
+    prm = B.Params(64, 7, 11)
+    segs, _ = _segments(B, bt, rng, 64, 7, 11, [30000, 777, 5000])
+    g = bt.RaggedBatch(prm, B.Seeds(3, 4, 5), segs).capture()
+    gc.collect()
+    churn = [torch.full((n,), -1, dtype=torch.int64, device="cuda") for n in (64, 512, 4096, 1 << 16)]
+    for s in segs:
+        s.y0.zero_()
+        s.y1.zero_()
+    g.replay()
+    torch.cuda.synchronize()
+    for s in segs:
+        fn = B.relu if s.op == B.BC_OP_RELU else B.drelu
+        z0, z1 = fn(s.x0, s.x1, prm, B.Seeds(3, 4, 5, s.nonce), elem_base=s.elem_base)
+        assert same(z0, s.y0) and same(z1, s.y1)
+    del churn
+
+
+@pytest.mark.parametrize("ell_in,k_in,lx,k_lo", [(64, 13, 11, 13), (32, 8, 7, 10), (64, 20, 7, 11)])
+def test_batch_with_input_truncation(M, ell_in, k_in, lx, k_lo):
+    """A layer chain in one launch: segments whose inputs are products in
+    Z_2^ell_in, truncated by k_in bits first (Alg. 5), mixed with segments
+    already in the ring.  Each equals bc_trunc_drelu / bc_trunc_relu (or the
+    plain call) on its own, and the oracle on samples."""
+    B, bt = M
+    ell = ell_in - k_in
+    rng = np.random.default_rng(ell_in + k_in)
+    prm, seeds = B.Params(ell, lx, k_lo), (15, 16, 17)
+    sizes = [5000, 0, 1, 77777, 1025, 4096]
+    segs, inputs, base = [], [], 0
+    for i, n in enumerate(sizes):
+        kin = k_in if i % 3 != 1 else 0
+        ring = ell + kin
+        bound = 1 << (k_lo + lx - 2 + kin)
+        x = np.array([v % (1 << ring) for v in rng.integers(-bound + 1, bound, size=n).tolist()], dtype=np.uint64)
+        x0, x1 = W.share(x, ring, rng)
+        op = B.BC_OP_RELU if i % 2 else B.BC_OP_DRELU
+        d0, d1 = dev(x0), dev(x1)
+        segs.append(bt.Segment(d0, d1, torch.empty_like(d0), torch.empty_like(d1), op=op, nonce=300 + i,
+                               elem_base=base, k_in=kin))
+        inputs.append((x0, x1))
+        base += n + 5
+    bt.RaggedBatch(prm, B.Seeds(*seeds), segs).run()
+    p = default_prime(lx)
+    for s, (x0, x1) in zip(segs, inputs):
+        sd = B.Seeds(*seeds, s.nonce)
+        if s.k_in:
+            fn = B.trunc_relu if s.op == B.BC_OP_RELU else B.trunc_drelu
+            z0, z1 = fn(s.x0, s.x1, ell + s.k_in, s.k_in, prm, sd, elem_base=s.elem_base)
+        else:
+            fn = B.relu if s.op == B.BC_OP_RELU else B.drelu
+            z0, z1 = fn(s.x0, s.x1, prm, sd, elem_base=s.elem_base)
+        assert same(z0, s.y0) and same(z1, s.y1), (s.x0.numel(), s.k_in)
+        k = min(300, x0.size)
+        if k:
+            t0, t1 = OPR.trunc_det(x0[:k].astype(np.uint64), x1[:k].astype(np.uint64), ell + s.k_in, s.k_in, 0)
+            ofn = OPR.relu if s.op == B.BC_OP_RELU else OPR.drelu
+            e0, e1, _, _ = ofn(t0, t1, ell, lx, k_lo, p, seeds, s.nonce, elem_base=s.elem_base)
+            assert np.array_equal(host(s.y0)[:k].astype(np.uint64), e0)
+            assert np.array_equal(host(s.y1)[:k].astype(np.uint64), e1)

@@ -165,14 +165,16 @@ def resnet18_sizes(batch: int = 32):
     return [batch * c * h * w for (c, h, w) in RESNET18_SHAPES]
 
 
-def resnet18_relu(seed: int = 4, batch: int = 32, layers=None):
-    """List of (x, (x0, x1)) per ReLU tensor of a ResNet-18 pass, flattened."""
+def resnet18_relu(seed: int = 4, batch: int = 32, layers=None, f: int = F):
+    """List of (x, (x0, x1)) per ReLU tensor of a ResNet-18 pass, flattened:
+    N(0, 1) values with f fractional bits in Z_2^64 (f = 2 F: the layer's
+    products before their truncation)."""
     rng = np.random.default_rng(seed)
     out = []
     for i, n in enumerate(resnet18_sizes(batch)):
         if layers is not None and i not in layers:
             continue
-        x = encode(fixed_point(rng.standard_normal(n), F), 64)
+        x = encode(fixed_point(rng.standard_normal(n), f), 64)
         out.append((x, share(x, 64, rng)))
     return out
 
