@@ -255,17 +255,7 @@ def run_batched_vs_plain(torch, B, steps, warmup, batch=32):
             B.relu(s.x0, s.x1, prm, B.Seeds(*seeds, s.nonce), out=(s.y0, s.y1))
 
     def timed(fn):
-        for _ in range(warmup):
-            fn()
-        torch.cuda.synchronize()
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(steps):
-            fn()
-        b.record()
-        torch.cuda.synchronize()
-        return a.elapsed_time(b) / steps
+        return _event_ms(torch, fn, steps, warmup)
 
     ms_plain = timed(plain)
     ref = [(s.y0.clone(), s.y1.clone()) for s in segs]
@@ -339,17 +329,7 @@ def run_plain_drelu(torch, B, steps, warmup):
     for lx in (32, 31):
         prm = B.Params(64, lx, 0)
         sd = B.Seeds(*SEEDS, 11)
-        for _ in range(warmup):
-            B.drelu(d0, d1, prm, sd, out=(y0, y1))
-        torch.cuda.synchronize()
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(steps):
-            B.drelu(d0, d1, prm, sd, out=(y0, y1))
-        b.record()
-        torch.cuda.synchronize()
-        ms = a.elapsed_time(b) / steps
+        ms = _event_ms(torch, lambda: B.drelu(d0, d1, prm, sd, out=(y0, y1)), steps, warmup)
         out[f"lx{lx}_us_per_call"] = round(ms * 1e3, 2)
         out[f"lx{lx}_gelem_s"] = round(d0.numel() / ms / 1e6, 3)
     return out
@@ -421,17 +401,7 @@ def run_matmul_relu(torch, B, steps, warmup):
 
         res = {}
         for name, fn in (("two_pass", two_pass), ("fused", fused)):
-            for _ in range(warmup):
-                fn()
-            torch.cuda.synchronize()
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            a.record()
-            for _ in range(steps):
-                fn()
-            b.record()
-            torch.cuda.synchronize()
-            ms = a.elapsed_time(b) / steps
+            ms = _event_ms(torch, fn, steps, warmup)
             res[f"{name}_ms"] = round(ms, 4)
             res[f"{name}_gelem_s"] = round(d0.numel() / ms / 1e6, 3)
         out[f"l{ell}"] = dict(res, setting=f"trunc {f} -> Z_2^{ell - f}, k_lo={k_lo}, l_x={lx}")
@@ -459,25 +429,23 @@ def run_sweep(torch, B, steps, warmup):
         rows = {}
         for n in (1, 1000, 10000, 100000, 1000000):
             a0, a1, b0, b1 = d0[:n], d1[:n], y0[:n], y1[:n]
-            for _ in range(warmup):
-                fn(a0, a1, prm, sd, out=(b0, b1))
-            torch.cuda.synchronize()
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            a.record()
-            for _ in range(steps):
-                fn(a0, a1, prm, sd, out=(b0, b1))
-            b.record()
-            torch.cuda.synchronize()
-            us = a.elapsed_time(b) / steps * 1e3
+            us = _event_ms(torch, lambda: fn(a0, a1, prm, sd, out=(b0, b1)), steps, warmup) * 1e3
             rows[str(n)] = {"us": round(us, 2), "gelem_s": round(n / us / 1e3, 4), "paper_lan1_us": PAPER_LAN1_US[op][n]}
         out[op] = rows
     return out
 
 
-def _event_ms(torch, fn, steps, warmup):
-    for _ in range(warmup):
+def _event_ms(torch, fn, steps, warmup, warm_s=0.03):
+    """Average milliseconds per call of fn over `steps` calls, timed with HIP
+    events on the current stream, after at least `warmup` calls and warm_s
+    seconds of untimed calls (a section's first timing otherwise catches the
+    GPU still clocking up after the host-side setup)."""
+    t0 = time.perf_counter()
+    done = 0
+    while done < warmup or time.perf_counter() - t0 < warm_s:
         fn()
+        torch.cuda.synchronize()
+        done += 1
     torch.cuda.synchronize()
     a = torch.cuda.Event(enable_timing=True)
     b = torch.cuda.Event(enable_timing=True)
@@ -625,17 +593,7 @@ def run_copy(torch, steps, warmup, mib=512):
     n = (mib << 20) // 8
     src = torch.empty(n, dtype=torch.int64, device="cuda").fill_(3)
     dst = torch.empty_like(src)
-    for _ in range(warmup):
-        dst.copy_(src)
-    torch.cuda.synchronize()
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(steps):
-        dst.copy_(src)
-    b.record()
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b) / steps
+    ms = _event_ms(torch, lambda: dst.copy_(src), steps, warmup)
     return {"bytes_per_copy": 2 * n * 8, "ms": round(ms, 4), "gbs": round(2 * n * 8 / ms / 1e6, 1),
             "hbm_frac": round(2 * n * 8 / ms / 1e6 / HBM_PEAK_GBS, 4)}
 
@@ -648,7 +606,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--sections",
                     default="cpu,batched,chain,precomputed,rss,linear,split,plain,serving,copy,matmul,sweep",
                     help="comma list of extra sections: cpu, batched, chain, precomputed, rss, linear, split, "
