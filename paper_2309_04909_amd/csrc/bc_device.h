@@ -32,6 +32,10 @@ constexpr uint32_t PHILOX_M1 = 0xCD9E8D57u;
 constexpr uint32_t PHILOX_W0 = 0x9E3779B9u;
 constexpr uint32_t PHILOX_W1 = 0xBB67AE85u;
 
+// V consecutive elements of T, for one vector load or store per thread.
+template <typename T, int V>
+using vec_t = T __attribute__((ext_vector_type(V)));
+
 constexpr uint32_t TAG_SHUFFLE = 1;
 constexpr uint32_t TAG_MASK = 2;
 constexpr uint32_t TAG_RESP = 3;

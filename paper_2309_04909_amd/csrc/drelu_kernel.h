@@ -110,6 +110,45 @@ __device__ __forceinline__ void relu_finish(T dp, T in0, T in1, T ba0, T bb0, T 
     y1 = t ? (T)(in1 - m1) & mask : m1;
 }
 
+// The flip bit t and the sorted shuffle keys of one element, both from
+// seed_01 (Alg. 7): key j is word j of the TAG_SHUFFLE stream with its low
+// six bits replaced by j (ties broken by position); slot s takes the
+// position in the low bits of the s-th smallest key.  t is bit 0 of word 0,
+// which the key of position 0 does not use.
+template <int N>
+__device__ __forceinline__ uint32_t shuffle_keys(const StreamAt& r01, uint32_t (&key)[N]) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int b = 0; b < (N + 3) / 4; ++b) {
+        const Words4 w = r01.block(TAG_SHUFFLE, b);
+        if (b == 0) t = w.w0 & 1u;
+        const uint32_t ws[4] = {w.w0, w.w1, w.w2, w.w3};
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (4 * b + q < N) key[4 * b + q] = (ws[q] & ~63u) | (uint32_t)(4 * b + q);
+    }
+    sort_keys<N>(key);
+    return t;
+}
+
+// Slot j's mask r in Z_p^* and reshare z in Z_p, from seed_01 (Alg. 7).  For
+// p < 2^32 slots j and j + 1 (j even) share block j / 2 (words 0, 1 and 2, 3),
+// kept in wm between the two; for p > 2^32 slot j takes block j, whose 64-bit
+// words give r and z.  j is a compile-time constant after unrolling.
+template <typename F>
+__device__ __forceinline__ void slot_draws(const StreamAt& r01, int j, Words4& wm, const F& f, typename F::T& r,
+                                           typename F::T& z) {
+    if constexpr (std::is_same<typename F::T, uint64_t>::value) {
+        const Words4 w = r01.block(TAG_MASK, (uint32_t)j);
+        r = 1 + __umul64hi(join64(w.w0, w.w1), f.p - 1);
+        z = __umul64hi(join64(w.w2, w.w3), f.p);
+    } else {
+        if ((j & 1) == 0) wm = r01.block(TAG_MASK, (uint32_t)(j >> 1));
+        r = draw_r((j & 1) ? wm.w2 : wm.w0, f.p);
+        z = draw_z((j & 1) ? wm.w3 : wm.w1, f.p);
+    }
+}
+
 // Alg. 7 from the flip through P2's zero test for one element: the 2-of-2
 // input (in0, in1) of Z_{2^l}, randomness of global index g.  Returns D'
 // (1 when some slot reconstructs to 0) and the flip bit t.  With CAP the
@@ -126,17 +165,7 @@ __device__ __forceinline__ T drelu_round1(T in0, T in1, uint64_t g, T mask, uint
     // The flip bit t and the shuffle keys, both from seed_01.
     const StreamAt r01 = s01.at(g);
     uint32_t key[N];
-    uint32_t t = 0;
-#pragma unroll
-    for (int b = 0; b < (N + 3) / 4; ++b) {
-        const Words4 w = r01.block(TAG_SHUFFLE, b);
-        if (b == 0) t = w.w0 & 1u;
-        const uint32_t ws[4] = {w.w0, w.w1, w.w2, w.w3};
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (4 * b + q < N) key[4 * b + q] = (ws[q] & ~63u) | (uint32_t)(4 * b + q);
-    }
-    sort_keys<N>(key);
+    const uint32_t t = shuffle_keys<N>(r01, key);
 
     // Flip: [x] := (-1)^t [x]  (both parties).
     const T a0 = t ? (T)((T)0 - in0) & mask : in0;
@@ -150,15 +179,7 @@ __device__ __forceinline__ T drelu_round1(T in0, T in1, uint64_t g, T mask, uint
     for (int j = 0; j < N; ++j) {
         // Mask r and reshare z of slot j.
         FT r, z;
-        if constexpr (WIDE) {
-            const Words4 w = r01.block(TAG_MASK, (uint32_t)j);
-            r = 1 + __umul64hi(join64(w.w0, w.w1), f.p - 1);
-            z = __umul64hi(join64(w.w2, w.w3), f.p);
-        } else {
-            if ((j & 1) == 0) wm = r01.block(TAG_MASK, (uint32_t)(j >> 1));
-            r = draw_r((j & 1) ? wm.w2 : wm.w0, f.p);
-            z = draw_z((j & 1) ? wm.w3 : wm.w1, f.p);
-        }
+        slot_draws<F>(r01, j, wm, f, r, z);
         FT w0, w1;
         const FT w = slot_messages<T, N, F>(a0k, nb1k, key[j] & 63u, r, z, f, w0, w1);
         least = w < least ? w : least;
@@ -267,17 +288,7 @@ __device__ __forceinline__ void drelu_element_group(const T* __restrict__ X0, co
 
     const StreamAt r01 = s01.at(g);
     uint32_t key[N];
-    uint32_t t = 0;
-#pragma unroll
-    for (int b = 0; b < (N + 3) / 4; ++b) {
-        const Words4 w = r01.block(TAG_SHUFFLE, b);
-        if (b == 0) t = w.w0 & 1u;
-        const uint32_t ws[4] = {w.w0, w.w1, w.w2, w.w3};
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (4 * b + q < N) key[4 * b + q] = (ws[q] & ~63u) | (uint32_t)(4 * b + q);
-    }
-    sort_keys<N>(key);
+    const uint32_t t = shuffle_keys<N>(r01, key);
 
     const T a0 = t ? (T)((T)0 - in0) & mask : in0;
     const T a1 = t ? (T)((T)0 - in1) & mask : in1;

@@ -12,9 +12,6 @@
 
 namespace bc {
 
-template <typename T, int V>
-using vec_t = T __attribute__((ext_vector_type(V)));
-
 // Alg. 4 / Alg. 5: P0 cut(x0, k1, k2), P1 -cut(-x1, k1, k2), in Z_{2^(l-k1-k2)}.
 template <typename TI, typename TO>
 struct OpTruncDet {

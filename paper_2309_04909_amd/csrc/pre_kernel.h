@@ -62,17 +62,7 @@ __global__ BC_KERNEL_ATTRS void k_expand(ExpandKArgs A, F f) {
         const uint64_t g = A.elem_base + e;
         const StreamAt r01 = A.s01.at(g);
         uint32_t key[N];
-        uint32_t t = 0;
-#pragma unroll
-        for (int b = 0; b < (N + 3) / 4; ++b) {
-            const Words4 w = r01.block(TAG_SHUFFLE, b);
-            if (b == 0) t = w.w0 & 1u;
-            const uint32_t ws[4] = {w.w0, w.w1, w.w2, w.w3};
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (4 * b + q < N) key[4 * b + q] = (ws[q] & ~63u) | (uint32_t)(4 * b + q);
-        }
-        sort_keys<N>(key);
+        const uint32_t t = shuffle_keys<N>(r01, key);
 #pragma unroll
         for (int k = 0; k < (N + 3) / 4; ++k) {
             uint32_t word = (k == 0) ? (t << 7) : 0u;

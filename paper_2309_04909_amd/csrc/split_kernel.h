@@ -74,7 +74,6 @@ __device__ __forceinline__ uint64_t unpack_slot(const uint32_t (&w)[Packing<N>::
 template <typename T, int N, typename F, int PARTY>
 __global__ BC_KERNEL_ATTRS void k_send(SplitKArgs A, F f_arg) {
     using FT = typename F::T;
-    constexpr bool WIDE = std::is_same<FT, uint64_t>::value;
     constexpr int W = Packing<N>::W;
     const F f = f_arg.vgpr();
     const T* X = static_cast<const T*>(A.in0);
@@ -86,17 +85,7 @@ __global__ BC_KERNEL_ATTRS void k_send(SplitKArgs A, F f_arg) {
         const T x = X[e] & mask;
         const StreamAt r01 = A.s01.at(g);
         uint32_t key[N];
-        uint32_t t = 0;
-#pragma unroll
-        for (int b = 0; b < (N + 3) / 4; ++b) {
-            const Words4 w = r01.block(TAG_SHUFFLE, b);
-            if (b == 0) t = w.w0 & 1u;
-            const uint32_t ws[4] = {w.w0, w.w1, w.w2, w.w3};
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (4 * b + q < N) key[4 * b + q] = (ws[q] & ~63u) | (uint32_t)(4 * b + q);
-        }
-        sort_keys<N>(key);
+        const uint32_t t = shuffle_keys<N>(r01, key);
         const T a = t ? (T)((T)0 - x) & mask : x;                    // flip
         const T ak = (PARTY == 0 ? a : (T)((T)0 - a) & mask) >> A.k_lo;
         uint32_t words[W];
@@ -106,15 +95,7 @@ __global__ BC_KERNEL_ATTRS void k_send(SplitKArgs A, F f_arg) {
 #pragma unroll
         for (int j = 0; j < N; ++j) {
             FT r, z;
-            if constexpr (WIDE) {
-                const Words4 w = r01.block(TAG_MASK, (uint32_t)j);
-                r = 1 + __umul64hi(join64(w.w0, w.w1), f.p - 1);
-                z = __umul64hi(join64(w.w2, w.w3), f.p);
-            } else {
-                if ((j & 1) == 0) wm = r01.block(TAG_MASK, (uint32_t)(j >> 1));
-                r = draw_r((j & 1) ? wm.w2 : wm.w0, f.p);
-                z = draw_z((j & 1) ? wm.w3 : wm.w1, f.p);
-            }
+            slot_draws<F>(r01, j, wm, f, r, z);
             pack_slot<N>(words, j, (uint64_t)party_message<T, N, F, PARTY>(ak, key[j] & 63u, r, z, f));
         }
 #pragma unroll
