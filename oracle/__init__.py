@@ -15,12 +15,16 @@ eye.  Module map:
 * ``params``     -- the prime p (bit length l_x + 1, Tab. 2), parameter checks,
                     the key-bit window (Sec. 6.1).
 * ``protocols``  -- Alg. 1 (SecureML truncation), Alg. 4/5 (deterministic
-                    truncation), Alg. 6 (modulo switch), Alg. 7 (DReLU),
-                    Alg. 8 (UBL ReLU), message accounting (Tab. 1).
+                    truncation), Alg. 6 (modulo switch), Alg. 7 (DReLU) also
+                    with the parties apart (packed round-1 messages), Alg. 8
+                    (UBL ReLU), Alg. drelu2 and the RSS ReLU (replicated
+                    sharing), Alg. linear (truncate-then-multiply) and
+                    multiply-then-truncate, message accounting (Tab. 1).
 * ``philox``     -- Philox4x32-10 (Salmon et al., SC'11) and the draws that
-                    turn its words into t, the shuffle, r_i, z_i, rho and the
-                    Beaver triple.  The paper does not fix a PRG; this is the
-                    build's definition of "generate ... using seed".
+                    turn its words into t, the shuffle, r_i, z_i, rho, the
+                    Beaver triples and the replicated-sharing values.  The
+                    paper fixes no PRG for the seeded draws; this module is
+                    the build's definition of them.
 
 Pins (what ties each part to the paper rather than to itself) live in
 ``tests/test_oracle_*.py``.  The Philox stream itself has no external

@@ -186,3 +186,31 @@ def test_rss_keybit_2p24(B, lx, k_lo):
     e, _, _ = OPR.rss_relu(*(v[idx] for v in xs), 64, lx, k_lo, default_prime(lx), seeds5, 41, g=idx.astype(U64))
     for j in range(3):
         assert np.array_equal(yr[j][idx], e[j])
+
+
+def test_layer_chain_73859072(B):
+    """The bench's layer chain: all 17 ResNet-18 tensors as products (f = 26)
+    in Z_2^64, truncated by 13 and ReLU'd in Z_2^51 by one batch launch with
+    per-segment truncation, replayed from a HIP graph: equal to the fused
+    single calls on every element, the oracle on samples of every segment."""
+    from paper_2309_04909_amd import batch as BT
+    prm = B.Params(51, 7, 11)
+    data = W.resnet18_relu(seed=4, batch=32, f=26)
+    segs = []
+    for i, (_, (x0, x1)) in enumerate(data):
+        d0, d1 = dev(x0), dev(x1)
+        segs.append(BT.Segment(d0, d1, torch.empty_like(d0), torch.empty_like(d1), op=B.BC_OP_RELU, nonce=200 + i,
+                               k_in=13))
+    rb = BT.RaggedBatch(prm, B.Seeds(*SEEDS), segs)
+    graph = rb.capture()
+    graph.replay()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(10)
+    for i, ((_, (x0, x1)), s) in enumerate(zip(data, segs)):
+        f0, f1 = B.trunc_relu(s.x0, s.x1, 64, 13, prm, B.Seeds(*SEEDS, s.nonce))
+        assert torch.equal(f0.view(torch.int64), s.y0.view(torch.int64)), f"segment {i}"
+        assert torch.equal(f1.view(torch.int64), s.y1.view(torch.int64)), f"segment {i}"
+        idx = sample_indices(x0.size, rng, k=200)
+        t0, t1 = OPR.trunc_det(x0[idx], x1[idx], 64, 13, 0)
+        o0, o1, _, _ = OPR.relu(t0, t1, 51, 7, 11, 251, SEEDS, 200 + i, g=idx.astype(U64))
+        assert np.array_equal(host(s.y0)[idx], o0) and np.array_equal(host(s.y1)[idx], o1), f"segment {i}"

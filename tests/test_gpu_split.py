@@ -113,3 +113,12 @@ def test_split_equals_fused_2p24(B, lx, k_lo):
                                     np.random.default_rng(4).integers(0, n, size=500)]))
     o0 = OPR.drelu_send(0, x0[idx], 64, lx, k_lo, default_prime(lx), SEEDS, 61, g=idx.astype(U64))
     assert np.array_equal(host(m0)[:, idx], o0)
+
+
+def test_split_zero_length(B):
+    prm, sd = B.Params(64, 18, 13), B.Seeds(*SEEDS)
+    e = torch.empty(0, dtype=torch.int64, device="cuda")
+    m0, m1 = B.drelu_send(0, e, prm, sd), B.drelu_send(1, e, prm, sd)
+    assert tuple(m0.shape) == (B.msg_words(19), 0)
+    r0, r1 = B.drelu_reply(m0, m1, prm, sd)
+    assert r0.numel() == 0 and B.drelu_finish(0, r0, prm, sd).numel() == 0
