@@ -156,6 +156,14 @@ bc::StreamKey stream_key(uint64_t seed, uint64_t nonce) {
 
 constexpr uint64_t kMaxIndex = 1ull << 48;
 
+// Element i of a call has global index elem_base + i, which must stay below
+// 2^48 (the counter layout of the draws).
+int check_indices(uint64_t n, uint64_t elem_base) {
+    if (elem_base > kMaxIndex || n > kMaxIndex - elem_base)
+        return fail(BC_ERR_ARG, "element indices must stay below 2^48");
+    return BC_OK;
+}
+
 int grid_cap(int per_cu) { return bc::device_cus() * per_cu; }
 
 // Schedule table: blocks per compute unit of the grid, per kernel kind and
@@ -203,8 +211,7 @@ int drelu_common(uint32_t op, const void* x0, const void* x1, void* y0, void* y1
             return fail(BC_ERR_RING, "input ring %u and output ring %u must share a storage width", ell_in, r.ell);
     }
     if (!seeds) return fail(BC_ERR_NULL, "seeds is NULL");
-    if (elem_base > kMaxIndex || n > kMaxIndex - elem_base)
-        return fail(BC_ERR_ARG, "element indices must stay below 2^48");
+    if (int rc_i = check_indices(n, elem_base)) return rc_i;
     if (acct) account(op, r, n, acct);
     if (n == 0) return BC_OK;
     if (!x0 || !x1 || !y0 || !y1) return fail(BC_ERR_NULL, "share pointer is NULL");
@@ -257,8 +264,7 @@ int rss_common(bool relu, const void* x0, const void* x1, const void* x2, void* 
     int rc = check_params(prm, &r);
     if (rc) return rc;
     if (!seeds) return fail(BC_ERR_NULL, "seeds is NULL");
-    if (elem_base > kMaxIndex || n > kMaxIndex - elem_base)
-        return fail(BC_ERR_ARG, "element indices must stay below 2^48");
+    if (int rc_i = check_indices(n, elem_base)) return rc_i;
     if (acct) account(relu ? BC_OP_RSS_RELU : BC_OP_RSS_DRELU, r, n, acct);
     if (n == 0) return BC_OK;
     if (!x0 || !x1 || !x2 || !y0 || !y1 || !y2) return fail(BC_ERR_NULL, "share pointer is NULL");
@@ -306,8 +312,7 @@ int split_common(bc::SplitLaunch::Kind kind, uint32_t party, const void* in0, co
     int rc = check_params(prm, &r);
     if (rc) return rc;
     if (!seeds) return fail(BC_ERR_NULL, "seeds is NULL");
-    if (elem_base > kMaxIndex || n > kMaxIndex - elem_base)
-        return fail(BC_ERR_ARG, "element indices must stay below 2^48");
+    if (int rc_i = check_indices(n, elem_base)) return rc_i;
     if (n == 0) return BC_OK;
     const bool reply = kind == bc::SplitLaunch::REPLY;
     if (!in0 || !out0 || (reply && (!in1 || !out1))) return fail(BC_ERR_NULL, "array pointer is NULL");
@@ -436,8 +441,7 @@ int pre_common(bool expand, uint32_t op, const void* x0, const void* x1, void* y
     int rc = check_params(prm, &r);
     if (rc) return rc;
     if (expand && !seeds) return fail(BC_ERR_NULL, "seeds is NULL");
-    if (elem_base > kMaxIndex || n > kMaxIndex - elem_base)
-        return fail(BC_ERR_ARG, "element indices must stay below 2^48");
+    if (int rc_i = check_indices(n, elem_base)) return rc_i;
     if (acct) account(op, r, n, acct);
     if (n == 0) return BC_OK;
     const uint32_t w = width_of_ring(r.ell);
@@ -577,7 +581,7 @@ int bc_prg_blocks(uint32_t* out, uint64_t n, uint32_t nblocks, uint64_t seed, ui
                   uint64_t elem_base, void* stream) {
     if (nblocks < 1 || nblocks > 256) return fail(BC_ERR_ARG, "nblocks = %u outside [1, 256]", nblocks);
     if (tag > 255) return fail(BC_ERR_ARG, "tag = %u outside [0, 255]", tag);
-    if (elem_base > kMaxIndex || n > kMaxIndex - elem_base) return fail(BC_ERR_ARG, "element indices must stay below 2^48");
+    if (int rc_i = check_indices(n, elem_base)) return rc_i;
     if (n == 0) return BC_OK;
     if (!out) return fail(BC_ERR_NULL, "out is NULL");
     if (!aligned(out, 4)) return fail(BC_ERR_ALIGN, "out misaligned");
@@ -738,8 +742,7 @@ int bc_mul_trunc(const void* x0, const void* x1, const void* y0, const void* y1,
         return fail(BC_ERR_ARG, "unknown truncation order %u", order);
     }
     if (!seeds) return fail(BC_ERR_NULL, "seeds is NULL");
-    if (elem_base > kMaxIndex || n > kMaxIndex - elem_base)
-        return fail(BC_ERR_ARG, "element indices must stay below 2^48");
+    if (int rc_i = check_indices(n, elem_base)) return rc_i;
     if (n == 0) return BC_OK;
     if (!x0 || !x1 || !y0 || !y1 || !z0 || !z1) return fail(BC_ERR_NULL, "share pointer is NULL");
     const uint32_t w = width_of_ring(ell);
