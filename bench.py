@@ -14,6 +14,7 @@ Printed as one JSON line (rank 0), with extra sections:
   kernels           per-kernel average durations (HIP events on the launch stream)
   roofline          the dominant kernel (the fused DReLU) against its ALU roofline
   cpu_baseline      the CPU oracle timed on a bounded sample of the same workload
+  kernels_alone     the step's two kernels each on its own
   batched_vs_plain  ResNet-18 ragged ReLU: one persistent graph launch vs 17 launches
   layer_chain       truncate-then-ReLU of every ResNet-18 layer in one batch launch
   precomputed_randomness  offline seed expansion, online call on shares + record
@@ -241,12 +242,20 @@ def run_keybit(torch, B, inputs, steps, warmup):
         wall = time.perf_counter() - t_start
     finally:
         B.set_schedule("stream", 0, standalone_bpc)
-    kern = {"trunc_det": timer.avg_ms("trunc_det"), "drelu": timer.avg_ms("drelu")}
-    # after the timed region: each kernel alone, on the standalone schedule
-    kern["trunc_det_alone"] = _event_ms(torch, lambda: B.trunc_det(z0, z1, c["ell"], c["trunc_k"], 0, out=(t0, t1)),
-                                        20, 5)
-    kern["drelu_alone"] = _event_ms(torch, lambda: B.drelu(x0, x1, prm, sd, out=(y0, y1)), 20, 5)
-    return wall, kern
+    return wall, {"trunc_det": timer.avg_ms("trunc_det"), "drelu": timer.avg_ms("drelu")}
+
+
+def run_alone(torch, B, inputs, steps, warmup):
+    """The step's two kernels each alone (one stream, the standalone schedule)."""
+    c = KEYBIT
+    x0, x1, z0, z1 = (to_dev(torch, a) for a in inputs)
+    prm, sd = B.Params(c["ell"], c["lx"], c["k_lo"]), B.Seeds(*SEEDS, 7)
+    y0, y1, t0, t1 = (torch.empty_like(a) for a in (x0, x1, z0, z1))
+    td = _event_ms(torch, lambda: B.trunc_det(z0, z1, c["ell"], c["trunc_k"], 0, out=(t0, t1)), steps, warmup)
+    dr = _event_ms(torch, lambda: B.drelu(x0, x1, prm, sd, out=(y0, y1)), steps, warmup)
+    gbs = 32 * c["n"] / (td * 1e-3) / 1e9
+    return {"drelu_ms": round(dr, 4), "drelu_gelem_s": round(c["n"] / dr / 1e6, 3), "trunc_det_ms": round(td, 4),
+            "trunc_det_gbs": round(gbs, 1), "trunc_det_hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def run_batched_vs_plain(torch, B, steps, warmup, batch=32):
@@ -623,8 +632,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--sections",
-                    default="cpu,batched,chain,precomputed,rss,linear,split,plain,serving,copy,matmul,sweep",
-                    help="comma list of extra sections: cpu, batched, chain, precomputed, rss, linear, split, "
+                    default="cpu,alone,batched,chain,precomputed,rss,linear,split,plain,serving,copy,matmul,sweep",
+                    help="comma list of extra sections: cpu, alone, batched, chain, precomputed, rss, linear, split, "
                          "plain, serving, copy, matmul, sweep")
     ap.add_argument("--cpu-sample", type=int, default=1 << 24)
     ap.add_argument("--cpu-workers", type=int, default=min(16, os.cpu_count() or 1))
@@ -664,7 +673,6 @@ def main():
                 "hbm_alg_bytes_per_launch": hbm_bytes,
                 "hbm_frac": round(hbm_bytes / (kern["drelu"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     td_gbs = 32 * c["n"] / (kern["trunc_det"] * 1e-3) / 1e9
-    td_alone_gbs = 32 * c["n"] / (kern["trunc_det_alone"] * 1e-3) / 1e9
     line = {
         "metric": METRIC, "value": round(value, 4), "unit": "Gelem/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
@@ -677,15 +685,12 @@ def main():
         "kernels": {"drelu_ms": round(kern["drelu"], 4), "trunc_det_ms": round(kern["trunc_det"], 4),
                     "drelu_gelem_s": round(c["n"] / kern["drelu"] / 1e6, 3),
                     "trunc_det_in_step_gbs": round(td_gbs, 1),
-                    "drelu_alone_ms": round(kern["drelu_alone"], 4),
-                    "trunc_det_alone_ms": round(kern["trunc_det_alone"], 4),
-                    "trunc_det_alone_gbs": round(td_alone_gbs, 1),
-                    "trunc_det_alone_hbm_frac": round(td_alone_gbs / HBM_PEAK_GBS, 4),
-                    "note": "*_ms without 'alone': HIP events around each kernel inside the timed steps; the "
-                            "truncation there runs on the narrow side grid, overlapped with the DReLU"},
+                    "note": "HIP events around each kernel inside the timed steps; the truncation runs on the "
+                            "narrow side grid, overlapped with the DReLU (kernels_alone: each on its own)"},
     }
     progress(f"headline: {value:.3f} Gelem/s, {ms_step:.4f} ms per step")
-    runs = [("batched", "batched_vs_plain", lambda: run_batched_vs_plain(torch, B, max(3, args.steps // 5), 2)),
+    runs = [("alone", "kernels_alone", lambda: run_alone(torch, B, inputs, 20, 5)),
+            ("batched", "batched_vs_plain", lambda: run_batched_vs_plain(torch, B, max(3, args.steps // 5), 2)),
             ("chain", "layer_chain", lambda: run_chain(torch, B, 10, 2)),
             ("precomputed", "precomputed_randomness", lambda: run_precomputed(torch, B, inputs, 10, 2)),
             ("rss", "replicated_sharing", lambda: run_rss(torch, B, inputs, 20, 5)),
