@@ -15,6 +15,7 @@ Printed as one JSON line (rank 0), with extra sections:
   roofline          the dominant kernel (the fused DReLU) against its ALU roofline
   cpu_baseline      the CPU oracle timed on a bounded sample of the same workload
   kernels_alone     the step's two kernels each on its own
+  streaming         trunc_det, trunc_prob and mod_switch alone: GB/s and %HBM
   batched_vs_plain  ResNet-18 ragged ReLU: one persistent graph launch vs 17 launches
   layer_chain       truncate-then-ReLU of every ResNet-18 layer in one batch launch
   precomputed_randomness  offline seed expansion, online call on shares + record
@@ -611,6 +612,30 @@ def run_split(torch, B, inputs, steps, warmup):
     return out
 
 
+def run_streaming(torch, B, inputs, steps, warmup):
+    """The HBM-bound streaming calls alone on the 2^24 products z (Z_2^64):
+    deterministic truncation (Alg. 5, 13 low bits), SecureML truncation
+    (Alg. 1, 13 bits) and the modulo switch (Alg. 6) of the shares read in
+    Z_2^60 into Z_p, p = 2^61 - 1.  Algorithmic bytes: both shares in, both
+    out, 8 bytes each."""
+    z0, z1 = to_dev(torch, inputs[2]), to_dev(torch, inputs[3])
+    n = z0.numel()
+    out = {"workload": f"{n} shared products in Z_2^64"}
+    o0, o1 = torch.empty_like(z0), torch.empty_like(z1)
+    calls = (("trunc_det", lambda: B.trunc_det(z0, z1, 64, 13, 0, out=(o0, o1))),
+             ("trunc_prob", lambda: B.trunc_prob(z0, z1, 64, 13, out=(o0, o1))))
+    for name, fn in calls:
+        ms = _event_ms(torch, fn, steps, warmup)
+        out[name] = {"ms": round(ms, 4), "gbs": round(32 * n / ms / 1e6, 1),
+                     "hbm_frac": round(32 * n / ms / 1e6 / HBM_PEAK_GBS, 4)}
+    p = (1 << 61) - 1
+    ms = _event_ms(torch, lambda: B.mod_switch(z0, z1, 60, p, out=(o0, o1)), steps, warmup)
+    out["mod_switch"] = {"ms": round(ms, 4), "gbs": round(32 * n / ms / 1e6, 1),
+                         "hbm_frac": round(32 * n / ms / 1e6 / HBM_PEAK_GBS, 4),
+                         "setting": "l' = 60 (shares read mod 2^60), p = 2^61 - 1"}
+    return out
+
+
 def run_copy(torch, steps, warmup, mib=512):
     """A plain device-to-device copy of known size: the reference for achievable
     HBM bandwidth and for scaling rocprofv3's FETCH_SIZE / WRITE_SIZE counters."""
@@ -632,9 +657,10 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--sections",
-                    default="cpu,alone,batched,chain,precomputed,rss,linear,split,plain,serving,copy,matmul,sweep",
-                    help="comma list of extra sections: cpu, alone, batched, chain, precomputed, rss, linear, split, "
-                         "plain, serving, copy, matmul, sweep")
+                    default="cpu,alone,streaming,batched,chain,precomputed,rss,linear,split,plain,serving,copy,"
+                            "matmul,sweep",
+                    help="comma list of extra sections: cpu, alone, streaming, batched, chain, precomputed, rss, "
+                         "linear, split, plain, serving, copy, matmul, sweep")
     ap.add_argument("--cpu-sample", type=int, default=1 << 24)
     ap.add_argument("--cpu-workers", type=int, default=min(16, os.cpu_count() or 1))
     args = ap.parse_args()
@@ -690,6 +716,7 @@ def main():
     }
     progress(f"headline: {value:.3f} Gelem/s, {ms_step:.4f} ms per step")
     runs = [("alone", "kernels_alone", lambda: run_alone(torch, B, inputs, 20, 5)),
+            ("streaming", "streaming", lambda: run_streaming(torch, B, inputs, 20, 5)),
             ("batched", "batched_vs_plain", lambda: run_batched_vs_plain(torch, B, max(3, args.steps // 5), 2)),
             ("chain", "layer_chain", lambda: run_chain(torch, B, 10, 2)),
             ("precomputed", "precomputed_randomness", lambda: run_precomputed(torch, B, inputs, 10, 2)),
