@@ -203,7 +203,9 @@ def to_dev(torch, a):
 def run_keybit(torch, B, inputs, steps, warmup):
     c = KEYBIT
     x0, x1, z0, z1 = (to_dev(torch, a) for a in inputs)
-    prm = B.Params(c["ell"], c["lx"], c["k_lo"])
+    # the key-bit window of Sec. 6.1 for |x| < 2^30 at f = 13 fractional bits
+    prm = B.keybit_params(c["ell"], 13, B.keybit_int_bits(1 << 30, 13), 0)
+    assert (prm.lx, prm.k_lo) == (c["lx"], c["k_lo"]), prm
     sd = B.Seeds(*SEEDS, 7)
     y0, y1 = torch.empty_like(x0), torch.empty_like(x1)
     t0, t1 = torch.empty_like(z0), torch.empty_like(z1)
@@ -708,6 +710,8 @@ def main():
                    "f": 13, "parallelism": "1 GPU, 3 simulated parties",
                    "streams": f"trunc_det on a second stream, {SIDE_TRUNC_BPC} block(s) per CU, beside the DReLU"},
         "roofline": roofline,
+        "messages": {"per_element_bits": B.msg_account(B.BC_OP_DRELU, B.Params(c["ell"], c["lx"], c["k_lo"]), 1)["bits"],
+                     "rounds": 2, "counted_by": "bc_msg_account (Tab. 1: (l_x + 1)^2 bits per share-holder)"},
         "kernels": {"drelu_ms": round(kern["drelu"], 4), "trunc_det_ms": round(kern["trunc_det"], 4),
                     "drelu_gelem_s": round(c["n"] / kern["drelu"] / 1e6, 3),
                     "trunc_det_in_step_gbs": round(td_gbs, 1),
