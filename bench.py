@@ -61,23 +61,30 @@ SEEDS = (0x243F6A8885A308D3, 0x13198A2E03707344, 0xA4093822299F31D0)
 # ------------------------------------------------------------- ALU op model
 
 
-def batcher_comparators(n: int) -> int:
-    """Comparators of the pruned Batcher network the kernel sorts keys with."""
+def pairwise_network(n: int):
+    """Comparators (lo, hi) of Parberry's pairwise sorting network on the next
+    power of two P >= n, pruned to the pairs inside [0, n): the network the
+    kernels sort the shuffle keys with."""
     P = 1
     while P < n:
         P *= 2
-    c = 0
-    p = 1
-    while p < P:
-        k = p
-        while k >= 1:
-            for j in range(k % p, P - k, 2 * k):
-                for i in range(min(k, P - j - k)):
-                    if (i + j) // (2 * p) == (i + j + k) // (2 * p) and i + j + k < n:
-                        c += 1
-            k //= 2
-        p *= 2
-    return c
+    net = []
+    a = 1
+    while a < P:                        # pairs at distance a: blocks of a, gaps of a
+        for start in range(a, P, 2 * a):
+            net.extend((b - a, b) for b in range(start, start + a))
+        a *= 2
+    a //= 4
+    e = 1
+    while a > 0:                        # merges at distances d a, d = e, e/2, ..., 1
+        d = e
+        while d > 0:
+            for start in range((d + 1) * a, P, 2 * a):
+                net.extend((b - d * a, b) for b in range(start, min(start + a, P)))
+            d //= 2
+        a //= 2
+        e = 2 * e + 1
+    return [(lo, hi) for lo, hi in net if hi < n]
 
 
 PHILOX_OPS = 60          # 10 rounds x (two 32x32->64 multiplies + four XORs)
@@ -97,7 +104,7 @@ def alg_ops_per_elem(op: str, lx: int) -> int:
     n = lx + 1
     wide = lx == 32
     blocks = (n + 3) // 4 + (n if wide else (n + 1) // 2) + TAIL_BLOCKS[op]
-    return (blocks * PHILOX_OPS + n * (SLOT_OPS_WIDE if wide else SLOT_OPS) + 2 * batcher_comparators(n)
+    return (blocks * PHILOX_OPS + n * (SLOT_OPS_WIDE if wide else SLOT_OPS) + 2 * len(pairwise_network(n))
             + TAIL_OPS[op])
 
 
