@@ -39,6 +39,7 @@
 #define K_MIN3(k) asm volatile("v_min3_u32 %0, %0, %1, %1" : "+v"(a##k) : "v"(b));
 #define K_ADD3(k) asm volatile("v_add3_u32 %0, %0, %1, %1" : "+v"(a##k) : "v"(b));
 #define K_BITOP3(k) asm volatile("v_bitop3_b32 %0, %0, %1, %1 bitop3:0x96" : "+v"(a##k) : "v"(b));
+#define K_BITOP3_S(k) asm volatile("v_bitop3_b32 %0, %0, %1, %2 bitop3:0x96" : "+v"(a##k) : "v"(b), "s"(bs));
 #define K_ALIGN(k) asm volatile("v_alignbit_b32 %0, %0, %1, %1" : "+v"(a##k) : "v"(b));
 #define K_CND(k) asm volatile("v_cndmask_b32_e64 %0, %0, %1, %2" : "+v"(a##k) : "v"(b), "s"(m));
 #define K_MULHI(k) asm volatile("v_mul_hi_u32 %0, %0, %1" : "+v"(a##k) : "v"(b));
@@ -94,6 +95,7 @@ KIND(22, mul_f32, K_MULF)
 KIND(23, add_f32, K_ADDF)
 KIND(24, cvt_f32_u32, K_CVTF)
 KIND(25, fma_f64, K_FMA64)
+KIND(26, bitop3_sgpr, K_BITOP3_S)
 
 typedef void (*KernelFn)(uint32_t*, int, uint32_t, uint32_t, uint64_t);
 
@@ -127,7 +129,7 @@ int main() {
         {"xor", k_xor}, {"xor_sgpr", k_xor_sgpr}, {"add", k_add}, {"add_inline_const", k_add_inline_const},
         {"sub", k_sub}, {"and", k_and}, {"and_literal", k_and_literal}, {"or", k_or}, {"lshr", k_lshr},
         {"ashr", k_ashr}, {"min_u32", k_min_u32}, {"max_u32", k_max_u32}, {"min3_u32", k_min3_u32},
-        {"add3_u32", k_add3_u32}, {"bitop3", k_bitop3}, {"alignbit", k_alignbit}, {"cndmask_e64", k_cndmask_e64},
+        {"add3_u32", k_add3_u32}, {"bitop3", k_bitop3}, {"bitop3_sgpr", k_bitop3_sgpr}, {"alignbit", k_alignbit}, {"cndmask_e64", k_cndmask_e64},
         {"mul_hi_u32", k_mul_hi_u32}, {"mul_lo_u32", k_mul_lo_u32}, {"mul_u32_u24", k_mul_u32_u24},
         {"mad_u64_u32", k_mad_u64_u32}, {"lshr_b64", k_lshr_b64}, {"mul_f32", k_mul_f32}, {"add_f32", k_add_f32},
         {"cvt_f32_u32", k_cvt_f32_u32}, {"fma_f64", k_fma_f64},
