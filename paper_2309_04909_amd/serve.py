@@ -16,6 +16,12 @@ The loop:
 Latency of a job = GPU completion time of its launch - its arrival time.
 Each job's result is exactly what a single call on it would give (per-job
 nonce, element indices 0..n-1), whichever launch it lands in.
+
+With a randomness budget, prepare() runs the offline phase before the
+arrivals: it expands the seeds' draws of jobs (in arrival order, while they
+fit the budget) into records kept resident in HBM.  Those jobs then run the
+online kernel (bc_drelu_pre / bc_relu_pre) on their shares and record, with
+the same results; a record is released when its launch has completed.
 """
 
 import time
@@ -41,6 +47,7 @@ class Job:
     y1: torch.Tensor = None
     done: float = None      # completion time (s after the start)
     admitted: float = None
+    rand: torch.Tensor = None   # resident randomness record (prepare), or None
 
 
 @dataclass
@@ -48,13 +55,16 @@ class Launch:
     event: torch.cuda.Event
     jobs: list
     batches: list = field(default_factory=list)
+    records: list = field(default_factory=list)   # kept alive until the launch has completed
     bytes: int = 0
 
 
 class Server:
     def __init__(self, pools, params, seeds: B.Seeds, hbm_budget: int, max_slots: int = 256, nstreams: int = 4,
-                 keep_outputs: bool = False):
-        """pools[ell] = (x0, x1) device share pools; params[ell] = B.Params of that ring."""
+                 keep_outputs: bool = False, rand_budget: int = 0):
+        """pools[ell] = (x0, x1) device share pools; params[ell] = B.Params of that ring;
+        rand_budget = HBM bytes for resident randomness records (0 = none)."""
+        self.rand_budget = rand_budget
         self.pools = pools
         self.params = params
         self.seeds = seeds
@@ -73,6 +83,24 @@ class Server:
                     fn(x0[:m], x1[:m], self.params[ell], self.seeds)
         torch.cuda.synchronize()
 
+    def _seeds(self, nonce):
+        return B.Seeds(self.seeds.seed01, self.seeds.seed02, self.seeds.seed12, nonce)
+
+    def prepare(self, jobs):
+        """Offline phase: records for jobs in arrival order while they fit the
+        randomness budget.  Returns (jobs given a record, record bytes, seconds)."""
+        t = time.perf_counter()
+        used = count = 0
+        for j in sorted(jobs, key=lambda j: j.arrival):
+            nb = B.rand_bytes(j.op, self.params[j.ell], j.n)
+            if used + nb > self.rand_budget:
+                continue
+            j.rand = B.rand_expand(j.op, self.params[j.ell], self._seeds(j.nonce), j.n)
+            used += nb
+            count += 1
+        torch.cuda.synchronize()
+        return count, used, time.perf_counter() - t
+
     def job_bytes(self, j: Job) -> int:
         return 4 * j.n * B.ring_width(j.ell)           # resident input shares + output shares
 
@@ -85,14 +113,21 @@ class Server:
                 x0, x1 = self.pools[j.ell]
                 j.y0 = torch.empty(j.n, dtype=x0.dtype, device=x0.device)
                 j.y1 = torch.empty(j.n, dtype=x1.dtype, device=x1.device)
+                L.bytes += self.job_bytes(j)
+                if j.rand is not None:               # online kernel on the resident record
+                    fn = B.relu_pre if j.op == B.BC_OP_RELU else B.drelu_pre
+                    fn(x0[j.offset:j.offset + j.n], x1[j.offset:j.offset + j.n], self.params[j.ell], j.rand,
+                       out=(j.y0, j.y1), stream=stream)
+                    L.records.append(j.rand)
+                    j.rand = None
+                    continue
                 seg = BT.Segment(x0[j.offset:j.offset + j.n], x1[j.offset:j.offset + j.n], j.y0, j.y1, op=j.op,
                                  nonce=j.nonce, elem_base=0)
                 by_ell.setdefault(j.ell, []).append(seg)
-                L.bytes += self.job_bytes(j)
             for ell, segs in by_ell.items():
                 if len(segs) == 1:
                     sg = segs[0]
-                    sd = B.Seeds(self.seeds.seed01, self.seeds.seed02, self.seeds.seed12, sg.nonce)
+                    sd = self._seeds(sg.nonce)
                     fn = B.relu if sg.op == B.BC_OP_RELU else B.drelu
                     fn(sg.x0, sg.x1, self.params[ell], sd, elem_base=sg.elem_base, out=(sg.y0, sg.y1), stream=stream)
                     continue

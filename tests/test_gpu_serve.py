@@ -67,3 +67,37 @@ def test_results_identical_alone_and_in_the_mix():
                            ell, lx, k_lo, default_prime(lx), seeds, j.nonce)
         assert np.array_equal(host(j.y0)[:k].astype(np.uint64), e0)
         assert np.array_equal(host(j.y1)[:k].astype(np.uint64), e1)
+
+
+def test_precomputed_randomness_in_the_mix():
+    """Jobs whose randomness was expanded offline (resident records, about half
+    of them by the budget) run the online kernel; every result still equals
+    the single fused call on that job."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_04909_amd import bicop as B
+    from paper_2309_04909_amd import serve as S
+    pool_n = 1 << 18
+    settings = {64: (64, 18, 13), 32: (32, 8, 8)}
+    pools = {}
+    for ell in (64, 32):
+        _, (x0, x1) = W.serving_values(60 + ell, pool_n, ell)
+        pools[ell] = (dev(x0), dev(x1))
+    params = {ell: B.Params(*settings[ell]) for ell in settings}
+    seeds = (27, 18, 28)
+    rng = np.random.default_rng(1)
+    arr = W.serving_arrivals(4, 20000.0, 60, min_log2=4, max_log2=16)
+    jobs = [S.Job(i, t, n, 0 if op == "drelu" else 1, ell, int(rng.integers(0, pool_n - n + 1)), 9000 + i)
+            for i, (t, n, op, ell) in enumerate(arr)]
+    total = sum(B.rand_bytes(j.op, params[j.ell], j.n) for j in jobs)
+    srv = S.Server(pools, params, B.Seeds(*seeds), hbm_budget=1 << 22, max_slots=5, nstreams=3, keep_outputs=True,
+                   rand_budget=int(total * 0.4))
+    with_rec, used, _ = srv.prepare(jobs)
+    assert 0 < with_rec < len(jobs) and used <= int(total * 0.4)
+    done = srv.run(jobs)
+    assert len(done) == len(jobs) and all(j.rand is None for j in done)
+    for j in done:
+        x0, x1 = pools[j.ell]
+        fn = B.relu if j.op == B.BC_OP_RELU else B.drelu
+        a0, a1 = fn(x0[j.offset:j.offset + j.n], x1[j.offset:j.offset + j.n], params[j.ell], B.Seeds(*seeds, j.nonce))
+        assert same(a0, j.y0) and same(a1, j.y1), j.jid
