@@ -3,15 +3,18 @@
  * AMD MI355X (gfx950).  Implemented by libbicop.so.
  *
  * Three parties are simulated on one GPU.  P0 holds share [x]_0, P1 holds
- * [x]_1, P2 is the helper.  Every call takes both share-holders' arrays;
- * P2's view exists only inside the library.  Round-1 messages live in
- * registers and are counted in bytes (bc_msg_account).  A caller-provided
- * capture buffer can materialise them for inspection.
+ * [x]_1, P2 is the helper.  The protocol calls take both share-holders'
+ * arrays (the replicated-sharing calls all three shares), so P2's view
+ * exists only inside the library; round-1 messages live in registers and
+ * are counted in bytes (bc_msg_account), and a caller-provided capture
+ * buffer can materialise them for inspection.  The parties-apart calls
+ * (bc_drelu_send, bc_drelu_reply, bc_drelu_finish) run one party's part
+ * each, with the messages bit-packed in device memory.
  *
  * Conventions for every entry point below:
- *  - Pointers named x*, y*, capture and out are DEVICE pointers owned by the
- *    caller.  None of these calls allocates or frees device memory, and
- *    none retains a pointer after it returns.
+ *  - Pointers named x*, y*, z*, d*, msg*, capture, rand and out are DEVICE
+ *    pointers owned by the caller.  None of these calls allocates or frees
+ *    device memory, and none retains a pointer after it returns.
  *  - Storage width follows the ring.  An element of Z_{2^l} is a uint32_t
  *    when l <= 32, else a uint64_t.  An element of Z_p is a uint32_t when
  *    p < 2^32, else a uint64_t.  Inputs are read modulo 2^l, so bits above
