@@ -85,12 +85,19 @@ struct RandOffsets {
 
 inline uint64_t align256(uint64_t v) { return (v + 255) & ~255ull; }
 
+// 64-bit words per element of a record's r/z section: the 2 npos values of
+// npos bits (p < 2^npos) packed floor(64 / npos) to a word; npos = 33 keeps
+// one value per word.
+constexpr uint32_t rz_words(uint32_t npos) {
+    return npos >= 33 ? 2 * npos : (2 * npos + 64 / npos - 1) / (64 / npos);
+}
+
 inline RandOffsets rand_offsets(uint32_t npos, bool relu, uint32_t ring_width, uint64_t n) {
     RandOffsets o;
     o.perm = 0;
     const uint64_t perm_bytes = 4ull * ((npos + 3) / 4) * n;
     o.rz = align256(perm_bytes);
-    const uint64_t rz_bytes = n * (npos <= 16 ? 4ull * npos : (npos <= 32 ? 8ull * npos : 16ull * npos));
+    const uint64_t rz_bytes = n * 8ull * rz_words(npos);
     o.tail = align256(o.rz + rz_bytes);
     o.total = o.tail + (uint64_t)ring_width * n * (relu ? 6 : 1);
     return o;

@@ -11,9 +11,10 @@
 // Record of a call on n elements, structure of arrays (each array [.][n]):
 //   perm  uint32[ceil(N/4)][n]: byte q of word k is sigma(4k + q); bit 7 of
 //         byte 0 of word 0 is t
-//   rz    N <= 16: uint32[N][n], r_j | z_j << 16            (p < 2^16)
-//         N <= 32: uint32[2N][n], r_j at row 2j, z_j at 2j+1
-//         N == 33: uint64[2N][n], same rows
+//   rz    uint64[rz_words(N)][n]: the values r_0, z_0, r_1, z_1, ... (value
+//         v = 2j for r_j, 2j + 1 for z_j) in N-bit fields (p < 2^N),
+//         floor(64 / N) to a word: value v is bits N (v % K) .. of word
+//         v / K, K = floor(64 / N).  N == 33: one value per word.
 //   tail  DReLU: T[n] rho.  ReLU: T[6][n] = [a]_0 [b]_0 [c]_0 [a]_1 [b]_1 [c]_1
 // Sections start at 256-byte boundaries.
 #pragma once
@@ -48,8 +49,9 @@ struct ExpandKArgs {
 
 template <int N>
 struct RzLayout {
-    static constexpr bool PACK16 = N <= 16;
     static constexpr bool WIDE = N == 33;
+    static constexpr int K = WIDE ? 1 : 64 / N;          // values per word
+    static constexpr uint64_t FIELD = WIDE ? ~0ull : (1ull << N) - 1;
 };
 
 // Offline: expand the seeds of n elements into the record.
@@ -72,23 +74,20 @@ __global__ BC_KERNEL_ATTRS void k_expand(ExpandKArgs A, F f) {
             A.perm[(uint64_t)k * n + e] = word;
         }
         Words4 wm = {0, 0, 0, 0};
+        uint64_t* rz = static_cast<uint64_t*>(A.rz);
+        constexpr int K = RzLayout<N>::K;
+        uint64_t acc = 0;                                  // the word being filled
 #pragma unroll
         for (int j = 0; j < N; ++j) {
-            if constexpr (RzLayout<N>::WIDE) {
-                const Words4 w = r01.block(TAG_MASK, (uint32_t)j);
-                uint64_t* rz = static_cast<uint64_t*>(A.rz);
-                rz[(uint64_t)(2 * j) * n + e] = 1 + __umul64hi(join64(w.w0, w.w1), f.p - 1);
-                rz[(uint64_t)(2 * j + 1) * n + e] = __umul64hi(join64(w.w2, w.w3), f.p);
-            } else {
-                if ((j & 1) == 0) wm = r01.block(TAG_MASK, (uint32_t)(j >> 1));
-                const uint32_t r = draw_r((j & 1) ? wm.w2 : wm.w0, (uint32_t)f.p);
-                const uint32_t z = draw_z((j & 1) ? wm.w3 : wm.w1, (uint32_t)f.p);
-                uint32_t* rz = static_cast<uint32_t*>(A.rz);
-                if constexpr (RzLayout<N>::PACK16) {
-                    rz[(uint64_t)j * n + e] = r | (z << 16);
-                } else {
-                    rz[(uint64_t)(2 * j) * n + e] = r;
-                    rz[(uint64_t)(2 * j + 1) * n + e] = z;
+            typename F::T r, z;
+            slot_draws<F>(r01, j, wm, f, r, z);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int v = 2 * j + h;
+                acc |= (uint64_t)(h ? z : r) << (N * (v % K) % 64);
+                if (v % K == K - 1 || v == 2 * N - 1) {
+                    rz[(uint64_t)(v / K) * n + e] = acc;
+                    acc = 0;
                 }
             }
         }
@@ -143,22 +142,19 @@ __global__ BC_KERNEL_ATTRS void k_drelu_pre(PreKArgs A, F f_arg) {
         const T nb1 = (T)((T)0 - a1) & mask;
         const T a0k = a0 >> k_lo, nb1k = nb1 >> k_lo;
         FT least = f.p;
+        const uint64_t* rz = static_cast<const uint64_t*>(A.rz);
+        constexpr int K = RzLayout<N>::K;
+        uint64_t cur = 0;                                  // the word being read
 #pragma unroll
         for (int j = 0; j < N; ++j) {
-            FT r, z;
-            if constexpr (RzLayout<N>::WIDE) {
-                const uint64_t* rz = static_cast<const uint64_t*>(A.rz);
-                r = rz[(uint64_t)(2 * j) * n + e];
-                z = rz[(uint64_t)(2 * j + 1) * n + e];
-            } else if constexpr (RzLayout<N>::PACK16) {
-                const uint32_t v = static_cast<const uint32_t*>(A.rz)[(uint64_t)j * n + e];
-                r = v & 0xFFFFu;
-                z = v >> 16;
-            } else {
-                const uint32_t* rz = static_cast<const uint32_t*>(A.rz);
-                r = rz[(uint64_t)(2 * j) * n + e];
-                z = rz[(uint64_t)(2 * j + 1) * n + e];
+            FT rv[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int v = 2 * j + h;
+                if (v % K == 0) cur = rz[(uint64_t)(v / K) * n + e];
+                rv[h] = (FT)((cur >> (N * (v % K) % 64)) & RzLayout<N>::FIELD);
             }
+            const FT r = rv[0], z = rv[1];
             const uint32_t pos = (perm[j >> 2] >> (8 * (j & 3))) & 63u;
             FT w0, w1;
             const FT w = slot_messages<T, N, F>(a0k, nb1k, pos, r, z, f, w0, w1);
