@@ -1,7 +1,9 @@
 """Summarise rocprofv3 runs of bench.py into profiles/.
 
 Inputs are the output directories of four runs of the same command:
-  --trace   rocprofv3 --kernel-trace --stats
+  --trace   rocprofv3 --kernel-trace --stats (with --timed-calls K, the
+            mean of each kernel's last K dispatches is listed beside the
+            all-call average: the timed steps without the warm-up launches)
   --fetch   rocprofv3 --pmc FETCH_SIZE
   --write   rocprofv3 --pmc WRITE_SIZE
   --valu    rocprofv3 --pmc SQ_INSTS_VALU SQ_WAVES SQ_ACTIVE_INST_VALU GRBM_GUI_ACTIVE   (optional)
@@ -91,6 +93,20 @@ def counters(d):
     return acc
 
 
+def last_calls_mean(d, k):
+    """{kernel name: mean duration in ns of its last k dispatches} from the
+    kernel trace (dispatches ordered by start time)."""
+    per = defaultdict(list)
+    for r in _rows(d, "kernel_trace.csv"):
+        per[r["Kernel_Name"]].append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    out = {}
+    for name, v in per.items():
+        v.sort()
+        tail = [dur for _, dur in v[-k:]]
+        out[name] = sum(tail) / len(tail)
+    return out
+
+
 def _match(name, key):
     return key in name
 
@@ -100,14 +116,20 @@ def _copy_name(names):
     return cands[0] if cands else None
 
 
-def summarise(trace, fetch, write, valu, name, cmd):
+def summarise(trace, fetch, write, valu, name, cmd, timed_calls=0):
     os.makedirs(PROFILES, exist_ok=True)
     stats = kernel_stats(trace)
+    last = last_calls_mean(trace, timed_calls) if timed_calls else {}
+    extra = f" Last {timed_calls} calls (us) |" if timed_calls else ""
     lines = [f"# rocprofv3 kernel statistics: {name}", "", f"Command: `{cmd}`", "",
-             "| Kernel | Calls | Average (us) | Total (ms) | Share |", "|---|---|---|---|---|"]
+             "| Kernel | Calls | Average (us) | Total (ms) | Share |" + extra,
+             "|---|---|---|---|---|" + ("---|" if timed_calls else "")]
     for r in sorted(stats, key=lambda r: -float(r.get("TotalDurationNs", 0))):
+        col = ""
+        if timed_calls:
+            col = f" {last[r['Name']] / 1e3:.2f} |" if r["Name"] in last else " |"
         lines.append(f"| `{r['Name'][:150]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
-                     f"{float(r['TotalDurationNs']) / 1e6:.3f} | {float(r['Percentage']):.1f}% |")
+                     f"{float(r['TotalDurationNs']) / 1e6:.3f} | {float(r['Percentage']):.1f}% |" + col)
     with open(os.path.join(PROFILES, f"{name}_kernel_stats.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
 
@@ -161,8 +183,9 @@ def main():
     ap.add_argument("--valu", default=None)
     ap.add_argument("--name", default="bench_keybit")
     ap.add_argument("--cmd", required=True)
+    ap.add_argument("--timed-calls", type=int, default=0)
     a = ap.parse_args()
-    print(json.dumps(summarise(a.trace, a.fetch, a.write, a.valu, a.name, a.cmd), indent=1))
+    print(json.dumps(summarise(a.trace, a.fetch, a.write, a.valu, a.name, a.cmd, a.timed_calls), indent=1))
 
 
 if __name__ == "__main__":

@@ -265,6 +265,18 @@ def test_profile_hash_ignores_comments_only():
     assert source_hash(["x.h"], read=lambda nm: src.replace('"a // b"', '"a // c"')) != base
 
 
+def test_profile_last_calls_mean(tmp_path):
+    """The timed-step column of the kernel statistics averages each kernel's
+    last k dispatches in start-time order, whatever order the trace lists."""
+    from paper_2309_04909_amd.prof_summary import last_calls_mean
+    rows = [("A", 50, 150), ("B", 0, 10), ("A", 0, 200), ("A", 300, 330), ("B", 20, 24)]   # A: 200, 100, 30
+    lines = ['"Kernel_Name","Start_Timestamp","End_Timestamp"'] + [f'"{k}",{s},{e}' for k, s, e in rows]
+    (tmp_path / "run").mkdir()
+    (tmp_path / "run" / "bench_kernel_trace.csv").write_text("\n".join(lines) + "\n")
+    assert last_calls_mean(str(tmp_path), 2) == {"A": 65.0, "B": 7.0}
+    assert last_calls_mean(str(tmp_path), 5) == {"A": 110.0, "B": 7.0}
+
+
 def test_rss_error_paths_without_gpu():
     """The replicated-sharing calls validate on the host like bc_drelu: every
     call below fails validation (or has n = 0), so nothing is launched."""
