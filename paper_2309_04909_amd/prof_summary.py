@@ -14,7 +14,8 @@ known number of bytes read and written), giving HBM bytes per launch.
 Writes profiles/<name>_kernel_stats.md, profiles/<name>_counters.md and
 profiles/traffic.json (bytes per launch per kernel, with the hash of the
 kernel sources they were measured on; bench.py reports null for a kernel
-whose sources changed since).
+whose sources changed since).  Given --trace alone it writes only the
+kernel statistics.
 
     python -m paper_2309_04909_amd.prof_summary --trace D1 --fetch D2 --write D3 [--valu D4] \\
         --name bench_keybit --cmd "<the profiled command>"
@@ -132,6 +133,8 @@ def summarise(trace, fetch, write, valu, name, cmd, timed_calls=0):
                      f"{float(r['TotalDurationNs']) / 1e6:.3f} | {float(r['Percentage']):.1f}% |" + col)
     with open(os.path.join(PROFILES, f"{name}_kernel_stats.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
+    if fetch is None or write is None:
+        return None
 
     fc, wc = counters(fetch), counters(write)
     names = sorted({k for k, _ in fc} | {k for k, _ in wc})
@@ -178,8 +181,8 @@ def summarise(trace, fetch, write, valu, name, cmd, timed_calls=0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True)
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
+    ap.add_argument("--fetch", default=None, help="without --fetch and --write only the kernel statistics are written")
+    ap.add_argument("--write", default=None)
     ap.add_argument("--valu", default=None)
     ap.add_argument("--name", default="bench_keybit")
     ap.add_argument("--cmd", required=True)
