@@ -82,3 +82,35 @@ def test_pre_rejects_small_buffer(B):
     assert ei.value.code == -7
     with pytest.raises(B.BicopError):
         B.rand_expand(B.BC_OP_RELU, prm, B.Seeds(1, 2, 3), 100, out=small)
+
+
+PACKING_CASES = [(64, 3, 5), (64, 4, 5), (64, 5, 5), (64, 6, 5), (64, 9, 5), (64, 10, 5), (64, 12, 5), (64, 21, 5),
+                 (64, 24, 5), (64, 25, 5), (32, 3, 2), (32, 5, 4), (20, 6, 3)]
+
+
+@pytest.mark.parametrize("op", ["drelu", "relu"])
+@pytest.mark.parametrize("ell,lx,k_lo", PACKING_CASES)
+def test_pre_record_packing_against_oracle(B, op, ell, lx, k_lo):
+    """Window counts N = l_x + 1 whose 2N draws fill the record's N-bit
+    fields (floor(64 / N) per word) exactly, or leave a partial last word:
+    every output and every captured message against the oracle, for n from
+    one element to a ragged block."""
+    rng = np.random.default_rng(7 * ell + lx)
+    prm = B.Params(ell, lx, k_lo)
+    seeds = B.Seeds(0x5151, 0x6262, 0x7373, 0x8484 + lx)
+    opc = B.BC_OP_RELU if op == "relu" else B.BC_OP_DRELU
+    ofn = OPR.relu if op == "relu" else OPR.drelu
+    bound = 1 << (k_lo + lx - 1)
+    for n in (1, 2, 63, 300):
+        print(f"pre packing op={op} ell={ell} lx={lx} k_lo={k_lo} n={n}", flush=True)
+        x = np.array([v % (1 << ell) for v in rng.integers(-bound + 1, bound, size=n).tolist()], dtype=np.uint64)
+        x0, x1 = W.share(x, ell, rng)
+        rand = B.rand_expand(opc, prm, seeds, n, elem_base=17)
+        y0, y1, cap = (B.relu_pre if op == "relu" else B.drelu_pre)(dev(x0), dev(x1), prm, rand, capture=True)
+        e0, e1, w0, w1 = ofn(x0.astype(np.uint64), x1.astype(np.uint64), ell, lx, k_lo, default_prime(lx),
+                             (0x5151, 0x6262, 0x7373), 0x8484 + lx, elem_base=17)
+        assert np.array_equal(host(y0).astype(np.uint64), e0)
+        assert np.array_equal(host(y1).astype(np.uint64), e1)
+        c = host(cap).astype(object).reshape(2, n, lx + 1)
+        assert np.array_equal(c[0], np.asarray(w0, dtype=object))
+        assert np.array_equal(c[1], np.asarray(w1, dtype=object))
