@@ -291,7 +291,9 @@ int bc_drelu_send(uint32_t party, const void* x, uint32_t* msg, uint64_t n, cons
 /* P2's part: unpacks both parties' messages (as bc_drelu_send writes them),
  * sets D' = 1 when some slot reconstructs to 0 mod p, and writes its reply,
  * a fresh sharing of D' in Z_{2^ell}: d0 = rho (to P0, rho from seed02) and
- * d1 = D' - rho (to P1). */
+ * d1 = D' - rho (to P1).  Slot values are not range-checked: a message with
+ * a slot value >= p (not one bc_drelu_send wrote) gives an unspecified D'
+ * for that element, and nothing else. */
 int bc_drelu_reply(const uint32_t* msg0, const uint32_t* msg1, void* d0, void* d1, uint64_t n,
                    const bc_drelu_params* prm, const bc_seeds* seeds, uint64_t elem_base, void* stream);
 
