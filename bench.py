@@ -100,7 +100,9 @@ TAIL_BLOCKS = {"drelu": 1, "relu": 3, "rss_drelu": 6, "rss_relu": 7}
 
 
 def alg_ops_per_elem(op: str, lx: int) -> int:
-    """32-bit integer operations per element of the fused kernel (the model in the design doc)."""
+    """32-bit integer operations per element of the fused kernel: 60 per Philox
+    block, a fixed count per slot, two per comparator of the sorting network and
+    a per-op tail (the method's work, as a GEMM's flops count 2mnk)."""
     n = lx + 1
     wide = lx == 32
     blocks = (n + 3) // 4 + (n if wide else (n + 1) // 2) + TAIL_BLOCKS[op]

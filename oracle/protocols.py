@@ -4,7 +4,7 @@ Shares are NumPy uint64 arrays with canonical values.  Party P_j holds
 [x]_j; all three parties are evaluated here side by side, and each step is
 labelled with the party that performs it.
 
-Readings of the paper taken here (each is listed in the design doc):
+Readings of the paper taken here, where it is silent or ambiguous:
 * Alg. 1 / Alg. 4 / Alg. 5, P1's share: 2^l - [x]_1 is reduced mod 2^l
   before the cut, i.e. P1 cuts -[x]_1 mod 2^l (the worked examples of Sec. 1
   and Sec. 5.1 write cut(-[x]_1, .)).
