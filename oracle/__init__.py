@@ -27,9 +27,10 @@ eye.  Module map:
                     the build's definition of them.
 
 Pins (what ties each part to the paper rather than to itself) live in
-``tests/test_oracle_*.py``.  The Philox stream itself has no external
-known-answer vector in this environment: it is pinned only by statistical
-and structural properties ("parity unpinned" against a published KAT).
+``tests/test_oracle_*.py``.  The Philox4x32-10 function is pinned against
+an independent implementation, rocRAND's header-only engine (every counter
+and key word), and by statistical and structural properties; no published
+known-answer vector is available in this environment.
 """
 
 from . import ring, params, protocols, philox  # noqa: F401

@@ -92,7 +92,7 @@ def test_tab1_row_through_the_abi():
 
 def test_error_paths_without_gpu():
     """Invalid arguments are rejected on the host before any GPU work.  Every call
-    here fails validation (or has n = 0), so nothing is launched even on a GPU machine."""
+    here fails validation (or has n = 0), so nothing is launched even where a GPU is present."""
     from paper_2309_04909_amd import bicop as B
     L = B.lib
     assert L.bc_trunc_det(None, None, None, None, 10, 65, 1, 0, None) == -2

@@ -1,9 +1,10 @@
 """Properties of the oracle's Philox4x32-10 stream and draws.
 
-No published known-answer vector for Philox is available in this
-environment, so the exact stream is "parity unpinned" against an external
-reference; these tests pin what the definition guarantees structurally and
-statistically: uniform, balanced words, avalanche after ten rounds, disjoint
+The function itself is pinned against rocRAND's engine in
+test_oracle_philox_rocrand.py (no published known-answer vector is
+available in this environment); these tests pin what the definition and the
+stream layout guarantee structurally and statistically: uniform, balanced
+words, avalanche after ten rounds, disjoint
 streams per (element, tag, block), valid permutations, draws in range and
 uniform, and element-local randomness.
 """
