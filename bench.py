@@ -182,26 +182,85 @@ def _cpu_model():
 # ------------------------------------------------------------------- GPU parts
 
 
+HIP_EVENT_DISABLE_SYSTEM_FENCE = 0x20000000      # hipEventCreateWithFlags flag (hip_runtime_api.h)
+
+
+def _hip_runtime():
+    """The HIP runtime this process already has loaded (torch's, which the
+    library resolves to as well), or None if there is not exactly one."""
+    import ctypes
+    try:
+        with open("/proc/self/maps") as f:
+            paths = sorted({ln.split()[-1] for ln in f if "libamdhip64" in ln})
+    except OSError:
+        return None
+    if len(paths) != 1:
+        return None
+    hip = ctypes.CDLL(paths[0])
+    hip.hipEventCreateWithFlags.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint]
+    hip.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+    hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+    return hip
+
+
 class Timer:
-    """HIP events on the stream a kernel is launched on (default: torch's current stream)."""
+    """HIP events on the stream a kernel is launched on (default: torch's
+    current stream), created with hipEventDisableSystemFence: they only time,
+    so recording them skips the system-scope cache writeback that a default
+    event does, which would also slow the launch after it.  Falls back to
+    torch's events if the runtime cannot be found."""
 
     def __init__(self, torch):
         self.torch = torch
         self.pairs = {}
+        self.hip = _hip_runtime()
+        self.kind = "HIP events without the system-scope fence" if self.hip else "torch.cuda.Event"
 
-    def start(self, stream=None):
-        e = self.torch.cuda.Event(enable_timing=True)
-        e.record(stream)
+    def _record(self, stream):
+        if self.hip is None:
+            e = self.torch.cuda.Event(enable_timing=True)
+            e.record(stream)
+            return e
+        import ctypes
+        e = ctypes.c_void_p()
+        rc = self.hip.hipEventCreateWithFlags(ctypes.byref(e), HIP_EVENT_DISABLE_SYSTEM_FENCE)
+        if rc != 0:
+            raise RuntimeError(f"hipEventCreateWithFlags failed ({rc})")
+        st = stream if stream is not None else self.torch.cuda.current_stream()
+        rc = self.hip.hipEventRecord(e, st.cuda_stream)
+        if rc != 0:
+            raise RuntimeError(f"hipEventRecord failed ({rc})")
         return e
 
+    def start(self, stream=None):
+        return self._record(stream)
+
     def stop(self, name, s, stream=None):
-        e = self.torch.cuda.Event(enable_timing=True)
-        e.record(stream)
-        self.pairs.setdefault(name, []).append((s, e))
+        self.pairs.setdefault(name, []).append((s, self._record(stream)))
 
     def avg_ms(self, name):
+        """Mean duration; call after the device has synchronised."""
         ps = self.pairs.get(name, [])
-        return sum(s.elapsed_time(e) for s, e in ps) / max(1, len(ps))
+        if self.hip is None:
+            return sum(s.elapsed_time(e) for s, e in ps) / max(1, len(ps))
+        import ctypes
+        tot = 0.0
+        for s, e in ps:
+            ms = ctypes.c_float()
+            rc = self.hip.hipEventElapsedTime(ctypes.byref(ms), s, e)
+            if rc != 0:
+                raise RuntimeError(f"hipEventElapsedTime failed ({rc})")
+            tot += ms.value
+        return tot / max(1, len(ps))
+
+    def release(self):
+        if self.hip is not None:
+            for ps in self.pairs.values():
+                for s, e in ps:
+                    self.hip.hipEventDestroy(s)
+                    self.hip.hipEventDestroy(e)
+        self.pairs = {}
 
 
 def to_dev(torch, a):
@@ -254,7 +313,9 @@ def run_keybit(torch, B, inputs, steps, warmup):
         wall = time.perf_counter() - t_start
     finally:
         B.set_schedule("stream", 0, standalone_bpc)
-    return wall, {"trunc_det": timer.avg_ms("trunc_det"), "drelu": timer.avg_ms("drelu")}
+    times = {"trunc_det": timer.avg_ms("trunc_det"), "drelu": timer.avg_ms("drelu"), "events": timer.kind}
+    timer.release()
+    return wall, times
 
 
 def run_alone(torch, B, inputs, steps, warmup):
@@ -733,7 +794,7 @@ def main():
                      "rounds": 2, "counted_by": "bc_msg_account (Tab. 1: (l_x + 1)^2 bits per share-holder)"},
         "kernels": {"drelu_ms": round(kern["drelu"], 4), "trunc_det_ms": round(kern["trunc_det"], 4),
                     "drelu_gelem_s": round(c["n"] / kern["drelu"] / 1e6, 3),
-                    "trunc_det_in_step_gbs": round(td_gbs, 1),
+                    "trunc_det_in_step_gbs": round(td_gbs, 1), "events": kern["events"],
                     "note": "HIP events around each kernel inside the timed steps; the truncation runs on the "
                             "narrow side grid, overlapped with the DReLU (kernels_alone: each on its own)"},
     }
