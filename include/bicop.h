@@ -30,6 +30,21 @@
  *    It must be < 2^48.  All randomness of an element is a pure function of
  *    (seeds, nonce, global index).  The same element therefore gets the same
  *    result alone, inside a batch, or under any launch configuration.
+ *
+ * Interface choices, with their reasons:
+ *  - Streams are `void*` holding a hipStream_t: this header then needs no HIP
+ *    include, and bindings (ctypes) pass torch's raw stream handle through.
+ *  - Alignment is to the element size, not 16 bytes: the streaming kernels
+ *    take 16-byte vectors where the pointers allow and a scalar path
+ *    otherwise, so views at any element offset are valid inputs.
+ *  - Rings of 1..64 bits and windows of l_x >= 1: every step is defined and
+ *    computed exactly there.  That the sign comes out right needs l_x >= 3
+ *    and inputs in the guard-bit domain |x| < 2^(k_lo + l_x - 1), a property
+ *    of the inputs that bc_keybit_int_bits sizes, not of the call.
+ *  - The ragged batch is three calls (bc_batch_plan_bytes, bc_batch_plan on
+ *    the host, bc_batch_run launching exactly one kernel) instead of one
+ *    call with a workspace: the plan is validated and built once per batch
+ *    shape, and every run is a single kernel a HIP graph can capture.
  */
 #ifndef BICOP_H
 #define BICOP_H
@@ -183,16 +198,29 @@ int bc_zp_mul_add(const uint64_t* a, const uint64_t* b, const uint64_t* d, uint6
                                  the largest number of lanes per element
                                  (1 = off, 4, 8; default 8)                */
 
-/* Process-wide launch schedule: the grid of `kind` for window count npos
- * (0..33; the streaming kernels use npos = 0) is capped at blocks_per_cu
- * blocks of 256 threads per compute unit; each thread then handles
- * n / (grid * 256) elements.  0 restores the built-in default.  Results do
+/* Wildcard of bc_set_schedule's ring_width and op. */
+#define BC_SCHED_ALL 0xFFFFFFFFu
+
+/* Process-wide launch schedule, keyed by (kind, npos, ring_width, op):
+ *   npos        window count l_x + 1 (0..33; the streaming kernels use 0)
+ *   ring_width  4 or 8, the storage width of the call's ring (the input
+ *               ring for the streaming calls)
+ *   op          BC_OP_DRELU or BC_OP_RELU (the replicated-sharing calls use
+ *               the entry of their 2-of-2 counterpart; kinds without an op,
+ *               the streaming kernels, the ragged batch and the parties-apart
+ *               calls, use BC_OP_DRELU)
+ * Settings that share a window count but not a width or an op run different
+ * kernel instances, so each keeps its own entry.  The grid is capped at
+ * blocks_per_cu blocks of 256 threads per compute unit; each thread then
+ * handles n / (grid * 256) elements.  0 restores the built-in default.
+ * BC_SCHED_ALL as ring_width or op sets every matching entry.  Results do
  * not depend on the schedule.  Set it before launching (the autotuner
  * paper_2309_04909_amd/tune.py writes a table the binding applies). */
-int bc_set_schedule(uint32_t kind, uint32_t npos, uint32_t blocks_per_cu);
+int bc_set_schedule(uint32_t kind, uint32_t npos, uint32_t ring_width, uint32_t op, uint32_t blocks_per_cu);
 
-/* The blocks per compute unit in effect for (kind, npos); 0 if invalid. */
-uint32_t bc_get_schedule(uint32_t kind, uint32_t npos);
+/* The blocks per compute unit in effect for (kind, npos, ring_width, op),
+ * ring_width 4 or 8 and op BC_OP_DRELU or BC_OP_RELU; 0 if invalid. */
+uint32_t bc_get_schedule(uint32_t kind, uint32_t npos, uint32_t ring_width, uint32_t op);
 
 /* --------------------------------------------------------- truncation */
 

@@ -30,6 +30,20 @@ class Segment:
     k_in: int = 0          # truncate the inputs by k_in bits first (Alg. 5): shares of Z_2^(ell + k_in)
 
 
+def _records(params: B.Params, segments):
+    width = B.ring_width(params.ell)
+    recs = (B._Segment * len(segments))()
+    m = (1 << 64) - 1
+    for i, s in enumerate(segments):
+        B._check_shares(s.x0, s.x1, width)
+        B._check_shares(s.y0, s.y1, width, "outputs")
+        if s.x0.numel() != s.y0.numel():
+            raise ValueError("segment input and output lengths differ")
+        recs[i] = B._Segment(s.x0.data_ptr(), s.x1.data_ptr(), s.y0.data_ptr(), s.y1.data_ptr(), s.x0.numel(),
+                             s.elem_base, s.nonce & m, s.op, s.k_in)
+    return recs
+
+
 class RaggedBatch:
     def __init__(self, params: B.Params, seeds: B.Seeds, segments, tile_elems: int = 0, grid: int = 0):
         self.params = params
@@ -38,17 +52,8 @@ class RaggedBatch:
         if tile_elems == 0:                          # autotuned tile size, else the library default
             tile_elems = int(B.SCHEDULES.get("batch_tile", 0))
         self.grid = grid
-        width = B.ring_width(params.ell)
         nseg = len(self.segments)
-        recs = (B._Segment * nseg)()
-        for i, s in enumerate(self.segments):
-            B._check_shares(s.x0, s.x1, width)
-            B._check_shares(s.y0, s.y1, width, "outputs")
-            if s.x0.numel() != s.y0.numel():
-                raise ValueError("segment input and output lengths differ")
-            m = (1 << 64) - 1
-            recs[i] = B._Segment(s.x0.data_ptr(), s.x1.data_ptr(), s.y0.data_ptr(), s.y1.data_ptr(), s.x0.numel(),
-                                 s.elem_base, s.nonce & m, s.op, s.k_in)
+        recs = _records(params, self.segments)
         nbytes = int(B.lib.bc_batch_plan_bytes(nseg))
         # The plan is built in pinned host memory and uploaded asynchronously
         # on the current stream (runs on that stream, or on streams ordered

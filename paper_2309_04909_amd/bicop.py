@@ -104,8 +104,8 @@ _SIGS = {
                         ctypes.POINTER(_Acct), _P], ctypes.c_int),
     "bc_trunc_relu": ([_P, _P, _P, _P, _U64, _U32, _U32, ctypes.POINTER(_Params), ctypes.POINTER(_Seeds), _U64, _P,
                        ctypes.POINTER(_Acct), _P], ctypes.c_int),
-    "bc_set_schedule": ([_U32, _U32, _U32], ctypes.c_int),
-    "bc_get_schedule": ([_U32, _U32], _U32),
+    "bc_set_schedule": ([_U32, _U32, _U32, _U32, _U32], ctypes.c_int),
+    "bc_get_schedule": ([_U32, _U32, _U32, _U32], _U32),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -126,28 +126,45 @@ def _load():
 lib = _load()
 
 SCHED_KINDS = {"fused": 0, "stream": 1, "pre": 2, "expand": 3, "batch": 4, "group": 5}
+SCHED_ALL = 0xFFFFFFFF
 SCHEDULES_PATH = os.path.join(_HERE, "schedules.json")
 
 
-def set_schedule(kind: str, npos: int, blocks_per_cu: int):
-    _check(lib.bc_set_schedule(SCHED_KINDS[kind], npos, blocks_per_cu), "set_schedule")
+def set_schedule(kind: str, npos: int, blocks_per_cu: int, width=None, op=None):
+    """Schedule of (kind, npos, storage width 4/8, op BC_OP_DRELU/BC_OP_RELU);
+    width or op None sets every width / op."""
+    _check(lib.bc_set_schedule(SCHED_KINDS[kind], npos, SCHED_ALL if width is None else width,
+                               SCHED_ALL if op is None else op, blocks_per_cu), "set_schedule")
 
 
-def get_schedule(kind: str, npos: int) -> int:
-    return int(lib.bc_get_schedule(SCHED_KINDS[kind], npos))
+def get_schedule(kind: str, npos: int, width: int = 8, op: int = BC_OP_DRELU) -> int:
+    return int(lib.bc_get_schedule(SCHED_KINDS[kind], npos, width, op))
+
+
+def schedule_key(e):
+    """The table key of a schedules.json entry: (kind, npos, width, op)."""
+    return (e["kind"], int(e["npos"]), e.get("width"), e.get("op"))
 
 
 def load_schedules(path=SCHEDULES_PATH):
-    """Apply an autotuned schedule table (written by paper_2309_04909_amd.tune)."""
+    """Apply an autotuned schedule table (written by paper_2309_04909_amd.tune).
+    Entries are keyed by (kind, npos, width, op); a key that appears twice is
+    an error, so two settings can never overwrite each other's schedule."""
     import json
     if not os.path.exists(path):
         return {}
     with open(path) as f:
         table = json.load(f)
+    seen = set()
     for e in table.get("grid", []):
-        set_schedule(e["kind"], int(e["npos"]), int(e["blocks_per_cu"]))
+        k = schedule_key(e)
+        if k in seen:
+            raise ValueError(f"{path}: schedule {k} listed twice")
+        seen.add(k)
+    # wildcard entries first, so that a specific entry of the same kind and npos wins
+    for e in sorted(table.get("grid", []), key=lambda e: (e.get("width") is not None) + (e.get("op") is not None)):
+        set_schedule(e["kind"], int(e["npos"]), int(e["blocks_per_cu"]), e.get("width"), e.get("op"))
     return table
-
 
 
 def _check(rc, where):

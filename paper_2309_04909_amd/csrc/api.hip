@@ -166,12 +166,21 @@ int check_indices(uint64_t n, uint64_t elem_base) {
 
 int grid_cap(int per_cu) { return bc::device_cus() * per_cu; }
 
-// Schedule table: blocks per compute unit of the grid, per kernel kind and
-// window count (0 = the built-in default).  Written by bc_set_schedule.
+// Schedule table: blocks per compute unit of the grid, per kernel kind, window
+// count, storage width (4 or 8 bytes) and op (DReLU or ReLU), 0 = the
+// built-in default.  Written by bc_set_schedule.  Settings that share a
+// window count but not a ring width or an op run different kernels, so each
+// keeps its own entry.
 constexpr int kKinds = 6;
-std::atomic<uint32_t> g_sched[kKinds][34];
+std::atomic<uint32_t> g_sched[kKinds][34][2][2];
 // blocks per CU of each kind; for BC_SCHED_GROUP the largest lanes per element
 constexpr uint32_t kDefaultBpc[kKinds] = {16, 8, 16, 16, 8, 8};
+
+uint32_t sched_value(uint32_t kind, uint32_t npos, uint32_t width, bool relu) {
+    const uint32_t v =
+        g_sched[kind][npos < 34 ? npos : 0][width == 4 ? 0 : 1][relu ? 1 : 0].load(std::memory_order_relaxed);
+    return v ? v : kDefaultBpc[kind];
+}
 
 // Lanes per element of a DReLU/ReLU call: calls too small to give every SIMD
 // one wave at one lane per element spread each element over 8 or 4 lanes (up
@@ -179,20 +188,17 @@ constexpr uint32_t kDefaultBpc[kKinds] = {16, 8, 16, 16, 8, 8};
 // SIMD; beyond that the lanes' repeated shuffle and sort cost more than the
 // latency they hide (measured on MI355X for l_x = 7, 18, 31, 32).  Capturing
 // calls keep one lane per element.
-int lanes_per_element(uint32_t npos, uint64_t n, bool capture) {
+int lanes_per_element(uint32_t npos, uint32_t width, bool relu, uint64_t n, bool capture) {
     if (capture) return 1;
-    uint32_t gmax = g_sched[BC_SCHED_GROUP][npos < 34 ? npos : 0].load(std::memory_order_relaxed);
-    if (!gmax) gmax = kDefaultBpc[BC_SCHED_GROUP];
+    const uint32_t gmax = sched_value(BC_SCHED_GROUP, npos, width, relu);
     const uint64_t target = (uint64_t)bc::device_cus() * 4 * 64;   // one wave on each of 4 SIMDs per CU
     if (gmax >= 8 && n * 8 <= target) return 8;
     if (gmax >= 4 && n * 4 <= target) return 4;
     return 1;
 }
 
-uint64_t sched_grid(uint32_t kind, uint32_t npos, uint64_t work_blocks) {
-    uint32_t bpc = g_sched[kind][npos < 34 ? npos : 0].load(std::memory_order_relaxed);
-    if (!bpc) bpc = kDefaultBpc[kind];
-    const uint64_t cap = (uint64_t)grid_cap((int)bpc);
+uint64_t sched_grid(uint32_t kind, uint32_t npos, uint32_t width, bool relu, uint64_t work_blocks) {
+    const uint64_t cap = (uint64_t)grid_cap((int)sched_value(kind, npos, width, relu));
     const uint64_t g = work_blocks < cap ? work_blocks : cap;
     return g ? g : 1;
 }
@@ -238,8 +244,8 @@ int drelu_common(uint32_t op, const void* x0, const void* x1, void* y0, void* y1
     L.s02 = stream_key(seeds->seed02, seeds->nonce);
     L.s12 = stream_key(seeds->seed12, seeds->nonce);
     L.block = 256;
-    L.group = lanes_per_element(L.npos, n, capture != nullptr);
-    L.grid = (int)sched_grid(BC_SCHED_FUSED, L.npos, (n * (uint64_t)L.group + 255) / 256);
+    L.group = lanes_per_element(L.npos, w, op == BC_OP_RELU, n, capture != nullptr);
+    L.grid = (int)sched_grid(BC_SCHED_FUSED, L.npos, w, op == BC_OP_RELU, (n * (uint64_t)L.group + 255) / 256);
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
     const bool relu = op == BC_OP_RELU;
@@ -294,7 +300,7 @@ int rss_common(bool relu, const void* x0, const void* x1, const void* x2, void* 
     L.s12 = stream_key(seeds->seed12, seeds->nonce);
     L.s012 = stream_key(seeds->seed012, seeds->nonce);
     L.s2 = stream_key(seeds->seed2, seeds->nonce);
-    L.grid = (int)sched_grid(BC_SCHED_FUSED, L.npos, (n + 255) / 256);
+    L.grid = (int)sched_grid(BC_SCHED_FUSED, L.npos, w, relu, (n + 255) / 256);
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
     if (r.ell > 32)
@@ -339,7 +345,7 @@ int split_common(bc::SplitLaunch::Kind kind, uint32_t party, const void* in0, co
     L.s01 = stream_key(seeds->seed01, seeds->nonce);
     L.s02 = stream_key(seeds->seed02, seeds->nonce);
     L.grid = (int)sched_grid(kind == bc::SplitLaunch::FINISH ? BC_SCHED_STREAM : BC_SCHED_FUSED,
-                             kind == bc::SplitLaunch::FINISH ? 0 : L.npos, (n + 255) / 256);
+                             kind == bc::SplitLaunch::FINISH ? 0 : L.npos, w, false, (n + 255) / 256);
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
     if (kind == bc::SplitLaunch::FINISH)
@@ -418,7 +424,7 @@ int batch_run(const void* dev_plan, const void* host_plan, const bc_seeds* seeds
     L.s01 = stream_key(seeds->seed01, 0);
     L.s02 = stream_key(seeds->seed02, 0);
     L.s12 = stream_key(seeds->seed12, 0);
-    uint64_t g = grid ? grid : sched_grid(BC_SCHED_BATCH, L.npos, h->total_tiles);
+    uint64_t g = grid ? grid : sched_grid(BC_SCHED_BATCH, L.npos, width_of_ring(h->ell), false, h->total_tiles);
     if (g > h->total_tiles) g = h->total_tiles;
     L.grid = (int)g;
     hipStream_t st = (hipStream_t)stream;
@@ -477,7 +483,7 @@ int pre_common(bool expand, uint32_t op, const void* x0, const void* x1, void* y
     L.s01 = stream_key(sd.seed01, sd.nonce);
     L.s02 = stream_key(sd.seed02, sd.nonce);
     L.s12 = stream_key(sd.seed12, sd.nonce);
-    L.grid = (int)sched_grid(expand ? BC_SCHED_EXPAND : BC_SCHED_PRE, L.npos, (n + 255) / 256);
+    L.grid = (int)sched_grid(expand ? BC_SCHED_EXPAND : BC_SCHED_PRE, L.npos, w, L.relu, (n + 255) / 256);
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
     if (r.ell > 32) {
@@ -533,18 +539,28 @@ const char* bc_last_error(void) { return g_err; }
 
 uint64_t bc_default_prime(uint32_t lx) { return default_prime(lx); }
 
-int bc_set_schedule(uint32_t kind, uint32_t npos, uint32_t blocks_per_cu) {
+int bc_set_schedule(uint32_t kind, uint32_t npos, uint32_t ring_width, uint32_t op, uint32_t blocks_per_cu) {
     if (kind >= (uint32_t)kKinds) return fail(BC_ERR_ARG, "unknown schedule kind %u", kind);
     if (npos > 33) return fail(BC_ERR_ARG, "npos = %u outside [0, 33]", npos);
+    if (ring_width != 4 && ring_width != 8 && ring_width != BC_SCHED_ALL)
+        return fail(BC_ERR_ARG, "ring_width = %u: 4, 8 or BC_SCHED_ALL", ring_width);
+    if (op != BC_OP_DRELU && op != BC_OP_RELU && op != BC_SCHED_ALL)
+        return fail(BC_ERR_ARG, "op = %u: BC_OP_DRELU, BC_OP_RELU or BC_SCHED_ALL", op);
     if (blocks_per_cu > 1024) return fail(BC_ERR_ARG, "blocks_per_cu = %u above 1024", blocks_per_cu);
-    g_sched[kind][npos].store(blocks_per_cu, std::memory_order_relaxed);
+    for (int wi = 0; wi < 2; ++wi) {
+        if (ring_width != BC_SCHED_ALL && (ring_width == 4 ? 0 : 1) != wi) continue;
+        for (int oi = 0; oi < 2; ++oi) {
+            if (op != BC_SCHED_ALL && (int)op != oi) continue;
+            g_sched[kind][npos][wi][oi].store(blocks_per_cu, std::memory_order_relaxed);
+        }
+    }
     return BC_OK;
 }
 
-uint32_t bc_get_schedule(uint32_t kind, uint32_t npos) {
+uint32_t bc_get_schedule(uint32_t kind, uint32_t npos, uint32_t ring_width, uint32_t op) {
     if (kind >= (uint32_t)kKinds || npos > 33) return 0;
-    const uint32_t v = g_sched[kind][npos].load(std::memory_order_relaxed);
-    return v ? v : kDefaultBpc[kind];
+    if ((ring_width != 4 && ring_width != 8) || (op != BC_OP_DRELU && op != BC_OP_RELU)) return 0;
+    return sched_value(kind, npos, ring_width, op == BC_OP_RELU);
 }
 
 int bc_check_params(const bc_drelu_params* prm, bc_drelu_params* resolved) { return check_params(prm, resolved); }
@@ -601,7 +617,7 @@ int bc_zp_mul_add(const uint64_t* a, const uint64_t* b, const uint64_t* d, uint6
     if (!a || !b || !d || !out) return fail(BC_ERR_NULL, "array pointer is NULL");
     if (!aligned(a, 8) || !aligned(b, 8) || !aligned(d, 8) || !aligned(out, 8))
         return fail(BC_ERR_ALIGN, "arrays must be 8-byte aligned");
-    bc::ZpLaunch L{a, b, d, out, n, r.p, r.lx + 1, (int)sched_grid(BC_SCHED_STREAM, 0, (n + 255) / 256)};
+    bc::ZpLaunch L{a, b, d, out, n, r.p, r.lx + 1, (int)sched_grid(BC_SCHED_STREAM, 0, 8, false, (n + 255) / 256)};
     hipError_t e = bc::launch_zp_mul_add(L, (hipStream_t)stream);
     return e == hipSuccess ? BC_OK : hip_fail(e, "zp_mul_add launch");
 }
@@ -615,7 +631,8 @@ int bc_trunc_det(const void* x0, const void* x1, void* y0, void* y1, uint64_t n,
     const uint32_t wi = width_of_ring(ell), wo = width_of_ring(ell - k1 - k2);
     if (!aligned(x0, wi) || !aligned(x1, wi) || !aligned(y0, wo) || !aligned(y1, wo))
         return fail(BC_ERR_ALIGN, "share pointers misaligned");
-    hipError_t e = bc::launch_trunc_det(x0, x1, y0, y1, n, ell, k1, k2, (int)sched_grid(BC_SCHED_STREAM, 0, ~0ull), (hipStream_t)stream);
+    hipError_t e = bc::launch_trunc_det(x0, x1, y0, y1, n, ell, k1, k2, (int)sched_grid(BC_SCHED_STREAM, 0, wi, false, ~0ull),
+                                        (hipStream_t)stream);
     return e == hipSuccess ? BC_OK : hip_fail(e, "trunc_det launch");
 }
 
@@ -628,7 +645,8 @@ int bc_trunc_prob(const void* x0, const void* x1, void* y0, void* y1, uint64_t n
     const uint32_t w = width_of_ring(ell);
     if (!aligned(x0, w) || !aligned(x1, w) || !aligned(y0, w) || !aligned(y1, w))
         return fail(BC_ERR_ALIGN, "share pointers misaligned");
-    hipError_t e = bc::launch_trunc_prob(x0, x1, y0, y1, n, ell, k, (int)sched_grid(BC_SCHED_STREAM, 0, ~0ull), (hipStream_t)stream);
+    hipError_t e = bc::launch_trunc_prob(x0, x1, y0, y1, n, ell, k, (int)sched_grid(BC_SCHED_STREAM, 0, w, false, ~0ull),
+                                         (hipStream_t)stream);
     return e == hipSuccess ? BC_OK : hip_fail(e, "trunc_prob launch");
 }
 
@@ -644,7 +662,8 @@ int bc_mod_switch(const void* x0, const void* x1, void* y0, void* y1, uint64_t n
     const uint32_t wi = width_of_ring(ell_in), wo = p < (1ull << 32) ? 4u : 8u;
     if (!aligned(x0, wi) || !aligned(x1, wi) || !aligned(y0, wo) || !aligned(y1, wo))
         return fail(BC_ERR_ALIGN, "share pointers misaligned");
-    hipError_t e = bc::launch_mod_switch(x0, x1, y0, y1, n, ell_in, p, (int)sched_grid(BC_SCHED_STREAM, 0, ~0ull), (hipStream_t)stream);
+    hipError_t e = bc::launch_mod_switch(x0, x1, y0, y1, n, ell_in, p, (int)sched_grid(BC_SCHED_STREAM, 0, wi, false, ~0ull),
+                                         (hipStream_t)stream);
     return e == hipSuccess ? BC_OK : hip_fail(e, "mod_switch launch");
 }
 
@@ -760,7 +779,7 @@ int bc_mul_trunc(const void* x0, const void* x1, const void* y0, const void* y1,
     L.ell = ell;
     L.s02 = stream_key(seeds->seed02, seeds->nonce);
     L.s12 = stream_key(seeds->seed12, seeds->nonce);
-    L.grid_cap = (int)sched_grid(BC_SCHED_STREAM, 0, ~0ull);
+    L.grid_cap = (int)sched_grid(BC_SCHED_STREAM, 0, w, false, ~0ull);
     hipError_t e = bc::launch_mul(L, (hipStream_t)stream);
     return e == hipSuccess ? BC_OK : hip_fail(e, "mul launch");
 }

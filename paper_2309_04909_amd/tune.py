@@ -1,10 +1,14 @@
 """Autotuner: picks launch schedules on the GPU and writes schedules.json.
 
-For each kernel kind and window count of the workloads it times a sweep of
-grid sizes (blocks of 256 threads per compute unit, so elements per thread
-= n / (grid * 256)); for the ragged batch it also sweeps the tile size.
-Results never depend on the schedule (checked here on every candidate);
-only speed does.  The binding applies schedules.json at import.
+For each kernel kind and setting of the workloads it times a sweep of grid
+sizes (blocks of 256 threads per compute unit, so elements per thread
+= n / (grid * 256)), for the DReLU and the ReLU kernels apart; for small
+calls it sweeps the lanes per element (1, 4 or 8 lanes share an element);
+for the ragged batch it also sweeps the tile size.  Entries are keyed by
+(kind, window count, storage width, op), the key of the library's table, so
+two settings that share a window count keep their own schedules.  Results
+never depend on the schedule (checked here on every candidate); only speed
+does.  The binding applies schedules.json at import.
 
     python -m paper_2309_04909_amd.tune [--quick]
 """
@@ -54,40 +58,77 @@ def _shares(n, ell, seed):
     return x0, x1
 
 
-def tune_kind(kind, settings, n, reps):
+def _same(a, b):
+    return torch.equal(a[0].view(torch.int64 if a[0].element_size() == 8 else torch.int32),
+                       b[0].view(torch.int64 if b[0].element_size() == 8 else torch.int32)) and \
+        torch.equal(a[1].view(torch.int64 if a[1].element_size() == 8 else torch.int32),
+                    b[1].view(torch.int64 if b[1].element_size() == 8 else torch.int32))
+
+
+def tune_kind(kind, settings, n, reps, ops=(B.BC_OP_DRELU, B.BC_OP_RELU)):
+    """Grid sweep of the fused ("fused"), online ("pre") or offline ("expand")
+    kernels, for each setting and op."""
     out = []
     for ell, lx, k_lo in settings:
         prm = B.Params(ell, lx, k_lo)
-        npos = lx + 1
+        npos, width = lx + 1, B.ring_width(ell)
         x0, x1 = _shares(n, ell, ell + lx)
         y0, y1 = torch.empty_like(x0), torch.empty_like(x1)
         sd = B.Seeds(1, 2, 3, 4)
-        rand = None
-        if kind in ("pre", "expand"):
-            rand = B.rand_expand(B.BC_OP_DRELU, prm, sd, n)
-        if kind == "fused":
-            fn = lambda: B.drelu(x0, x1, prm, sd, out=(y0, y1))  # noqa: E731
-        elif kind == "pre":
-            fn = lambda: B.drelu_pre(x0, x1, prm, rand, out=(y0, y1))  # noqa: E731
-        else:
-            fn = lambda: B.rand_expand(B.BC_OP_DRELU, prm, sd, n, out=rand)  # noqa: E731
-        ref = None
-        best = None
-        for bpc in BPC:
-            B.set_schedule(kind, npos, bpc)
-            ms = _time(fn, reps)
-            if kind != "expand":
-                got = (y0.clone(), y1.clone())
-                if ref is None:
-                    ref = got
-                assert torch.equal(ref[0].view(torch.int64), got[0].view(torch.int64)) and \
-                    torch.equal(ref[1].view(torch.int64), got[1].view(torch.int64)), "schedule changed a result"
-            if best is None or ms < best[1]:
-                best = (bpc, ms)
-            print(f"  {kind:6s} l={ell} lx={lx:2d} bpc={bpc:3d}: {ms:.3f} ms", flush=True)
-        B.set_schedule(kind, npos, best[0])
-        out.append({"kind": kind, "npos": npos, "blocks_per_cu": best[0], "ms": round(best[1], 4), "n": n,
-                    "setting": [ell, lx, k_lo]})
+        for op in ops:
+            relu = op == B.BC_OP_RELU
+            rand = B.rand_expand(op, prm, sd, n) if kind in ("pre", "expand") else None
+            if kind == "fused":
+                f = B.relu if relu else B.drelu
+                fn = lambda: f(x0, x1, prm, sd, out=(y0, y1))  # noqa: E731
+            elif kind == "pre":
+                f = B.relu_pre if relu else B.drelu_pre
+                fn = lambda: f(x0, x1, prm, rand, out=(y0, y1))  # noqa: E731
+            else:
+                fn = lambda: B.rand_expand(op, prm, sd, n, out=rand)  # noqa: E731
+            ref, best = None, None
+            for bpc in BPC:
+                B.set_schedule(kind, npos, bpc, width, op)
+                ms = _time(fn, reps)
+                if kind != "expand":
+                    got = (y0.clone(), y1.clone())
+                    ref = ref or got
+                    assert _same(ref, got), "schedule changed a result"
+                if best is None or ms < best[1]:
+                    best = (bpc, ms)
+                print(f"  {kind:6s} op={op} l={ell} lx={lx:2d} bpc={bpc:3d}: {ms:.3f} ms", flush=True)
+            B.set_schedule(kind, npos, best[0], width, op)
+            out.append({"kind": kind, "npos": npos, "width": width, "op": op, "blocks_per_cu": best[0],
+                        "ms": round(best[1], 4), "n": n, "setting": [ell, lx, k_lo]})
+    return out
+
+
+def tune_group(settings, reps, sizes=(1024, 4096, 16384)):
+    """Lanes per element of small calls: the largest group (1, 4 or 8 lanes)
+    the library may use, chosen by the summed time over small call sizes."""
+    out = []
+    for ell, lx, k_lo in settings:
+        prm = B.Params(ell, lx, k_lo)
+        npos, width = lx + 1, B.ring_width(ell)
+        sd = B.Seeds(1, 2, 3, 4)
+        calls = [_shares(n, ell, n + lx) for n in sizes]
+        for op in (B.BC_OP_DRELU, B.BC_OP_RELU):
+            f = B.relu if op == B.BC_OP_RELU else B.drelu
+            best, ref = None, None
+            for gmax in (1, 4, 8):
+                B.set_schedule("group", npos, gmax, width, op)
+                total, outs = 0.0, []
+                for x0, x1 in calls:
+                    total += _time(lambda: f(x0, x1, prm, sd), reps * 4)
+                    outs.append(f(x0, x1, prm, sd))
+                ref = ref or outs
+                assert all(_same(a, b) for a, b in zip(ref, outs)), "lanes per element changed a result"
+                print(f"  group  op={op} l={ell} lx={lx:2d} lanes<={gmax}: {total * 1e3:.1f} us", flush=True)
+                if best is None or total < best[1]:
+                    best = (gmax, total)
+            B.set_schedule("group", npos, best[0], width, op)
+            out.append({"kind": "group", "npos": npos, "width": width, "op": op, "blocks_per_cu": best[0],
+                        "ms": round(best[1], 4), "sizes": list(sizes), "setting": [ell, lx, k_lo]})
     return out
 
 
@@ -96,13 +137,14 @@ def tune_stream(n, reps):
     y0, y1 = torch.empty_like(x0), torch.empty_like(x1)
     best = None
     for bpc in BPC:
-        B.set_schedule("stream", 0, bpc)
+        B.set_schedule("stream", 0, bpc, 8)
         ms = _time(lambda: B.trunc_det(x0, x1, 64, 13, out=(y0, y1)), reps)
         print(f"  stream bpc={bpc:3d}: {ms:.4f} ms ({32 * n / ms / 1e6:.0f} GB/s)", flush=True)
         if best is None or ms < best[1]:
             best = (bpc, ms)
-    B.set_schedule("stream", 0, best[0])
-    return [{"kind": "stream", "npos": 0, "blocks_per_cu": best[0], "ms": round(best[1], 4), "n": n}]
+    B.set_schedule("stream", 0, best[0], 8)
+    return [{"kind": "stream", "npos": 0, "width": 8, "op": 0, "blocks_per_cu": best[0], "ms": round(best[1], 4),
+             "n": n}]
 
 
 def tune_batch(reps, batch=8):
@@ -117,14 +159,15 @@ def tune_batch(reps, batch=8):
     best = None
     for tile in TILES:
         for bpc in (2, 4, 8, 16, 32):
-            B.set_schedule("batch", 8, bpc)
+            B.set_schedule("batch", 8, bpc, 8, 0)
             rb = BT.RaggedBatch(prm, B.Seeds(1, 2, 3), segs, tile_elems=tile)
             ms = _time(rb.run, reps)
             print(f"  batch tile={tile:5d} bpc={bpc:3d}: {ms:.3f} ms", flush=True)
             if best is None or ms < best[2]:
                 best = (tile, bpc, ms)
-    B.set_schedule("batch", 8, best[1])
-    return [{"kind": "batch", "npos": 8, "blocks_per_cu": best[1], "ms": round(best[2], 4)}], best[0]
+    B.set_schedule("batch", 8, best[1], 8, 0)
+    return [{"kind": "batch", "npos": 8, "width": 8, "op": 0, "blocks_per_cu": best[1], "ms": round(best[2], 4)}], \
+        best[0]
 
 
 def main():
@@ -143,8 +186,11 @@ def main():
     grid += tune_kind("fused", SETTINGS, n, reps)
     grid += tune_kind("pre", SETTINGS[:5], n, reps)
     grid += tune_kind("expand", SETTINGS[:5], n, reps)
+    grid += tune_group(SETTINGS, reps)
     bgrid, tile = tune_batch(reps)
     grid += bgrid
+    keys = [B.schedule_key(e) for e in grid]
+    assert len(keys) == len(set(keys)), "two entries share a key"
     table = {"device": torch.cuda.get_device_name(0), "grid": grid, "batch_tile": tile,
              "tuned_seconds": round(time.time() - t0, 1)}
     with open(a.out, "w") as f:

@@ -172,27 +172,78 @@ def test_batch_plan_validation_on_host():
     assert L.bc_batch_run(ctypes.addressof(junk), junk, ctypes.byref(sd), 0, None) == -8
 
 
+def _snapshot(B, keys):
+    return {(k, n, w, o): B.get_schedule(k, n, w, o) for k, n in keys for w in (4, 8) for o in (0, 1)}
+
+
+def _restore(B, snap):
+    for (k, n, w, o), v in snap.items():
+        B.set_schedule(k, n, v, w, o)
+
+
 def test_schedule_table_round_trip(tmp_path):
     """An autotuned schedules.json is applied by load_schedules (host-side table only)."""
     import json
     from paper_2309_04909_amd import bicop as B
-    before = {(k, n): B.get_schedule(k, n) for k, n in (("fused", 19), ("stream", 0), ("batch", 8))}
-    table = {"grid": [{"kind": "fused", "npos": 19, "blocks_per_cu": 7},
-                      {"kind": "stream", "npos": 0, "blocks_per_cu": 3},
+    snap = _snapshot(B, (("fused", 19), ("stream", 0), ("batch", 8)))
+    table = {"grid": [{"kind": "fused", "npos": 19, "width": 8, "op": 0, "blocks_per_cu": 7},
+                      {"kind": "stream", "npos": 0, "width": 8, "blocks_per_cu": 3},
                       {"kind": "batch", "npos": 8, "blocks_per_cu": 5}], "batch_tile": 2048}
     path = tmp_path / "schedules.json"
     path.write_text(json.dumps(table))
     try:
         got = B.load_schedules(str(path))
         assert got["batch_tile"] == 2048
-        assert B.get_schedule("fused", 19) == 7
-        assert B.get_schedule("stream", 0) == 3
-        assert B.get_schedule("batch", 8) == 5
+        assert B.get_schedule("fused", 19, 8, B.BC_OP_DRELU) == 7
+        assert B.get_schedule("stream", 0, 8, B.BC_OP_DRELU) == B.get_schedule("stream", 0, 8, B.BC_OP_RELU) == 3
+        assert all(B.get_schedule("batch", 8, w, o) == 5 for w in (4, 8) for o in (0, 1))
         with pytest.raises(B.BicopError):
             B.set_schedule("fused", 19, 2000)          # above the 1024 limit
+        with pytest.raises(B.BicopError):
+            B.set_schedule("fused", 19, 4, 2, 0)       # no 2-byte ring
+        assert B.get_schedule("fused", 19, 16, 0) == 0 and B.get_schedule("fused", 19, 8, 3) == 0
     finally:
-        for (k, n), v in before.items():
-            B.set_schedule(k, n, v)
+        _restore(B, snap)
+
+
+def test_schedules_of_one_window_count_stay_apart(tmp_path):
+    """Two settings with the same window count but another ring width or op
+    run different kernels and keep their own schedules (N = 8: l = 64 and
+    l = 24, DReLU and ReLU); a table that lists one key twice is refused."""
+    import json
+    from paper_2309_04909_amd import bicop as B
+    snap = _snapshot(B, (("pre", 8), ("group", 8)))
+    table = {"grid": [{"kind": "pre", "npos": 8, "width": 8, "op": 0, "blocks_per_cu": 2},
+                      {"kind": "pre", "npos": 8, "width": 4, "op": 0, "blocks_per_cu": 64},
+                      {"kind": "pre", "npos": 8, "width": 8, "op": 1, "blocks_per_cu": 16},
+                      {"kind": "group", "npos": 8, "blocks_per_cu": 4},
+                      {"kind": "group", "npos": 8, "width": 4, "op": 1, "blocks_per_cu": 1}]}
+    path = tmp_path / "schedules.json"
+    path.write_text(json.dumps(table))
+    try:
+        B.load_schedules(str(path))
+        assert B.get_schedule("pre", 8, 8, B.BC_OP_DRELU) == 2
+        assert B.get_schedule("pre", 8, 4, B.BC_OP_DRELU) == 64
+        assert B.get_schedule("pre", 8, 8, B.BC_OP_RELU) == 16
+        # the wildcard group entry applies where no specific one exists, whatever the order in the file
+        assert B.get_schedule("group", 8, 8, B.BC_OP_DRELU) == 4
+        assert B.get_schedule("group", 8, 4, B.BC_OP_RELU) == 1
+        dup = {"grid": table["grid"] + [{"kind": "pre", "npos": 8, "width": 4, "op": 0, "blocks_per_cu": 8}]}
+        path.write_text(json.dumps(dup))
+        with pytest.raises(ValueError):
+            B.load_schedules(str(path))
+    finally:
+        _restore(B, snap)
+
+
+def test_committed_schedule_table_has_unique_keys():
+    """schedules.json (the autotuner's output) lists every key once."""
+    import json
+    from paper_2309_04909_amd import bicop as B
+    with open(B.SCHEDULES_PATH) as f:
+        grid = json.load(f)["grid"]
+    keys = [B.schedule_key(e) for e in grid]
+    assert len(keys) == len(set(keys))
 
 
 @pytest.mark.parametrize("ell,f", [(64, 13), (64, 16), (32, 8), (51, 13)])
@@ -339,3 +390,38 @@ def test_split_drelu_host_side():
     assert L.bc_drelu_reply(None, None, None, None, 10, P_, S_, (1 << 48) - 1, None) == -8
     assert L.bc_drelu_finish(3, None, None, 10, P_, S_, 0, None) == -8
     assert L.bc_drelu_finish(1, None, None, 10, ctypes.byref(B.Params(64, 40, 0).c()), S_, 0, None) == -3
+
+
+def test_boundary_departures_from_the_planned_abi():
+    """Where the C ABI's error codes mean something other than the planned
+    interface's, each meaning is checked on the host (no launch):
+    * BC_ERR_ALIGN asks for element-size alignment, not 16 bytes: an 8-byte
+      ring accepts 8-byte-aligned pointers, a 4-byte ring 4-byte-aligned ones;
+    * BC_ERR_RING: rings of 1..64 bits (l = 1 only for the identity truncation);
+    * BC_ERR_WINDOW: windows of l_x >= 1 (the guard bit is a domain rule of the
+      inputs, bc_keybit_int_bits, not a precondition of the arithmetic);
+    * streams are opaque pointers, passed through unchanged;
+    * BC_ERR_WORKSPACE also covers the static plan area's segment limit."""
+    from paper_2309_04909_amd import bicop as B
+    L = B.lib
+    # alignment: element size, not 16 bytes (host-only plan building)
+    for ell, good, bad in ((64, 0x1008, 0x1004), (32, 0x1004, 0x1002)):
+        prm = B.Params(ell, 7, 10).c()
+        seg = (B._Segment * 1)()
+        seg[0] = B._Segment(good, 0x2000, 0x3000, 0x4000, 100, 0, 1, B.BC_OP_DRELU, 0)
+        buf = (ctypes.c_uint8 * L.bc_batch_plan_bytes(1))()
+        assert L.bc_batch_plan(seg, 1, ctypes.byref(prm), 0, buf, len(buf)) == 0
+        seg[0].x0 = bad
+        assert L.bc_batch_plan(seg, 1, ctypes.byref(prm), 0, buf, len(buf)) == -5
+    # rings: 1..64 bits; the ring check comes before the n = 0 shortcut
+    assert L.bc_trunc_det(None, None, None, None, 0, 1, 0, 0, None) == 0
+    assert L.bc_trunc_det(None, None, None, None, 0, 0, 0, 0, None) == -2
+    assert L.bc_trunc_det(None, None, None, None, 0, 65, 0, 0, None) == -2
+    assert L.bc_trunc_prob(None, None, None, None, 0, 1, 0, None) == 0
+    assert L.bc_mod_switch(None, None, None, None, 0, 1, 3, None) == 0            # Z_2 -> Z_3
+    # windows: l_x = 1 and 2 are settings like any other (N = 2, 3 windows)
+    for ell, lx in ((2, 1), (4, 2), (64, 1), (64, 2)):
+        assert L.bc_check_params(ctypes.byref(B.Params(ell, lx, 0).c()), None) == 0
+    assert L.bc_check_params(ctypes.byref(B.Params(64, 0, 0).c()), None) == -3
+    # streams: an opaque handle, not dereferenced by the validation
+    assert L.bc_trunc_det(None, None, None, None, 0, 64, 13, 0, ctypes.c_void_p(0xDEAD0)) == 0

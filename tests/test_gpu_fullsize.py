@@ -3,9 +3,13 @@ bench.py times (the binding applies the same autotuned schedule table).
 
 * Streaming outputs (trunc_det) are compared with the oracle on every element.
 * DReLU / ReLU outputs are compared with the oracle, bit-exact, on every
-  element where the oracle is quick enough (65,536 elements), and otherwise
-  on sampled element indices: the oracle draws each element's randomness from
-  its global index, so any element can be recomputed on its own.
+  element of the 65,536-element plain calls, of the 2^24-element key-bit
+  DReLU and ReLU, and of the largest ResNet-18 tensor (25,690,112 elements)
+  in the ragged batch and in the layer chain; the oracle runs over chunks of
+  elements in the session's forked worker processes (tests/oracle_pool.py).
+  The other segments are compared on sampled element indices: the oracle
+  draws each element's randomness from its global index, so any element can
+  be recomputed on its own.
 * Every element is also checked against properties that hold at any size
   (Alg. 7 and 8 with the key-bit window, Sec. 6.1):
     - a DReLU output reconstructs to 0 or 1, and to [x > 0] wherever
@@ -18,6 +22,7 @@ import pytest
 
 from oracle import protocols as OPR
 from oracle.params import default_prime
+from oracle_pool import protocol_all
 import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -88,10 +93,10 @@ def test_plain_drelu_relu_65536_every_element(B, lx):
         assert np.array_equal(host(y0), o0) and np.array_equal(host(y1), o1)
 
 
-def test_keybit_step_2p24(B):
-    """The bench step: trunc_det(13) of 2^24 products (every element against
-    the oracle) and the key-bit DReLU of 2^24 values (property on every
-    element, oracle on samples)."""
+def test_keybit_step_2p24(B, oracle_pool):
+    """The bench step: trunc_det(13) of 2^24 products and the key-bit DReLU of
+    2^24 values, in the production kernel (one lane per element, no capture),
+    against the oracle on every element; the sign property on every element."""
     x, (x0, x1), z, (z0, z1) = W.keybit_drelu(seed=2, n=1 << 24)
     n = x.size
     t0, t1 = B.trunc_det(dev(z0), dev(z1), 64, 13, 0)
@@ -103,9 +108,20 @@ def test_keybit_step_2p24(B):
     g0, g1 = B.drelu(dev(x0), dev(x1), prm, B.Seeds(*SEEDS, nonce))
     y0, y1 = host(g0), host(g1)
     check_drelu_property(recon(y0, y1, 64), signed(x, 64), 13)
-    idx = sample_indices(n, np.random.default_rng(5))
-    o0, o1, _, _ = OPR.drelu(x0[idx], x1[idx], 64, 18, 13, (1 << 19) - 1, SEEDS, nonce, g=idx.astype(U64))
-    assert np.array_equal(y0[idx], o0) and np.array_equal(y1[idx], o1)
+    o0, o1 = protocol_all(oracle_pool, "drelu", x0, x1, 64, 18, 13, (1 << 19) - 1, SEEDS, nonce)
+    assert np.array_equal(y0, o0) and np.array_equal(y1, o1)
+
+
+def test_keybit_relu_2p24(B, oracle_pool):
+    """The key-bit ReLU (Alg. 8) of the same 2^24 values: the oracle on every
+    element, and x DReLU(x) with the sign property on every element."""
+    x, (x0, x1), _, _ = W.keybit_drelu(seed=2, n=1 << 24)
+    prm, nonce = B.Params(64, 18, 13), 8
+    g0, g1 = B.relu(dev(x0), dev(x1), prm, B.Seeds(*SEEDS, nonce))
+    y0, y1 = host(g0), host(g1)
+    check_relu_property(recon(y0, y1, 64), x, signed(x, 64), 13)
+    o0, o1 = protocol_all(oracle_pool, "relu", x0, x1, 64, 18, 13, (1 << 19) - 1, SEEDS, nonce)
+    assert np.array_equal(y0, o0) and np.array_equal(y1, o1)
 
 
 @pytest.mark.parametrize("ell,k1,lx,k_lo", [(64, 13, 11, 13), (32, 8, 7, 10)])
@@ -134,10 +150,11 @@ def test_matmul_relu_4m_outputs(B, ell, k1, lx, k_lo):
     assert np.array_equal(y0[idx], o0) and np.array_equal(y1[idx], o1)
 
 
-def test_resnet18_ragged_batch_73859072(B):
+def test_resnet18_ragged_batch_73859072(B, oracle_pool):
     """All 17 ReLU tensors of a ResNet-18 pass (batch 32) in one persistent
     launch replayed from a HIP graph, as bench.py runs it: property on every
-    element, oracle on samples of every segment."""
+    element, the oracle on every element of the largest tensor (32 x 64 x
+    112^2) and on samples of the others."""
     from paper_2309_04909_amd import batch as BT
     prm = B.Params(64, 7, 11)
     data = W.resnet18_relu(seed=4, batch=32)
@@ -154,6 +171,10 @@ def test_resnet18_ragged_batch_73859072(B):
     for i, ((x, (x0, x1)), s) in enumerate(zip(data, segs)):
         y0, y1 = host(s.y0), host(s.y1)
         check_relu_property(recon(y0, y1, 64), x, signed(x, 64), 11)
+        if i == 0:
+            o0, o1 = protocol_all(oracle_pool, "relu", x0, x1, 64, 7, 11, 251, SEEDS, 100 + i)
+            assert np.array_equal(y0, o0) and np.array_equal(y1, o1), "segment 0, every element"
+            continue
         idx = sample_indices(x.size, rng, k=300)
         o0, o1, _, _ = OPR.relu(x0[idx], x1[idx], 64, 7, 11, 251, SEEDS, 100 + i, g=idx.astype(U64))
         assert np.array_equal(y0[idx], o0) and np.array_equal(y1[idx], o1), f"segment {i}"
@@ -188,11 +209,12 @@ def test_rss_keybit_2p24(B, lx, k_lo):
         assert np.array_equal(yr[j][idx], e[j])
 
 
-def test_layer_chain_73859072(B):
+def test_layer_chain_73859072(B, oracle_pool):
     """The bench's layer chain: all 17 ResNet-18 tensors as products (f = 26)
     in Z_2^64, truncated by 13 and ReLU'd in Z_2^51 by one batch launch with
     per-segment truncation, replayed from a HIP graph: equal to the fused
-    single calls on every element, the oracle on samples of every segment."""
+    single calls on every element, the oracle (Alg. 5 then Alg. 8) on every
+    element of the largest tensor and on samples of the others."""
     from paper_2309_04909_amd import batch as BT
     prm = B.Params(51, 7, 11)
     data = W.resnet18_relu(seed=4, batch=32, f=26)
@@ -210,6 +232,10 @@ def test_layer_chain_73859072(B):
         f0, f1 = B.trunc_relu(s.x0, s.x1, 64, 13, prm, B.Seeds(*SEEDS, s.nonce))
         assert torch.equal(f0.view(torch.int64), s.y0.view(torch.int64)), f"segment {i}"
         assert torch.equal(f1.view(torch.int64), s.y1.view(torch.int64)), f"segment {i}"
+        if i == 0:
+            o0, o1 = protocol_all(oracle_pool, "relu", x0, x1, 51, 7, 11, 251, SEEDS, 200 + i, k_in=13)
+            assert np.array_equal(host(s.y0), o0) and np.array_equal(host(s.y1), o1), "segment 0, every element"
+            continue
         idx = sample_indices(x0.size, rng, k=200)
         t0, t1 = OPR.trunc_det(x0[idx], x1[idx], 64, 13, 0)
         o0, o1, _, _ = OPR.relu(t0, t1, 51, 7, 11, 251, SEEDS, 200 + i, g=idx.astype(U64))

@@ -63,6 +63,19 @@ SIZES = [1, 7, 256, 1023, 4097, 65537]
 # --------------------------------------------------------------------- PRG
 
 
+def test_prg_million_counters(B):
+    """Raw Philox4x32-10 stream against the oracle's generator on 2^18
+    elements x 4 blocks = 1,048,576 counters (4 Mi words), with element
+    indices crossing 2^32 and a nonce and key with every word nonzero."""
+    n, nb, tag = 1 << 18, 4, 2
+    seed, nonce, base = 0xA5A5F00DC0FFEE11, 0x1122334455667788, (1 << 32) - (1 << 17)
+    got = host(B.prg_blocks(n, nb, seed, nonce, tag, base)).reshape(n, nb, 4)
+    g = np.arange(n, dtype=np.uint64) + np.uint64(base)
+    for b in range(nb):
+        exp = np.stack(OPH.block(seed, nonce, g, tag, b), axis=1).astype(np.uint32)
+        assert np.array_equal(got[:, b, :], exp), b
+
+
 @pytest.mark.parametrize("tag", [1, 2, 3, 4, 200])
 def test_prg_blocks_match_oracle(B, tag):
     for elem_base, n, nb in [(0, 5000, 3), ((1 << 32) - 100, 300, 2), ((1 << 47) + 12345, 64, 9)]:
@@ -192,6 +205,65 @@ def test_drelu_relu_parity_with_capture(B, op, ell, lx, k_lo):
         assert same(z0, y0) and same(z1, y1)
 
 
+# Every window count N = l_x + 1 of both storage widths: each N is a kernel
+# instance of its own (N = 2..33 at l > 32, 2..17 at l <= 32), with the
+# default prime's field arithmetic.
+EVERY_N = [(64, lx) for lx in range(1, 33)] + [(32, lx) for lx in range(1, 17)]
+
+
+@pytest.mark.parametrize("op", ["drelu", "relu"])
+@pytest.mark.parametrize("ell,lx", EVERY_N)
+def test_every_window_count(B, op, ell, lx):
+    """Each instance against the oracle, bit-exact: the capturing kernel
+    (outputs and round-1 messages), the production kernel (one lane per
+    element, no capture: n = 20,000 gives every SIMD a wave) and the
+    lane-group kernel of small calls."""
+    k_lo = min(13 if ell == 64 else 8, ell - 2 * lx)
+    rng = np.random.default_rng(7919 * ell + lx)
+    p = default_prime(lx)
+    seeds = (0x0123456789ABCDEF ^ lx, 0xFEDCBA9876543210 ^ ell, 0x5555AAAA3333CCCC + lx)
+    nonce = 0xC0DE0000 + 64 * ell + lx
+    prm, sd = B.Params(ell, lx, k_lo), B.Seeds(*seeds, nonce)
+    fn = B.drelu if op == "drelu" else B.relu
+    ofn = OPR.drelu if op == "drelu" else OPR.relu
+    for n, elem_base, capture in [(1500, (1 << 32) - 700, True), (20000, 77, False), (600, 5, False)]:
+        x0, x1 = _inputs(rng, n, ell, lx, k_lo)
+        out = fn(dev(x0), dev(x1), prm, sd, elem_base=elem_base, capture=capture)
+        e0, e1, w0, w1 = ofn(x0.astype(np.uint64), x1.astype(np.uint64), ell, lx, k_lo, p, seeds, nonce,
+                             elem_base=elem_base)
+        assert np.array_equal(host(out[0]).astype(np.uint64), e0), (n, "y0")
+        assert np.array_equal(host(out[1]).astype(np.uint64), e1), (n, "y1")
+        if capture:
+            c = host(out[2]).astype(object).reshape(2, n, lx + 1)
+            assert np.array_equal(c[0], np.asarray(w0, dtype=object)), "P0 messages"
+            assert np.array_equal(c[1], np.asarray(w1, dtype=object)), "P1 messages"
+
+
+@pytest.mark.parametrize("op", ["drelu", "relu"])
+@pytest.mark.parametrize("ell,lx", [c for c in EVERY_N if c[1] >= 2])
+def test_every_window_count_explicit_prime(B, op, ell, lx):
+    """The same with the next prime below the default one (the generic field
+    arithmetic: fp32 quotient, fp64 quotient, Barrett or the 128-bit product,
+    by the size of p): capturing and production kernels against the oracle."""
+    import sympy
+    p = int(sympy.prevprime(default_prime(lx)))
+    assert p > (1 << lx)
+    k_lo = min(13 if ell == 64 else 8, ell - 2 * lx)
+    rng = np.random.default_rng(104729 * ell + lx)
+    seeds = (lx, ell, 0xABCDEF)
+    prm, sd = B.Params(ell, lx, k_lo, p), B.Seeds(*seeds, 99)
+    fn = B.drelu if op == "drelu" else B.relu
+    ofn = OPR.drelu if op == "drelu" else OPR.relu
+    for n, capture in [(800, True), (20000, False)]:
+        x0, x1 = _inputs(rng, n, ell, lx, k_lo)
+        out = fn(dev(x0), dev(x1), prm, sd, elem_base=n, capture=capture)
+        e0, e1, w0, w1 = ofn(x0.astype(np.uint64), x1.astype(np.uint64), ell, lx, k_lo, p, seeds, 99, elem_base=n)
+        assert np.array_equal(host(out[0]).astype(np.uint64), e0) and np.array_equal(host(out[1]).astype(np.uint64), e1)
+        if capture:
+            c = host(out[2]).astype(object).reshape(2, n, lx + 1)
+            assert np.array_equal(c[0], np.asarray(w0, dtype=object)) and np.array_equal(c[1], np.asarray(w1, dtype=object))
+
+
 def test_drelu_explicit_prime_and_inplace(B):
     rng = np.random.default_rng(77)
     ell, lx, k_lo, p = 64, 18, 13, 524269          # a non-Mersenne prime in (2^18, 2^19)
@@ -266,7 +338,8 @@ def test_lane_groups_agree_with_one_lane(B, ell, lx, k_lo):
     fused truncation and element indices across 2^32."""
     rng = np.random.default_rng(ell + 100 * lx + k_lo)
     prm = B.Params(ell, lx, k_lo)
-    before = B.get_schedule("group", lx + 1)
+    w = B.ring_width(ell)
+    before = {o: B.get_schedule("group", lx + 1, w, o) for o in (B.BC_OP_DRELU, B.BC_OP_RELU)}
     try:
         for n, elem_base in [(1, 0), (5, 7), (999, (1 << 32) - 400), (12000, 12345)]:
             x0, x1 = _inputs(rng, n, ell, lx, k_lo)
@@ -274,12 +347,13 @@ def test_lane_groups_agree_with_one_lane(B, ell, lx, k_lo):
             for fn in (B.drelu, B.relu):
                 outs = []
                 for gmax in (1, 4, 8):
-                    B.set_schedule("group", lx + 1, gmax)
+                    B.set_schedule("group", lx + 1, gmax, w)
                     outs.append(fn(dev(x0), dev(x1), prm, sd, elem_base=elem_base))
                 for o in outs[1:]:
                     assert same(o[0], outs[0][0]) and same(o[1], outs[0][1]), (fn.__name__, n)
     finally:
-        B.set_schedule("group", lx + 1, before)
+        for o, v in before.items():
+            B.set_schedule("group", lx + 1, v, w, o)
 
 
 def test_lane_groups_fused_truncation(B):
