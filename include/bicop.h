@@ -461,6 +461,27 @@ int bc_batch_plan(const bc_segment* segs, uint32_t nseg, const bc_drelu_params* 
  * kernel and nothing else, so it can be captured into a HIP graph. */
 int bc_batch_run(const void* dev_plan, const void* host_plan, const bc_seeds* seeds, uint32_t grid, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): bc_batch_run
+ * without a device plan.  The plan built by bc_batch_plan (host memory, read
+ * during the call only) is copied, by upload kernels enqueued on `stream`
+ * that carry its bytes as launch arguments, into a fixed area of
+ * BC_STATIC_PLAN_BYTES in device memory that the library holds on each GPU it
+ * runs on until the process ends; the batch kernel then reads it from there.
+ * Outputs are those of bc_batch_run on the same plan.  Nothing is allocated:
+ * no hipMalloc, hipFree or allocating library call.
+ *   - Plans above BC_STATIC_PLAN_BYTES (more than BC_STATIC_MAX_SEGMENTS
+ *     segments) fail with BC_ERR_WORKSPACE before anything is enqueued.
+ *   - Every call on one GPU shares that GPU's area.  Calls ordered on one
+ *     stream are safe; calls that overlap on one GPU (other streams, other
+ *     threads without ordering) race for the area and give undefined results.
+ *   - The first call on a device looks up the area's address (with that
+ *     device current) and keeps it.
+ * Other arguments and conventions as bc_batch_run. */
+#define BC_STATIC_PLAN_BYTES 65536u
+#define BC_STATIC_MAX_SEGMENTS 909u   /* largest nseg with bc_batch_plan_bytes(nseg) <= BC_STATIC_PLAN_BYTES */
+int bc_batch_run_static(const void* host_plan, const bc_seeds* seeds, uint32_t grid, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

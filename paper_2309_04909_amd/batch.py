@@ -71,6 +71,14 @@ class RaggedBatch:
         B._check(B.lib.bc_batch_run(self.dev_plan.data_ptr(), self.host_plan.data_ptr(),
                                     ctypes.byref(self._c_seeds), self.grid, B._stream(stream, self.dev_plan)), "batch_run")
 
+    def run_static(self, stream=None):
+        """Enqueue the batch through bc_batch_run_static on `stream` (default:
+        current): the plan goes into the library's fixed device area and
+        nothing is allocated.  Calls that overlap on one GPU race for that
+        area; calls on one stream are ordered."""
+        B._check(B.lib.bc_batch_run_static(self.host_plan.data_ptr(), ctypes.byref(self._c_seeds), self.grid,
+                                           B._stream(stream, self.segments[0].x0)), "batch_run_static")
+
     def capture(self):
         """Capture run() into a CUDA/HIP graph; returns the torch.cuda.CUDAGraph.
 

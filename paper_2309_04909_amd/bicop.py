@@ -21,6 +21,8 @@ BC_OP_DRELU = 0
 BC_OP_RELU = 1
 BC_OP_RSS_DRELU = 2
 BC_OP_RSS_RELU = 3
+BC_STATIC_PLAN_BYTES = 65536      # fixed device plan area of bc_batch_run_static
+BC_STATIC_MAX_SEGMENTS = 909
 BC_TRUNC_NONE, BC_TRUNC_AFTER, BC_TRUNC_BEFORE = 0, 1, 2
 LINKS = ("P0->P2", "P1->P2", "P2->P0", "P2->P1", "P0->P1", "P1->P0")
 
@@ -93,6 +95,7 @@ _SIGS = {
     "bc_batch_plan_bytes": ([_U32], _U64),
     "bc_batch_plan": ([ctypes.POINTER(_Segment), _U32, ctypes.POINTER(_Params), _U32, _P, _U64], ctypes.c_int),
     "bc_batch_run": ([_P, _P, ctypes.POINTER(_Seeds), _U32, _P], ctypes.c_int),
+    "bc_batch_run_static": ([_P, ctypes.POINTER(_Seeds), _U32, _P], ctypes.c_int),
     "bc_rand_bytes": ([_U32, ctypes.POINTER(_Params), _U64], _U64),
     "bc_rand_expand": ([_P, _U64, _U64, _U32, ctypes.POINTER(_Params), ctypes.POINTER(_Seeds), _U64, _P],
                        ctypes.c_int),

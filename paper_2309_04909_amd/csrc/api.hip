@@ -685,6 +685,22 @@ int bc_batch_run(const void* dev_plan, const void* host_plan, const bc_seeds* se
     return batch_run(dev_plan, host_plan, seeds, grid, stream);
 }
 
+int bc_batch_run_static(const void* host_plan, const bc_seeds* seeds, uint32_t grid, void* stream) {
+    if (!host_plan || !seeds) return fail(BC_ERR_NULL, "plan or seeds is NULL");
+    bc::BatchPlanHeader h;
+    memcpy(&h, host_plan, sizeof(h));
+    if (h.magic != bc::kBatchMagic) return fail(BC_ERR_ARG, "host_plan is not a plan from bc_batch_plan");
+    const uint64_t bytes = bc_batch_plan_bytes(h.nseg);
+    if (bytes > BC_STATIC_PLAN_BYTES)
+        return fail(BC_ERR_WORKSPACE, "plan of %u segments needs %llu bytes; the fixed plan area holds %u (%u segments)",
+                    h.nseg, (unsigned long long)bytes, (unsigned)BC_STATIC_PLAN_BYTES, (unsigned)BC_STATIC_MAX_SEGMENTS);
+    if (h.total_tiles == 0) return BC_OK;
+    void* dev_plan = nullptr;
+    hipError_t e = bc::static_plan_upload(host_plan, bytes, (hipStream_t)stream, &dev_plan);
+    if (e != hipSuccess) return hip_fail(e, "static plan upload");
+    return batch_run(dev_plan, host_plan, seeds, grid, stream);
+}
+
 uint64_t bc_rand_bytes(uint32_t op, const bc_drelu_params* prm, uint64_t n) {
     bc_drelu_params r;
     if (op != BC_OP_DRELU && op != BC_OP_RELU) return 0;

@@ -61,6 +61,11 @@ hipError_t launch_batch_u64_mid(const BatchLaunch& L, hipStream_t st);   // N 13
 hipError_t launch_batch_u64_hi(const BatchLaunch& L, hipStream_t st);    // N 25..33
 hipError_t launch_batch_u32(const BatchLaunch& L, hipStream_t st);       // N 2..17
 
+// Enqueues on `st` the copy of a host plan of `bytes` bytes (a multiple of 8,
+// at most BC_STATIC_PLAN_BYTES) into the current device's fixed plan area,
+// and returns that area's device address in *dev_plan.  Allocates nothing.
+hipError_t static_plan_upload(const void* host_plan, uint64_t bytes, hipStream_t st, void** dev_plan);
+
 // Precomputed-randomness calls: the offline expansion (expand = true, writes
 // `rand`) or the online DReLU/ReLU (reads `rand`).
 struct PreLaunch {

@@ -172,6 +172,34 @@ def test_batch_plan_validation_on_host():
     assert L.bc_batch_run(ctypes.addressof(junk), junk, ctypes.byref(sd), 0, None) == -8
 
 
+def test_static_batch_run_checks_on_host():
+    """bc_batch_run_static refuses, before any HIP call, a NULL plan or seeds,
+    a buffer that is not a plan and a plan larger than its fixed device area;
+    the area's stated limits agree with bc_batch_plan_bytes."""
+    from paper_2309_04909_amd import bicop as B
+    L = B.lib
+    assert L.bc_batch_plan_bytes(B.BC_STATIC_MAX_SEGMENTS) <= B.BC_STATIC_PLAN_BYTES
+    assert L.bc_batch_plan_bytes(B.BC_STATIC_MAX_SEGMENTS + 1) > B.BC_STATIC_PLAN_BYTES
+    hdr = open(os.path.join(ROOT, "include", "bicop.h")).read()
+    assert re.search(r"#define BC_STATIC_PLAN_BYTES %du" % B.BC_STATIC_PLAN_BYTES, hdr)
+    assert re.search(r"#define BC_STATIC_MAX_SEGMENTS %du" % B.BC_STATIC_MAX_SEGMENTS, hdr)
+    prm = B.Params(64, 7, 11).c()
+    sd = B.Seeds(1, 2, 3).c()
+    nseg = B.BC_STATIC_MAX_SEGMENTS + 1
+    seg = (B._Segment * nseg)()                    # empty segments: valid, and no pointers needed
+    for i in range(nseg):
+        seg[i] = B._Segment(None, None, None, None, 0, i, i, B.BC_OP_DRELU, 0)
+    nbytes = L.bc_batch_plan_bytes(nseg)
+    buf = (ctypes.c_uint8 * nbytes)()
+    assert L.bc_batch_plan(seg, nseg, ctypes.byref(prm), 0, buf, nbytes) == 0
+    assert L.bc_batch_run_static(buf, ctypes.byref(sd), 0, None) == -7
+    assert b"fixed plan area" in L.bc_last_error()
+    assert L.bc_batch_run_static(None, ctypes.byref(sd), 0, None) == -1
+    assert L.bc_batch_run_static(buf, None, 0, None) == -1
+    junk = (ctypes.c_uint8 * 64)()
+    assert L.bc_batch_run_static(junk, ctypes.byref(sd), 0, None) == -8
+
+
 def _snapshot(B, keys):
     return {(k, n, w, o): B.get_schedule(k, n, w, o) for k, n in keys for w in (4, 8) for o in (0, 1)}
 
