@@ -410,22 +410,46 @@ def run_chain(torch, B, steps, warmup, batch=32):
             B.trunc_det(s.x0, s.x1, 64, 13, 0, out=t)
             B.relu(t[0], t[1], prm, B.Seeds(*SEEDS, s.nonce), out=o)
 
-    # the three variants interleaved over three rounds, best of each (the first
+    # precomputed randomness: every segment's draws expanded offline into a
+    # resident record; the same chain then runs as one batch launch of the
+    # online element (shares and records streamed, no PRG)
+    rsegs = [BT.Segment(s.x0, s.x1, torch.empty_like(s.x0), torch.empty_like(s.x1), op=s.op, k_in=13)
+             for s in segs]
+
+    def expand():
+        for s, r in zip(segs, rsegs):
+            r.rand = B.rand_expand(B.BC_OP_RELU, prm, B.Seeds(*SEEDS, s.nonce), s.x0.numel(), out=r.rand)
+
+    expand()
+    rec_bytes = sum(r.rand.numel() for r in rsegs)
+    rgraph = BT.RaggedBatch(prm, B.Seeds(*SEEDS), rsegs).capture()
+
+    # the variants interleaved over three rounds, best of each (the first
     # timings after the host-side setup run on a GPU that is still clocking up)
-    ms_batch = ms_fused = ms_two = float("inf")
-    same_fused = same_two = True
+    ms_batch = ms_fused = ms_two = ms_online = ms_offline = float("inf")
+    same_fused = same_two = same_online = True
     for _ in range(3):
         ms_batch = min(ms_batch, _event_ms(torch, graph.replay, steps, warmup))
+        ms_online = min(ms_online, _event_ms(torch, rgraph.replay, steps, warmup))
+        same_online &= all(torch.equal(r.y0, s.y0) and torch.equal(r.y1, s.y1) for s, r in zip(segs, rsegs))
+        ms_offline = min(ms_offline, _event_ms(torch, expand, 2, 1))
         ms_fused = min(ms_fused, _event_ms(torch, fused, steps, warmup))
         same_fused &= all(torch.equal(o[0], s.y0) and torch.equal(o[1], s.y1) for s, o in zip(segs, outs))
         ms_two = min(ms_two, _event_ms(torch, two_pass, steps, warmup))
         same_two &= all(torch.equal(o[0], s.y0) and torch.equal(o[1], s.y1) for s, o in zip(segs, outs))
+    online_bytes = 4 * 8 * total + rec_bytes            # shares in and out, plus the records
     return {"workload": f"ResNet-18 ReLU inputs as products (f = 26) in Z_2^64, batch {batch}: 17 tensors, {total} "
                         "elements; trunc_det by 13 into Z_2^51, then ReLU (k_lo = 11, l_x = 7, p = 251)",
             "elements": total, "batched_ms": round(ms_batch, 4), "fused_calls_ms": round(ms_fused, 4),
             "two_pass_ms": round(ms_two, 4), "batched_gelem_s": round(total / ms_batch / 1e6, 3),
-            "identical_outputs": bool(same_fused and same_two),
+            "online_batched_ms": round(ms_online, 4), "online_gelem_s": round(total / ms_online / 1e6, 3),
+            "online_gbs": round(online_bytes / ms_online / 1e6, 1),
+            "online_hbm_frac": round(online_bytes / ms_online / 1e6 / HBM_PEAK_GBS, 4),
+            "record_bytes_per_elem": round(rec_bytes / total, 2), "offline_ms": round(ms_offline, 4),
+            "identical_outputs": bool(same_fused and same_two and same_online),
             "batched": "one persistent launch with per-segment truncation, replayed from a HIP graph",
+            "online_batched": "the same launch with every segment on its precomputed record (no PRG); bytes = 32 "
+                              "per element of shares plus the records",
             "fused_calls": "17 bc_trunc_relu launches", "two_pass": "17 x (bc_trunc_det + bc_relu)"}
 
 
@@ -496,6 +520,27 @@ def run_serving(torch, B, count=600):
     res.update({"offered_jobs_per_s": round(rate, 1), "jobs_with_records": with_rec,
                 "record_gib": round(rec_bytes / 2 ** 30, 2), "offline_s": round(offline_s, 3)})
     out["load_0.6_precomputed"] = res
+    # the 0.6 load once more as layer-chain traffic: every third job is a
+    # truncate-then-DReLU/ReLU step (products with 26 fractional bits in
+    # Z_2^64, truncated by 13 bits into Z_2^51 inside the launch; k_lo = 11,
+    # l_x = 7), with records resident as above
+    _, (c0, c1) = W.chain_values(102, pool_n)
+    cpools = dict(pools)
+    cpools[51] = (to_dev(torch, c0), to_dev(torch, c1))
+    cparams = dict(params)
+    cparams[51] = B.Params(51, 7, 11)
+    jobs = serving_jobs(S, 16, rate, count, pool_n)
+    for j in jobs[::3]:
+        j.ell, j.k_in = 51, 13
+    srv_c = S.Server(cpools, cparams, seeds, hbm_budget=budget, max_slots=256, nstreams=4, rand_budget=32 << 30)
+    srv_c.warmup()
+    with_rec, rec_bytes, offline_s = srv_c.prepare(jobs)
+    chain_rec = sum(1 for j in jobs if j.k_in and j.rand is not None)
+    res = S.summarize(srv_c.run(jobs))
+    res.update({"offered_jobs_per_s": round(rate, 1), "chain_jobs": len(jobs[::3]), "jobs_with_records": with_rec,
+                "chain_jobs_with_records": chain_rec, "record_gib": round(rec_bytes / 2 ** 30, 2),
+                "offline_s": round(offline_s, 3)})
+    out["load_0.6_chain_precomputed"] = res
     return out
 
 

@@ -420,11 +420,16 @@ int bc_relu_pre(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, 
 /* ------------------------------------------------------ ragged batching */
 
 /* One segment of a ragged batch: a share pair of its own length, op, nonce,
- * global element offset and input truncation.  Every element of a segment
- * gets exactly the result of bc_drelu / bc_relu (k_in = 0) or bc_trunc_drelu /
- * bc_trunc_relu with k1 = k_in on that segment, with seeds->nonce = nonce and
- * the same elem_base.  Outputs of one segment must not overlap inputs or
- * outputs of another. */
+ * global element offset and input truncation, and optionally a precomputed
+ * randomness record.  Every element of a segment gets exactly the result of
+ * bc_drelu / bc_relu (k_in = 0) or bc_trunc_drelu / bc_trunc_relu with
+ * k1 = k_in on that segment, with seeds->nonce = nonce and the same
+ * elem_base.  A segment with a record (rand != NULL, from bc_rand_expand for
+ * the segment's op, the batch's setting and its n) takes every draw from the
+ * record instead of the seeds: its result is that of the fused call with the
+ * seeds, nonce and elem_base the record was expanded with, and the segment's
+ * own nonce and elem_base are not used.  Outputs of one segment must not
+ * overlap inputs or outputs of another. */
 typedef struct {
     const void* x0;
     const void* x1;
@@ -438,10 +443,13 @@ typedef struct {
                             input share (Alg. 5); the inputs are then
                             shares of Z_{2^(ell + k_in)}, of the storage
                             width of ell.  0 = none                      */
+    const void* rand;    /* NULL, or a device record of bc_rand_expand
+                            (16-byte aligned)                          */
+    uint64_t rand_bytes; /* bytes of rand, >= bc_rand_bytes(op, prm, n) */
 } bc_segment;
 
 /* Bytes of the plan buffer for nseg segments: a 64-byte header, the segment
- * table (64 bytes per segment) and the first tile of every segment
+ * table (80 bytes per segment) and the first tile of every segment
  * (8 bytes per segment, plus one). */
 uint64_t bc_batch_plan_bytes(uint32_t nseg);
 
@@ -479,7 +487,7 @@ int bc_batch_run(const void* dev_plan, const void* host_plan, const bc_seeds* se
  *     device current) and keeps it.
  * Other arguments and conventions as bc_batch_run. */
 #define BC_STATIC_PLAN_BYTES 65536u
-#define BC_STATIC_MAX_SEGMENTS 909u   /* largest nseg with bc_batch_plan_bytes(nseg) <= BC_STATIC_PLAN_BYTES */
+#define BC_STATIC_MAX_SEGMENTS 743u   /* largest nseg with bc_batch_plan_bytes(nseg) <= BC_STATIC_PLAN_BYTES */
 int bc_batch_run_static(const void* host_plan, const bc_seeds* seeds, uint32_t grid, void* stream);
 
 #ifdef __cplusplus

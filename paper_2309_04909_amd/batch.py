@@ -28,6 +28,7 @@ class Segment:
     nonce: int = 0
     elem_base: int = 0
     k_in: int = 0          # truncate the inputs by k_in bits first (Alg. 5): shares of Z_2^(ell + k_in)
+    rand: torch.Tensor = None   # precomputed randomness record (bicop.rand_expand), or None: draws from the seeds
 
 
 def _records(params: B.Params, segments):
@@ -39,8 +40,9 @@ def _records(params: B.Params, segments):
         B._check_shares(s.y0, s.y1, width, "outputs")
         if s.x0.numel() != s.y0.numel():
             raise ValueError("segment input and output lengths differ")
+        rp, rb = (s.rand.data_ptr(), s.rand.numel() * s.rand.element_size()) if s.rand is not None else (None, 0)
         recs[i] = B._Segment(s.x0.data_ptr(), s.x1.data_ptr(), s.y0.data_ptr(), s.y1.data_ptr(), s.x0.numel(),
-                             s.elem_base, s.nonce & m, s.op, s.k_in)
+                             s.elem_base, s.nonce & m, s.op, s.k_in, rp, rb)
     return recs
 
 

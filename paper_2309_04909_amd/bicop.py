@@ -22,7 +22,7 @@ BC_OP_RELU = 1
 BC_OP_RSS_DRELU = 2
 BC_OP_RSS_RELU = 3
 BC_STATIC_PLAN_BYTES = 65536      # fixed device plan area of bc_batch_run_static
-BC_STATIC_MAX_SEGMENTS = 909
+BC_STATIC_MAX_SEGMENTS = 743
 BC_TRUNC_NONE, BC_TRUNC_AFTER, BC_TRUNC_BEFORE = 0, 1, 2
 LINKS = ("P0->P2", "P1->P2", "P2->P0", "P2->P1", "P0->P1", "P1->P0")
 
@@ -56,7 +56,8 @@ class _Acct(ctypes.Structure):
 class _Segment(ctypes.Structure):
     _fields_ = [("x0", ctypes.c_void_p), ("x1", ctypes.c_void_p), ("y0", ctypes.c_void_p), ("y1", ctypes.c_void_p),
                 ("n", ctypes.c_uint64), ("elem_base", ctypes.c_uint64), ("nonce", ctypes.c_uint64),
-                ("op", ctypes.c_uint32), ("k_in", ctypes.c_uint32)]
+                ("op", ctypes.c_uint32), ("k_in", ctypes.c_uint32), ("rand", ctypes.c_void_p),
+                ("rand_bytes", ctypes.c_uint64)]
 
 
 _P = ctypes.c_void_p

@@ -384,6 +384,13 @@ int batch_plan(const bc_segment* segs, uint32_t nseg, const bc_drelu_params* prm
         if (s.n && (!s.x0 || !s.x1 || !s.y0 || !s.y1)) return fail(BC_ERR_NULL, "segment %u: NULL share pointer", i);
         if (s.n && (!aligned(s.x0, w) || !aligned(s.x1, w) || !aligned(s.y0, w) || !aligned(s.y1, w)))
             return fail(BC_ERR_ALIGN, "segment %u: share pointers must be %u-byte aligned", i, w);
+        if (s.rand) {
+            if (!aligned(s.rand, 16)) return fail(BC_ERR_ALIGN, "segment %u: record must be 16-byte aligned", i);
+            const uint64_t need = bc::rand_offsets(r.lx + 1, s.op == BC_OP_RELU, w, s.n).total;
+            if (s.rand_bytes < need)
+                return fail(BC_ERR_WORKSPACE, "segment %u: record holds %llu of %llu bytes", i,
+                            (unsigned long long)s.rand_bytes, (unsigned long long)need);
+        }
         out[i] = s;
         tb[i] = tiles;
         tiles += (s.n + tile_elems - 1) / tile_elems;

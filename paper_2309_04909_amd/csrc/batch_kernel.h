@@ -1,7 +1,7 @@
 // Ragged batch of DReLU / ReLU segments (one setting, one persistent launch).
 #pragma once
 
-#include "drelu_kernel.h"
+#include "pre_kernel.h"
 
 namespace bc {
 
@@ -17,6 +17,9 @@ struct BatchKArgs {
 // belongs to the segment s with tile_begin[s] <= t < tile_begin[s + 1]; each
 // segment has its own op, nonce and global element offset, so every element
 // gets exactly the randomness (and result) of a single call on its segment.
+// A segment with a precomputed record runs the online element (the draws
+// come from the record, as in bc_drelu_pre / bc_relu_pre), with the same
+// per-segment input truncation.
 // Each block takes tiles blockIdx.x, blockIdx.x + gridDim.x, ... until
 // total_tiles: every wave reaches the exit.
 template <typename T, int N, typename F>
@@ -52,7 +55,20 @@ __global__ BC_KERNEL_ATTRS void k_batch(const BatchPlanHeader* __restrict__ hdr,
         // the segment's input ring l + k_in (Alg. 5 by k_in first; 0 = the plain load)
         const uint32_t k_in = S.k_in, lin = A.ell + k_in;
         const T in_mask = lin >= 8 * sizeof(T) ? (T)~(T)0 : (T)(((T)1 << lin) - 1);
-        if (S.op == BC_OP_RELU) {
+        if (S.rand) {
+            // precomputed randomness: the segment's record replaces its seeds
+            const bool relu = S.op == BC_OP_RELU;
+            const RecordView<T> R = record_view<T>(S.rand, (uint32_t)N, relu, S.n);
+            if (relu) {
+                for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x)
+                    drelu_pre_element<T, N, F, true, false>(X0, X1, Y0, Y1, nullptr, R, e, mask, in_mask, k_in,
+                                                            A.k_lo, f);
+            } else {
+                for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x)
+                    drelu_pre_element<T, N, F, false, false>(X0, X1, Y0, Y1, nullptr, R, e, mask, in_mask, k_in,
+                                                             A.k_lo, f);
+            }
+        } else if (S.op == BC_OP_RELU) {
             for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x)
                 drelu_element<T, N, F, true, false>(X0, X1, Y0, Y1, nullptr, 0, e, base + e, mask, in_mask, k_in,
                                                     A.k_lo, s01, s02, s12, f);

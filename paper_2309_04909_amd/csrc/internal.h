@@ -43,7 +43,7 @@ struct BatchPlanHeader {
     uint32_t reserved[4];
 };
 static_assert(sizeof(BatchPlanHeader) == 64, "plan header is 64 bytes");
-static_assert(sizeof(bc_segment) == 64, "segment record is 64 bytes");
+static_assert(sizeof(bc_segment) == 80, "segment record is 80 bytes");
 constexpr uint32_t kBatchMagic = 0x4C504342u;   // "BCPL"
 
 struct BatchLaunch {
@@ -88,16 +88,16 @@ struct RandOffsets {
     uint64_t perm, rz, tail, total;
 };
 
-inline uint64_t align256(uint64_t v) { return (v + 255) & ~255ull; }
+__host__ __device__ inline uint64_t align256(uint64_t v) { return (v + 255) & ~255ull; }
 
 // 64-bit words per element of a record's r/z section: the 2 npos values of
 // npos bits (p < 2^npos) packed floor(64 / npos) to a word; npos = 33 keeps
 // one value per word.
-constexpr uint32_t rz_words(uint32_t npos) {
+__host__ __device__ constexpr uint32_t rz_words(uint32_t npos) {
     return npos >= 33 ? 2 * npos : (2 * npos + 64 / npos - 1) / (64 / npos);
 }
 
-inline RandOffsets rand_offsets(uint32_t npos, bool relu, uint32_t ring_width, uint64_t n) {
+__host__ __device__ inline RandOffsets rand_offsets(uint32_t npos, bool relu, uint32_t ring_width, uint64_t n) {
     RandOffsets o;
     o.perm = 0;
     const uint64_t perm_bytes = 4ull * ((npos + 3) / 4) * n;

@@ -115,66 +115,96 @@ __global__ BC_KERNEL_ATTRS void k_expand(ExpandKArgs A, F f) {
     }
 }
 
-// Online: the input-dependent part of Alg. 7 (and of Alg. 8), reading the record.
+// The sections of a record on n elements (rand_offsets).
+template <typename T>
+struct RecordView {
+    const uint32_t* perm;
+    const uint64_t* rz;
+    const T* tail;
+    uint64_t n;
+};
+
+template <typename T>
+__device__ __forceinline__ RecordView<T> record_view(const void* rand, uint32_t npos, bool relu, uint64_t n) {
+    const RandOffsets o = rand_offsets(npos, relu, sizeof(T), n);
+    const uint8_t* base = static_cast<const uint8_t*>(rand);
+    return RecordView<T>{reinterpret_cast<const uint32_t*>(base + o.perm), reinterpret_cast<const uint64_t*>(base + o.rz),
+                         reinterpret_cast<const T*>(base + o.tail), n};
+}
+
+// Online: the input-dependent part of Alg. 7 (and of Alg. 8) for element e,
+// reading its draws from the record.  Reads X0[e], X1[e] (with k_in > 0,
+// shares of Z_{2^(l + k_in)} truncated by k_in bits first, Alg. 5, as in
+// drelu_element) and writes Y0[e], Y1[e]; with CAP the round-1 messages go
+// to cap[e * N + slot] and cap[(R.n + e) * N + slot].
+template <typename T, int N, typename F, bool RELU, bool CAP>
+__device__ __forceinline__ void drelu_pre_element(const T* __restrict__ X0, const T* __restrict__ X1, T* Y0, T* Y1,
+                                                  typename F::T* cap, const RecordView<T>& R, uint64_t e, T mask,
+                                                  T in_mask, uint32_t k_in, uint32_t k_lo, const F& f) {
+    using FT = typename F::T;
+    const uint64_t n = R.n;
+    const T r0 = X0[e] & in_mask;
+    const T r1 = X1[e] & in_mask;
+    const T in0 = (T)(r0 >> k_in) & mask;                                           // P0: cut(x0, k_in)
+    const T nr1 = (T)((T)0 - r1) & in_mask;                                          // -x1 in the input ring
+    const T in1 = (T)((T)0 - (T)(nr1 >> k_in)) & mask;                              // P1: -cut(-x1, k_in)
+    uint32_t perm[(N + 3) / 4];
+#pragma unroll
+    for (int k = 0; k < (N + 3) / 4; ++k) perm[k] = R.perm[(uint64_t)k * n + e];
+    const uint32_t t = (perm[0] >> 7) & 1u;
+    const T a0 = t ? (T)((T)0 - in0) & mask : in0;
+    const T a1 = t ? (T)((T)0 - in1) & mask : in1;
+    const T nb1 = (T)((T)0 - a1) & mask;
+    const T a0k = a0 >> k_lo, nb1k = nb1 >> k_lo;
+    FT least = f.p;
+    constexpr int K = RzLayout<N>::K;
+    uint64_t cur = 0;                                  // the word being read
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        FT rv[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int v = 2 * j + h;
+            if (v % K == 0) cur = R.rz[(uint64_t)(v / K) * n + e];
+            rv[h] = (FT)((cur >> (N * (v % K) % 64)) & RzLayout<N>::FIELD);
+        }
+        const FT r = rv[0], z = rv[1];
+        const uint32_t pos = (perm[j >> 2] >> (8 * (j & 3))) & 63u;
+        FT w0, w1;
+        const FT w = slot_messages<T, N, F>(a0k, nb1k, pos, r, z, f, w0, w1);
+        least = w < least ? w : least;
+        if constexpr (CAP) {
+            cap[e * N + j] = w0;
+            cap[(n + e) * N + j] = w1;
+        }
+    }
+    const T dp = least == 0 ? 1 : 0;
+    const T* tail = R.tail;
+    T y0, y1;
+    if constexpr (!RELU) {
+        drelu_finish<T>(dp, tail[e], t, mask, y0, y1);
+    } else {
+        relu_finish<T>(dp, in0, in1, tail[e], tail[n + e], tail[2 * n + e], tail[3 * n + e], tail[4 * n + e],
+                       tail[5 * n + e], t, mask, y0, y1);
+    }
+    Y0[e] = y0;
+    Y1[e] = y1;
+}
+
+// Online call: grid-stride over the n elements of one share pair.
 template <typename T, int N, typename F, bool RELU, bool CAP>
 __global__ BC_KERNEL_ATTRS void k_drelu_pre(PreKArgs A, F f_arg) {
     const F f = f_arg.vgpr();
-    using FT = typename F::T;
-    const T* __restrict__ X0 = static_cast<const T*>(A.x0);
-    const T* __restrict__ X1 = static_cast<const T*>(A.x1);
+    const T* X0 = static_cast<const T*>(A.x0);
+    const T* X1 = static_cast<const T*>(A.x1);
     T* Y0 = static_cast<T*>(A.y0);
     T* Y1 = static_cast<T*>(A.y1);
-    FT* cap = static_cast<FT*>(A.cap);
-    const T* __restrict__ tail = static_cast<const T*>(A.tail);
+    typename F::T* cap = static_cast<typename F::T*>(A.cap);
+    const RecordView<T> R{A.perm, static_cast<const uint64_t*>(A.rz), static_cast<const T*>(A.tail), A.n};
     const T mask = in_vgpr((T)A.ring_mask);
-    const uint64_t n = A.n;
-    const uint32_t k_lo = A.k_lo;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
-        const T in0 = X0[e] & mask;
-        const T in1 = X1[e] & mask;
-        uint32_t perm[(N + 3) / 4];
-#pragma unroll
-        for (int k = 0; k < (N + 3) / 4; ++k) perm[k] = A.perm[(uint64_t)k * n + e];
-        const uint32_t t = (perm[0] >> 7) & 1u;
-        const T a0 = t ? (T)((T)0 - in0) & mask : in0;
-        const T a1 = t ? (T)((T)0 - in1) & mask : in1;
-        const T nb1 = (T)((T)0 - a1) & mask;
-        const T a0k = a0 >> k_lo, nb1k = nb1 >> k_lo;
-        FT least = f.p;
-        const uint64_t* rz = static_cast<const uint64_t*>(A.rz);
-        constexpr int K = RzLayout<N>::K;
-        uint64_t cur = 0;                                  // the word being read
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-            FT rv[2];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int v = 2 * j + h;
-                if (v % K == 0) cur = rz[(uint64_t)(v / K) * n + e];
-                rv[h] = (FT)((cur >> (N * (v % K) % 64)) & RzLayout<N>::FIELD);
-            }
-            const FT r = rv[0], z = rv[1];
-            const uint32_t pos = (perm[j >> 2] >> (8 * (j & 3))) & 63u;
-            FT w0, w1;
-            const FT w = slot_messages<T, N, F>(a0k, nb1k, pos, r, z, f, w0, w1);
-            least = w < least ? w : least;
-            if constexpr (CAP) {
-                cap[e * N + j] = w0;
-                cap[(n + e) * N + j] = w1;
-            }
-        }
-        const T dp = least == 0 ? 1 : 0;
-        T y0, y1;
-        if constexpr (!RELU) {
-            drelu_finish<T>(dp, tail[e], t, mask, y0, y1);
-        } else {
-            relu_finish<T>(dp, in0, in1, tail[e], tail[n + e], tail[2 * n + e], tail[3 * n + e], tail[4 * n + e],
-                           tail[5 * n + e], t, mask, y0, y1);
-        }
-        Y0[e] = y0;
-        Y1[e] = y1;
-    }
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < A.n; e += stride)
+        drelu_pre_element<T, N, F, RELU, CAP>(X0, X1, Y0, Y1, cap, R, e, mask, mask, 0, A.k_lo, f);
 }
 
 template <typename T, int N, typename F>

@@ -17,11 +17,17 @@ Latency of a job = GPU completion time of its launch - its arrival time.
 Each job's result is exactly what a single call on it would give (per-job
 nonce, element indices 0..n-1), whichever launch it lands in.
 
+A job may be one step of a layer chain: with k_in > 0 its inputs are shares
+of Z_2^(ell + k_in) (a product at 2f fractional bits, say) that each party
+first truncates by k_in bits (Alg. 5) inside the same launch; its result is
+that of bc_trunc_drelu / bc_trunc_relu.
+
 With a randomness budget, prepare() runs the offline phase before the
 arrivals: it expands the seeds' draws of jobs (in arrival order, while they
 fit the budget) into records kept resident in HBM.  Those jobs then run the
-online kernel (bc_drelu_pre / bc_relu_pre) on their shares and record, with
-the same results; a record is released when its launch has completed.
+online kernel on their shares and record (inside the ragged launch of their
+ring, or bc_drelu_pre / bc_relu_pre when alone), with the same results; a
+record is released when its launch has completed.
 """
 
 import time
@@ -48,6 +54,7 @@ class Job:
     done: float = None      # completion time (s after the start)
     admitted: float = None
     rand: torch.Tensor = None   # resident randomness record (prepare), or None
+    k_in: int = 0               # truncate the input shares by k_in bits first (a layer chain's step)
 
 
 @dataclass
@@ -77,10 +84,21 @@ class Server:
         """One small call per ring, op and lane-group size, so that no job pays
         for loading a kernel's code object on its first launch."""
         for ell, (x0, x1) in self.pools.items():
+            prm = self.params[ell]
             for fn in (B.drelu, B.relu):
                 for n in (100, 12000, 70000):
                     m = min(n, x0.numel())
-                    fn(x0[:m], x1[:m], self.params[ell], self.seeds)
+                    fn(x0[:m], x1[:m], prm, self.seeds)
+            m = min(1000, x0.numel())
+            ys = [torch.empty_like(x0[:m]) for _ in range(4)]
+            segs = [BT.Segment(x0[:m], x1[:m], ys[0], ys[1], op=B.BC_OP_DRELU),
+                    BT.Segment(x0[:m], x1[:m], ys[2], ys[3], op=B.BC_OP_RELU)]
+            if self.rand_budget:
+                for sg in segs:
+                    sg.rand = B.rand_expand(sg.op, prm, self.seeds, m)
+                B.drelu_pre(x0[:m], x1[:m], prm, segs[0].rand)
+                B.relu_pre(x0[:m], x1[:m], prm, segs[1].rand)
+            BT.RaggedBatch(prm, self.seeds, segs).run()
         torch.cuda.synchronize()
 
     def _seeds(self, nonce):
@@ -114,28 +132,36 @@ class Server:
                 j.y0 = torch.empty(j.n, dtype=x0.dtype, device=x0.device)
                 j.y1 = torch.empty(j.n, dtype=x1.dtype, device=x1.device)
                 L.bytes += self.job_bytes(j)
-                if j.rand is not None:               # online kernel on the resident record
-                    fn = B.relu_pre if j.op == B.BC_OP_RELU else B.drelu_pre
-                    fn(x0[j.offset:j.offset + j.n], x1[j.offset:j.offset + j.n], self.params[j.ell], j.rand,
-                       out=(j.y0, j.y1), stream=stream)
+                seg = BT.Segment(x0[j.offset:j.offset + j.n], x1[j.offset:j.offset + j.n], j.y0, j.y1, op=j.op,
+                                 nonce=j.nonce, elem_base=0, k_in=j.k_in, rand=j.rand)
+                if j.rand is not None:               # released with the launch, once it has completed
                     L.records.append(j.rand)
                     j.rand = None
-                    continue
-                seg = BT.Segment(x0[j.offset:j.offset + j.n], x1[j.offset:j.offset + j.n], j.y0, j.y1, op=j.op,
-                                 nonce=j.nonce, elem_base=0)
                 by_ell.setdefault(j.ell, []).append(seg)
             for ell, segs in by_ell.items():
-                if len(segs) == 1:
-                    sg = segs[0]
-                    sd = self._seeds(sg.nonce)
-                    fn = B.relu if sg.op == B.BC_OP_RELU else B.drelu
-                    fn(sg.x0, sg.x1, self.params[ell], sd, elem_base=sg.elem_base, out=(sg.y0, sg.y1), stream=stream)
+                prm = self.params[ell]
+                if len(segs) == 1 and not (segs[0].rand is not None and segs[0].k_in):
+                    self._single(segs[0], prm, stream)       # one job: the plain call needs no plan
                     continue
-                rb = BT.RaggedBatch(self.params[ell], self.seeds, segs)
+                rb = BT.RaggedBatch(prm, self.seeds, segs)
                 rb.run(stream)
                 L.batches.append(rb)
             ev.record(stream)
         return L
+
+    def _single(self, sg, prm, stream):
+        out = (sg.y0, sg.y1)
+        relu = sg.op == B.BC_OP_RELU
+        if sg.rand is not None:                      # online kernel on the resident record
+            fn = B.relu_pre if relu else B.drelu_pre
+            fn(sg.x0, sg.x1, prm, sg.rand, out=out, stream=stream)
+        elif sg.k_in:
+            fn = B.trunc_relu if relu else B.trunc_drelu
+            fn(sg.x0, sg.x1, prm.ell + sg.k_in, sg.k_in, prm, self._seeds(sg.nonce), elem_base=sg.elem_base, out=out,
+               stream=stream)
+        else:
+            fn = B.relu if relu else B.drelu
+            fn(sg.x0, sg.x1, prm, self._seeds(sg.nonce), elem_base=sg.elem_base, out=out, stream=stream)
 
     def run(self, jobs):
         """Serve `jobs` (arrival times relative to the start); returns them with

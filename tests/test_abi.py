@@ -135,11 +135,11 @@ def test_batch_plan_validation_on_host():
     seg[0] = B._Segment(0x1000, 0x2000, 0x3000, 0x4000, 5000, 0, 1, B.BC_OP_RELU, 0)
     seg[1] = B._Segment(0x5000, 0x6000, 0x7000, 0x8000, 0, 99, 2, B.BC_OP_DRELU, 0)
     nbytes = L.bc_batch_plan_bytes(2)
-    assert nbytes == 64 + 2 * 64 + 3 * 8
+    assert nbytes == 64 + 2 * 80 + 3 * 8
     buf = (ctypes.c_uint8 * nbytes)()
     assert L.bc_batch_plan(seg, 2, ctypes.byref(prm), 1024, buf, nbytes) == 0
     words = np.frombuffer(bytes(buf), dtype=np.uint64)
-    tb = words[(64 + 128) // 8:]
+    tb = words[(64 + 160) // 8:]
     assert list(tb) == [0, 5, 5]                                  # ceil(5000 / 1024) tiles, then the empty one
     assert L.bc_batch_plan(seg, 2, ctypes.byref(prm), 1024, buf, nbytes - 1) == -7
     assert L.bc_batch_plan(seg, 0, ctypes.byref(prm), 1024, buf, nbytes) == -8
@@ -166,6 +166,15 @@ def test_batch_plan_validation_on_host():
     seg[1].k_in = 9                                                                  # 33 bits: another width
     assert L.bc_batch_plan(seg, 2, ctypes.byref(r24), 1024, buf, nbytes) == -2
     seg[1].k_in = 0
+    # a record segment: 16-byte aligned record of at least bc_rand_bytes(op, prm, n)
+    need = L.bc_rand_bytes(B.BC_OP_RELU, ctypes.byref(prm), 5000)
+    seg[0].rand, seg[0].rand_bytes = 0x100000, need
+    assert L.bc_batch_plan(seg, 2, ctypes.byref(prm), 1024, buf, nbytes) == 0
+    seg[0].rand_bytes = need - 1
+    assert L.bc_batch_plan(seg, 2, ctypes.byref(prm), 1024, buf, nbytes) == -7
+    seg[0].rand, seg[0].rand_bytes = 0x100008, need
+    assert L.bc_batch_plan(seg, 2, ctypes.byref(prm), 1024, buf, nbytes) == -5
+    seg[0].rand, seg[0].rand_bytes = None, 0
     # bc_batch_run refuses a buffer that is not a plan (checked before any launch)
     junk = (ctypes.c_uint8 * nbytes)()
     sd = B.Seeds(1, 2, 3).c()

@@ -189,3 +189,87 @@ def test_batch_with_input_truncation(M, ell_in, k_in, lx, k_lo):
             e0, e1, _, _ = ofn(t0, t1, ell, lx, k_lo, p, seeds, s.nonce, elem_base=s.elem_base)
             assert np.array_equal(host(s.y0)[:k].astype(np.uint64), e0)
             assert np.array_equal(host(s.y1)[:k].astype(np.uint64), e1)
+
+
+@pytest.mark.parametrize("ell_in,k_in,lx,k_lo", [(64, 13, 7, 11), (64, 13, 18, 13), (32, 8, 7, 10), (64, 0, 18, 13)])
+def test_batch_with_records(M, ell_in, k_in, lx, k_lo):
+    """A layer chain on precomputed randomness: segments whose records were
+    expanded offline (bc_rand_expand with their own nonce and elem_base)
+    mixed with segments drawing from the seeds, with and without input
+    truncation.  A record segment equals bc_trunc_relu / bc_trunc_drelu (or
+    the plain call) with the seeds, nonce and elem_base of its record; its own
+    nonce and elem_base fields are ignored.  Oracle on samples."""
+    B, bt = M
+    ell = ell_in - k_in
+    rng = np.random.default_rng(7 * ell_in + k_in + lx)
+    prm, seeds = B.Params(ell, lx, k_lo), (25, 26, 27)
+    sizes = [4097, 0, 1, 30000, 1025, 256, 9999]
+    segs, inputs, base = [], [], 0
+    for i, n in enumerate(sizes):
+        kin = k_in if i % 3 != 1 else 0
+        ring = ell + kin
+        bound = 1 << (k_lo + lx - 2 + kin)
+        x = np.array([v % (1 << ring) for v in rng.integers(-bound + 1, bound, size=n).tolist()], dtype=np.uint64)
+        x0, x1 = W.share(x, ring, rng)
+        op = B.BC_OP_RELU if i % 2 else B.BC_OP_DRELU
+        d0, d1 = dev(x0), dev(x1)
+        nonce, eb = 500 + i, base
+        rec = None
+        if i % 2 == 0 or i == 3:              # records on most segments; the rest draw from the seeds
+            rec = B.rand_expand(op, prm, B.Seeds(*seeds, nonce), n, elem_base=eb)
+        seg = bt.Segment(d0, d1, torch.empty_like(d0), torch.empty_like(d1), op=op, nonce=nonce, elem_base=eb,
+                         k_in=kin, rand=rec)
+        if rec is not None:                   # fields a record segment does not use
+            seg.nonce, seg.elem_base = 0xDEAD, 1 << 40
+        segs.append(seg)
+        inputs.append((x0, x1, nonce, eb))
+        base += n + 3
+    bt.RaggedBatch(prm, B.Seeds(*seeds), segs).run()
+    torch.cuda.synchronize()
+    p = default_prime(lx)
+    for s, (x0, x1, nonce, eb) in zip(segs, inputs):
+        sd = B.Seeds(*seeds, nonce)
+        if s.k_in:
+            fn = B.trunc_relu if s.op == B.BC_OP_RELU else B.trunc_drelu
+            z0, z1 = fn(s.x0, s.x1, ell + s.k_in, s.k_in, prm, sd, elem_base=eb)
+        else:
+            fn = B.relu if s.op == B.BC_OP_RELU else B.drelu
+            z0, z1 = fn(s.x0, s.x1, prm, sd, elem_base=eb)
+        assert same(z0, s.y0) and same(z1, s.y1), (s.x0.numel(), s.k_in, s.rand is not None)
+        k = min(200, x0.size)
+        if k:
+            t0, t1 = x0[:k].astype(np.uint64), x1[:k].astype(np.uint64)
+            if s.k_in:
+                t0, t1 = OPR.trunc_det(t0, t1, ell + s.k_in, s.k_in, 0)
+            ofn = OPR.relu if s.op == B.BC_OP_RELU else OPR.drelu
+            e0, e1, _, _ = ofn(t0, t1, ell, lx, k_lo, p, seeds, nonce, elem_base=eb)
+            assert np.array_equal(host(s.y0)[:k].astype(np.uint64), e0)
+            assert np.array_equal(host(s.y1)[:k].astype(np.uint64), e1)
+
+
+def test_batch_record_graph_replays(M):
+    """A captured batch with record segments replays the eager result."""
+    B, bt = M
+    rng = np.random.default_rng(14)
+    prm = B.Params(64, 7, 11)
+    segs, _ = _segments(B, bt, rng, 64, 7, 11, [20000, 513, 40000])
+    for i, s in enumerate(segs):
+        if i != 1:
+            s.rand = B.rand_expand(s.op, prm, B.Seeds(9, 8, 7, s.nonce), s.x0.numel(), elem_base=s.elem_base)
+    batch = bt.RaggedBatch(prm, B.Seeds(9, 8, 7), segs)
+    batch.run()
+    torch.cuda.synchronize()
+    eager = [(s.y0.clone(), s.y1.clone()) for s in segs]
+    for s in segs:
+        fn = B.relu if s.op == B.BC_OP_RELU else B.drelu
+        z0, z1 = fn(s.x0, s.x1, prm, B.Seeds(9, 8, 7, s.nonce), elem_base=s.elem_base)
+        assert same(z0, s.y0) and same(z1, s.y1)
+    g = batch.capture()
+    for rep in range(3):
+        for s in segs:
+            s.y0.zero_()
+            s.y1.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        for (a0, a1), s in zip(eager, segs):
+            assert same(a0, s.y0) and same(a1, s.y1), rep

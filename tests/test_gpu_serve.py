@@ -101,3 +101,65 @@ def test_precomputed_randomness_in_the_mix():
         fn = B.relu if j.op == B.BC_OP_RELU else B.drelu
         a0, a1 = fn(x0[j.offset:j.offset + j.n], x1[j.offset:j.offset + j.n], params[j.ell], B.Seeds(*seeds, j.nonce))
         assert same(a0, j.y0) and same(a1, j.y1), j.jid
+
+
+def test_layer_chain_jobs_with_records_in_the_mix():
+    """Truncate-then-DReLU/ReLU jobs of a layer chain (products in Z_2^64,
+    truncated by 13 bits into Z_2^51 inside the launch) served beside plain
+    l = 64 and l = 32 jobs, about 40% of all jobs on resident records: each
+    result equals the single fused call on that job (bc_trunc_relu /
+    bc_trunc_drelu or bc_relu / bc_drelu), and chain jobs match the oracle on
+    samples."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_04909_amd import bicop as B
+    from paper_2309_04909_amd import serve as S
+    pool_n = 1 << 18
+    settings = {64: (64, 18, 13), 32: (32, 8, 8), 51: (51, 7, 11)}
+    host_pools, pools = {}, {}
+    for ell in (64, 32):
+        _, (x0, x1) = W.serving_values(70 + ell, pool_n, ell)
+        host_pools[ell] = (x0, x1)
+        pools[ell] = (dev(x0), dev(x1))
+    _, (c0, c1) = W.chain_values(81, pool_n)             # f = 26 products, truncated by 13 into Z_2^51
+    host_pools[51] = (c0, c1)
+    pools[51] = (dev(c0), dev(c1))
+    params = {ell: B.Params(*settings[ell]) for ell in settings}
+    seeds = (11, 12, 13)
+    rng = np.random.default_rng(2)
+    arr = W.serving_arrivals(5, 20000.0, 72, min_log2=4, max_log2=16)
+    jobs = []
+    for i, (t, n, op, ell) in enumerate(arr):
+        key, k_in = (51, 13) if i % 3 == 0 else (ell, 0)
+        jobs.append(S.Job(i, t, n, 0 if op == "drelu" else 1, key, int(rng.integers(0, pool_n - n + 1)), 4000 + i,
+                          k_in=k_in))
+    total = sum(B.rand_bytes(j.op, params[j.ell], j.n) for j in jobs)
+    srv = S.Server(pools, params, B.Seeds(*seeds), hbm_budget=1 << 22, max_slots=6, nstreams=3, keep_outputs=True,
+                   rand_budget=int(total * 0.4))
+    with_rec, _, _ = srv.prepare(jobs)
+    assert 0 < with_rec < len(jobs)
+    chain_rec = sum(1 for j in jobs if j.k_in and j.rand is not None)
+    assert chain_rec > 0
+    done = srv.run(jobs)
+    assert len(done) == len(jobs) and all(j.rand is None for j in done)
+    for j in done:
+        x0, x1 = pools[j.ell]
+        a, b = x0[j.offset:j.offset + j.n], x1[j.offset:j.offset + j.n]
+        sd = B.Seeds(*seeds, j.nonce)
+        relu = j.op == B.BC_OP_RELU
+        if j.k_in:
+            fn = B.trunc_relu if relu else B.trunc_drelu
+            z0, z1 = fn(a, b, j.ell + j.k_in, j.k_in, params[j.ell], sd)
+        else:
+            z0, z1 = (B.relu if relu else B.drelu)(a, b, params[j.ell], sd)
+        assert same(z0, j.y0) and same(z1, j.y1), (j.jid, j.ell, j.k_in)
+    for j in [j for j in done if j.k_in][:4]:
+        ell, lx, k_lo = settings[j.ell]
+        h0, h1 = host_pools[j.ell]
+        k = min(j.n, 200)
+        t0, t1 = OPR.trunc_det(h0[j.offset:j.offset + k].astype(np.uint64), h1[j.offset:j.offset + k].astype(np.uint64),
+                               64, 13, 0)
+        ofn = OPR.relu if j.op == B.BC_OP_RELU else OPR.drelu
+        e0, e1, _, _ = ofn(t0, t1, ell, lx, k_lo, default_prime(lx), seeds, j.nonce)
+        assert np.array_equal(host(j.y0)[:k].astype(np.uint64), e0)
+        assert np.array_equal(host(j.y1)[:k].astype(np.uint64), e1)

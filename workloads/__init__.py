@@ -179,6 +179,15 @@ def resnet18_relu(seed: int = 4, batch: int = 32, layers=None, f: int = F):
     return out
 
 
+def chain_values(seed: int, n: int, f: int = 2 * F):
+    """Inputs of one step of a layer chain: n values N(0, 1) at f = 2 F
+    fractional bits in Z_2^64 (a layer's products before their truncation by
+    F bits), and their 2-of-2 sharing."""
+    rng = np.random.default_rng(seed)
+    x = encode(fixed_point(rng.standard_normal(n), f), 64)
+    return x, share(x, 64, rng)
+
+
 def serving_arrivals(seed: int, rate_jobs_per_s: float, count: int,
                      min_log2: int = 10, max_log2: int = 24):
     """Seeded Poisson arrivals: (arrival_time_s, n_elems, op, ell) per job.
