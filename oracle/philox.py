@@ -20,8 +20,9 @@ Counter layout, for element index g (< 2^48), a tag, and a block index b:
 Every draw is therefore a pure function of (seed, nonce, g, tag, b): the same
 element gets the same randomness alone, in a batch, or under any schedule.
 
-Draws (all multiply-shift, no rejection; bias at most p / 2^32, or p / 2^64
-for p > 2^32):
+Draws (no rejection; multiply-shift, whose statistical distance from
+uniform is k (m - k) / (m 2^B) for m values drawn from B bits, k = 2^B mod m,
+or N-bit fields, below):
   TAG_SHUFFLE (seed_01): word j%4 of block j//4 is the sort key of position
     j: key_j = (word & ~63) | j.  Slot s of the shuffled array receives the
     position with the s-th smallest key.  t = bit 0 of word 0 of block 0
@@ -30,6 +31,16 @@ for p > 2^32):
     (R, Z) of slot s;  r_s = 1 + floor(R (p-1) / 2^32) in Z_p^*,
     z_s = floor(Z p / 2^32) in Z_p.   p > 2^32: block s gives 64-bit
     R = w0 | w1 << 32, Z = w2 | w3 << 32 and the same formulas over 2^64.
+  TAG_MASK, packed (``packed_masks``: the default prime p = 2^N - c of
+    N = l_x + 1 bits with 17 <= N <= 21): three slots to a block.  With the
+    block's bits numbered 0..127 (bit i is bit i % 32 of word i // 32), slot
+    s takes block s // 3 and, with h = s % 3, the N-bit fields
+    R = bits [2Nh, 2Nh + N) and Z = bits [2Nh + N, 2Nh + 2N);
+    r_s = min(max(R, 1), p - 1) in Z_p^*, z_s = Z mod p.  The distance from
+    uniform is then (c + 1) / 2^N for r and about c / 2^N for z: for these N
+    within a factor 2 of the 32-bit multiply-shift's (equal at N = 19..21),
+    at most 2^-15.4 (N = 18), while a block carries three slots instead of
+    two.
   TAG_RESP (seed_02): rho = (w0 | w1 << 32) mod 2^l of block 0.
   TAG_BEAVER: seed_02 block 0 -> [a]_0 = w0|w1<<32, [b]_0 = w2|w3<<32;
     seed_02 block 1 -> [c]_0 = w0|w1<<32;  seed_12 block 0 -> [a]_1, [b]_1.
@@ -47,6 +58,7 @@ for p > 2^32):
 
 import numpy as np
 
+from .params import default_prime
 from .ring import U64, red
 
 M0 = 0xD2511F53
@@ -108,9 +120,42 @@ def draw_shuffle(seed01: int, nonce: int, g, n: int):
     return t, sigma
 
 
+def packed_masks(n: int, p: int) -> bool:
+    """Whether the N = n slots' r and z are N-bit fields, three slots to a
+    block: the default prime, and 17 <= N <= 21 (six N-bit fields fit 128
+    bits, and N-bit fields keep the bias of the 32-bit draws)."""
+    return 17 <= n <= 21 and p == default_prime(n - 1)
+
+
+def _bits(lo, hi, off: int, width: int):
+    """Bits off .. off + width - 1 of the 128-bit values hi * 2^64 + lo."""
+    if off + width <= 64:
+        v = lo >> U64(off)
+    elif off >= 64:
+        v = hi >> U64(off - 64)
+    else:
+        v = (lo >> U64(off)) | (hi << U64(64 - off))
+    return v & U64((1 << width) - 1)
+
+
 def draw_masks(seed01: int, nonce: int, g, n: int, p: int):
     """r (in Z_p^*) and z (in Z_p), shape (N, n), indexed by slot."""
     g = np.asarray(g, dtype=U64)
+    if packed_masks(n, p):
+        r = np.empty((g.size, n), dtype=U64)
+        z = np.empty((g.size, n), dtype=U64)
+        for b in range((n + 2) // 3):
+            w = block(seed01, nonce, g, TAG_MASK, b)
+            lo = w[0] | (w[1] << U64(32))
+            hi = w[2] | (w[3] << U64(32))
+            for h in range(3):
+                s = 3 * b + h
+                if s < n:
+                    R = _bits(lo, hi, 2 * n * h, n)
+                    Z = _bits(lo, hi, 2 * n * h + n, n)
+                    r[:, s] = np.minimum(np.maximum(R, U64(1)), U64(p - 1))
+                    z[:, s] = Z % U64(p)
+        return r, z
     if p < (1 << 32):
         w = _words(seed01, nonce, g, TAG_MASK, 2 * n)
         R, Z = w[:, 0::2], w[:, 1::2]
