@@ -100,13 +100,22 @@ TAIL_OPS = {"drelu": 12, "relu": 40,
 TAIL_BLOCKS = {"drelu": 1, "relu": 3, "rss_drelu": 6, "rss_relu": 7}
 
 
+def mask_blocks(n: int) -> int:
+    """Philox blocks of an element's masks and reshares with the default prime:
+    three slots to a block for 17 <= N <= 21 (N-bit fields), one per block for
+    N = 33 (64-bit words), two otherwise (32-bit words)."""
+    if 17 <= n <= 21:
+        return (n + 2) // 3
+    return n if n == 33 else (n + 1) // 2
+
+
 def alg_ops_per_elem(op: str, lx: int) -> int:
     """32-bit integer operations per element of the fused kernel: 60 per Philox
     block, a fixed count per slot, two per comparator of the sorting network and
     a per-op tail (the method's work, as a GEMM's flops count 2mnk)."""
     n = lx + 1
     wide = lx == 32
-    blocks = (n + 3) // 4 + (n if wide else (n + 1) // 2) + TAIL_BLOCKS[op]
+    blocks = (n + 3) // 4 + mask_blocks(n) + TAIL_BLOCKS[op]
     return (blocks * PHILOX_OPS + n * (SLOT_OPS_WIDE if wide else SLOT_OPS) + 2 * len(pairwise_network(n))
             + TAIL_OPS[op])
 

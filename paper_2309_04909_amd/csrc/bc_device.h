@@ -194,6 +194,7 @@ __device__ __forceinline__ uint64_t mad_u64_u32(uint32_t a, uint32_t b, uint64_t
 struct FieldSmall {
     using T = uint32_t;
     static constexpr bool kWrap = false;
+    static constexpr bool kDefault = false;   // any prime below 2^12
     uint32_t p;
     float pinv;
     __device__ __forceinline__ uint32_t reduce24(uint32_t x) const {   // x < 2^24
@@ -217,6 +218,7 @@ template <int K>
 struct FieldMersenne {
     using T = uint32_t;
     static constexpr bool kWrap = false;
+    static constexpr bool kDefault = true;    // the largest prime below 2^K
     // A compile-time p becomes a literal operand: on gfx950 the VOP2 forms
     // issue at about twice the rate with literal or VGPR operands as with an
     // SGPR operand.
@@ -234,6 +236,17 @@ struct FieldMersenne {
         const uint32_t s = ((uint32_t)x & p) + (uint32_t)(x >> K);
         return min(s, s - p);
     }
+    // The same with b and c given shifted left by SH = 32 - K (b_sh = b 2^SH,
+    // c_sh = c 2^SH; a < p, b < p, c <= p): the product x 2^SH < 2^(K + 32)
+    // splits at bit 32 into x >> K (high word) and (x mod 2^K) 2^SH (low
+    // word), so the fold takes one shift instead of a funnel shift.
+    template <int SH>
+    __device__ __forceinline__ uint32_t mul_add_sh(uint32_t a, uint32_t b_sh, uint32_t c_sh) const {
+        static_assert(SH == 32 - K, "operands shifted to the top of the word");
+        const uint64_t x = mad_u64_u32(a, b_sh, c_sh);
+        const uint32_t s = ((uint32_t)x >> SH) + (uint32_t)(x >> 32);
+        return min(s, s - p);
+    }
 };
 
 // p = 2^K - c with c < 64 and c^2 < p (pseudo-Mersenne), K <= 32.  Every
@@ -248,6 +261,7 @@ struct FieldPM {
                   "pseudo-Mersenne 2^K - c with c^2 < p");
     using T = uint32_t;
     static constexpr bool kWrap = K == 32;   // p > 2^31: 32-bit sums can wrap
+    static constexpr bool kDefault = true;   // the largest prime below 2^K
     static constexpr uint32_t p = (uint32_t)((1ull << K) - CC);
     static constexpr uint32_t LOW = (uint32_t)((1ull << K) - 1);
     __device__ __forceinline__ FieldPM vgpr() const { return *this; }
@@ -295,6 +309,17 @@ struct FieldPM {
             return min(S, S - p);
         }
     }
+    // mul_add with b and d given shifted left by SH = 32 - K (12 < K <= 24):
+    // x 2^SH splits at bit 32 into H = x >> K and L 2^SH, L = x mod 2^K.
+    template <int SH>
+    __device__ __forceinline__ uint32_t mul_add_sh(uint32_t a, uint32_t b_sh, uint32_t d_sh) const {
+        static_assert(SH == 32 - K && K > 12 && K <= 24, "operands shifted to the top of the word");
+        const uint64_t x = mad_u64_u32(a, b_sh, d_sh);
+        const uint32_t H = (uint32_t)(x >> 32), L = (uint32_t)x >> SH;
+        const uint32_t t = __umul24(H, CC) + L;                    // < 2^(K + 6) <= 2^30
+        const uint32_t S = (t & LOW) + __umul24(t >> K, CC);       // < 2^K + c^2 < 2p
+        return min(S, S - p);
+    }
 };
 
 // p = 2^33 - 9, the default prime of l_x = 32 (64-bit field elements).
@@ -306,6 +331,7 @@ struct FieldPM {
 struct FieldPM33 {
     using T = uint64_t;
     static constexpr bool kWrap = false;
+    static constexpr bool kDefault = true;    // the largest prime below 2^33
     static constexpr uint64_t p = (1ull << 33) - 9;
     static constexpr uint64_t LOW33 = (1ull << 33) - 1;
     __device__ __forceinline__ FieldPM33 vgpr() const { return *this; }
@@ -335,6 +361,7 @@ constexpr uint32_t kPrimeDelta[34] = {0, 0, 1, 1, 3, 1, 3, 1, 5, 3, 3, 9, 3, 1, 
 struct Field24 {
     using T = uint32_t;
     static constexpr bool kWrap = false;
+    static constexpr bool kDefault = false;   // any prime of its range
     uint32_t p;
     double pd, pinv;
     __device__ __forceinline__ Field24 vgpr() const { return Field24{in_vgpr(p), pd, pinv}; }
@@ -359,6 +386,7 @@ struct Field24 {
 struct Field32 {
     using T = uint32_t;
     static constexpr bool kWrap = true;   // p may exceed 2^31: a + b can wrap
+    static constexpr bool kDefault = false;   // any prime of its range
     uint32_t p;
     uint64_t mu;
     __device__ __forceinline__ Field32 vgpr() const { return Field32{in_vgpr(p), mu}; }
@@ -383,6 +411,7 @@ struct Field32 {
 struct Field64 {
     using T = uint64_t;
     static constexpr bool kWrap = false;
+    static constexpr bool kDefault = false;   // any prime of its range
     uint64_t p;
     double pd, pinv;
     __device__ __forceinline__ Field64 vgpr() const { return *this; }

@@ -60,16 +60,54 @@ __device__ __forceinline__ FT window(T a, uint32_t pos) {
         return (FT)(a >> pos) & WIN1;
 }
 
+// a * b + c in Z_p with b and c given shifted left by SH bits (SH = 0: the
+// plain values; see MaskDraws).
+template <int SH, typename F>
+__device__ __forceinline__ typename F::T field_mul_add(const F& f, typename F::T a, typename F::T b, typename F::T c) {
+    if constexpr (SH == 0)
+        return f.mul_add(a, b, c);
+    else
+        return f.template mul_add_sh<SH>(a, b, c);
+}
+
+// v_min3_u32 written out: the compiler would otherwise re-associate P2's
+// running minimum into a tree over all slots, which defers every slot's
+// fold to the end and keeps all the products live at once.
+__device__ __forceinline__ uint32_t min3_in_order(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t d;
+    asm("v_min3_u32 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+
+// P2's running minimum over the slots of w0 + w1 mod p (a slot is zero
+// exactly when its reconstruction is 0): without wrap, min(least, s, s - p)
+// is one three-operand minimum, taken slot after slot.
+template <typename F>
+__device__ __forceinline__ typename F::T p2_least(typename F::T least, typename F::T w0, typename F::T w1, const F& f) {
+    using FT = typename F::T;
+    if constexpr (F::kWrap) {
+        const FT w = addmod(w0, w1, f);
+        return w < least ? w : least;
+    } else if constexpr (sizeof(FT) == 4) {
+        const FT s = w0 + w1;
+        return min3_in_order(least, s, s - f.p);
+    } else {
+        const FT s = w0 + w1;
+        return min(least, min(s, (FT)(s - f.p)));
+    }
+}
+
 // Windows through P2's reconstruction (Alg. 7) for one slot: the window
-// position `pos` (sigma of the slot), the slot's mask r and reshare z;
-// returns both parties' messages and P2's reconstruction w0 + w1 mod p (the
-// slot is zero when it is 0).
+// position `pos` (sigma of the slot), the slot's mask r and reshare z (both
+// shifted left by SH bits, see MaskDraws); returns both parties' messages
+// and folds P2's reconstruction w0 + w1 mod p into its running minimum
+// `least` (some slot is zero exactly when the minimum ends at 0).
 // a0 and nb1 are P0's share and P1's negated share, both shifted down by k_lo.
 // Every select is written as masks and adds so that it stays on the
 // full-rate VOP2 forms (no compare / cndmask pairs).
-template <typename T, int N, typename F>
-__device__ __forceinline__ typename F::T slot_messages(T a0, T nb1, uint32_t pos, typename F::T r, typename F::T z,
-                                                       const F& f, typename F::T& w0, typename F::T& w1) {
+template <typename T, int N, typename F, int SH = 0>
+__device__ __forceinline__ void slot_messages(T a0, T nb1, uint32_t pos, typename F::T r, typename F::T z, const F& f,
+                                              typename F::T& w0, typename F::T& w1, typename F::T& least) {
     using FT = typename F::T;
     constexpr int LX = N - 1;
     constexpr FT TWO_LX = (FT)1 << LX;                   // 2^l_x mod p = 2^l_x
@@ -84,9 +122,9 @@ __device__ __forceinline__ typename F::T slot_messages(T a0, T nb1, uint32_t pos
     const FT s0 = ((W0 + u0n - 2) & WIN) + 1;
     const FT v1 = ((FT)0 - W1 - u1n) & WIN;              // P1: -cut_i - cut_{i+1}
     const FT s1 = v1 + (f.p - TWO_LX);
-    w0 = f.mul_add(s0, r, z);                            // mask, reshare
-    w1 = f.mul_add(s1, r, (FT)(f.p - z));                // P1: s1 r - z
-    return addmod(w0, w1, f);                            // P2 reconstructs
+    w0 = field_mul_add<SH>(f, s0, r, z);                           // mask, reshare
+    w1 = field_mul_add<SH>(f, s1, r, (FT)((f.p << SH) - z));       // P1: s1 r - z
+    least = p2_least(least, w0, w1, f);                            // P2 reconstructs and tests
 }
 
 // DReLU's end (Alg. 7): P2's fresh sharing (rho, D' - rho), then the unflip.
@@ -131,21 +169,97 @@ __device__ __forceinline__ uint32_t shuffle_keys(const StreamAt& r01, uint32_t (
     return t;
 }
 
-// Slot j's mask r in Z_p^* and reshare z in Z_p, from seed_01 (Alg. 7).  For
-// p < 2^32 slots j and j + 1 (j even) share block j / 2 (words 0, 1 and 2, 3),
-// kept in wm between the two; for p > 2^32 slot j takes block j, whose 64-bit
-// words give r and z.  j is a compile-time constant after unrolling.
-template <typename F>
-__device__ __forceinline__ void slot_draws(const StreamAt& r01, int j, Words4& wm, const F& f, typename F::T& r,
-                                           typename F::T& z) {
-    if constexpr (std::is_same<typename F::T, uint64_t>::value) {
-        const Words4 w = r01.block(TAG_MASK, (uint32_t)j);
+// Layout of the masks r in Z_p^* and reshares z in Z_p of Alg. 7 in the
+// seed_01 stream TAG_MASK, per window count N and field:
+//  * the default prime at 17 <= N <= 21 (PACKED): three slots to a block,
+//    slot s of block s / 3 taking the N-bit fields at bits 2Nh and 2Nh + N
+//    of the block's 128 bits (h = s % 3); r = min(max(R, 1), p - 1),
+//    z = Z mod p.  The kernels keep both shifted left by SH = 32 - N, which
+//    the fields' mul_add_sh folds without a funnel shift.
+//  * otherwise, p < 2^32: two slots to a block, words (0, 1) and (2, 3), by
+//    32-bit multiply-shift; p > 2^32: one slot per block, 64-bit words.
+template <int N, typename F>
+struct MaskDraws {
+    static constexpr bool WIDE = std::is_same<typename F::T, uint64_t>::value;
+    static constexpr bool PACKED = F::kDefault && N >= 17 && 6 * N <= 128;
+    static constexpr int SPB = PACKED ? 3 : (WIDE ? 1 : 2);   // slots per block
+    static constexpr int SH = PACKED ? 32 - N : 0;            // shift of the kept r and z
+};
+
+// The N-bit field at bit O of a block's 128 bits, shifted to the top of a
+// 32-bit word (its low 32 - N bits zero).  O and N are compile-time.
+template <int N, int O>
+__device__ __forceinline__ uint32_t block_field_top(const Words4& w) {
+    constexpr int TOP = O + N;                     // the field ends below bit TOP
+    constexpr uint32_t KEEP = ~((1u << (32 - N)) - 1);
+    if constexpr (TOP <= 32) {
+        static_assert(O == 0, "only the first field ends inside word 0");
+        return w.w0 << (32 - N);
+    } else {
+        constexpr int LO = TOP - 32, K = LO / 32, S = LO % 32;   // the 32-bit window [LO, TOP)
+        const uint32_t ws[4] = {w.w0, w.w1, w.w2, w.w3};
+        if constexpr (S == 0)
+            return ws[K] & KEEP;
+        else
+            return __builtin_amdgcn_alignbit(ws[K + 1], ws[K], S) & KEEP;
+    }
+}
+
+// Slot H's r and z of mask block w (H < SPB, compile-time), in the kept
+// representation of MaskDraws.
+template <int N, typename F, int H>
+__device__ __forceinline__ void block_draws(const Words4& w, const F& f, typename F::T& r, typename F::T& z) {
+    using D = MaskDraws<N, F>;
+    if constexpr (D::PACKED) {
+        constexpr int SH = D::SH;
+        const uint32_t R = block_field_top<N, 2 * N * H>(w);
+        const uint32_t Z = block_field_top<N, 2 * N * H + N>(w);
+        r = min(max(R, 1u << SH), (F::p - 1) << SH);   // clamp into Z_p^* (one v_med3)
+        if constexpr (F::p == (1u << N) - 1)
+            z = Z;                                  // Mersenne: Z <= p already stands for Z mod p
+        else
+            z = min(Z, Z - (F::p << SH));           // Z mod p (Z < 2p)
+    } else if constexpr (D::WIDE) {
         r = 1 + __umul64hi(join64(w.w0, w.w1), f.p - 1);
         z = __umul64hi(join64(w.w2, w.w3), f.p);
     } else {
-        if ((j & 1) == 0) wm = r01.block(TAG_MASK, (uint32_t)(j >> 1));
-        r = draw_r((j & 1) ? wm.w2 : wm.w0, f.p);
-        z = draw_z((j & 1) ? wm.w3 : wm.w1, f.p);
+        r = draw_r(H ? w.w2 : w.w0, f.p);
+        z = draw_z(H ? w.w3 : w.w1, f.p);
+    }
+}
+
+// block_draws for a slot index h of the block that is constant after
+// unrolling (the branches not taken fold away).
+template <int N, typename F>
+__device__ __forceinline__ void block_draws_at(const Words4& w, int h, const F& f, typename F::T& r,
+                                               typename F::T& z) {
+    constexpr int SPB = MaskDraws<N, F>::SPB;
+    if (h == 0)
+        block_draws<N, F, 0>(w, f, r, z);
+    else if (h == 1)
+        block_draws<N, F, (SPB > 1 ? 1 : 0)>(w, f, r, z);
+    else
+        block_draws<N, F, (SPB > 2 ? 2 : 0)>(w, f, r, z);
+}
+
+// Slot j's r and z (j compile-time after unrolling): block j / SPB, fetched
+// into wm at the block's first slot and kept there for the rest.
+template <int N, typename F>
+__device__ __forceinline__ void slot_draws(const StreamAt& r01, int j, Words4& wm, const F& f, typename F::T& r,
+                                           typename F::T& z) {
+    constexpr int SPB = MaskDraws<N, F>::SPB;
+    if (j % SPB == 0) wm = r01.block(TAG_MASK, (uint32_t)(j / SPB));
+    block_draws_at<N, F>(wm, j % SPB, f, r, z);
+}
+
+// Plain canonical values of kept draws (the record of the precomputed mode).
+template <int N, typename F>
+__device__ __forceinline__ void plain_draws(const F& f, typename F::T& r, typename F::T& z) {
+    constexpr int SH = MaskDraws<N, F>::SH;
+    if constexpr (SH > 0) {
+        r >>= SH;
+        z >>= SH;
+        z = min(z, z - f.p);                        // a Mersenne Z = p stands for 0
     }
 }
 
@@ -179,10 +293,9 @@ __device__ __forceinline__ T drelu_round1(T in0, T in1, uint64_t g, T mask, uint
     for (int j = 0; j < N; ++j) {
         // Mask r and reshare z of slot j.
         FT r, z;
-        slot_draws<F>(r01, j, wm, f, r, z);
+        slot_draws<N, F>(r01, j, wm, f, r, z);
         FT w0, w1;
-        const FT w = slot_messages<T, N, F>(a0k, nb1k, key[j] & 63u, r, z, f, w0, w1);
-        least = w < least ? w : least;
+        slot_messages<T, N, F, MaskDraws<N, F>::SH>(a0k, nb1k, key[j] & 63u, r, z, f, w0, w1, least);
         if constexpr (CAP) {
             cap[e * N + j] = w0;
             cap[(ncap + e) * N + j] = w1;
@@ -236,20 +349,9 @@ __device__ __forceinline__ void drelu_element(const T* __restrict__ X0, const T*
     Y1[e] = y1;
 }
 
-// Occupancy hint per window count.  At N = 19 (the key-bit setting of l = 64)
-// the kernel otherwise allocates just above the 96 VGPRs that allow 5 waves
-// per SIMD, and 5 waves measure 1-2% faster than 4; elsewhere the hint
-// (1 wave) leaves the allocation alone, since forcing more waves for wide
-// windows spills to scratch.
-template <int N>
-struct WavesHint {
-    static constexpr int value = N == 19 ? 5 : 1;
-};
-
 // One call: grid-stride over the n elements of one share pair.
 template <typename T, int N, typename F, bool RELU, bool CAP>
-__global__ BC_KERNEL_ATTRS __attribute__((amdgpu_waves_per_eu(WavesHint<N>::value))) void k_drelu(DreluKArgs A,
-                                                                                                      F f_arg) {
+__global__ BC_KERNEL_ATTRS void k_drelu(DreluKArgs A, F f_arg) {
     const F f = f_arg.vgpr();
     const T* X0 = static_cast<const T*>(A.x0);
     const T* X1 = static_cast<const T*>(A.x1);
@@ -275,8 +377,9 @@ __device__ __forceinline__ void drelu_element_group(const T* __restrict__ X0, co
                                                     uint32_t k_in, uint32_t k_lo, const Stream& s01,
                                                     const Stream& s02, const Stream& s12, const F& f) {
     using FT = typename F::T;
-    constexpr bool WIDE = std::is_same<FT, uint64_t>::value;
-    constexpr int SPB = WIDE ? 1 : 2;                       // slots per mask block
+    constexpr bool WIDE = MaskDraws<N, F>::WIDE;
+    constexpr int SPB = MaskDraws<N, F>::SPB;               // slots per mask block
+    constexpr int SH = MaskDraws<N, F>::SH;
     constexpr int NB = (N + SPB - 1) / SPB;                 // mask blocks
     constexpr int ROUNDS = (NB + G - 1) / G;
 
@@ -308,15 +411,9 @@ __device__ __forceinline__ void drelu_element_group(const T* __restrict__ X0, co
             for (int q = 1; q < G; ++q)
                 if (SPB * (k * G + q) + h < N) kj = lane == (uint32_t)q ? key[SPB * (k * G + q) + h] : kj;
             FT r, z;
-            if constexpr (WIDE) {
-                r = 1 + __umul64hi(join64(w.w0, w.w1), f.p - 1);
-                z = __umul64hi(join64(w.w2, w.w3), f.p);
-            } else {
-                r = draw_r(h ? w.w2 : w.w0, f.p);
-                z = draw_z(h ? w.w3 : w.w1, f.p);
-            }
-            FT w0, w1;
-            const FT v = slot_messages<T, N, F>(a0k, nb1k, kj & 63u, r, z, f, w0, w1);
+            block_draws_at<N, F>(w, h, f, r, z);
+            FT w0, w1, v = f.p;
+            slot_messages<T, N, F, SH>(a0k, nb1k, kj & 63u, r, z, f, w0, w1, v);
             const bool valid = SPB * blk + h < (uint32_t)N;
             least = (valid && v < least) ? v : least;
         }

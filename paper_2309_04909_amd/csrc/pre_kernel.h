@@ -80,7 +80,8 @@ __global__ BC_KERNEL_ATTRS void k_expand(ExpandKArgs A, F f) {
 #pragma unroll
         for (int j = 0; j < N; ++j) {
             typename F::T r, z;
-            slot_draws<F>(r01, j, wm, f, r, z);
+            slot_draws<N, F>(r01, j, wm, f, r, z);
+            plain_draws<N, F>(f, r, z);                   // the record keeps plain values
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int v = 2 * j + h;
@@ -171,8 +172,7 @@ __device__ __forceinline__ void drelu_pre_element(const T* __restrict__ X0, cons
         const FT r = rv[0], z = rv[1];
         const uint32_t pos = (perm[j >> 2] >> (8 * (j & 3))) & 63u;
         FT w0, w1;
-        const FT w = slot_messages<T, N, F>(a0k, nb1k, pos, r, z, f, w0, w1);
-        least = w < least ? w : least;
+        slot_messages<T, N, F>(a0k, nb1k, pos, r, z, f, w0, w1, least);
         if constexpr (CAP) {
             cap[e * N + j] = w0;
             cap[(n + e) * N + j] = w1;

@@ -29,8 +29,9 @@ struct SplitKArgs {
 };
 
 // One party's message for one slot (the P0 or P1 half of slot_messages).
-// ak: the party's flipped share (P1: its negation) shifted down by k_lo.
-template <typename T, int N, typename F, int PARTY>
+// ak: the party's flipped share (P1: its negation) shifted down by k_lo; r
+// and z in the kept representation of MaskDraws (shifted left by SH).
+template <typename T, int N, typename F, int PARTY, int SH = MaskDraws<N, F>::SH>
 __device__ __forceinline__ typename F::T party_message(T ak, uint32_t pos, typename F::T r, typename F::T z,
                                                        const F& f) {
     using FT = typename F::T;
@@ -42,10 +43,10 @@ __device__ __forceinline__ typename F::T party_message(T ak, uint32_t pos, typen
     const FT un = (Wv >> 1) & more;                                   // u_{i+1}, u_{l_x+1} := 0
     if constexpr (PARTY == 0) {
         const FT s0 = ((Wv + un - 2) & WIN) + 1;                     // v0, or 2^l_x when v0 = 0
-        return f.mul_add(s0, r, z);
+        return field_mul_add<SH>(f, s0, r, z);
     } else {
         const FT s1 = (((FT)0 - Wv - un) & WIN) + (f.p - TWO_LX);    // v1 + p - 2^l_x
-        return f.mul_add(s1, r, (FT)(f.p - z));
+        return field_mul_add<SH>(f, s1, r, (FT)((f.p << SH) - z));
     }
 }
 
@@ -95,7 +96,7 @@ __global__ BC_KERNEL_ATTRS void k_send(SplitKArgs A, F f_arg) {
 #pragma unroll
         for (int j = 0; j < N; ++j) {
             FT r, z;
-            slot_draws<F>(r01, j, wm, f, r, z);
+            slot_draws<N, F>(r01, j, wm, f, r, z);
             pack_slot<N>(words, j, (uint64_t)party_message<T, N, F, PARTY>(ak, key[j] & 63u, r, z, f));
         }
 #pragma unroll

@@ -49,5 +49,9 @@ def test_pairwise_network_sorts_random_keys(bench, n):
 def test_network_sizes_and_op_model(bench):
     sizes = {n: len(bench.pairwise_network(n)) for n in (8, 19, 33)}
     assert sizes == {8: 19, 19: 91, 33: 207}
-    # the headline's N = 19 DReLU: 16 Philox blocks, 19 slots, 91 comparators, the tail
-    assert bench.alg_ops_per_elem("drelu", 18) == 16 * 60 + 19 * 40 + 2 * 91 + 12
+    # the headline's N = 19 DReLU: 13 Philox blocks (5 for the keys, 7 for the
+    # masks at three slots a block, 1 for rho), 19 slots, 91 comparators, the tail
+    assert bench.alg_ops_per_elem("drelu", 18) == 13 * 60 + 19 * 40 + 2 * 91 + 12
+    # N = 8 (two slots a block) and N = 33 (one): 2 + 4 + 1 and 9 + 33 + 1 blocks
+    assert bench.alg_ops_per_elem("drelu", 7) == 7 * 60 + 8 * 40 + 2 * 19 + 12
+    assert [bench.mask_blocks(n) for n in (16, 17, 21, 22, 33)] == [8, 6, 7, 11, 33]
