@@ -41,6 +41,12 @@ KERNELS = {
                      ["bc_device.h", "drelu_kernel.h"], 32 * N_KEYBIT),
     "trunc_det_keybit": ("OpTruncDet<unsigned long, unsigned long>", ["bc_device.h", "k_stream.hip"],
                          32 * N_KEYBIT),
+    # the online kernels of the precomputed mode: shares plus the record (132 B per element at
+    # N = 19 for the DReLU, 72 B at N = 8 for the ReLU)
+    "drelu_pre_lx18": ("k_drelu_pre<unsigned long, 19, bc::FieldMersenne<19>, false, false>",
+                       ["bc_device.h", "drelu_kernel.h", "pre_kernel.h"], (32 + 132) * N_KEYBIT),
+    "relu_pre_lx7": ("k_drelu_pre<unsigned long, 8, bc::FieldPM<8, 5u>, true, false>",
+                     ["bc_device.h", "drelu_kernel.h", "pre_kernel.h"], (32 + 72) * N_KEYBIT),
 }
 COPY_BYTES = 512 << 20          # bench.py copy_reference: 512 MiB read and 512 MiB written per copy
 
@@ -94,6 +100,26 @@ def counters(d):
     return acc
 
 
+XCDS = 8            # MI355X: GRBM_GUI_ACTIVE is reported summed over its 8 accelerator dies
+CUS = 256
+SIMDS = 4 * CUS
+
+
+def valu_busy(vc, k):
+    """(VALUBusy in %, cycles per VALU wave-instruction per SIMD) of kernel k
+    from SQ_ACTIVE_INST_VALU (quad-cycles, summed over SIMDs), SQ_INSTS_VALU
+    and GRBM_GUI_ACTIVE (summed over the dies; its per-die value is the
+    kernel's cycles).  VALUBusy is rocprofv3's expression
+    100 * sum(SQ_ACTIVE_INST_VALU) / CU_NUM / max(GRBM_GUI_ACTIVE)."""
+    mean = lambda v: sum(v) / len(v)  # noqa: E731
+    if (k, "GRBM_GUI_ACTIVE") not in vc or (k, "SQ_ACTIVE_INST_VALU") not in vc:
+        return None, None
+    cyc = mean(vc[(k, "GRBM_GUI_ACTIVE")]) / XCDS
+    busy = 100 * mean(vc[(k, "SQ_ACTIVE_INST_VALU")]) / CUS / cyc
+    per = cyc / (mean(vc[(k, "SQ_INSTS_VALU")]) / SIMDS) if (k, "SQ_INSTS_VALU") in vc else None
+    return busy, per
+
+
 def last_calls_mean(d, k):
     """{kernel name: mean duration in ns of its last k dispatches} from the
     kernel trace (dispatches ordered by start time)."""
@@ -142,14 +168,20 @@ def summarise(trace, fetch, write, valu, name, cmd, timed_calls=0):
     if copy is None:
         raise SystemExit("no copy kernel found in the counter runs")
     mean = lambda v: sum(v) / len(v)  # noqa: E731
-    scale_f = COPY_BYTES / (mean(fc[(copy, "FETCH_SIZE")]) * 1024)
-    scale_w = COPY_BYTES / (mean(wc[(copy, "WRITE_SIZE")]) * 1024)
+
+    def big(v):
+        # the bench's 512 MiB copies: other sections' small copies of the same
+        # kernel (plans, records) are left out of the calibration
+        return [x for x in v if x >= 0.5 * max(v)]
+
+    scale_f = COPY_BYTES / (mean(big(fc[(copy, "FETCH_SIZE")])) * 1024)
+    scale_w = COPY_BYTES / (mean(big(wc[(copy, "WRITE_SIZE")])) * 1024)
     vc = counters(valu) if valu else {}
     tab = ["# HBM traffic and VALU instructions per launch: " + name, "", f"Command: `{cmd}`", "",
            f"Counters scaled by the plain copy `{copy[:80]}` of {COPY_BYTES} B read + {COPY_BYTES} B written: "
            f"FETCH_SIZE x {scale_f:.4f}, WRITE_SIZE x {scale_w:.4f}.", "",
            "| Kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes (scaled) | Algorithmic bytes | Ratio | "
-           "VALU instr / wave |", "|---|---|---|---|---|---|---|"]
+           "VALU instr / wave | VALUBusy | cycles / VALU instr / SIMD |", "|---|---|---|---|---|---|---|---|---|"]
     traffic = {}
     path = os.path.join(PROFILES, "traffic.json")
     if os.path.exists(path):
@@ -162,15 +194,26 @@ def summarise(trace, fetch, write, valu, name, cmd, timed_calls=0):
         k = kn[0]
         fk, wk = mean(fc[(k, "FETCH_SIZE")]), mean(wc[(k, "WRITE_SIZE")])
         hbm = fk * 1024 * scale_f + wk * 1024 * scale_w
-        vi = ""
+        vi = vb = vp = ""
         if vc:
             vk = [n for n in {a for a, _ in vc} if _match(n, sub)]
             if vk and (vk[0], "SQ_INSTS_VALU") in vc and (vk[0], "SQ_WAVES") in vc:
                 vi = f"{mean(vc[(vk[0], 'SQ_INSTS_VALU')]) / mean(vc[(vk[0], 'SQ_WAVES')]):.0f}"
-        tab.append(f"| `{key}` | {fk:.0f} | {wk:.0f} | {hbm:.4g} | {alg:.4g} | {hbm / alg:.3f} | {vi} |")
+            if vk:
+                b, per = valu_busy(vc, vk[0])
+                vb = f"{b:.1f}%" if b is not None else ""
+                vp = f"{per:.2f}" if per is not None else ""
+        tab.append(f"| `{key}` | {fk:.0f} | {wk:.0f} | {hbm:.4g} | {alg:.4g} | {hbm / alg:.3f} | {vi} | {vb} | {vp} |")
         traffic[key] = {"bytes_per_launch": round(hbm), "fetch_kib": fk, "write_kib": wk,
                         "scale_fetch": scale_f, "scale_write": scale_w, "algorithmic_bytes": alg,
                         "source_hash": source_hash(srcs), "command": cmd}
+    tab += ["", "VALUBusy is rocprofv3's expression 100 * sum(SQ_ACTIVE_INST_VALU) / CU_NUM / max(GRBM_GUI_ACTIVE), "
+            f"with GRBM_GUI_ACTIVE divided by the {XCDS} dies it is summed over (its per-die value over the kernel's "
+            "duration gives the ~2.4 GHz counter clock). On gfx950 SQ_ACTIVE_INST_VALU equals SQ_INSTS_VALU: one "
+            "quad-cycle per wave instruction, while simple VOP2 operations issue two per quad-cycle, so VALUBusy can "
+            "exceed 100%. Cycles per VALU instruction per SIMD = per-die GRBM_GUI_ACTIVE / (SQ_INSTS_VALU / "
+            f"{SIMDS} SIMDs): 4 for an issue-bound stream of half-rate (VOP3-class) instructions, about 2 for "
+            "full-rate ones."]
     with open(os.path.join(PROFILES, f"{name}_counters.md"), "w") as f:
         f.write("\n".join(tab) + "\n")
     with open(path, "w") as f:
