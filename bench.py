@@ -353,9 +353,10 @@ def run_alone(torch, B, inputs, steps, warmup):
             "trunc_det_gbs": round(gbs, 1), "trunc_det_hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
-def run_batched_vs_plain(torch, B, steps, warmup, batch=32):
-    """All 17 ReLU activation tensors of a ResNet-18 pass (batch 32, 224x224):
-    one persistent launch replayed from a HIP graph vs 17 plain launches."""
+def _batched_vs_plain(torch, B, steps, warmup, batch):
+    """The 17 ReLU activation tensors of a ResNet-18 pass at `batch`, 224x224:
+    one persistent launch replayed from a HIP graph against 17 plain launches,
+    called one by one and captured into a graph of their own."""
     from paper_2309_04909_amd import batch as BT
     prm = B.Params(64, 7, 11)
     seeds = SEEDS
@@ -368,25 +369,47 @@ def run_batched_vs_plain(torch, B, steps, warmup, batch=32):
     total = sum(s.x0.numel() for s in segs)
     rb = BT.RaggedBatch(prm, B.Seeds(*seeds), segs)
     graph = rb.capture()
+    sds = [B.Seeds(*seeds, s.nonce) for s in segs]
 
     def plain():
-        for s in segs:
-            B.relu(s.x0, s.x1, prm, B.Seeds(*seeds, s.nonce), out=(s.y0, s.y1))
+        for s, sd in zip(segs, sds):
+            B.relu(s.x0, s.x1, prm, sd, out=(s.y0, s.y1))
 
-    def timed(fn):
-        return _event_ms(torch, fn, steps, warmup)
-
-    ms_plain = timed(plain)
+    plain()
+    torch.cuda.synchronize()
     ref = [(s.y0.clone(), s.y1.clone()) for s in segs]
-    ms_batch = timed(graph.replay)
+    side = torch.cuda.Stream()                    # the 17 plain launches captured as one graph
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plain()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    plain_graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(plain_graph):
+        plain()
+
+    ms_plain = _event_ms(torch, plain, steps, warmup)
+    ms_plain_graph = _event_ms(torch, plain_graph.replay, steps, warmup)
     same = all(torch.equal(a, s.y0) and torch.equal(b, s.y1) for (a, b), s in zip(ref, segs))
+    ms_batch = _event_ms(torch, graph.replay, steps, warmup)
+    same &= all(torch.equal(a, s.y0) and torch.equal(b, s.y1) for (a, b), s in zip(ref, segs))
     return {"workload": f"ResNet-18 ReLU activations, batch {batch}, 224x224: 17 tensors, {total} elements, "
                         "l=64, k_lo=11, l_x=7 (p=251)",
-            "elements": total, "plain_ms": round(ms_plain, 4), "batched_ms": round(ms_batch, 4),
-            "plain_gelem_s": round(total / ms_plain / 1e6, 3), "batched_gelem_s": round(total / ms_batch / 1e6, 3),
-            "speedup": round(ms_plain / ms_batch, 4), "identical_outputs": bool(same),
+            "elements": total, "plain_ms": round(ms_plain, 4), "plain_graph_ms": round(ms_plain_graph, 4),
+            "batched_ms": round(ms_batch, 4), "plain_gelem_s": round(total / ms_plain / 1e6, 3),
+            "batched_gelem_s": round(total / ms_batch / 1e6, 3), "speedup": round(ms_plain / ms_batch, 4),
+            "speedup_vs_plain_graph": round(ms_plain_graph / ms_batch, 4), "identical_outputs": bool(same),
             "batched": "one persistent launch (bc_batch_run) replayed from a HIP graph",
-            "plain": "17 bc_relu launches"}
+            "plain": "17 bc_relu launches", "plain_graph": "the 17 bc_relu launches captured in one HIP graph"}
+
+
+def run_batched_vs_plain(torch, B, steps, warmup):
+    """Batched against per-layer plain launches at batch 32 (large segments,
+    the configured workload) and at batch 1 (17 segments of 1,568 to 802,816
+    elements, where launch and tail costs show)."""
+    out = _batched_vs_plain(torch, B, steps, warmup, 32)
+    out["batch1"] = _batched_vs_plain(torch, B, max(steps, 50), max(warmup, 10), 1)
+    return out
 
 
 def run_chain(torch, B, steps, warmup, batch=32):

@@ -402,20 +402,36 @@ int bc_rss_relu(const void* x0, const void* x1, const void* x2, void* y0, void* 
  * P2's response share rho, for ReLU the triple [a]_0 [b]_0 [c]_0 [a]_1 [b]_1
  * [c]_1 (ring width each, [c]_1 formed by P2). */
 
+/* What a record was expanded for, in host memory: bc_rand_expand fills it,
+ * and every call that reads the record checks it against its own op,
+ * setting and n before anything is enqueued (a record read with another
+ * stride or field packing would give wrong outputs without any error). */
+#define BC_RAND_MAGIC 0x44524342u   /* "BCRD" */
+typedef struct {
+    uint32_t magic;          /* BC_RAND_MAGIC once filled                  */
+    uint32_t op;             /* BC_OP_DRELU or BC_OP_RELU                  */
+    bc_drelu_params prm;     /* the setting, with p resolved               */
+    uint64_t n;              /* elements                                   */
+    uint64_t bytes;          /* bytes of the record, bc_rand_bytes(op, prm, n) */
+} bc_rand_desc;
+
 /* Bytes of the record of `op` on n elements; 0 if the setting is invalid. */
 uint64_t bc_rand_bytes(uint32_t op, const bc_drelu_params* prm, uint64_t n);
 
 /* Offline: expand the seeds of elements elem_base .. elem_base + n - 1 into
- * `rand` (device, 16-byte aligned, rand_bytes >= bc_rand_bytes). */
+ * `rand` (device, 16-byte aligned, rand_bytes >= bc_rand_bytes).  desc:
+ * NULL, or host memory that receives the record's description. */
 int bc_rand_expand(void* rand, uint64_t rand_bytes, uint64_t n, uint32_t op, const bc_drelu_params* prm,
-                   const bc_seeds* seeds, uint64_t elem_base, void* stream);
+                   const bc_seeds* seeds, uint64_t elem_base, bc_rand_desc* desc, void* stream);
 
-/* Online DReLU (Alg. 7) / ReLU (Alg. 8) from an expanded record of the same
- * op, setting and n.  Other arguments as bc_drelu. */
+/* Online DReLU (Alg. 7) / ReLU (Alg. 8) from an expanded record.  desc is
+ * the record's description from bc_rand_expand (host memory, required): a
+ * record of another op, setting or n is refused with BC_ERR_ARG.  Other
+ * arguments as bc_drelu. */
 int bc_drelu_pre(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, const bc_drelu_params* prm,
-                 const void* rand, uint64_t rand_bytes, void* capture, bc_msg_acct* acct, void* stream);
+                 const void* rand, const bc_rand_desc* desc, void* capture, bc_msg_acct* acct, void* stream);
 int bc_relu_pre(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, const bc_drelu_params* prm,
-                const void* rand, uint64_t rand_bytes, void* capture, bc_msg_acct* acct, void* stream);
+                const void* rand, const bc_rand_desc* desc, void* capture, bc_msg_acct* acct, void* stream);
 
 /* ------------------------------------------------------ ragged batching */
 
@@ -425,8 +441,8 @@ int bc_relu_pre(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, 
  * bc_drelu / bc_relu (k_in = 0) or bc_trunc_drelu / bc_trunc_relu with
  * k1 = k_in on that segment, with seeds->nonce = nonce and the same
  * elem_base.  A segment with a record (rand != NULL, from bc_rand_expand for
- * the segment's op, the batch's setting and its n) takes every draw from the
- * record instead of the seeds: its result is that of the fused call with the
+ * the segment's op, the batch's setting and its n, as its rand_desc must
+ * say) takes every draw from the record instead of the seeds: its result is that of the fused call with the
  * seeds, nonce and elem_base the record was expanded with, and the segment's
  * own nonce and elem_base are not used.  Outputs of one segment must not
  * overlap inputs or outputs of another. */
@@ -445,7 +461,8 @@ typedef struct {
                             width of ell.  0 = none                      */
     const void* rand;    /* NULL, or a device record of bc_rand_expand
                             (16-byte aligned)                          */
-    uint64_t rand_bytes; /* bytes of rand, >= bc_rand_bytes(op, prm, n) */
+    const bc_rand_desc* rand_desc; /* its description (host memory, read
+                            by bc_batch_plan only); required with rand  */
 } bc_segment;
 
 /* Bytes of the plan buffer for nseg segments: a 64-byte header, the segment

@@ -40,9 +40,9 @@ def _records(params: B.Params, segments):
         B._check_shares(s.y0, s.y1, width, "outputs")
         if s.x0.numel() != s.y0.numel():
             raise ValueError("segment input and output lengths differ")
-        rp, rb = (s.rand.data_ptr(), s.rand.numel() * s.rand.element_size()) if s.rand is not None else (None, 0)
+        rp, rd = (s.rand.data_ptr(), ctypes.pointer(B.rand_desc(s.rand))) if s.rand is not None else (None, None)
         recs[i] = B._Segment(s.x0.data_ptr(), s.x1.data_ptr(), s.y0.data_ptr(), s.y1.data_ptr(), s.x0.numel(),
-                             s.elem_base, s.nonce & m, s.op, s.k_in, rp, rb)
+                             s.elem_base, s.nonce & m, s.op, s.k_in, rp, rd)
     return recs
 
 

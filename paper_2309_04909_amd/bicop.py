@@ -23,6 +23,7 @@ BC_OP_RSS_DRELU = 2
 BC_OP_RSS_RELU = 3
 BC_STATIC_PLAN_BYTES = 65536      # fixed device plan area of bc_batch_run_static
 BC_STATIC_MAX_SEGMENTS = 743
+BC_RAND_MAGIC = 0x44524342       # bc_rand_desc.magic once bc_rand_expand has filled it
 BC_TRUNC_NONE, BC_TRUNC_AFTER, BC_TRUNC_BEFORE = 0, 1, 2
 LINKS = ("P0->P2", "P1->P2", "P2->P0", "P2->P1", "P0->P1", "P1->P0")
 
@@ -53,11 +54,16 @@ class _Acct(ctypes.Structure):
                 ("reserved", ctypes.c_uint32)]
 
 
+class _RandDesc(ctypes.Structure):
+    _fields_ = [("magic", ctypes.c_uint32), ("op", ctypes.c_uint32), ("prm", _Params), ("n", ctypes.c_uint64),
+                ("bytes", ctypes.c_uint64)]
+
+
 class _Segment(ctypes.Structure):
     _fields_ = [("x0", ctypes.c_void_p), ("x1", ctypes.c_void_p), ("y0", ctypes.c_void_p), ("y1", ctypes.c_void_p),
                 ("n", ctypes.c_uint64), ("elem_base", ctypes.c_uint64), ("nonce", ctypes.c_uint64),
                 ("op", ctypes.c_uint32), ("k_in", ctypes.c_uint32), ("rand", ctypes.c_void_p),
-                ("rand_bytes", ctypes.c_uint64)]
+                ("rand_desc", ctypes.POINTER(_RandDesc))]
 
 
 _P = ctypes.c_void_p
@@ -98,12 +104,12 @@ _SIGS = {
     "bc_batch_run": ([_P, _P, ctypes.POINTER(_Seeds), _U32, _P], ctypes.c_int),
     "bc_batch_run_static": ([_P, ctypes.POINTER(_Seeds), _U32, _P], ctypes.c_int),
     "bc_rand_bytes": ([_U32, ctypes.POINTER(_Params), _U64], _U64),
-    "bc_rand_expand": ([_P, _U64, _U64, _U32, ctypes.POINTER(_Params), ctypes.POINTER(_Seeds), _U64, _P],
-                       ctypes.c_int),
-    "bc_drelu_pre": ([_P, _P, _P, _P, _U64, ctypes.POINTER(_Params), _P, _U64, _P, ctypes.POINTER(_Acct), _P],
-                     ctypes.c_int),
-    "bc_relu_pre": ([_P, _P, _P, _P, _U64, ctypes.POINTER(_Params), _P, _U64, _P, ctypes.POINTER(_Acct), _P],
-                    ctypes.c_int),
+    "bc_rand_expand": ([_P, _U64, _U64, _U32, ctypes.POINTER(_Params), ctypes.POINTER(_Seeds), _U64,
+                        ctypes.POINTER(_RandDesc), _P], ctypes.c_int),
+    "bc_drelu_pre": ([_P, _P, _P, _P, _U64, ctypes.POINTER(_Params), _P, ctypes.POINTER(_RandDesc), _P,
+                      ctypes.POINTER(_Acct), _P], ctypes.c_int),
+    "bc_relu_pre": ([_P, _P, _P, _P, _U64, ctypes.POINTER(_Params), _P, ctypes.POINTER(_RandDesc), _P,
+                     ctypes.POINTER(_Acct), _P], ctypes.c_int),
     "bc_trunc_drelu": ([_P, _P, _P, _P, _U64, _U32, _U32, ctypes.POINTER(_Params), ctypes.POINTER(_Seeds), _U64, _P,
                         ctypes.POINTER(_Acct), _P], ctypes.c_int),
     "bc_trunc_relu": ([_P, _P, _P, _P, _U64, _U32, _U32, ctypes.POINTER(_Params), ctypes.POINTER(_Seeds), _U64, _P,
@@ -526,14 +532,27 @@ def rand_bytes(op, params: Params, n):
 
 
 def rand_expand(op, params: Params, seeds: Seeds, n, elem_base=0, out=None, device="cuda", stream=None):
-    """Offline phase: the seeds' draws for n elements, as a device byte buffer."""
+    """Offline phase: the seeds' draws for n elements, as a device byte buffer.
+    The record's description (bc_rand_desc) rides on the buffer as
+    `bicop_desc`; the online calls and batch segments pass it to the library,
+    which refuses a record of another op, setting or n."""
     nb = rand_bytes(op, params, n)
     if nb == 0 and n:
         _check(lib.bc_check_params(ctypes.byref(params.c()), None), "rand_expand")
     buf = out if out is not None else torch.empty(max(nb, 1), dtype=torch.uint8, device=device)
+    desc = _RandDesc()
     _check(lib.bc_rand_expand(buf.data_ptr(), buf.numel(), n, op, ctypes.byref(params.c()), ctypes.byref(seeds.c()),
-                              elem_base, _stream(stream, buf)), "rand_expand")
+                              elem_base, ctypes.byref(desc), _stream(stream, buf)), "rand_expand")
+    buf.bicop_desc = desc
     return buf
+
+
+def rand_desc(rand):
+    """The description bc_rand_expand gave the record `rand`."""
+    desc = getattr(rand, "bicop_desc", None)
+    if desc is None:
+        raise ValueError("the record has no description: make it with rand_expand")
+    return desc
 
 
 def _pre_like(fn, name, x0, x1, params, rand, capture, out, stream):
@@ -544,7 +563,7 @@ def _pre_like(fn, name, x0, x1, params, rand, capture, out, stream):
     if capture:
         cap = torch.empty((2, x0.numel(), params.npos), dtype=field_dtype(params.resolved().p), device=x0.device)
     _check(fn(x0.data_ptr(), x1.data_ptr(), y0.data_ptr(), y1.data_ptr(), x0.numel(), ctypes.byref(params.c()),
-              rand.data_ptr(), rand.numel() * rand.element_size(), None if cap is None else cap.data_ptr(), None,
+              rand.data_ptr(), ctypes.byref(rand_desc(rand)), None if cap is None else cap.data_ptr(), None,
               _stream(stream, x0)), name)
     return (y0, y1, cap) if capture else (y0, y1)
 

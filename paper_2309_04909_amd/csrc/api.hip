@@ -116,6 +116,26 @@ int check_params(const bc_drelu_params* prm, bc_drelu_params* out) {
     return BC_OK;
 }
 
+// A record's description against the op, resolved setting and n of the call
+// that reads it.
+int check_desc(const bc_rand_desc* d, uint32_t op, const bc_drelu_params& r, uint64_t n) {
+    if (!d) return fail(BC_ERR_NULL, "record description is NULL");
+    if (d->magic != BC_RAND_MAGIC) return fail(BC_ERR_ARG, "record description was not filled by bc_rand_expand");
+    if (d->op != op || d->prm.ell != r.ell || d->prm.lx != r.lx || d->prm.k_lo != r.k_lo || d->prm.p != r.p ||
+        d->n != n)
+        return fail(BC_ERR_ARG,
+                    "record was expanded for op %u, l = %u, l_x = %u, k_lo = %u, p = %llu, n = %llu; the call has op "
+                    "%u, l = %u, l_x = %u, k_lo = %u, p = %llu, n = %llu",
+                    d->op, d->prm.ell, d->prm.lx, d->prm.k_lo, (unsigned long long)d->prm.p,
+                    (unsigned long long)d->n, op, r.ell, r.lx, r.k_lo, (unsigned long long)r.p,
+                    (unsigned long long)n);
+    const uint64_t need = bc::rand_offsets(r.lx + 1, op == BC_OP_RELU, width_of_ring(r.ell), n).total;
+    if (d->bytes < need)
+        return fail(BC_ERR_WORKSPACE, "record holds %llu of %llu bytes", (unsigned long long)d->bytes,
+                    (unsigned long long)need);
+    return BC_OK;
+}
+
 int account(uint32_t op, const bc_drelu_params& r, uint64_t n, bc_msg_acct* a) {
     memset(a, 0, sizeof(*a));
     const uint64_t npos = r.lx + 1;
@@ -386,10 +406,12 @@ int batch_plan(const bc_segment* segs, uint32_t nseg, const bc_drelu_params* prm
             return fail(BC_ERR_ALIGN, "segment %u: share pointers must be %u-byte aligned", i, w);
         if (s.rand) {
             if (!aligned(s.rand, 16)) return fail(BC_ERR_ALIGN, "segment %u: record must be 16-byte aligned", i);
-            const uint64_t need = bc::rand_offsets(r.lx + 1, s.op == BC_OP_RELU, w, s.n).total;
-            if (s.rand_bytes < need)
-                return fail(BC_ERR_WORKSPACE, "segment %u: record holds %llu of %llu bytes", i,
-                            (unsigned long long)s.rand_bytes, (unsigned long long)need);
+            if (int rc_d = check_desc(s.rand_desc, s.op, r, s.n)) {
+                const int rc_seg = rc_d;
+                char why[sizeof(g_err)];
+                snprintf(why, sizeof(why), "%s", g_err);
+                return fail(rc_seg, "segment %u: %s", i, why);
+            }
         }
         out[i] = s;
         tb[i] = tiles;
@@ -446,19 +468,36 @@ int batch_run(const void* dev_plan, const void* host_plan, const bc_seeds* seeds
     return e == hipSuccess ? BC_OK : hip_fail(e, "batch launch");
 }
 
+// The offline expansion (expand: writes `rand`, rand_bytes is its size, the
+// description goes to desc_out when given) or the online call (reads `rand`,
+// whose description desc_in must match the call).
 int pre_common(bool expand, uint32_t op, const void* x0, const void* x1, void* y0, void* y1, uint64_t n,
                const bc_drelu_params* prm, const bc_seeds* seeds, uint64_t elem_base, void* rand, uint64_t rand_bytes,
-               void* capture, bc_msg_acct* acct, void* stream) {
+               const bc_rand_desc* desc_in, bc_rand_desc* desc_out, void* capture, bc_msg_acct* acct, void* stream) {
     if (op != BC_OP_DRELU && op != BC_OP_RELU) return fail(BC_ERR_ARG, "unknown op %u", op);
     bc_drelu_params r;
     int rc = check_params(prm, &r);
     if (rc) return rc;
     if (expand && !seeds) return fail(BC_ERR_NULL, "seeds is NULL");
     if (int rc_i = check_indices(n, elem_base)) return rc_i;
-    if (acct) account(op, r, n, acct);
-    if (n == 0) return BC_OK;
     const uint32_t w = width_of_ring(r.ell);
     const bc::RandOffsets o = bc::rand_offsets(r.lx + 1, op == BC_OP_RELU, w, n);
+    if (!expand) {
+        if (int rc_d = check_desc(desc_in, op, r, n)) return rc_d;
+        rand_bytes = desc_in->bytes;
+    }
+    if (acct) account(op, r, n, acct);
+    if (expand && desc_out) {
+        if (rand_bytes < o.total) return fail(BC_ERR_WORKSPACE, "randomness buffer holds %llu of %llu bytes",
+                                              (unsigned long long)rand_bytes, (unsigned long long)o.total);
+        memset(desc_out, 0, sizeof(*desc_out));
+        desc_out->magic = BC_RAND_MAGIC;
+        desc_out->op = op;
+        desc_out->prm = r;
+        desc_out->n = n;
+        desc_out->bytes = o.total;
+    }
+    if (n == 0) return BC_OK;
     if (!rand) return fail(BC_ERR_NULL, "randomness buffer is NULL");
     if (!aligned(rand, 16)) return fail(BC_ERR_ALIGN, "randomness buffer must be 16-byte aligned");
     if (rand_bytes < o.total) return fail(BC_ERR_WORKSPACE, "randomness buffer holds %llu of %llu bytes",
@@ -716,21 +755,21 @@ uint64_t bc_rand_bytes(uint32_t op, const bc_drelu_params* prm, uint64_t n) {
 }
 
 int bc_rand_expand(void* rand, uint64_t rand_bytes, uint64_t n, uint32_t op, const bc_drelu_params* prm,
-                   const bc_seeds* seeds, uint64_t elem_base, void* stream) {
+                   const bc_seeds* seeds, uint64_t elem_base, bc_rand_desc* desc, void* stream) {
     return pre_common(true, op, nullptr, nullptr, nullptr, nullptr, n, prm, seeds, elem_base, rand, rand_bytes, nullptr,
-                      nullptr, stream);
+                      desc, nullptr, nullptr, stream);
 }
 
 int bc_drelu_pre(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, const bc_drelu_params* prm,
-                 const void* rand, uint64_t rand_bytes, void* capture, bc_msg_acct* acct, void* stream) {
-    return pre_common(false, BC_OP_DRELU, x0, x1, y0, y1, n, prm, nullptr, 0, const_cast<void*>(rand), rand_bytes,
-                      capture, acct, stream);
+                 const void* rand, const bc_rand_desc* desc, void* capture, bc_msg_acct* acct, void* stream) {
+    return pre_common(false, BC_OP_DRELU, x0, x1, y0, y1, n, prm, nullptr, 0, const_cast<void*>(rand), 0, desc,
+                      nullptr, capture, acct, stream);
 }
 
 int bc_relu_pre(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, const bc_drelu_params* prm,
-                const void* rand, uint64_t rand_bytes, void* capture, bc_msg_acct* acct, void* stream) {
-    return pre_common(false, BC_OP_RELU, x0, x1, y0, y1, n, prm, nullptr, 0, const_cast<void*>(rand), rand_bytes,
-                      capture, acct, stream);
+                const void* rand, const bc_rand_desc* desc, void* capture, bc_msg_acct* acct, void* stream) {
+    return pre_common(false, BC_OP_RELU, x0, x1, y0, y1, n, prm, nullptr, 0, const_cast<void*>(rand), 0, desc,
+                      nullptr, capture, acct, stream);
 }
 
 int bc_trunc_drelu(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, uint32_t ell_in, uint32_t k1,

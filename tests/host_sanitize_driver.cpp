@@ -93,6 +93,7 @@ int main() {
     for (int trial = 0; trial < 200; ++trial) {
         const uint32_t nseg = 1 + (uint32_t)(lcg(seed) % 1200);
         std::vector<bc_segment> segs(nseg);
+        std::vector<bc_rand_desc> descs(nseg);
         for (uint32_t i = 0; i < nseg; ++i) {
             bc_segment& s = segs[i];
             memset(&s, 0, sizeof(s));
@@ -109,7 +110,15 @@ int main() {
             s.k_in = (r >> 44) % 3 == 0 ? 13u : ((r >> 46) % 53 == 0 ? 14u : 0u);
             if ((r >> 50) % 4 == 0) {
                 s.rand = (const void*)(0x40000000ull + 0x10000ull * i + ((r >> 52) % 89 == 0 ? 8 : 0));
-                s.rand_bytes = bc_rand_bytes(s.op & 1, &prm, s.n) - ((r >> 55) % 71 == 0 ? 1 : 0);
+                bc_rand_desc& d = descs[i];
+                // the description of a real expansion, sometimes for another n or op, or missing
+                bc_rand_expand(nullptr, 0, 0, s.op & 1, &prm, nullptr, 0, &d, nullptr);   // refused: seeds NULL
+                bc_seeds sd0 = {1, 2, 3, 4};
+                const uint64_t dn = s.n + ((r >> 55) % 71 == 0 ? 1 : 0);
+                bc_rand_expand(nullptr, ~0ull, 0, s.op & 1, &prm, &sd0, 0, &d, nullptr);  // n = 0: fills d
+                d.n = dn;
+                d.bytes = bc_rand_bytes(s.op & 1, &prm, dn);
+                s.rand_desc = (r >> 57) % 97 == 0 ? nullptr : &d;
             }
         }
         const uint64_t nbytes = bc_batch_plan_bytes(nseg);
@@ -171,9 +180,12 @@ int main() {
                 mix((uint64_t)(bc_trunc_relu(P, P, Q, Q, n, ell + 1, 0, &p2, &sd, 0, nullptr, nullptr, nullptr) + 16));
                 mix((uint64_t)(bc_rss_drelu(P, P, P, Q, Q, Q, n, &p2, &rsd, 0, nullptr, &acct, nullptr) + 16));
                 mix((uint64_t)(bc_rss_relu(P, nullptr, P, Q, Q, Q, n, &p2, &rsd, 0, nullptr, nullptr, nullptr) + 16));
-                mix((uint64_t)(bc_drelu_pre(P, P, Q, Q, n, &p2, nullptr, 0, nullptr, nullptr, nullptr) + 16));
-                mix((uint64_t)(bc_relu_pre(P, P, Q, Q, n, &p2, M, 64, nullptr, nullptr, nullptr) + 16));
-                mix((uint64_t)(bc_rand_expand(M, 0, n, 0, &p2, &sd, 0, nullptr) + 16));
+                bc_rand_desc d;
+                memset(&d, 0, sizeof(d));
+                mix((uint64_t)(bc_rand_expand(M, 0, n, 0, &p2, &sd, 0, &d, nullptr) + 16));
+                mix((uint64_t)(bc_drelu_pre(P, P, Q, Q, n, &p2, nullptr, &d, nullptr, nullptr, nullptr) + 16));
+                mix((uint64_t)(bc_relu_pre(P, P, Q, Q, n, &p2, M, &d, nullptr, nullptr, nullptr) + 16));
+                mix((uint64_t)(bc_relu_pre(P, P, Q, Q, n, &p2, M, nullptr, nullptr, nullptr, nullptr) + 16));
                 mix((uint64_t)(bc_drelu_send(2, P, (uint32_t*)Q, n, &p2, &sd, 0, nullptr) + 16));
                 mix((uint64_t)(bc_drelu_reply(nullptr, (const uint32_t*)P, Q, Q, n, &p2, &sd, 0, nullptr) + 16));
                 mix((uint64_t)(bc_drelu_finish(0, P, M, n, &p2, &sd, 0, nullptr) + 16));

@@ -166,15 +166,34 @@ def test_batch_plan_validation_on_host():
     seg[1].k_in = 9                                                                  # 33 bits: another width
     assert L.bc_batch_plan(seg, 2, ctypes.byref(r24), 1024, buf, nbytes) == -2
     seg[1].k_in = 0
-    # a record segment: 16-byte aligned record of at least bc_rand_bytes(op, prm, n)
-    need = L.bc_rand_bytes(B.BC_OP_RELU, ctypes.byref(prm), 5000)
-    seg[0].rand, seg[0].rand_bytes = 0x100000, need
+    # a record segment: a 16-byte aligned record whose description (filled by
+    # bc_rand_expand: here an empty expansion, then n set) matches the segment
+    desc = B._RandDesc()
+    sd0 = B.Seeds(1, 2, 3).c()
+    assert L.bc_rand_expand(None, 0, 0, B.BC_OP_RELU, ctypes.byref(prm), ctypes.byref(sd0), 0, ctypes.byref(desc),
+                            None) == 0
+    assert desc.magic == B.BC_RAND_MAGIC and desc.op == B.BC_OP_RELU and desc.prm.p == 251 and desc.n == 0
+    desc.n, desc.bytes = 5000, L.bc_rand_bytes(B.BC_OP_RELU, ctypes.byref(prm), 5000)
+    seg[0].rand, seg[0].rand_desc = 0x100000, ctypes.pointer(desc)
     assert L.bc_batch_plan(seg, 2, ctypes.byref(prm), 1024, buf, nbytes) == 0
-    seg[0].rand_bytes = need - 1
+    desc.bytes -= 1
     assert L.bc_batch_plan(seg, 2, ctypes.byref(prm), 1024, buf, nbytes) == -7
-    seg[0].rand, seg[0].rand_bytes = 0x100008, need
+    desc.bytes += 1
+    desc.n = 4999                                                      # expanded for another n
+    assert L.bc_batch_plan(seg, 2, ctypes.byref(prm), 1024, buf, nbytes) == -8
+    assert b"record was expanded for" in L.bc_last_error()
+    desc.n, desc.op = 5000, B.BC_OP_DRELU                              # for another op
+    assert L.bc_batch_plan(seg, 2, ctypes.byref(prm), 1024, buf, nbytes) == -8
+    desc.op, desc.prm.k_lo = B.BC_OP_RELU, 10                          # for another setting
+    assert L.bc_batch_plan(seg, 2, ctypes.byref(prm), 1024, buf, nbytes) == -8
+    desc.prm.k_lo, desc.magic = 11, 0                                  # not filled by bc_rand_expand
+    assert L.bc_batch_plan(seg, 2, ctypes.byref(prm), 1024, buf, nbytes) == -8
+    desc.magic = B.BC_RAND_MAGIC
+    seg[0].rand_desc = None                                            # missing
+    assert L.bc_batch_plan(seg, 2, ctypes.byref(prm), 1024, buf, nbytes) == -1
+    seg[0].rand, seg[0].rand_desc = 0x100008, ctypes.pointer(desc)     # misaligned record
     assert L.bc_batch_plan(seg, 2, ctypes.byref(prm), 1024, buf, nbytes) == -5
-    seg[0].rand, seg[0].rand_bytes = None, 0
+    seg[0].rand, seg[0].rand_desc = None, None
     # bc_batch_run refuses a buffer that is not a plan (checked before any launch)
     junk = (ctypes.c_uint8 * nbytes)()
     sd = B.Seeds(1, 2, 3).c()

@@ -75,13 +75,33 @@ def test_pre_equals_fused(B, op, ell, lx, k_lo):
 
 def test_pre_rejects_small_buffer(B):
     prm = B.Params(64, 7, 11)
-    x = torch.zeros(100, dtype=torch.int64, device="cuda")
     small = torch.empty(B.rand_bytes(B.BC_OP_RELU, prm, 100) - 8, dtype=torch.uint8, device="cuda")
     with pytest.raises(B.BicopError) as ei:
-        B.relu_pre(x, x, prm, small)
-    assert ei.value.code == -7
-    with pytest.raises(B.BicopError):
         B.rand_expand(B.BC_OP_RELU, prm, B.Seeds(1, 2, 3), 100, out=small)
+    assert ei.value.code == -7
+    x = torch.zeros(100, dtype=torch.int64, device="cuda")
+    with pytest.raises(ValueError):                      # a buffer bc_rand_expand did not describe
+        B.relu_pre(x, x, prm, small)
+
+
+def test_pre_refuses_a_record_of_another_call(B):
+    """A record read with another op, setting or length is refused on the host
+    with BC_ERR_ARG (its description says what it was expanded for); nothing
+    is launched and the outputs stay as they were."""
+    prm = B.Params(64, 7, 11)
+    rec = B.rand_expand(B.BC_OP_RELU, prm, B.Seeds(1, 2, 3, 4), 100)
+    x = torch.ones(100, dtype=torch.int64, device="cuda")
+    y = (torch.full_like(x, 7), torch.full_like(x, 7))
+    cases = [(B.relu_pre, x[:99], prm), (B.drelu_pre, x, prm), (B.relu_pre, x, B.Params(64, 7, 10)),
+             (B.relu_pre, x, B.Params(64, 8, 11)), (B.relu_pre, x, B.Params(51, 7, 11))]
+    for fn, xs, p in cases:
+        with pytest.raises(B.BicopError) as ei:
+            fn(xs, xs, p, rec, out=(y[0][:xs.numel()], y[1][:xs.numel()]))
+        assert ei.value.code == -8, (fn.__name__, xs.numel(), p)
+    torch.cuda.synchronize()
+    assert bool((y[0] == 7).all()) and bool((y[1] == 7).all())
+    z0, z1 = B.relu_pre(x, x, prm, rec)                  # the matching call runs
+    assert z0.numel() == 100
 
 
 PACKING_CASES = [(64, 3, 5), (64, 4, 5), (64, 5, 5), (64, 6, 5), (64, 9, 5), (64, 10, 5), (64, 12, 5), (64, 21, 5),
