@@ -197,6 +197,9 @@ int bc_zp_mul_add(const uint64_t* a, const uint64_t* b, const uint64_t* d, uint6
 #define BC_SCHED_GROUP   5u   /* bc_drelu, bc_relu on small n: the value is
                                  the largest number of lanes per element
                                  (1 = off, 4, 8; default 8)                */
+#define BC_SCHED_GROUP_FILL 6u /* bc_drelu, bc_relu: lane groups are used
+                                 while n times the lanes per element stays
+                                 within this many waves per SIMD (default 1) */
 
 /* Wildcard of bc_set_schedule's ring_width and op. */
 #define BC_SCHED_ALL 0xFFFFFFFFu

@@ -135,7 +135,7 @@ def _load():
 
 lib = _load()
 
-SCHED_KINDS = {"fused": 0, "stream": 1, "pre": 2, "expand": 3, "batch": 4, "group": 5}
+SCHED_KINDS = {"fused": 0, "stream": 1, "pre": 2, "expand": 3, "batch": 4, "group": 5, "group_fill": 6}
 SCHED_ALL = 0xFFFFFFFF
 SCHEDULES_PATH = os.path.join(_HERE, "schedules.json")
 

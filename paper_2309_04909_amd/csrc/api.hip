@@ -191,10 +191,11 @@ int grid_cap(int per_cu) { return bc::device_cus() * per_cu; }
 // built-in default.  Written by bc_set_schedule.  Settings that share a
 // window count but not a ring width or an op run different kernels, so each
 // keeps its own entry.
-constexpr int kKinds = 6;
+constexpr int kKinds = 7;
 std::atomic<uint32_t> g_sched[kKinds][34][2][2];
-// blocks per CU of each kind; for BC_SCHED_GROUP the largest lanes per element
-constexpr uint32_t kDefaultBpc[kKinds] = {16, 8, 16, 16, 8, 8};
+// blocks per CU of each kind; for BC_SCHED_GROUP the largest lanes per element,
+// for BC_SCHED_GROUP_FILL the waves per SIMD lane groups may fill
+constexpr uint32_t kDefaultBpc[kKinds] = {16, 8, 16, 16, 8, 8, 1};
 
 uint32_t sched_value(uint32_t kind, uint32_t npos, uint32_t width, bool relu) {
     const uint32_t v =
@@ -203,15 +204,17 @@ uint32_t sched_value(uint32_t kind, uint32_t npos, uint32_t width, bool relu) {
 }
 
 // Lanes per element of a DReLU/ReLU call: calls too small to give every SIMD
-// one wave at one lane per element spread each element over 8 or 4 lanes (up
-// to the group schedule's limit) while the grid stays within one wave per
-// SIMD; beyond that the lanes' repeated shuffle and sort cost more than the
-// latency they hide (measured on MI355X for l_x = 7, 18, 31, 32).  Capturing
-// calls keep one lane per element.
+// `fill` waves at one lane per element (BC_SCHED_GROUP_FILL, default one)
+// spread each element over 8 or 4 lanes (up to the group schedule's limit)
+// while the grid stays within `fill` waves per SIMD; beyond that the lanes'
+// repeated shuffle and sort cost more than the latency they hide (measured
+// on MI355X per window count; the tuner sets both limits).  Capturing calls
+// keep one lane per element.
 int lanes_per_element(uint32_t npos, uint32_t width, bool relu, uint64_t n, bool capture) {
     if (capture) return 1;
     const uint32_t gmax = sched_value(BC_SCHED_GROUP, npos, width, relu);
-    const uint64_t target = (uint64_t)bc::device_cus() * 4 * 64;   // one wave on each of 4 SIMDs per CU
+    const uint64_t fill = sched_value(BC_SCHED_GROUP_FILL, npos, width, relu);
+    const uint64_t target = (uint64_t)bc::device_cus() * 4 * 64 * fill;   // `fill` waves on each of 4 SIMDs per CU
     if (gmax >= 8 && n * 8 <= target) return 8;
     if (gmax >= 4 && n * 4 <= target) return 4;
     return 1;

@@ -47,6 +47,33 @@ def _time(fn, reps=10, warm=2):
     return a.elapsed_time(b) / reps
 
 
+def _time_graph(fn, reps=20, replays=5):
+    """GPU milliseconds per call of fn, with `reps` calls captured into one HIP
+    graph and the graph replayed: small calls are not timed by the host's
+    launch rate.  fn must enqueue GPU work only (outputs preallocated)."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(reps):
+            fn()
+    g.replay()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(replays):
+        g.replay()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / (replays * reps)
+
+
 def _shares(n, ell, seed):
     rng = np.random.default_rng(seed)
     dt = np.uint64 if ell > 32 else np.uint32
@@ -112,14 +139,16 @@ def tune_group(settings, reps, sizes=(1024, 4096, 16384)):
         npos, width = lx + 1, B.ring_width(ell)
         sd = B.Seeds(1, 2, 3, 4)
         calls = [_shares(n, ell, n + lx) for n in sizes]
+        outs_buf = [(torch.empty_like(x0), torch.empty_like(x1)) for x0, x1 in calls]
         for op in (B.BC_OP_DRELU, B.BC_OP_RELU):
             f = B.relu if op == B.BC_OP_RELU else B.drelu
             best, ref = None, None
+            B.set_schedule("group_fill", npos, 1, width, op)     # groups within one wave per SIMD here
             for gmax in (1, 4, 8):
                 B.set_schedule("group", npos, gmax, width, op)
                 total, outs = 0.0, []
-                for x0, x1 in calls:
-                    total += _time(lambda: f(x0, x1, prm, sd), reps * 4)
+                for (x0, x1), o in zip(calls, outs_buf):
+                    total += _time_graph(lambda: f(x0, x1, prm, sd, out=o), reps * 2)
                     outs.append(f(x0, x1, prm, sd))
                 ref = ref or outs
                 assert all(_same(a, b) for a, b in zip(ref, outs)), "lanes per element changed a result"
@@ -128,6 +157,39 @@ def tune_group(settings, reps, sizes=(1024, 4096, 16384)):
                     best = (gmax, total)
             B.set_schedule("group", npos, best[0], width, op)
             out.append({"kind": "group", "npos": npos, "width": width, "op": op, "blocks_per_cu": best[0],
+                        "ms": round(best[1], 4), "sizes": list(sizes), "setting": [ell, lx, k_lo]})
+    return out
+
+
+def tune_group_fill(settings, reps, sizes=(16384, 32768, 65536)):
+    """How many waves per SIMD lane groups may fill (1, 2 or 4): at the
+    larger call sizes one lane per element leaves each SIMD with one or two
+    long dependent chains, while lane groups split the slots over more waves
+    and repeat the shuffle in each.  Chosen by the summed time over sizes,
+    with the group schedule already set."""
+    out = []
+    for ell, lx, k_lo in settings:
+        prm = B.Params(ell, lx, k_lo)
+        npos, width = lx + 1, B.ring_width(ell)
+        sd = B.Seeds(1, 2, 3, 4)
+        calls = [_shares(n, ell, n + lx + 1) for n in sizes]
+        outs_buf = [(torch.empty_like(x0), torch.empty_like(x1)) for x0, x1 in calls]
+        for op in (B.BC_OP_DRELU, B.BC_OP_RELU):
+            f = B.relu if op == B.BC_OP_RELU else B.drelu
+            best, ref = None, None
+            for fill in (1, 2, 4):
+                B.set_schedule("group_fill", npos, fill, width, op)
+                total, outs = 0.0, []
+                for (x0, x1), o in zip(calls, outs_buf):
+                    total += _time_graph(lambda: f(x0, x1, prm, sd, out=o), reps * 2)
+                    outs.append(f(x0, x1, prm, sd))
+                ref = ref or outs
+                assert all(_same(a, b) for a, b in zip(ref, outs)), "lane groups changed a result"
+                print(f"  fill   op={op} l={ell} lx={lx:2d} waves<={fill}: {total * 1e3:.1f} us", flush=True)
+                if best is None or total < best[1]:
+                    best = (fill, total)
+            B.set_schedule("group_fill", npos, best[0], width, op)
+            out.append({"kind": "group_fill", "npos": npos, "width": width, "op": op, "blocks_per_cu": best[0],
                         "ms": round(best[1], 4), "sizes": list(sizes), "setting": [ell, lx, k_lo]})
     return out
 
@@ -187,6 +249,7 @@ def main():
     grid += tune_kind("pre", SETTINGS[:5], n, reps)
     grid += tune_kind("expand", SETTINGS[:5], n, reps)
     grid += tune_group(SETTINGS, reps)
+    grid += tune_group_fill(SETTINGS, reps)
     bgrid, tile = tune_batch(reps)
     grid += bgrid
     keys = [B.schedule_key(e) for e in grid]
