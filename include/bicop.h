@@ -180,7 +180,9 @@ int bc_prg_blocks(uint32_t* out, uint64_t n, uint32_t nblocks, uint64_t seed,
  * v r + z).  For a setting (lx, p) as in bc_drelu_params (p = 0:
  * the default prime) it writes out[i] = (a[i] b[i] + d[i]) mod p using the
  * same field code as the kernels: fp32-quotient products, Mersenne or
- * pseudo-Mersenne folds, fp64 quotient, Barrett or the 128-bit product.
+ * pseudo-Mersenne folds (with b and d shifted to the top of the word, as the
+ * kernels keep their masks for the default prime at l_x = 16..20), fp64
+ * quotient, Barrett or the 128-bit product.
  * Requires a[i], b[i] < p and d[i] <= p (other values give unspecified
  * results).  Device arrays of n uint64, 8-byte aligned. */
 int bc_zp_mul_add(const uint64_t* a, const uint64_t* b, const uint64_t* d, uint64_t* out, uint64_t n,

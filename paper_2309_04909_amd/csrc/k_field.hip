@@ -1,25 +1,29 @@
 // Diagnostic: the Z_p multiply-add of the DReLU/ReLU kernels (the field that
-// with_field picks for l_x and p), applied elementwise to arrays, so the
-// arithmetic can be checked against exact integers at its bounds.
+// with_field picks for l_x and p, in the operand representation the kernels
+// keep their masks in: shifted to the top of the word where the draws are
+// packed, see MaskDraws), applied elementwise to arrays, so the arithmetic
+// can be checked against exact integers at its bounds.
 #include "drelu_kernel.h"
 
 namespace bc {
 
-template <typename F>
+template <int N, typename F>
 __global__ __launch_bounds__(256) void k_zp_mul_add(const uint64_t* __restrict__ a, const uint64_t* __restrict__ b,
                                                     const uint64_t* __restrict__ d, uint64_t* out, uint64_t n,
                                                     F f_arg) {
     using FT = typename F::T;
+    constexpr int SH = MaskDraws<N, F>::SH;
     const F f = f_arg.vgpr();
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-        out[i] = (uint64_t)f.mul_add((FT)a[i], (FT)b[i], (FT)d[i]);
+        out[i] = (uint64_t)field_mul_add<SH>(f, (FT)a[i], (FT)((FT)b[i] << SH), (FT)((FT)d[i] << SH));
 }
 
 template <int N>
 hipError_t launch_zp_exact(const ZpLaunch& L, hipStream_t st) {
     return with_field<N>(L.p, [&](auto f) {
-        hipLaunchKernelGGL((k_zp_mul_add<decltype(f)>), dim3(L.grid), dim3(256), 0, st, L.a, L.b, L.d, L.out, L.n, f);
+        hipLaunchKernelGGL((k_zp_mul_add<N, decltype(f)>), dim3(L.grid), dim3(256), 0, st, L.a, L.b, L.d, L.out, L.n,
+                           f);
         return hipGetLastError();
     });
 }
