@@ -445,7 +445,7 @@ def run_chain(torch, B, steps, warmup, batch=32):
     # precomputed randomness: every segment's draws expanded offline into a
     # resident record; the same chain then runs as one batch launch of the
     # online element (shares and records streamed, no PRG)
-    rsegs = [BT.Segment(s.x0, s.x1, torch.empty_like(s.x0), torch.empty_like(s.x1), op=s.op, k_in=13)
+    rsegs = [BT.Segment(s.x0, s.x1, torch.empty_like(s.x0), torch.empty_like(s.x1), op=s.op, nonce=s.nonce, k_in=13)
              for s in segs]
 
     def expand():
@@ -480,8 +480,9 @@ def run_chain(torch, B, steps, warmup, batch=32):
             "record_bytes_per_elem": round(rec_bytes / total, 2), "offline_ms": round(ms_offline, 4),
             "identical_outputs": bool(same_fused and same_two and same_online),
             "batched": "one persistent launch with per-segment truncation, replayed from a HIP graph",
-            "online_batched": "the same launch with every segment on its precomputed record (no PRG); bytes = 32 "
-                              "per element of shares plus the records",
+            "online_batched": "the same launch with every segment on its precomputed record (shuffle, masks and "
+                              "P2's [c]_1; the parties regenerate their triple shares); bytes = 32 per element of "
+                              "shares plus the records",
             "fused_calls": "17 bc_trunc_relu launches", "two_pass": "17 x (bc_trunc_det + bc_relu)"}
 
 

@@ -395,17 +395,22 @@ int bc_rss_relu(const void* x0, const void* x1, const void* x2, void* y0, void* 
 /* ------------------------------------------ precomputed randomness */
 
 /* Everything the parties draw from their seeds is independent of the input
- * (Alg. 7: flip, shuffle, masks, reshares, P2's reply; Alg. 8's preprocessing), so it can be
- * expanded ahead of time and kept resident; the online call then streams
- * shares plus this record.  Results and messages are bit-identical to
- * bc_drelu / bc_relu with the same seeds, nonce and element indices.
+ * (Alg. 7: flip, shuffle, masks, reshares, P2's reply; Alg. 8's
+ * preprocessing), so it can be expanded ahead of time and kept resident; the
+ * online call then streams shares plus this record.  The record keeps what
+ * would cost the online phase its sort, its seed_01 draws or a message: the
+ * flip and the shuffle, r and z, and for the ReLU P2's [c]_1 of the Beaver
+ * triple.  What a party draws from seed_02 or seed_12 alone (rho, and the
+ * parties' own triple shares) the online call regenerates from the seeds, so
+ * it takes the seeds, nonce and element offset the record was expanded with.
+ * Results and messages are bit-identical to bc_drelu / bc_relu with the same
+ * seeds, nonce and element indices.
  *
  * Record of n elements (structure of arrays, sections at 256-byte
  * boundaries): the shuffle as bytes sigma(slot) packed four per uint32 with
- * t in bit 7 of the first byte; r and z per slot (one uint32 r | z << 16 when
- * p < 2^16, two uint32 when p < 2^32, two uint64 otherwise); then for DReLU
- * P2's response share rho, for ReLU the triple [a]_0 [b]_0 [c]_0 [a]_1 [b]_1
- * [c]_1 (ring width each, [c]_1 formed by P2). */
+ * t in bit 7 of the first byte; r and z per slot in N-bit fields,
+ * floor(64 / N) to a uint64 (one per uint64 at N = 33); for the ReLU then
+ * [c]_1 (ring width). */
 
 /* What a record was expanded for, in host memory: bc_rand_expand fills it,
  * and every call that reads the record checks it against its own op,
@@ -418,6 +423,8 @@ typedef struct {
     bc_drelu_params prm;     /* the setting, with p resolved               */
     uint64_t n;              /* elements                                   */
     uint64_t bytes;          /* bytes of the record, bc_rand_bytes(op, prm, n) */
+    uint64_t nonce;          /* seeds->nonce of the expansion              */
+    uint64_t elem_base;      /* global index of element 0                  */
 } bc_rand_desc;
 
 /* Bytes of the record of `op` on n elements; 0 if the setting is invalid. */
@@ -431,12 +438,16 @@ int bc_rand_expand(void* rand, uint64_t rand_bytes, uint64_t n, uint32_t op, con
 
 /* Online DReLU (Alg. 7) / ReLU (Alg. 8) from an expanded record.  desc is
  * the record's description from bc_rand_expand (host memory, required): a
- * record of another op, setting or n is refused with BC_ERR_ARG.  Other
+ * record of another op, setting, n, nonce (seeds->nonce) or elem_base is
+ * refused with BC_ERR_ARG.  seeds must be those of the expansion (seed02
+ * and seed12 regenerate rho and the parties' triple shares).  Other
  * arguments as bc_drelu. */
 int bc_drelu_pre(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, const bc_drelu_params* prm,
-                 const void* rand, const bc_rand_desc* desc, void* capture, bc_msg_acct* acct, void* stream);
+                 const bc_seeds* seeds, uint64_t elem_base, const void* rand, const bc_rand_desc* desc, void* capture,
+                 bc_msg_acct* acct, void* stream);
 int bc_relu_pre(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, const bc_drelu_params* prm,
-                const void* rand, const bc_rand_desc* desc, void* capture, bc_msg_acct* acct, void* stream);
+                const bc_seeds* seeds, uint64_t elem_base, const void* rand, const bc_rand_desc* desc, void* capture,
+                bc_msg_acct* acct, void* stream);
 
 /* ------------------------------------------------------ ragged batching */
 
@@ -446,11 +457,10 @@ int bc_relu_pre(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, 
  * bc_drelu / bc_relu (k_in = 0) or bc_trunc_drelu / bc_trunc_relu with
  * k1 = k_in on that segment, with seeds->nonce = nonce and the same
  * elem_base.  A segment with a record (rand != NULL, from bc_rand_expand for
- * the segment's op, the batch's setting and its n, as its rand_desc must
- * say) takes every draw from the record instead of the seeds: its result is that of the fused call with the
- * seeds, nonce and elem_base the record was expanded with, and the segment's
- * own nonce and elem_base are not used.  Outputs of one segment must not
- * overlap inputs or outputs of another. */
+ * the segment's op, the batch's setting, its n, its nonce and its elem_base
+ * under the batch's seeds, as its rand_desc must say) takes its seed_01 draws
+ * and P2's [c]_1 from the record, with the same result.  Outputs of one
+ * segment must not overlap inputs or outputs of another. */
 typedef struct {
     const void* x0;
     const void* x1;

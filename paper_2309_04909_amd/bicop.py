@@ -56,7 +56,7 @@ class _Acct(ctypes.Structure):
 
 class _RandDesc(ctypes.Structure):
     _fields_ = [("magic", ctypes.c_uint32), ("op", ctypes.c_uint32), ("prm", _Params), ("n", ctypes.c_uint64),
-                ("bytes", ctypes.c_uint64)]
+                ("bytes", ctypes.c_uint64), ("nonce", ctypes.c_uint64), ("elem_base", ctypes.c_uint64)]
 
 
 class _Segment(ctypes.Structure):
@@ -106,10 +106,10 @@ _SIGS = {
     "bc_rand_bytes": ([_U32, ctypes.POINTER(_Params), _U64], _U64),
     "bc_rand_expand": ([_P, _U64, _U64, _U32, ctypes.POINTER(_Params), ctypes.POINTER(_Seeds), _U64,
                         ctypes.POINTER(_RandDesc), _P], ctypes.c_int),
-    "bc_drelu_pre": ([_P, _P, _P, _P, _U64, ctypes.POINTER(_Params), _P, ctypes.POINTER(_RandDesc), _P,
-                      ctypes.POINTER(_Acct), _P], ctypes.c_int),
-    "bc_relu_pre": ([_P, _P, _P, _P, _U64, ctypes.POINTER(_Params), _P, ctypes.POINTER(_RandDesc), _P,
-                     ctypes.POINTER(_Acct), _P], ctypes.c_int),
+    "bc_drelu_pre": ([_P, _P, _P, _P, _U64, ctypes.POINTER(_Params), ctypes.POINTER(_Seeds), _U64, _P,
+                      ctypes.POINTER(_RandDesc), _P, ctypes.POINTER(_Acct), _P], ctypes.c_int),
+    "bc_relu_pre": ([_P, _P, _P, _P, _U64, ctypes.POINTER(_Params), ctypes.POINTER(_Seeds), _U64, _P,
+                     ctypes.POINTER(_RandDesc), _P, ctypes.POINTER(_Acct), _P], ctypes.c_int),
     "bc_trunc_drelu": ([_P, _P, _P, _P, _U64, _U32, _U32, ctypes.POINTER(_Params), ctypes.POINTER(_Seeds), _U64, _P,
                         ctypes.POINTER(_Acct), _P], ctypes.c_int),
     "bc_trunc_relu": ([_P, _P, _P, _P, _U64, _U32, _U32, ctypes.POINTER(_Params), ctypes.POINTER(_Seeds), _U64, _P,
@@ -534,8 +534,10 @@ def rand_bytes(op, params: Params, n):
 def rand_expand(op, params: Params, seeds: Seeds, n, elem_base=0, out=None, device="cuda", stream=None):
     """Offline phase: the seeds' draws for n elements, as a device byte buffer.
     The record's description (bc_rand_desc) rides on the buffer as
-    `bicop_desc`; the online calls and batch segments pass it to the library,
-    which refuses a record of another op, setting or n."""
+    `bicop_desc`, and the seeds and element offset of the expansion as
+    `bicop_seeds` and `bicop_elem_base`; the online calls and batch segments
+    pass them to the library, which refuses a record of another op, setting,
+    n, nonce or offset."""
     nb = rand_bytes(op, params, n)
     if nb == 0 and n:
         _check(lib.bc_check_params(ctypes.byref(params.c()), None), "rand_expand")
@@ -544,6 +546,8 @@ def rand_expand(op, params: Params, seeds: Seeds, n, elem_base=0, out=None, devi
     _check(lib.bc_rand_expand(buf.data_ptr(), buf.numel(), n, op, ctypes.byref(params.c()), ctypes.byref(seeds.c()),
                               elem_base, ctypes.byref(desc), _stream(stream, buf)), "rand_expand")
     buf.bicop_desc = desc
+    buf.bicop_seeds = seeds
+    buf.bicop_elem_base = elem_base
     return buf
 
 
@@ -555,27 +559,33 @@ def rand_desc(rand):
     return desc
 
 
-def _pre_like(fn, name, x0, x1, params, rand, capture, out, stream):
+def _pre_like(fn, name, x0, x1, params, rand, capture, out, stream, seeds=None, elem_base=None):
     _check_shares(x0, x1, ring_width(params.ell))
     y0 = _out(x0, ring_width(params.ell), ring_dtype(params.ell), None if out is None else out[0])
     y1 = _out(x1, ring_width(params.ell), ring_dtype(params.ell), None if out is None else out[1])
     cap = None
     if capture:
         cap = torch.empty((2, x0.numel(), params.npos), dtype=field_dtype(params.resolved().p), device=x0.device)
+    seeds = seeds if seeds is not None else getattr(rand, "bicop_seeds", None)
+    if seeds is None:
+        raise ValueError("the online call needs the seeds the record was expanded with")
+    elem_base = elem_base if elem_base is not None else getattr(rand, "bicop_elem_base", 0)
     _check(fn(x0.data_ptr(), x1.data_ptr(), y0.data_ptr(), y1.data_ptr(), x0.numel(), ctypes.byref(params.c()),
-              rand.data_ptr(), ctypes.byref(rand_desc(rand)), None if cap is None else cap.data_ptr(), None,
-              _stream(stream, x0)), name)
+              ctypes.byref(seeds.c()), elem_base, rand.data_ptr(), ctypes.byref(rand_desc(rand)),
+              None if cap is None else cap.data_ptr(), None, _stream(stream, x0)), name)
     return (y0, y1, cap) if capture else (y0, y1)
 
 
-def drelu_pre(x0, x1, params: Params, rand, capture=False, out=None, stream=None):
-    """Online Alg. 7 from a record made by rand_expand(BC_OP_DRELU, ...)."""
-    return _pre_like(lib.bc_drelu_pre, "drelu_pre", x0, x1, params, rand, capture, out, stream)
+def drelu_pre(x0, x1, params: Params, rand, capture=False, out=None, stream=None, seeds=None, elem_base=None):
+    """Online Alg. 7 from a record made by rand_expand(BC_OP_DRELU, ...); the
+    seeds and offset default to those of the expansion."""
+    return _pre_like(lib.bc_drelu_pre, "drelu_pre", x0, x1, params, rand, capture, out, stream, seeds, elem_base)
 
 
-def relu_pre(x0, x1, params: Params, rand, capture=False, out=None, stream=None):
-    """Online Alg. 8 from a record made by rand_expand(BC_OP_RELU, ...)."""
-    return _pre_like(lib.bc_relu_pre, "relu_pre", x0, x1, params, rand, capture, out, stream)
+def relu_pre(x0, x1, params: Params, rand, capture=False, out=None, stream=None, seeds=None, elem_base=None):
+    """Online Alg. 8 from a record made by rand_expand(BC_OP_RELU, ...); the
+    seeds and offset default to those of the expansion."""
+    return _pre_like(lib.bc_relu_pre, "relu_pre", x0, x1, params, rand, capture, out, stream, seeds, elem_base)
 
 
 # The autotuned schedule table, applied once the whole binding is defined.

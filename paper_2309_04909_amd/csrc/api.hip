@@ -118,7 +118,8 @@ int check_params(const bc_drelu_params* prm, bc_drelu_params* out) {
 
 // A record's description against the op, resolved setting and n of the call
 // that reads it.
-int check_desc(const bc_rand_desc* d, uint32_t op, const bc_drelu_params& r, uint64_t n) {
+int check_desc(const bc_rand_desc* d, uint32_t op, const bc_drelu_params& r, uint64_t n, uint64_t nonce,
+               uint64_t elem_base) {
     if (!d) return fail(BC_ERR_NULL, "record description is NULL");
     if (d->magic != BC_RAND_MAGIC) return fail(BC_ERR_ARG, "record description was not filled by bc_rand_expand");
     if (d->op != op || d->prm.ell != r.ell || d->prm.lx != r.lx || d->prm.k_lo != r.k_lo || d->prm.p != r.p ||
@@ -129,6 +130,10 @@ int check_desc(const bc_rand_desc* d, uint32_t op, const bc_drelu_params& r, uin
                     d->op, d->prm.ell, d->prm.lx, d->prm.k_lo, (unsigned long long)d->prm.p,
                     (unsigned long long)d->n, op, r.ell, r.lx, r.k_lo, (unsigned long long)r.p,
                     (unsigned long long)n);
+    if (d->nonce != nonce || d->elem_base != elem_base)
+        return fail(BC_ERR_ARG, "record was expanded for nonce %llu, elem_base %llu; the call has %llu, %llu",
+                    (unsigned long long)d->nonce, (unsigned long long)d->elem_base, (unsigned long long)nonce,
+                    (unsigned long long)elem_base);
     const uint64_t need = bc::rand_offsets(r.lx + 1, op == BC_OP_RELU, width_of_ring(r.ell), n).total;
     if (d->bytes < need)
         return fail(BC_ERR_WORKSPACE, "record holds %llu of %llu bytes", (unsigned long long)d->bytes,
@@ -409,7 +414,7 @@ int batch_plan(const bc_segment* segs, uint32_t nseg, const bc_drelu_params* prm
             return fail(BC_ERR_ALIGN, "segment %u: share pointers must be %u-byte aligned", i, w);
         if (s.rand) {
             if (!aligned(s.rand, 16)) return fail(BC_ERR_ALIGN, "segment %u: record must be 16-byte aligned", i);
-            if (int rc_d = check_desc(s.rand_desc, s.op, r, s.n)) {
+            if (int rc_d = check_desc(s.rand_desc, s.op, r, s.n, s.nonce, s.elem_base)) {
                 const int rc_seg = rc_d;
                 char why[sizeof(g_err)];
                 snprintf(why, sizeof(why), "%s", g_err);
@@ -481,12 +486,12 @@ int pre_common(bool expand, uint32_t op, const void* x0, const void* x1, void* y
     bc_drelu_params r;
     int rc = check_params(prm, &r);
     if (rc) return rc;
-    if (expand && !seeds) return fail(BC_ERR_NULL, "seeds is NULL");
+    if (!seeds) return fail(BC_ERR_NULL, "seeds is NULL");
     if (int rc_i = check_indices(n, elem_base)) return rc_i;
     const uint32_t w = width_of_ring(r.ell);
     const bc::RandOffsets o = bc::rand_offsets(r.lx + 1, op == BC_OP_RELU, w, n);
     if (!expand) {
-        if (int rc_d = check_desc(desc_in, op, r, n)) return rc_d;
+        if (int rc_d = check_desc(desc_in, op, r, n, seeds->nonce, elem_base)) return rc_d;
         rand_bytes = desc_in->bytes;
     }
     if (acct) account(op, r, n, acct);
@@ -499,6 +504,8 @@ int pre_common(bool expand, uint32_t op, const void* x0, const void* x1, void* y
         desc_out->prm = r;
         desc_out->n = n;
         desc_out->bytes = o.total;
+        desc_out->nonce = seeds->nonce;
+        desc_out->elem_base = elem_base;
     }
     if (n == 0) return BC_OK;
     if (!rand) return fail(BC_ERR_NULL, "randomness buffer is NULL");
@@ -527,8 +534,7 @@ int pre_common(bool expand, uint32_t op, const void* x0, const void* x1, void* y
     L.npos = r.lx + 1;
     L.relu = op == BC_OP_RELU;
     L.expand = expand;
-    const bc_seeds zero{0, 0, 0, 0};
-    const bc_seeds& sd = seeds ? *seeds : zero;
+    const bc_seeds& sd = *seeds;
     L.s01 = stream_key(sd.seed01, sd.nonce);
     L.s02 = stream_key(sd.seed02, sd.nonce);
     L.s12 = stream_key(sd.seed12, sd.nonce);
@@ -764,14 +770,16 @@ int bc_rand_expand(void* rand, uint64_t rand_bytes, uint64_t n, uint32_t op, con
 }
 
 int bc_drelu_pre(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, const bc_drelu_params* prm,
-                 const void* rand, const bc_rand_desc* desc, void* capture, bc_msg_acct* acct, void* stream) {
-    return pre_common(false, BC_OP_DRELU, x0, x1, y0, y1, n, prm, nullptr, 0, const_cast<void*>(rand), 0, desc,
+                 const bc_seeds* seeds, uint64_t elem_base, const void* rand, const bc_rand_desc* desc, void* capture,
+                 bc_msg_acct* acct, void* stream) {
+    return pre_common(false, BC_OP_DRELU, x0, x1, y0, y1, n, prm, seeds, elem_base, const_cast<void*>(rand), 0, desc,
                       nullptr, capture, acct, stream);
 }
 
 int bc_relu_pre(const void* x0, const void* x1, void* y0, void* y1, uint64_t n, const bc_drelu_params* prm,
-                const void* rand, const bc_rand_desc* desc, void* capture, bc_msg_acct* acct, void* stream) {
-    return pre_common(false, BC_OP_RELU, x0, x1, y0, y1, n, prm, nullptr, 0, const_cast<void*>(rand), 0, desc,
+                const bc_seeds* seeds, uint64_t elem_base, const void* rand, const bc_rand_desc* desc, void* capture,
+                bc_msg_acct* acct, void* stream) {
+    return pre_common(false, BC_OP_RELU, x0, x1, y0, y1, n, prm, seeds, elem_base, const_cast<void*>(rand), 0, desc,
                       nullptr, capture, acct, stream);
 }
 

@@ -56,17 +56,18 @@ __global__ BC_KERNEL_ATTRS void k_batch(const BatchPlanHeader* __restrict__ hdr,
         const uint32_t k_in = S.k_in, lin = A.ell + k_in;
         const T in_mask = lin >= 8 * sizeof(T) ? (T)~(T)0 : (T)(((T)1 << lin) - 1);
         if (S.rand) {
-            // precomputed randomness: the segment's record replaces its seeds
+            // precomputed randomness: the segment's record replaces its seed_01
+            // draws (and holds P2's [c]_1); seed_02 / seed_12 draws are regenerated
             const bool relu = S.op == BC_OP_RELU;
             const RecordView<T> R = record_view<T>(S.rand, (uint32_t)N, relu, S.n);
             if (relu) {
                 for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x)
-                    drelu_pre_element<T, N, F, true, false>(X0, X1, Y0, Y1, nullptr, R, e, mask, in_mask, k_in,
-                                                            A.k_lo, f);
+                    drelu_pre_element<T, N, F, true, false>(X0, X1, Y0, Y1, nullptr, R, e, base + e, mask, in_mask,
+                                                            k_in, A.k_lo, s02, s12, f);
             } else {
                 for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x)
-                    drelu_pre_element<T, N, F, false, false>(X0, X1, Y0, Y1, nullptr, R, e, mask, in_mask, k_in,
-                                                             A.k_lo, f);
+                    drelu_pre_element<T, N, F, false, false>(X0, X1, Y0, Y1, nullptr, R, e, base + e, mask, in_mask,
+                                                             k_in, A.k_lo, s02, s12, f);
             }
         } else if (S.op == BC_OP_RELU) {
             for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x)

@@ -135,6 +135,23 @@ __device__ __forceinline__ void drelu_finish(T dp, T rho, uint32_t t, T mask, T&
     y1 = t ? (T)((T)0 - d1) & mask : d1;
 }
 
+// Alg. 8's preprocessing draws of element g: [a]_0, [b]_0, [c]_0 from
+// seed_02 (blocks 0 and 1 of TAG_BEAVER), [a]_1, [b]_1 from seed_12 (block 0);
+// P2 forms [c]_1 = (a0 + a1)(b0 + b1) - c0 from them.
+template <typename T>
+__device__ __forceinline__ void beaver_shares(const Stream& s02, const Stream& s12, uint64_t g, T mask, T& ba0, T& bb0,
+                                              T& bc0, T& ba1, T& bb1) {
+    const StreamAt r02 = s02.at(g);
+    const Words4 w0 = r02.block(TAG_BEAVER, 0);
+    const Words4 w1 = r02.block(TAG_BEAVER, 1);
+    const Words4 w2 = s12.block(g, TAG_BEAVER, 0);
+    ba0 = (T)join64(w0.w0, w0.w1) & mask;
+    bb0 = (T)join64(w0.w2, w0.w3) & mask;
+    bc0 = (T)join64(w1.w0, w1.w1) & mask;
+    ba1 = (T)join64(w2.w0, w2.w1) & mask;
+    bb1 = (T)join64(w2.w2, w2.w3) & mask;
+}
+
 // Alg. 8 after the zero test: e = D' - b, d = x - a and the product, with
 // the triple ([a]_j, [b]_j, [c]_j) and the unflipped inputs.
 template <typename T>
@@ -331,17 +348,9 @@ __device__ __forceinline__ void drelu_element(const T* __restrict__ X0, const T*
         const Words4 w = s02.block(g, TAG_RESP, 0);               // rho from seed_02
         drelu_finish<T>(dp, (T)join64(w.w0, w.w1) & mask, t, mask, y0, y1);
     } else {
-        // Alg. 8 preprocessing: [a]_0, [b]_0, [c]_0 from seed_02, [a]_1, [b]_1
-        // from seed_12; P2 forms [c]_1 = (a0 + a1)(b0 + b1) - c0.
-        const StreamAt r02 = s02.at(g);
-        const Words4 w0 = r02.block(TAG_BEAVER, 0);
-        const Words4 w1 = r02.block(TAG_BEAVER, 1);
-        const Words4 w2 = s12.block(g, TAG_BEAVER, 0);
-        const T ba0 = (T)join64(w0.w0, w0.w1) & mask;
-        const T bb0 = (T)join64(w0.w2, w0.w3) & mask;
-        const T bc0 = (T)join64(w1.w0, w1.w1) & mask;
-        const T ba1 = (T)join64(w2.w0, w2.w1) & mask;
-        const T bb1 = (T)join64(w2.w2, w2.w3) & mask;
+        // Alg. 8 preprocessing; P2 forms [c]_1 = (a0 + a1)(b0 + b1) - c0.
+        T ba0, bb0, bc0, ba1, bb1;
+        beaver_shares<T>(s02, s12, g, mask, ba0, bb0, bc0, ba1, bb1);
         const T bc1 = (T)((T)(ba0 + ba1) * (T)(bb0 + bb1) - bc0) & mask;
         relu_finish<T>(dp, in0, in1, ba0, bb0, bc0, ba1, bb1, bc1, t, mask, y0, y1);
     }

@@ -104,7 +104,7 @@ __host__ __device__ inline RandOffsets rand_offsets(uint32_t npos, bool relu, ui
     o.rz = align256(perm_bytes);
     const uint64_t rz_bytes = n * 8ull * rz_words(npos);
     o.tail = align256(o.rz + rz_bytes);
-    o.total = o.tail + (uint64_t)ring_width * n * (relu ? 6 : 1);
+    o.total = o.tail + (relu ? (uint64_t)ring_width * n : 0);   // the ReLU's [c]_1
     return o;
 }
 

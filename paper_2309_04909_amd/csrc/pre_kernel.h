@@ -1,12 +1,17 @@
 // Precomputed-randomness form of the DReLU (Alg. 7) and ReLU (Alg. 8) kernels.
 //
 // Everything the parties draw from their seeds is independent of the input,
-// so it can be expanded ahead of time (an offline phase) and kept resident:
-// P0/P1's flip t, shuffle and masks from seed_01, P2's response share from
-// seed_02, and the Beaver triple of Alg. 8's preprocessing including P2's
-// [c]_1.  The online kernel then streams the shares plus this record and does
-// flip, windows, sums, modulo switch, mask and zero test and the finish; it reuses the slot arithmetic of the fused
-// kernel, so both give bit-identical results and messages.
+// so it can be expanded ahead of time (an offline phase) and kept resident.
+// The record keeps what would cost the online phase its sort, its mask
+// draws or a message: P0/P1's flip t and shuffle and the masks from seed_01,
+// and for the ReLU P2's [c]_1 of the Beaver triple (Alg. 8's preprocessing,
+// sent to P1).  What a party draws from seed_02 or seed_12 alone (P2's
+// response share rho, the triple shares [a]_0 [b]_0 [c]_0 and [a]_1 [b]_1)
+// it regenerates online from its seed, one to three Philox blocks, as
+// holders of a triple's seeds would.  The online kernel streams the shares
+// plus the record and does flip, windows, sums, modulo switch, mask and zero
+// test and the finish; it reuses the slot arithmetic of the fused kernel, so
+// both give bit-identical results and messages.
 //
 // Record of a call on n elements, structure of arrays (each array [.][n]):
 //   perm  uint32[ceil(N/4)][n]: byte q of word k is sigma(4k + q); bit 7 of
@@ -15,7 +20,7 @@
 //         v = 2j for r_j, 2j + 1 for z_j) in N-bit fields (p < 2^N),
 //         floor(64 / N) to a word: value v is bits N (v % K) .. of word
 //         v / K, K = floor(64 / N).  N == 33: one value per word.
-//   tail  DReLU: T[n] rho.  ReLU: T[6][n] = [a]_0 [b]_0 [c]_0 [a]_1 [b]_1 [c]_1
+//   tail  ReLU only: T[n] = [c]_1
 // Sections start at 256-byte boundaries.
 #pragma once
 
@@ -33,8 +38,10 @@ struct PreKArgs {
     const void* rz;
     const void* tail;
     uint64_t n;
+    uint64_t elem_base;
     uint64_t ring_mask;
     uint32_t k_lo, pad;
+    Stream s02, s12;
 };
 
 struct ExpandKArgs {
@@ -92,26 +99,10 @@ __global__ BC_KERNEL_ATTRS void k_expand(ExpandKArgs A, F f) {
                 }
             }
         }
-        T* tail = static_cast<T*>(A.tail);
-        if constexpr (!RELU) {
-            const Words4 w = A.s02.block(g, TAG_RESP, 0);
-            tail[e] = (T)join64(w.w0, w.w1) & mask;
-        } else {
-            const StreamAt r02 = A.s02.at(g);
-            const Words4 w0 = r02.block(TAG_BEAVER, 0);
-            const Words4 w1 = r02.block(TAG_BEAVER, 1);
-            const Words4 w2 = A.s12.block(g, TAG_BEAVER, 0);
-            const T ba0 = (T)join64(w0.w0, w0.w1) & mask;
-            const T bb0 = (T)join64(w0.w2, w0.w3) & mask;
-            const T bc0 = (T)join64(w1.w0, w1.w1) & mask;
-            const T ba1 = (T)join64(w2.w0, w2.w1) & mask;
-            const T bb1 = (T)join64(w2.w2, w2.w3) & mask;
-            tail[e] = ba0;
-            tail[n + e] = bb0;
-            tail[2 * n + e] = bc0;
-            tail[3 * n + e] = ba1;
-            tail[4 * n + e] = bb1;
-            tail[5 * n + e] = (T)((T)(ba0 + ba1) * (T)(bb0 + bb1) - bc0) & mask;   // P2's [c]_1
+        if constexpr (RELU) {
+            T ba0, bb0, bc0, ba1, bb1;
+            beaver_shares<T>(A.s02, A.s12, g, mask, ba0, bb0, bc0, ba1, bb1);
+            static_cast<T*>(A.tail)[e] = (T)((T)(ba0 + ba1) * (T)(bb0 + bb1) - bc0) & mask;   // P2's [c]_1
         }
     }
 }
@@ -140,8 +131,9 @@ __device__ __forceinline__ RecordView<T> record_view(const void* rand, uint32_t 
 // to cap[e * N + slot] and cap[(R.n + e) * N + slot].
 template <typename T, int N, typename F, bool RELU, bool CAP>
 __device__ __forceinline__ void drelu_pre_element(const T* __restrict__ X0, const T* __restrict__ X1, T* Y0, T* Y1,
-                                                  typename F::T* cap, const RecordView<T>& R, uint64_t e, T mask,
-                                                  T in_mask, uint32_t k_in, uint32_t k_lo, const F& f) {
+                                                  typename F::T* cap, const RecordView<T>& R, uint64_t e, uint64_t g,
+                                                  T mask, T in_mask, uint32_t k_in, uint32_t k_lo, const Stream& s02,
+                                                  const Stream& s12, const F& f) {
     using FT = typename F::T;
     const uint64_t n = R.n;
     const T r0 = X0[e] & in_mask;
@@ -179,13 +171,14 @@ __device__ __forceinline__ void drelu_pre_element(const T* __restrict__ X0, cons
         }
     }
     const T dp = least == 0 ? 1 : 0;
-    const T* tail = R.tail;
     T y0, y1;
     if constexpr (!RELU) {
-        drelu_finish<T>(dp, tail[e], t, mask, y0, y1);
+        const Words4 w = s02.block(g, TAG_RESP, 0);                 // rho, regenerated from seed_02
+        drelu_finish<T>(dp, (T)join64(w.w0, w.w1) & mask, t, mask, y0, y1);
     } else {
-        relu_finish<T>(dp, in0, in1, tail[e], tail[n + e], tail[2 * n + e], tail[3 * n + e], tail[4 * n + e],
-                       tail[5 * n + e], t, mask, y0, y1);
+        T ba0, bb0, bc0, ba1, bb1;                                  // the parties' triple shares, regenerated
+        beaver_shares<T>(s02, s12, g, mask, ba0, bb0, bc0, ba1, bb1);
+        relu_finish<T>(dp, in0, in1, ba0, bb0, bc0, ba1, bb1, R.tail[e], t, mask, y0, y1);
     }
     Y0[e] = y0;
     Y1[e] = y1;
@@ -204,7 +197,8 @@ __global__ BC_KERNEL_ATTRS void k_drelu_pre(PreKArgs A, F f_arg) {
     const T mask = in_vgpr((T)A.ring_mask);
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < A.n; e += stride)
-        drelu_pre_element<T, N, F, RELU, CAP>(X0, X1, Y0, Y1, cap, R, e, mask, mask, 0, A.k_lo, f);
+        drelu_pre_element<T, N, F, RELU, CAP>(X0, X1, Y0, Y1, cap, R, e, A.elem_base + e, mask, mask, 0, A.k_lo,
+                                              A.s02, A.s12, f);
 }
 
 template <typename T, int N, typename F>
@@ -239,9 +233,12 @@ hipError_t launch_pre_field(const PreLaunch& L, const F& f, hipStream_t st) {
     A.rz = base + o.rz;
     A.tail = base + o.tail;
     A.n = L.n;
+    A.elem_base = L.elem_base;
     A.ring_mask = mask;
     A.k_lo = L.k_lo;
     A.pad = 0;
+    A.s02 = Stream{L.s02.k0, L.s02.k1, L.s02.n0, L.s02.n1};
+    A.s12 = Stream{L.s12.k0, L.s12.k1, L.s12.n0, L.s12.n1};
     if (L.relu) {
         if (L.cap) hipLaunchKernelGGL((k_drelu_pre<T, N, F, true, true>), dim3(L.grid), dim3(256), 0, st, A, f);
         else hipLaunchKernelGGL((k_drelu_pre<T, N, F, true, false>), dim3(L.grid), dim3(256), 0, st, A, f);

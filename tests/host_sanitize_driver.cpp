@@ -115,8 +115,10 @@ int main() {
                 bc_rand_expand(nullptr, 0, 0, s.op & 1, &prm, nullptr, 0, &d, nullptr);   // refused: seeds NULL
                 bc_seeds sd0 = {1, 2, 3, 4};
                 const uint64_t dn = s.n + ((r >> 55) % 71 == 0 ? 1 : 0);
+                sd0.nonce = (r >> 58) % 67 == 0 ? s.nonce + 1 : s.nonce;            // rarely another nonce
                 bc_rand_expand(nullptr, ~0ull, 0, s.op & 1, &prm, &sd0, 0, &d, nullptr);  // n = 0: fills d
                 d.n = dn;
+                d.elem_base = s.elem_base;
                 d.bytes = bc_rand_bytes(s.op & 1, &prm, dn);
                 s.rand_desc = (r >> 57) % 97 == 0 ? nullptr : &d;
             }
@@ -183,9 +185,11 @@ int main() {
                 bc_rand_desc d;
                 memset(&d, 0, sizeof(d));
                 mix((uint64_t)(bc_rand_expand(M, 0, n, 0, &p2, &sd, 0, &d, nullptr) + 16));
-                mix((uint64_t)(bc_drelu_pre(P, P, Q, Q, n, &p2, nullptr, &d, nullptr, nullptr, nullptr) + 16));
-                mix((uint64_t)(bc_relu_pre(P, P, Q, Q, n, &p2, M, &d, nullptr, nullptr, nullptr) + 16));
-                mix((uint64_t)(bc_relu_pre(P, P, Q, Q, n, &p2, M, nullptr, nullptr, nullptr, nullptr) + 16));
+                mix((uint64_t)(bc_drelu_pre(P, P, Q, Q, n, &p2, &sd, 0, nullptr, &d, nullptr, nullptr, nullptr) + 16));
+                mix((uint64_t)(bc_relu_pre(P, P, Q, Q, n, &p2, &sd, 0, M, &d, nullptr, nullptr, nullptr) + 16));
+                mix((uint64_t)(bc_relu_pre(P, P, Q, Q, n, &p2, &sd, 0, M, nullptr, nullptr, nullptr, nullptr) + 16));
+                mix((uint64_t)(bc_drelu_pre(P, P, Q, Q, n, &p2, nullptr, 0, M, &d, nullptr, nullptr, nullptr) + 16));
+                mix((uint64_t)(bc_drelu_pre(P, P, Q, Q, n, &p2, &sd, 9, M, &d, nullptr, nullptr, nullptr) + 16));
                 mix((uint64_t)(bc_drelu_send(2, P, (uint32_t*)Q, n, &p2, &sd, 0, nullptr) + 16));
                 mix((uint64_t)(bc_drelu_reply(nullptr, (const uint32_t*)P, Q, Q, n, &p2, &sd, 0, nullptr) + 16));
                 mix((uint64_t)(bc_drelu_finish(0, P, M, n, &p2, &sd, 0, nullptr) + 16));

@@ -126,6 +126,32 @@ def test_error_paths_without_gpu():
     assert L.bc_zp_mul_add(None, None, None, None, (1 << 48) + 1, 7, 0, None) == -8  # n above 2^48
 
 
+def _record_bytes(npos, relu, width, n):
+    """A record's size written out from its layout: one key index byte per
+    window position (a whole 32-bit word per four), the 2 npos masks r and
+    reshares z of npos bits packed floor(64 / npos) to a 64-bit word, and for
+    the ReLU P2's share [c]_1 of the triple's product; each section starts on a
+    256-byte boundary."""
+    def up(b):
+        return (b + 255) // 256 * 256
+    per_word = 64 // npos
+    words = 2 * npos if npos >= 33 else -(-2 * npos // per_word)
+    return up(up(4 * -(-npos // 4) * n) + 8 * words * n) + (width * n if relu else 0)
+
+
+@pytest.mark.parametrize("op,ell,lx,k_lo", [(0, 64, 7, 11), (1, 64, 7, 11), (0, 64, 18, 13), (1, 64, 18, 13),
+                                            (1, 32, 8, 8), (0, 64, 32, 0), (1, 64, 32, 0), (1, 51, 7, 11)])
+@pytest.mark.parametrize("n", [0, 1, 1000, 1 << 20])
+def test_record_sizes(op, ell, lx, k_lo, n):
+    """bc_rand_bytes against the record layout, and the per-element figures the
+    precomputed mode is quoted with (ReLU l_x = 7: 32 B, DReLU l_x = 18: 124 B)."""
+    from paper_2309_04909_amd import bicop as B
+    prm = B.Params(ell, lx, k_lo)
+    assert B.rand_bytes(op, prm, n) == _record_bytes(lx + 1, op == B.BC_OP_RELU, B.ring_width(ell), n)
+    if n == 1 << 20 and ell == 64 and (op, lx) in ((1, 7), (0, 18)):
+        assert B.rand_bytes(op, prm, n) == n * {7: 32, 18: 124}[lx]
+
+
 def test_batch_plan_validation_on_host():
     """bc_batch_plan is host-only: it validates and fills a host buffer, never launches."""
     from paper_2309_04909_amd import bicop as B
@@ -169,10 +195,11 @@ def test_batch_plan_validation_on_host():
     # a record segment: a 16-byte aligned record whose description (filled by
     # bc_rand_expand: here an empty expansion, then n set) matches the segment
     desc = B._RandDesc()
-    sd0 = B.Seeds(1, 2, 3).c()
+    sd0 = B.Seeds(1, 2, 3, 1).c()                                      # the nonce of seg[0]
     assert L.bc_rand_expand(None, 0, 0, B.BC_OP_RELU, ctypes.byref(prm), ctypes.byref(sd0), 0, ctypes.byref(desc),
                             None) == 0
     assert desc.magic == B.BC_RAND_MAGIC and desc.op == B.BC_OP_RELU and desc.prm.p == 251 and desc.n == 0
+    assert desc.nonce == 1 and desc.elem_base == 0
     desc.n, desc.bytes = 5000, L.bc_rand_bytes(B.BC_OP_RELU, ctypes.byref(prm), 5000)
     seg[0].rand, seg[0].rand_desc = 0x100000, ctypes.pointer(desc)
     assert L.bc_batch_plan(seg, 2, ctypes.byref(prm), 1024, buf, nbytes) == 0
@@ -186,7 +213,11 @@ def test_batch_plan_validation_on_host():
     assert L.bc_batch_plan(seg, 2, ctypes.byref(prm), 1024, buf, nbytes) == -8
     desc.op, desc.prm.k_lo = B.BC_OP_RELU, 10                          # for another setting
     assert L.bc_batch_plan(seg, 2, ctypes.byref(prm), 1024, buf, nbytes) == -8
-    desc.prm.k_lo, desc.magic = 11, 0                                  # not filled by bc_rand_expand
+    desc.prm.k_lo, desc.nonce = 11, 2                                  # for another nonce
+    assert L.bc_batch_plan(seg, 2, ctypes.byref(prm), 1024, buf, nbytes) == -8
+    desc.nonce, desc.elem_base = 1, 5                                  # for another element offset
+    assert L.bc_batch_plan(seg, 2, ctypes.byref(prm), 1024, buf, nbytes) == -8
+    desc.elem_base, desc.magic = 0, 0                                  # not filled by bc_rand_expand
     assert L.bc_batch_plan(seg, 2, ctypes.byref(prm), 1024, buf, nbytes) == -8
     desc.magic = B.BC_RAND_MAGIC
     seg[0].rand_desc = None                                            # missing

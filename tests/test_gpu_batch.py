@@ -197,8 +197,8 @@ def test_batch_with_records(M, ell_in, k_in, lx, k_lo):
     expanded offline (bc_rand_expand with their own nonce and elem_base)
     mixed with segments drawing from the seeds, with and without input
     truncation.  A record segment equals bc_trunc_relu / bc_trunc_drelu (or
-    the plain call) with the seeds, nonce and elem_base of its record; its own
-    nonce and elem_base fields are ignored.  Oracle on samples."""
+    the plain call) with the same seeds, nonce and elem_base.  Oracle on
+    samples."""
     B, bt = M
     ell = ell_in - k_in
     rng = np.random.default_rng(7 * ell_in + k_in + lx)
@@ -219,8 +219,6 @@ def test_batch_with_records(M, ell_in, k_in, lx, k_lo):
             rec = B.rand_expand(op, prm, B.Seeds(*seeds, nonce), n, elem_base=eb)
         seg = bt.Segment(d0, d1, torch.empty_like(d0), torch.empty_like(d1), op=op, nonce=nonce, elem_base=eb,
                          k_in=kin, rand=rec)
-        if rec is not None:                   # fields a record segment does not use
-            seg.nonce, seg.elem_base = 0xDEAD, 1 << 40
         segs.append(seg)
         inputs.append((x0, x1, nonce, eb))
         base += n + 3

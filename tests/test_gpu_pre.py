@@ -85,19 +85,20 @@ def test_pre_rejects_small_buffer(B):
 
 
 def test_pre_refuses_a_record_of_another_call(B):
-    """A record read with another op, setting or length is refused on the host
-    with BC_ERR_ARG (its description says what it was expanded for); nothing
-    is launched and the outputs stay as they were."""
+    """A record read with another op, setting, length, nonce or element offset
+    is refused on the host with BC_ERR_ARG (its description says what it was
+    expanded for); nothing is launched and the outputs stay as they were."""
     prm = B.Params(64, 7, 11)
     rec = B.rand_expand(B.BC_OP_RELU, prm, B.Seeds(1, 2, 3, 4), 100)
     x = torch.ones(100, dtype=torch.int64, device="cuda")
     y = (torch.full_like(x, 7), torch.full_like(x, 7))
-    cases = [(B.relu_pre, x[:99], prm), (B.drelu_pre, x, prm), (B.relu_pre, x, B.Params(64, 7, 10)),
-             (B.relu_pre, x, B.Params(64, 8, 11)), (B.relu_pre, x, B.Params(51, 7, 11))]
-    for fn, xs, p in cases:
+    cases = [(B.relu_pre, x[:99], prm, {}), (B.drelu_pre, x, prm, {}), (B.relu_pre, x, B.Params(64, 7, 10), {}),
+             (B.relu_pre, x, B.Params(64, 8, 11), {}), (B.relu_pre, x, B.Params(51, 7, 11), {}),
+             (B.relu_pre, x, prm, {"seeds": B.Seeds(1, 2, 3, 5)}), (B.relu_pre, x, prm, {"elem_base": 7})]
+    for fn, xs, p, kw in cases:
         with pytest.raises(B.BicopError) as ei:
-            fn(xs, xs, p, rec, out=(y[0][:xs.numel()], y[1][:xs.numel()]))
-        assert ei.value.code == -8, (fn.__name__, xs.numel(), p)
+            fn(xs, xs, p, rec, out=(y[0][:xs.numel()], y[1][:xs.numel()]), **kw)
+        assert ei.value.code == -8, (fn.__name__, xs.numel(), p, kw)
     torch.cuda.synchronize()
     assert bool((y[0] == 7).all()) and bool((y[1] == 7).all())
     z0, z1 = B.relu_pre(x, x, prm, rec)                  # the matching call runs
