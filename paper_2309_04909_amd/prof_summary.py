@@ -41,12 +41,12 @@ KERNELS = {
                      ["bc_device.h", "drelu_kernel.h"], 32 * N_KEYBIT),
     "trunc_det_keybit": ("OpTruncDet<unsigned long, unsigned long>", ["bc_device.h", "k_stream.hip"],
                          32 * N_KEYBIT),
-    # the online kernels of the precomputed mode: shares plus the record (132 B per element at
-    # N = 19 for the DReLU, 72 B at N = 8 for the ReLU)
+    # the online kernels of the precomputed mode: shares plus the record (124 B per element at
+    # N = 19 for the DReLU, 32 B at N = 8 for the ReLU)
     "drelu_pre_lx18": ("k_drelu_pre<unsigned long, 19, bc::FieldMersenne<19>, false, false>",
-                       ["bc_device.h", "drelu_kernel.h", "pre_kernel.h"], (32 + 132) * N_KEYBIT),
+                       ["bc_device.h", "drelu_kernel.h", "pre_kernel.h"], (32 + 124) * N_KEYBIT),
     "relu_pre_lx7": ("k_drelu_pre<unsigned long, 8, bc::FieldPM<8, 5u>, true, false>",
-                     ["bc_device.h", "drelu_kernel.h", "pre_kernel.h"], (32 + 72) * N_KEYBIT),
+                     ["bc_device.h", "drelu_kernel.h", "pre_kernel.h"], (32 + 32) * N_KEYBIT),
 }
 COPY_BYTES = 512 << 20          # bench.py copy_reference: 512 MiB read and 512 MiB written per copy
 
