@@ -23,10 +23,21 @@ element gets the same randomness alone, in a batch, or under any schedule.
 Draws (no rejection; multiply-shift, whose statistical distance from
 uniform is k (m - k) / (m 2^B) for m values drawn from B bits, k = 2^B mod m,
 or N-bit fields, below):
-  TAG_SHUFFLE (seed_01): word j%4 of block j//4 is the sort key of position
-    j: key_j = (word & ~63) | j.  Slot s of the shuffled array receives the
-    position with the s-th smallest key.  t = bit 0 of word 0 of block 0
-    (disjoint from the key bits of position 0).
+  TAG_SHUFFLE (seed_01): the flip t and the permutation sigma of the N
+    window positions come from N digits: digit 0 is t (radix 2), digit i
+    (1 <= i < N) is j_i in [0, i] (radix i + 1), the choices of an
+    inside-out Fisher-Yates shuffle: A[0] = 0, then for i = 1..N-1
+    A[i] = A[j_i], A[j_i] = i; slot s of the shuffled array receives window
+    position sigma(s) = A[s].  The digits are cut from 64-bit chunks
+    F_c = w_{2c} | w_{2c+1} << 32 of the stream (word i is word i % 4 of
+    block i // 4): digits go to chunk 0 in order while the product M_c of
+    the chunk's radices stays <= 2^32, then to chunk 1, and so on.  Within a
+    chunk, digit d of radix m is floor(F m / 2^64) and F becomes F m mod
+    2^64, so the chunk's digits are the mixed-radix digits of
+    floor(F_c M_c / 2^64), whose distance from uniform on [0, M_c) is at
+    most M_c / 2^64 <= 2^-32.  The shuffle is a bijection from the digit
+    tuples onto (t, sigma), so (t, sigma) is within (number of chunks) *
+    2^-32 of uniform: two chunks (one block) at N <= 19, five at N = 33.
   TAG_MASK (seed_01), p < 2^32: block s//2 words 2(s%2), 2(s%2)+1 are
     (R, Z) of slot s;  r_s = 1 + floor(R (p-1) / 2^32) in Z_p^*,
     z_s = floor(Z p / 2^32) in Z_p.   p > 2^32: block s gives 64-bit
@@ -110,14 +121,75 @@ def _words(seed, nonce, g, tag, count):
     return np.stack(out[:count], axis=1)
 
 
+SHUFFLE_CHUNK_MAX = 1 << 32       # the largest product of radices one 64-bit chunk carries
+
+
+def shuffle_radices(n: int):
+    """Radices of the shuffle's n digits: t, then j_1 .. j_{n-1}."""
+    return [2] + [i + 1 for i in range(1, n)]
+
+
+def shuffle_chunks(n: int):
+    """For each 64-bit chunk, the indices of the digits cut from it."""
+    chunks, cur, prod = [], [], 1
+    for k, m in enumerate(shuffle_radices(n)):
+        if prod * m > SHUFFLE_CHUNK_MAX:
+            chunks.append(cur)
+            cur, prod = [], 1
+        cur.append(k)
+        prod *= m
+    chunks.append(cur)
+    return chunks
+
+
+def chunk_digits(lo, hi, radices):
+    """Digits of radices m_1, m_2, ... cut from the 64-bit fractions
+    F = lo | hi << 32 (uint64 arrays of 32-bit words): F times m, the part
+    above 2^64 is the digit and the rest the next F.  The 64 x 6-bit product
+    is formed in two 32-bit halves, each exact in uint64."""
+    lo = np.asarray(lo, dtype=U64).copy()
+    hi = np.asarray(hi, dtype=U64).copy()
+    out = []
+    for m in radices:
+        m = U64(m)
+        p_lo = lo * m                              # < 2^38
+        p_hi = hi * m + (p_lo >> U64(32))          # < 2^39
+        lo, hi = p_lo & _M32, p_hi & _M32
+        out.append(p_hi >> U64(32))
+    return out
+
+
+def shuffle_digits(seed01: int, nonce: int, g, n: int):
+    """The n shuffle digits per element (shape (len(g), n))."""
+    chunks = shuffle_chunks(n)
+    radix = shuffle_radices(n)
+    w = _words(seed01, nonce, g, TAG_SHUFFLE, 2 * len(chunks))
+    digits = np.zeros((w.shape[0], n), dtype=U64)
+    for c, idx in enumerate(chunks):
+        for k, d in zip(idx, chunk_digits(w[:, 2 * c], w[:, 2 * c + 1], [radix[k] for k in idx])):
+            digits[:, k] = d
+    return digits
+
+
+def fisher_yates(digits):
+    """sigma (shape (len, n)) from the digits j_1 .. j_{n-1} (columns 1..):
+    the inside-out shuffle A[i] = A[j_i], A[j_i] = i."""
+    digits = np.asarray(digits)
+    rows = np.arange(digits.shape[0])
+    n = digits.shape[1]
+    a = np.zeros((digits.shape[0], n), dtype=np.int64)
+    for i in range(1, n):
+        j = digits[:, i].astype(np.int64)
+        a[:, i] = a[rows, j]
+        a[rows, j] = i
+    return a
+
+
 def draw_shuffle(seed01: int, nonce: int, g, n: int):
-    """t (uint64 0/1 per element) and sigma (N x n): sigma[:, s] is the window
-    position placed in slot s by the shuffle of Alg. 7."""
-    w = _words(seed01, nonce, g, TAG_SHUFFLE, n)
-    t = w[:, 0] & U64(1)
-    keys = (w & U64(0xFFFFFFC0)) | np.arange(n, dtype=U64)[None, :]
-    sigma = np.argsort(keys, axis=1, kind="stable").astype(np.int64)
-    return t, sigma
+    """t (uint64 0/1 per element) and sigma (shape (len(g), n)): sigma[:, s]
+    is the window position placed in slot s by the shuffle of Alg. 7."""
+    digits = shuffle_digits(seed01, nonce, g, n)
+    return digits[:, 0].copy(), fisher_yates(digits)
 
 
 def packed_masks(n: int, p: int) -> bool:

@@ -10,6 +10,7 @@ uniform, and element-local randomness.
 """
 
 import numpy as np
+import pytest
 
 from oracle import philox
 from oracle.params import default_prime
@@ -85,6 +86,84 @@ def test_shuffle_is_uniform_permutation():
         [i * n + j for i in range(n) for j in range(n) if i != j]])
     # t independent of the first key's bits
     assert abs(np.mean(t[sigma[:, 0] == 0].astype(float)) - 0.5) < 0.03
+
+
+# ------------------------------------------------------------ the shuffle
+# Pins of the digit-driven inside-out Fisher-Yates shuffle: the chunking rule
+# against the product of the radices, each chunk's digits against the
+# mixed-radix expansion of one big product floor(F M / 2^64) (Python
+# integers, a different computation from the oracle's digit-by-digit
+# extraction), the shuffle against brute force (a bijection onto all
+# permutations) and hand-worked cases.
+
+@pytest.mark.parametrize("n", range(2, 34))
+def test_shuffle_chunks_follow_the_greedy_rule(n):
+    import math
+    chunks = philox.shuffle_chunks(n)
+    radix = philox.shuffle_radices(n)
+    assert radix == [2] + list(range(2, n + 1))
+    assert [k for c in chunks for k in c] == list(range(n))       # in order, each digit once
+    prods = [math.prod(radix[k] for k in c) for c in chunks]
+    assert all(pr <= 1 << 32 for pr in prods)
+    assert math.prod(prods) == 2 * math.factorial(n)
+    for c, nxt in zip(chunks, chunks[1:]):                            # a chunk closes only when full
+        assert math.prod(radix[k] for k in c) * radix[nxt[0]] > 1 << 32
+    assert len(chunks) == (1 if n <= 12 else 2 if n <= 19 else 3 if n <= 26 else 4 if n <= 32 else 5)
+    # the bias bound: the sum of M_c / 2^64 over the chunks
+    assert sum(prods) / 2.0 ** 64 <= len(chunks) * 2.0 ** -32
+
+
+def test_chunk_digits_extremes():
+    radices = [2, 2, 3, 4, 5, 6, 7]
+    zero = philox.chunk_digits(np.array([0], dtype=U), np.array([0], dtype=U), radices)
+    assert [int(d[0]) for d in zero] == [0] * len(radices)
+    top = philox.chunk_digits(np.array([0xFFFFFFFF], dtype=U), np.array([0xFFFFFFFF], dtype=U), radices)
+    assert [int(d[0]) for d in top] == [m - 1 for m in radices]     # F = 2^64 - 1: every digit at its maximum
+    half = philox.chunk_digits(np.array([0], dtype=U), np.array([1 << 31], dtype=U), [2, 2, 3])
+    assert [int(d[0]) for d in half] == [1, 0, 0]                      # F = 1/2: t = 1, then F = 0
+
+
+@pytest.mark.parametrize("n", [2, 3, 8, 12, 19, 20, 26, 33])
+def test_shuffle_digits_are_one_mixed_radix_number_per_chunk(n):
+    g = np.arange(7, 7 + 400, dtype=U) * U(2654435761)
+    digits = philox.shuffle_digits(5, 9, g, n)
+    radix = philox.shuffle_radices(n)
+    for c, idx in enumerate(philox.shuffle_chunks(n)):
+        blk = philox.block(5, 9, g, philox.TAG_SHUFFLE, c // 2)
+        lo, hi = blk[2 * (c % 2)], blk[2 * (c % 2) + 1]
+        M = 1
+        for k in idx:
+            M *= radix[k]
+        for e in range(g.size):
+            F = int(lo[e]) | int(hi[e]) << 32
+            D = (F * M) >> 64                                          # one product, then its digits
+            want = []
+            for k in reversed(idx):
+                D, d = divmod(D, radix[k])
+                want.append(d)
+            assert D == 0
+            assert [int(digits[e, k]) for k in idx] == want[::-1], (n, c, e)
+
+
+@pytest.mark.parametrize("n", range(1, 7))
+def test_fisher_yates_is_a_bijection(n):
+    import itertools
+    import math
+    tuples = list(itertools.product(*[range(i + 1) for i in range(n)]))   # j_0 = 0 (digit 0 is t), j_i in [0, i]
+    perms = philox.fisher_yates(np.array(tuples, dtype=np.int64))
+    assert len({tuple(p) for p in perms.tolist()}) == math.factorial(n) == len(tuples)
+    assert np.all(np.sort(perms, axis=1) == np.arange(n))
+
+
+def test_fisher_yates_worked_cases():
+    # j = (t, 1, 0, 2): A = [0]; i=1, j=1: A[1] = 1; i=2, j=0: A[2] = A[0] = 0, A[0] = 2;
+    # i=3, j=2: A[3] = A[2] = 0, A[2] = 3  ->  [2, 1, 3, 0]
+    assert philox.fisher_yates(np.array([[1, 1, 0, 2]])).tolist() == [[2, 1, 3, 0]]
+    for n in (2, 5, 19, 33):
+        zero = philox.fisher_yates(np.zeros((1, n), dtype=np.int64))
+        assert zero.tolist() == [[n - 1] + list(range(n - 1))]         # every j_i = 0: a rotation
+        top = philox.fisher_yates(np.array([list(range(n))]))
+        assert top.tolist() == [list(range(n))]                         # every j_i = i: the identity
 
 
 def test_masks_in_range_and_uniform():
