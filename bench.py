@@ -62,41 +62,29 @@ SEEDS = (0x243F6A8885A308D3, 0x13198A2E03707344, 0xA4093822299F31D0)
 # ------------------------------------------------------------- ALU op model
 
 
-def pairwise_network(n: int):
-    """Comparators (lo, hi) of Parberry's pairwise sorting network on the next
-    power of two P >= n, pruned to the pairs inside [0, n): the network the
-    kernels sort the shuffle keys with."""
-    P = 1
-    while P < n:
-        P *= 2
-    net = []
-    a = 1
-    while a < P:                        # pairs at distance a: blocks of a, gaps of a
-        for start in range(a, P, 2 * a):
-            net.extend((b - a, b) for b in range(start, start + a))
-        a *= 2
-    a //= 4
-    e = 1
-    while a > 0:                        # merges at distances d a, d = e, e/2, ..., 1
-        d = e
-        while d > 0:
-            for start in range((d + 1) * a, P, 2 * a):
-                net.extend((b - d * a, b) for b in range(start, min(start + a, P)))
-            d //= 2
-        a //= 2
-        e = 2 * e + 1
-    return [(lo, hi) for lo, hi in net if hi < n]
+def shuffle_blocks(n: int) -> int:
+    """Philox blocks of an element's shuffle: its n digits (the flip t of radix
+    2, then the Fisher-Yates choices of radices 2..n) go to 64-bit chunks while
+    the product of a chunk's radices stays <= 2^32, two chunks to a block."""
+    chunks, prod = 1, 1
+    for m in [2] + list(range(2, n + 1)):
+        if prod * m > 1 << 32:
+            chunks, prod = chunks + 1, 1
+        prod *= m
+    return (chunks + 1) // 2
 
 
 PHILOX_OPS = 60          # 10 rounds x (two 32x32->64 multiplies + four XORs)
 SLOT_OPS = 40            # per slot: two windows, adjacent sums, mod switch, two draws,
                          # two masked products with reshare, P2's sum and zero test
 SLOT_OPS_WIDE = 64       # same with 64-bit field elements (l_x = 32)
+DIGIT_OPS = 6            # per shuffle digit: two 32-bit multiplies and a carry add to cut it,
+                         # then the Fisher-Yates step's read and two writes
 TAIL_OPS = {"drelu": 12, "relu": 40,
             # replicated sharing at l = 64: [t], [s], the zero sharing, the product [s][t]
             # (two 64-bit multiplies per share), [s xor t], the finish; the ReLU adds a product
             "rss_drelu": 100, "rss_relu": 160}
-# Philox blocks per element beyond the shuffle keys and the masks
+# Philox blocks per element beyond the shuffle and the masks
 TAIL_BLOCKS = {"drelu": 1, "relu": 3, "rss_drelu": 6, "rss_relu": 7}
 
 
@@ -111,13 +99,12 @@ def mask_blocks(n: int) -> int:
 
 def alg_ops_per_elem(op: str, lx: int) -> int:
     """32-bit integer operations per element of the fused kernel: 60 per Philox
-    block, a fixed count per slot, two per comparator of the sorting network and
-    a per-op tail (the method's work, as a GEMM's flops count 2mnk)."""
+    block, a fixed count per slot and per shuffle digit, and a per-op tail (the
+    method's work, as a GEMM's flops count 2mnk)."""
     n = lx + 1
     wide = lx == 32
-    blocks = (n + 3) // 4 + mask_blocks(n) + TAIL_BLOCKS[op]
-    return (blocks * PHILOX_OPS + n * (SLOT_OPS_WIDE if wide else SLOT_OPS) + 2 * len(pairwise_network(n))
-            + TAIL_OPS[op])
+    blocks = shuffle_blocks(n) + mask_blocks(n) + TAIL_BLOCKS[op]
+    return blocks * PHILOX_OPS + n * ((SLOT_OPS_WIDE if wide else SLOT_OPS) + DIGIT_OPS) + TAIL_OPS[op]
 
 
 def measured_traffic(kernel: str):

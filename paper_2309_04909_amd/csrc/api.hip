@@ -212,7 +212,7 @@ uint32_t sched_value(uint32_t kind, uint32_t npos, uint32_t width, bool relu) {
 // `fill` waves at one lane per element (BC_SCHED_GROUP_FILL, default one)
 // spread each element over 8 or 4 lanes (up to the group schedule's limit)
 // while the grid stays within `fill` waves per SIMD; beyond that the lanes'
-// repeated shuffle and sort cost more than the latency they hide (measured
+// repeated shuffle costs more than the latency it hides (measured
 // on MI355X per window count; the tuner sets both limits).  Capturing calls
 // keep one lane per element.
 int lanes_per_element(uint32_t npos, uint32_t width, bool relu, uint64_t n, bool capture) {

@@ -9,9 +9,6 @@
 //      Field24     p < 2^24   products exact in fp64, fp64 quotient
 //      Field32     p < 2^32   64-bit products, Barrett with a 64-bit reciprocal
 //      Field64     p < 2^34   l_x = 32; 66-bit products, fp64 quotient
-//  * A pairwise sorting network (Parberry) over the N keys, generated at
-//    compile time, used to turn the per-position random keys into the
-//    shuffle of Alg. 7 without any dynamically indexed register array.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -458,96 +455,5 @@ __device__ __forceinline__ typename F::T submod(typename F::T a, typename F::T b
 // (p < 2^32): r = 1 + floor(R (p - 1) / 2^32), z = floor(Z p / 2^32).
 __device__ __forceinline__ uint32_t draw_r(uint32_t R, uint32_t p) { return 1u + __umulhi(R, p - 1u); }
 __device__ __forceinline__ uint32_t draw_z(uint32_t Z, uint32_t p) { return __umulhi(Z, p); }
-
-// ---------------------------------------------------------- sorting network
-
-// Parberry's pairwise sorting network (1992) over the next power of two
-// P >= N, keeping only comparators whose both ends are < N.  Every comparator
-// puts its minimum at the lower index, so padding entries >= N (taken as
-// +inf) never move and dropping their comparators leaves a sorting network
-// on N keys.  For the window counts used here it needs no more comparators
-// than Batcher's odd-even merge sort and fewer for N in 9..12, 17..28 and 33
-// (N = 19: 91 instead of 98; N = 33: 207 instead of 246).  Comparator c puts
-// min at a[c], max at b[c].
-template <int N>
-struct SortNet {
-    static constexpr int P = N <= 1 ? 1 : (N <= 2 ? 2 : (N <= 4 ? 4 : (N <= 8 ? 8 : (N <= 16 ? 16 : (N <= 32 ? 32 : 64)))));
-
-    // Calls emit(lo, hi) for every comparator, in network order.
-    template <typename Emit>
-    static constexpr void walk(Emit&& emit) {
-        // phase 1: pairs at distance a, for a = 1, 2, 4, ...: blocks of a
-        // comparators (b - a, b), separated by gaps of a
-        int a = 1;
-        for (; a < P; a *= 2) {
-            int b = a, c = 0;
-            while (b < P) {
-                emit(b - a, b);
-                ++b;
-                c = (c + 1) % a;
-                if (c == 0) b += a;
-            }
-        }
-        // phase 2: for a = P/4, P/8, ..., 1 and d = e, e/2, ..., 1 (e = 1, 3, 7, ...):
-        // comparators (b - d a, b) from b = (d + 1) a on, in blocks of a
-        a /= 4;
-        for (int e = 1; a > 0; a /= 2, e = 2 * e + 1) {
-            for (int d = e; d > 0; d /= 2) {
-                int b = (d + 1) * a, c = 0;
-                while (b < P) {
-                    emit(b - d * a, b);
-                    ++b;
-                    c = (c + 1) % a;
-                    if (c == 0) b += a;
-                }
-            }
-        }
-    }
-    static constexpr int count() {
-        int c = 0;
-        walk([&](int lo, int hi) {
-            if (lo < N && hi < N) ++c;
-        });
-        return c;
-    }
-    static constexpr int C = count();
-    struct Table {
-        int a[C > 0 ? C : 1];
-        int b[C > 0 ? C : 1];
-    };
-    static constexpr Table table() {
-        Table t{};
-        int c = 0;
-        walk([&](int lo, int hi) {
-            if (lo < N && hi < N) {
-                t.a[c] = lo;
-                t.b[c] = hi;
-                ++c;
-            }
-        });
-        return t;
-    }
-    static constexpr Table tab = table();
-};
-
-template <int N, int C, int I = 0>
-struct ApplyNet {
-    __device__ static __forceinline__ void run(uint32_t (&k)[N]) {
-        if constexpr (I < C) {
-            constexpr int a = SortNet<N>::tab.a[I];
-            constexpr int b = SortNet<N>::tab.b[I];
-            const uint32_t lo = k[a] < k[b] ? k[a] : k[b];
-            const uint32_t hi = k[a] < k[b] ? k[b] : k[a];
-            k[a] = lo;
-            k[b] = hi;
-            ApplyNet<N, C, I + 1>::run(k);
-        }
-    }
-};
-
-template <int N>
-__device__ __forceinline__ void sort_keys(uint32_t (&k)[N]) {
-    ApplyNet<N, SortNet<N>::C>::run(k);
-}
 
 }  // namespace bc

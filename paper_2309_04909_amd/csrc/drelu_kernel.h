@@ -6,8 +6,8 @@
 //          windows  l_x + 1 windows trc(x, k_lo + i, l - l_x - k_lo - i)
 //          sums     adjacent sums v_i = u_i + u_{i+1} - 1 (P0 adds the -1)
 //          switch   modulo switch to Z_p (Alg. 6)
-//          shuffle  slot s takes the position with the s-th smallest
-//                   seed_01 key (sorting network on 32-bit keys)
+//          shuffle  slot s takes position sigma(s) of a seed_01 Fisher-Yates
+//                   shuffle run in the thread's slice of LDS
 //          mask     multiply by r_s in Z_p^*, reshare by +-z_s
 //   P2     test     reconstruct every slot, D' = [some slot is 0]
 //          reply    reshare D' with rho from seed_02 (DReLU)
@@ -19,7 +19,7 @@
 // The l_x + 1 window values never leave VGPRs.  Kernels are instantiated
 // per window count N = l_x + 1, so every loop over windows is unrolled.  The
 // shuffle is applied by computing, for slot s, the window of the position
-// the sorted key names: the message in slot s is v_{sigma(s)} r_s + z_s,
+// sigma(s) read back from LDS: the message in slot s is v_{sigma(s)} r_s + z_s,
 // exactly the array that the shuffle and mask produce.  With a capture
 // pointer the same code also stores both parties' round-1 messages.
 #pragma once
@@ -165,24 +165,84 @@ __device__ __forceinline__ void relu_finish(T dp, T in0, T in1, T ba0, T bb0, T 
     y1 = t ? (T)(in1 - m1) & mask : m1;
 }
 
-// The flip bit t and the sorted shuffle keys of one element, both from
-// seed_01 (Alg. 7): key j is word j of the TAG_SHUFFLE stream with its low
-// six bits replaced by j (ties broken by position); slot s takes the
-// position in the low bits of the s-th smallest key.  t is bit 0 of word 0,
-// which the key of position 0 does not use.
+// The flip bit t and the shuffle of one element, both from seed_01 (Alg. 7).
+// N digits: t (radix 2), then j_i in [0, i] (radix i + 1) for i = 1..N-1, the
+// choices of an inside-out Fisher-Yates shuffle: A[0] = 0, and for each i,
+// A[i] = A[j_i], A[j_i] = i; slot s takes window position A[s].  The digits
+// are cut from 64-bit chunks F of the TAG_SHUFFLE stream (chunk c: words
+// 2 (c % 2) and 2 (c % 2) + 1 of block c / 2, low word first); a chunk takes
+// digits in order while the product of their radices stays <= 2^32, and a
+// digit of radix m is the part of F m above 2^64, F m mod 2^64 the next F.
 template <int N>
-__device__ __forceinline__ uint32_t shuffle_keys(const StreamAt& r01, uint32_t (&key)[N]) {
-    uint32_t t = 0;
-#pragma unroll
-    for (int b = 0; b < (N + 3) / 4; ++b) {
-        const Words4 w = r01.block(TAG_SHUFFLE, b);
-        if (b == 0) t = w.w0 & 1u;
-        const uint32_t ws[4] = {w.w0, w.w1, w.w2, w.w3};
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (4 * b + q < N) key[4 * b + q] = (ws[q] & ~63u) | (uint32_t)(4 * b + q);
+struct ShufflePlan {
+    int chunk[N];      // the chunk of digit k
+    constexpr ShufflePlan() : chunk() {
+        uint64_t prod = 1;
+        int c = 0;
+        for (int k = 0; k < N; ++k) {
+            const uint64_t m = k == 0 ? 2 : (uint64_t)k + 1;
+            if (prod * m > (1ull << 32)) {
+                ++c;
+                prod = 1;
+            }
+            prod *= m;
+            chunk[k] = c;
+        }
     }
-    sort_keys<N>(key);
+};
+
+// Runs the shuffle in this thread's slice of a per-block LDS array (blocks of
+// at most 256 threads: every kernel is launched with __launch_bounds__(256))
+// and returns the slice: A[k] is byte 1024 (k / 4) + (k % 4) of it, so the 64
+// lanes of a wave touch 64 different banks whatever their k.  The slice stays
+// valid until the thread's next call.
+template <int N>
+__device__ __forceinline__ uint8_t* shuffle_fill(const StreamAt& r01, uint32_t& t) {
+    constexpr ShufflePlan<N> plan{};
+    __shared__ uint32_t lds[((N + 3) / 4) * 256];
+    uint8_t* A = reinterpret_cast<uint8_t*>(lds) + 4 * threadIdx.x;
+    Words4 w = {0, 0, 0, 0};
+    uint32_t lo = 0, hi = 0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const int c = plan.chunk[k];
+        if (k == 0 || plan.chunk[k > 0 ? k - 1 : 0] != c) {
+            if (c % 2 == 0) w = r01.block(TAG_SHUFFLE, (uint32_t)(c / 2));
+            lo = c % 2 ? w.w2 : w.w0;
+            hi = c % 2 ? w.w3 : w.w1;
+        }
+        const uint32_t m = k == 0 ? 2u : (uint32_t)k + 1u;
+        const uint64_t pl = (uint64_t)lo * m;
+        const uint64_t ph = (uint64_t)hi * m + (uint32_t)(pl >> 32);
+        lo = (uint32_t)pl;
+        hi = (uint32_t)ph;
+        const uint32_t d = (uint32_t)(ph >> 32);              // t, or j_k <= k
+        if (k == 0) {
+            t = d;
+            A[0] = 0;
+        } else {
+            uint8_t* aj = A + (((d >> 2) << 10) | (d & 3u));
+            A[1024 * (k >> 2) + (k & 3)] = *aj;                 // A[k] = A[j_k]
+            *aj = (uint8_t)k;                                   // A[j_k] = k
+        }
+    }
+    return A;
+}
+
+// Window position of slot s after shuffle_fill.
+__device__ __forceinline__ uint32_t shuffle_pos(const uint8_t* A, uint32_t s) {
+    return A[((s >> 2) << 10) | (s & 3u)];
+}
+
+// The shuffle as words: byte q of perm[k] is the position of slot 4k + q
+// (bytes past N zero).
+template <int N>
+__device__ __forceinline__ uint32_t shuffle_perm(const StreamAt& r01, uint32_t (&perm)[(N + 3) / 4]) {
+    uint32_t t;
+    const uint8_t* A = shuffle_fill<N>(r01, t);
+#pragma unroll
+    for (int k = 0; k < (N + 3) / 4; ++k) perm[k] = reinterpret_cast<const uint32_t*>(A)[256 * k];
+    if constexpr (N % 4 != 0) perm[(N + 3) / 4 - 1] &= (1u << (8 * (N % 4))) - 1u;
     return t;
 }
 
@@ -293,10 +353,10 @@ __device__ __forceinline__ T drelu_round1(T in0, T in1, uint64_t g, T mask, uint
     constexpr bool WIDE = std::is_same<FT, uint64_t>::value;
     static_assert(WIDE == (N == 33), "64-bit field elements exactly when l_x = 32");
 
-    // The flip bit t and the shuffle keys, both from seed_01.
+    // The flip bit t and the shuffle, both from seed_01.
     const StreamAt r01 = s01.at(g);
-    uint32_t key[N];
-    const uint32_t t = shuffle_keys<N>(r01, key);
+    uint32_t t;
+    const uint8_t* A = shuffle_fill<N>(r01, t);
 
     // Flip: [x] := (-1)^t [x]  (both parties).
     const T a0 = t ? (T)((T)0 - in0) & mask : in0;
@@ -312,7 +372,7 @@ __device__ __forceinline__ T drelu_round1(T in0, T in1, uint64_t g, T mask, uint
         FT r, z;
         slot_draws<N, F>(r01, j, wm, f, r, z);
         FT w0, w1;
-        slot_messages<T, N, F, MaskDraws<N, F>::SH>(a0k, nb1k, key[j] & 63u, r, z, f, w0, w1, least);
+        slot_messages<T, N, F, MaskDraws<N, F>::SH>(a0k, nb1k, shuffle_pos(A, j), r, z, f, w0, w1, least);
         if constexpr (CAP) {
             cap[e * N + j] = w0;
             cap[(ncap + e) * N + j] = w1;
@@ -375,8 +435,8 @@ __global__ BC_KERNEL_ATTRS void k_drelu(DreluKArgs A, F f_arg) {
 }
 
 // Lane groups for small calls: G consecutive lanes share one element, so a
-// call of n elements still runs n * G threads.  Every lane of the group draws
-// and sorts the shuffle keys (cheap next to the slots), lane l takes mask
+// call of n elements still runs n * G threads.  Every lane of the group runs
+// the whole shuffle in its own LDS slice, lane l takes mask
 // block kG + l in round k (its two slots, or one slot when l_x = 32), and the
 // group's P2 minimum is combined by lane shuffles; lane 0 finishes and writes.
 // Results are those of drelu_element: same draws, same slots, same messages.
@@ -399,8 +459,8 @@ __device__ __forceinline__ void drelu_element_group(const T* __restrict__ X0, co
     const T in1 = (T)((T)0 - (T)(nr1 >> k_in)) & mask;
 
     const StreamAt r01 = s01.at(g);
-    uint32_t key[N];
-    const uint32_t t = shuffle_keys<N>(r01, key);
+    uint32_t t;
+    const uint8_t* A = shuffle_fill<N>(r01, t);
 
     const T a0 = t ? (T)((T)0 - in0) & mask : in0;
     const T a1 = t ? (T)((T)0 - in1) & mask : in1;
@@ -414,16 +474,13 @@ __device__ __forceinline__ void drelu_element_group(const T* __restrict__ X0, co
         const Words4 w = r01.block(TAG_MASK, blk);
 #pragma unroll
         for (int h = 0; h < SPB; ++h) {
-            // slot j = SPB * blk + h; its sorted key, chosen among the G lanes' candidates
-            uint32_t kj = key[SPB * k * G + h < N ? SPB * k * G + h : N - 1];
-#pragma unroll
-            for (int q = 1; q < G; ++q)
-                if (SPB * (k * G + q) + h < N) kj = lane == (uint32_t)q ? key[SPB * (k * G + q) + h] : kj;
+            // slot j = SPB * blk + h (past the last slot: any slot, its message is not counted)
+            const bool valid = SPB * blk + h < (uint32_t)N;
+            const uint32_t pos = shuffle_pos(A, valid ? SPB * blk + h : 0u);
             FT r, z;
             block_draws_at<N, F>(w, h, f, r, z);
             FT w0, w1, v = f.p;
-            slot_messages<T, N, F, SH>(a0k, nb1k, kj & 63u, r, z, f, w0, w1, v);
-            const bool valid = SPB * blk + h < (uint32_t)N;
+            slot_messages<T, N, F, SH>(a0k, nb1k, pos, r, z, f, w0, w1, v);
             least = (valid && v < least) ? v : least;
         }
     }

@@ -2,7 +2,7 @@
 //
 // Everything the parties draw from their seeds is independent of the input,
 // so it can be expanded ahead of time (an offline phase) and kept resident.
-// The record keeps what would cost the online phase its sort, its mask
+// The record keeps what would cost the online phase its shuffle, its mask
 // draws or a message: P0/P1's flip t and shuffle and the masks from seed_01,
 // and for the ReLU P2's [c]_1 of the Beaver triple (Alg. 8's preprocessing,
 // sent to P1).  What a party draws from seed_02 or seed_12 alone (P2's
@@ -70,16 +70,10 @@ __global__ BC_KERNEL_ATTRS void k_expand(ExpandKArgs A, F f) {
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
         const uint64_t g = A.elem_base + e;
         const StreamAt r01 = A.s01.at(g);
-        uint32_t key[N];
-        const uint32_t t = shuffle_keys<N>(r01, key);
+        uint32_t perm[(N + 3) / 4];
+        const uint32_t t = shuffle_perm<N>(r01, perm);
 #pragma unroll
-        for (int k = 0; k < (N + 3) / 4; ++k) {
-            uint32_t word = (k == 0) ? (t << 7) : 0u;
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (4 * k + q < N) word |= (key[4 * k + q] & 63u) << (8 * q);
-            A.perm[(uint64_t)k * n + e] = word;
-        }
+        for (int k = 0; k < (N + 3) / 4; ++k) A.perm[(uint64_t)k * n + e] = k == 0 ? perm[0] | t << 7 : perm[k];
         Words4 wm = {0, 0, 0, 0};
         uint64_t* rz = static_cast<uint64_t*>(A.rz);
         constexpr int K = RzLayout<N>::K;

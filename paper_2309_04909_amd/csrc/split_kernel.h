@@ -85,8 +85,8 @@ __global__ BC_KERNEL_ATTRS void k_send(SplitKArgs A, F f_arg) {
         const uint64_t g = A.elem_base + e;
         const T x = X[e] & mask;
         const StreamAt r01 = A.s01.at(g);
-        uint32_t key[N];
-        const uint32_t t = shuffle_keys<N>(r01, key);
+        uint32_t t;
+        const uint8_t* sig = shuffle_fill<N>(r01, t);
         const T a = t ? (T)((T)0 - x) & mask : x;                    // flip
         const T ak = (PARTY == 0 ? a : (T)((T)0 - a) & mask) >> A.k_lo;
         uint32_t words[W];
@@ -97,7 +97,7 @@ __global__ BC_KERNEL_ATTRS void k_send(SplitKArgs A, F f_arg) {
         for (int j = 0; j < N; ++j) {
             FT r, z;
             slot_draws<N, F>(r01, j, wm, f, r, z);
-            pack_slot<N>(words, j, (uint64_t)party_message<T, N, F, PARTY>(ak, key[j] & 63u, r, z, f));
+            pack_slot<N>(words, j, (uint64_t)party_message<T, N, F, PARTY>(ak, shuffle_pos(sig, j), r, z, f));
         }
 #pragma unroll
         for (int k = 0; k < W; ++k) M[(uint64_t)k * A.n + e] = words[k];
@@ -143,7 +143,8 @@ __global__ __launch_bounds__(256) void k_finish(SplitKArgs A) {
     const T mask = (T)A.ring_mask;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < A.n; e += stride) {
-        const uint32_t t = A.s01.block(A.elem_base + e, TAG_SHUFFLE, 0).w0 & 1u;
+        // t is the shuffle's first digit (radix 2) of chunk 0: the top bit of its high word
+        const uint32_t t = A.s01.block(A.elem_base + e, TAG_SHUFFLE, 0).w1 >> 31;
         const T d = D[e] & mask;
         if constexpr (PARTY == 0)
             Y[e] = t ? (T)((T)1 - d) & mask : d;
