@@ -179,7 +179,8 @@ def _cpu_model():
 # ------------------------------------------------------------------- GPU parts
 
 
-HIP_EVENT_DISABLE_SYSTEM_FENCE = 0x20000000      # hipEventCreateWithFlags flag (hip_runtime_api.h)
+HIP_EVENT_DISABLE_SYSTEM_FENCE = 0x20000000      # hipEventCreateWithFlags flags (hip_runtime_api.h)
+HIP_EVENT_DISABLE_TIMING = 0x2
 
 
 def _hip_runtime():
@@ -198,6 +199,7 @@ def _hip_runtime():
     hip.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
     hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+    hip.hipStreamWaitEvent.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint]
     return hip
 
 
@@ -260,6 +262,46 @@ class Timer:
         self.pairs = {}
 
 
+class StreamJoins:
+    """Cross-stream waits of the two-stream step: a HIP event recorded on the
+    producing stream and waited on by the other, created without timing and
+    without the system-scope fence (both streams are on one device and
+    nothing on the host reads the data).  One event serves every join: a
+    wait takes the event's state when it is enqueued, so recording it again
+    for the next join leaves earlier waits alone.  Falls back to torch's
+    wait_stream if the runtime cannot be found."""
+
+    def __init__(self, torch):
+        import ctypes
+        self.hip = _hip_runtime()
+        self.event = None
+        self.kind = "HIP events without timing or the system-scope fence" if self.hip else "torch wait_stream"
+        if self.hip is not None:
+            e = ctypes.c_void_p()
+            rc = self.hip.hipEventCreateWithFlags(ctypes.byref(e), HIP_EVENT_DISABLE_SYSTEM_FENCE |
+                                                  HIP_EVENT_DISABLE_TIMING)
+            if rc != 0:
+                raise RuntimeError(f"hipEventCreateWithFlags failed ({rc})")
+            self.event = e
+
+    def wait(self, dst, src):
+        """dst waits for the work enqueued on src so far."""
+        if self.hip is None:
+            dst.wait_stream(src)
+            return
+        import ctypes
+        rc = self.hip.hipEventRecord(self.event, ctypes.c_void_p(src.cuda_stream))
+        if rc == 0:
+            rc = self.hip.hipStreamWaitEvent(ctypes.c_void_p(dst.cuda_stream), self.event, 0)
+        if rc != 0:
+            raise RuntimeError(f"stream join failed ({rc})")
+
+    def release(self):
+        if self.event is not None:
+            self.hip.hipEventDestroy(self.event)
+        self.event = None
+
+
 def to_dev(torch, a):
     a = np.ascontiguousarray(a)
     return torch.from_numpy(a.view(np.int64 if a.dtype == np.uint64 else np.int32)).cuda()
@@ -277,9 +319,10 @@ def run_keybit(torch, B, inputs, steps, warmup):
 
     main = torch.cuda.current_stream()
     side = torch.cuda.Stream()                     # default priority
+    joins = StreamJoins(torch)
 
     def step(timer=None):
-        side.wait_stream(main)                      # the step starts on both streams together
+        joins.wait(side, main)                      # the step starts on both streams together
         s = timer.start(side) if timer else None
         B.trunc_det(z0, z1, c["ell"], c["trunc_k"], 0, out=(t0, t1), stream=side)
         if timer:
@@ -288,7 +331,7 @@ def run_keybit(torch, B, inputs, steps, warmup):
         B.drelu(x0, x1, prm, sd, out=(y0, y1))
         if timer:
             timer.stop("drelu", s)
-        main.wait_stream(side)                      # and ends when both are done
+        joins.wait(main, side)                      # and ends when both are done
 
     # The truncation beside the DReLU runs on one block per compute unit: it
     # needs well under 1 TB/s to finish inside the DReLU, and a narrow grid
@@ -321,8 +364,9 @@ def run_keybit(torch, B, inputs, steps, warmup):
         wall = time.perf_counter() - t_start
     finally:
         B.set_schedule("stream", 0, standalone_bpc, 8)
+        joins.release()
     times = {"trunc_det": timer.avg_ms("trunc_det"), "drelu": timer.avg_ms("drelu"), "events": timer.kind,
-             "warmup_s": warm_s, "warmup_steps_run": warm_steps}
+             "joins": joins.kind, "warmup_s": warm_s, "warmup_steps_run": warm_steps}
     timer.release()
     return wall, times
 
@@ -873,7 +917,7 @@ def main():
                      "rounds": 2, "counted_by": "bc_msg_account (Tab. 1: (l_x + 1)^2 bits per share-holder)"},
         "kernels": {"drelu_ms": round(kern["drelu"], 4), "trunc_det_ms": round(kern["trunc_det"], 4),
                     "drelu_gelem_s": round(c["n"] / kern["drelu"] / 1e6, 3),
-                    "trunc_det_in_step_gbs": round(td_gbs, 1), "events": kern["events"],
+                    "trunc_det_in_step_gbs": round(td_gbs, 1), "events": kern["events"], "joins": kern["joins"],
                     "note": "HIP events around each kernel inside the timed steps; the truncation runs on the "
                             "narrow side grid, overlapped with the DReLU (kernels_alone: each on its own)"},
     }
