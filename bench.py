@@ -90,11 +90,11 @@ TAIL_BLOCKS = {"drelu": 1, "relu": 3, "rss_drelu": 6, "rss_relu": 7}
 
 def mask_blocks(n: int) -> int:
     """Philox blocks of an element's masks and reshares with the default prime:
-    three slots to a block for 17 <= N <= 21 (N-bit fields), one per block for
-    N = 33 (64-bit words), two otherwise (32-bit words)."""
-    if 17 <= n <= 21:
-        return (n + 2) // 3
-    return n if n == 33 else (n + 1) // 2
+    N-bit fields of one bit stream for N >= 17 (2N fields of N bits), else
+    two slots to a block (32-bit words)."""
+    if n >= 17:
+        return -(-2 * n * n // 128)
+    return (n + 1) // 2
 
 
 def alg_ops_per_elem(op: str, lx: int) -> int:

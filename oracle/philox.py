@@ -42,16 +42,17 @@ or N-bit fields, below):
     (R, Z) of slot s;  r_s = 1 + floor(R (p-1) / 2^32) in Z_p^*,
     z_s = floor(Z p / 2^32) in Z_p.   p > 2^32: block s gives 64-bit
     R = w0 | w1 << 32, Z = w2 | w3 << 32 and the same formulas over 2^64.
-  TAG_MASK, packed (``packed_masks``: the default prime p = 2^N - c of
-    N = l_x + 1 bits with 17 <= N <= 21): three slots to a block.  With the
-    block's bits numbered 0..127 (bit i is bit i % 32 of word i // 32), slot
-    s takes block s // 3 and, with h = s % 3, the N-bit fields
-    R = bits [2Nh, 2Nh + N) and Z = bits [2Nh + N, 2Nh + 2N);
-    r_s = min(max(R, 1), p - 1) in Z_p^*, z_s = Z mod p.  The distance from
-    uniform is then (c + 1) / 2^N for r and about c / 2^N for z: for these N
-    within a factor 2 of the 32-bit multiply-shift's (equal at N = 19..21),
-    at most 2^-15.4 (N = 18), while a block carries three slots instead of
-    two.
+  TAG_MASK, as a bit stream (``stream_masks``: the default prime
+    p = 2^N - c of N = l_x + 1 >= 17 bits): the stream's bits are numbered
+    0, 1, ... (bit i is bit i % 32 of word i // 32, word w is word w % 4 of
+    block w // 4), and value v = 2s (R of slot s) or 2s + 1 (Z of slot s)
+    is the N-bit field at bits [N v, N v + N); r_s = min(max(R, 1), p - 1)
+    in Z_p^*, z_s = Z mod p.  The distance from uniform is (c + 1) / 2^N for
+    r and about c / 2^N for z, at most 2^-15.4 (N = 18) and 2^-18 at
+    N = 19, within a factor 2 of the 32-bit multiply-shift's at N = 17..21;
+    an element's 2N fields take ceil(2 N^2 / 128) blocks (6 at N = 19, 18 at
+    N = 33), where 32- or 64-bit words per value would take ceil(N / 2) or
+    N.
   TAG_RESP (seed_02): rho = (w0 | w1 << 32) mod 2^l of block 0.
   TAG_BEAVER: seed_02 block 0 -> [a]_0 = w0|w1<<32, [b]_0 = w2|w3<<32;
     seed_02 block 1 -> [c]_0 = w0|w1<<32;  seed_12 block 0 -> [a]_1, [b]_1.
@@ -192,41 +193,39 @@ def draw_shuffle(seed01: int, nonce: int, g, n: int):
     return digits[:, 0].copy(), fisher_yates(digits)
 
 
-def packed_masks(n: int, p: int) -> bool:
-    """Whether the N = n slots' r and z are N-bit fields, three slots to a
-    block: the default prime, and 17 <= N <= 21 (six N-bit fields fit 128
-    bits, and N-bit fields keep the bias of the 32-bit draws)."""
-    return 17 <= n <= 21 and p == default_prime(n - 1)
+def stream_masks(n: int, p: int) -> bool:
+    """Whether the N = n slots' r and z are N-bit fields of the TAG_MASK bit
+    stream: the default prime with N >= 17 (below, N-bit fields would cost
+    more bias than the 32-bit multiply-shift)."""
+    return n >= 17 and p == default_prime(n - 1)
 
 
-def _bits(lo, hi, off: int, width: int):
-    """Bits off .. off + width - 1 of the 128-bit values hi * 2^64 + lo."""
-    if off + width <= 64:
-        v = lo >> U64(off)
-    elif off >= 64:
-        v = hi >> U64(off - 64)
-    else:
-        v = (lo >> U64(off)) | (hi << U64(64 - off))
-    return v & U64((1 << width) - 1)
+def mask_blocks(n: int, p: int) -> int:
+    """Philox blocks of one element's masks and reshares."""
+    if stream_masks(n, p):
+        return -(-2 * n * n // 128)
+    return n if p >= (1 << 32) else (n + 1) // 2
 
 
 def draw_masks(seed01: int, nonce: int, g, n: int, p: int):
     """r (in Z_p^*) and z (in Z_p), shape (N, n), indexed by slot."""
     g = np.asarray(g, dtype=U64)
-    if packed_masks(n, p):
+    if stream_masks(n, p):
+        w = _words(seed01, nonce, g, TAG_MASK, 4 * mask_blocks(n, p))
+        w = np.concatenate([w, np.zeros((g.size, 1), dtype=U64)], axis=1)   # a zero word past the end
         r = np.empty((g.size, n), dtype=U64)
         z = np.empty((g.size, n), dtype=U64)
-        for b in range((n + 2) // 3):
-            w = block(seed01, nonce, g, TAG_MASK, b)
-            lo = w[0] | (w[1] << U64(32))
-            hi = w[2] | (w[3] << U64(32))
-            for h in range(3):
-                s = 3 * b + h
-                if s < n:
-                    R = _bits(lo, hi, 2 * n * h, n)
-                    Z = _bits(lo, hi, 2 * n * h + n, n)
-                    r[:, s] = np.minimum(np.maximum(R, U64(1)), U64(p - 1))
-                    z[:, s] = Z % U64(p)
+        for v in range(2 * n):
+            off = n * v                                   # the field's first bit in the stream
+            k, sh = off // 32, off % 32
+            pair = w[:, k] | (w[:, k + 1] << U64(32))     # bits [32k, 32k + 64); the field ends below 32k + 64
+            f = (pair >> U64(sh)) & U64((1 << n) - 1)
+            if v % 2 == 0:
+                r[:, v // 2] = np.minimum(np.maximum(f, U64(1)), U64(p - 1))
+            else:
+                z[:, v // 2] = f % U64(p)
+        if p >= (1 << 32):                                # Python integers, as for the 64-bit words below
+            return r.astype(object), z.astype(object)
         return r, z
     if p < (1 << 32):
         w = _words(seed01, nonce, g, TAG_MASK, 2 * n)

@@ -29,10 +29,10 @@ def test_shuffle_blocks_hold_the_permutation(bench, n):
 
 
 def test_op_model(bench):
-    # the headline's N = 19 DReLU: 9 Philox blocks (1 for the shuffle, 7 for the
-    # masks at three slots a block, 1 for rho), 19 slots and 19 digits, the tail
-    assert bench.alg_ops_per_elem("drelu", 18) == 9 * 60 + 19 * (40 + 6) + 12
-    # N = 8 (two slots a block) and N = 33 (one): 1 + 4 + 1 and 3 + 33 + 1 blocks
+    # the headline's N = 19 DReLU: 8 Philox blocks (1 for the shuffle, 6 for the
+    # 38 mask fields of 19 bits, 1 for rho), 19 slots and 19 digits, the tail
+    assert bench.alg_ops_per_elem("drelu", 18) == 8 * 60 + 19 * (40 + 6) + 12
+    # N = 8 (two slots a block) and N = 33 (66 fields of 33 bits): 1 + 4 + 1 and 3 + 18 + 1 blocks
     assert bench.alg_ops_per_elem("drelu", 7) == 6 * 60 + 8 * (40 + 6) + 12
-    assert bench.alg_ops_per_elem("drelu", 32) == 37 * 60 + 33 * (64 + 6) + 12
-    assert [bench.mask_blocks(n) for n in (16, 17, 21, 22, 33)] == [8, 6, 7, 11, 33]
+    assert bench.alg_ops_per_elem("drelu", 32) == 22 * 60 + 33 * (64 + 6) + 12
+    assert [bench.mask_blocks(n) for n in (16, 17, 19, 21, 22, 33)] == [8, 5, 6, 7, 8, 18]

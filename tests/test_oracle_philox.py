@@ -199,39 +199,46 @@ def _tv(counts, m, total):
     return num / (2 * total * m)
 
 
-def test_packed_masks_only_where_the_layout_says():
-    """Three slots per block for the default prime at N = 17..21 only; an
-    explicit prime, or N outside that range, keeps the 32-bit words."""
+def test_stream_masks_only_where_the_layout_says():
+    """N-bit fields of the mask stream for the default prime at N >= 17 only;
+    an explicit prime, or N below 17, keeps the 32-bit words (64-bit words
+    above 2^32).  Blocks per element: ceil(2 N^2 / 128) for the stream."""
     for lx in range(1, 33):
         n = lx + 1
-        assert philox.packed_masks(n, default_prime(lx)) == (17 <= n <= 21), n
-    assert not philox.packed_masks(19, 524269)                    # a prime below 2^19 - 1, not the default
+        assert philox.stream_masks(n, default_prime(lx)) == (n >= 17), n
+    assert not philox.stream_masks(19, 524269)                    # a prime below 2^19 - 1, not the default
+    assert [philox.mask_blocks(n, default_prime(n - 1)) for n in (8, 16, 17, 19, 22, 32, 33)] == \
+        [4, 8, 5, 6, 8, 16, 18]
+    assert philox.mask_blocks(19, 524269) == 10 and philox.mask_blocks(33, 8589934487) == 33
 
 
-def test_packed_mask_fields_read_as_bit_strings():
-    """The fields R, Z of every slot, read from the block's 128 bits as a
-    string of characters (bit i at index i), against draw_masks: pins the
-    block of each slot, the offsets 2Nh and 2Nh + N and the clamp / mod."""
+def test_stream_mask_fields_read_as_bit_strings():
+    """The fields R, Z of every slot, read from the stream as a string of
+    characters (bit i of the stream at index i, the blocks in order), against
+    draw_masks: pins the offsets N v, the fields that straddle words and
+    blocks, and the clamp / mod."""
     g = np.array([0, 1, 77, (1 << 33) + 5, (1 << 47) + 123], dtype=U)
-    for lx in (16, 17, 18, 19, 20):
+    for lx in (16, 17, 18, 19, 20, 21, 24, 27, 31, 32):
         n, p = lx + 1, default_prime(lx)
         r, z = philox.draw_masks(0x1234567890ABCDEF, 0x55, g, n, p)
+        nb = -(-2 * n * n // 128)
         for e in range(g.size):
+            bits = ""
+            for b in range(nb):
+                w = philox.block(0x1234567890ABCDEF, 0x55, g[e:e + 1], philox.TAG_MASK, b)
+                bits += "".join(format(int(x[0]), "032b")[::-1] for x in w)   # bit i of the stream at index i
             for s in range(n):
-                w = philox.block(0x1234567890ABCDEF, 0x55, g[e:e + 1], philox.TAG_MASK, s // 3)
-                bits = "".join(format(int(x[0]), "032b")[::-1] for x in w)   # bit i of the block at index i
-                h = s % 3
-                R = int(bits[2 * n * h:2 * n * h + n][::-1], 2)
-                Z = int(bits[2 * n * h + n:2 * n * h + 2 * n][::-1], 2)
+                R = int(bits[2 * n * s:2 * n * s + n][::-1], 2)
+                Z = int(bits[2 * n * s + n:2 * n * s + 2 * n][::-1], 2)
                 assert int(r[e, s]) == min(max(R, 1), p - 1), (n, e, s)
                 assert int(z[e, s]) == Z % p, (n, e, s)
 
 
 def test_unpacked_masks_are_the_multiply_shift_of_words():
-    """An explicit prime at N = 19 and the default primes at N = 16 and 22 keep
-    the 32-bit words of block s // 2 (computed here with Python integers)."""
+    """An explicit prime at N = 19 and the default prime at N = 16 keep the
+    32-bit words of block s // 2 (computed here with Python integers)."""
     g = np.array([3, 99999], dtype=U)
-    for n, p in ((19, 524269), (16, default_prime(15)), (22, default_prime(21))):
+    for n, p in ((19, 524269), (16, default_prime(15))):
         r, z = philox.draw_masks(7, 8, g, n, p)
         for e in range(g.size):
             for s in range(n):
@@ -240,12 +247,26 @@ def test_unpacked_masks_are_the_multiply_shift_of_words():
                 assert int(r[e, s]) == 1 + (R * (p - 1) >> 32) and int(z[e, s]) == (Z * p) >> 32
 
 
-def test_packed_mask_bias_exhaustive():
-    """Over every N-bit field value, r = clamp(R, 1, p - 1) covers Z_p^* with
-    1 taking 2 values, p - 1 taking c + 1 and every other value one, and
-    z = Z mod p covers Z_p with 0..c-1 taking 2; the resulting distance from
-    uniform is at most 2^-15.4 and within a factor 2 of the 32-bit
-    multiply-shift's (computed exactly from its preimage counts)."""
+def _field_tv(n, p):
+    """Exact distance from uniform of r = clamp(R, 1, p - 1) and z = Z mod p
+    over the 2^N field values R, Z: r has 1 taking 2 values, p - 1 taking
+    c + 1 and the rest one; z has 0..c-1 taking 2 and the rest one."""
+    c, tot = (1 << n) - p, 1 << n
+    m = p - 1
+    num_r = abs(2 * m - tot) + abs((c + 1) * m - tot) + (m - 2) * abs(m - tot)
+    num_z = c * abs(2 * p - tot) + (p - c) * abs(p - tot)
+    return num_r / (2 * tot * m), num_z / (2 * tot * p)
+
+
+def test_stream_mask_bias_exhaustive():
+    """Over every N-bit field value (N <= 21), the clamp and the reduction
+    give the preimage counts the closed form assumes; the closed form then
+    bounds the distance from uniform by 2^-15.4 at every N >= 17, within a
+    factor 2 of the 32-bit multiply-shift's at N = 17..21 and far below it
+    above."""
+    def ms(m):                                      # the 32-bit multiply-shift: k values with q + 1 preimages
+        k = (1 << 32) % m
+        return 2 * k * (m - k) / (2 * (1 << 32) * m)
     for lx in (16, 17, 18, 19, 20):
         n, p = lx + 1, default_prime(lx)
         c = (1 << n) - p
@@ -255,29 +276,28 @@ def test_packed_mask_bias_exhaustive():
         assert cr[0] == 0 and cr[1] == 2 and cr[p - 1] == c + 1 and np.all(cr[2:p - 1] == 1)
         cz = np.bincount((R % U(p)).astype(np.int64), minlength=p)
         assert np.all(cz[:c] == 2) and np.all(cz[c:] == 1)
-        tv_r, tv_z = _tv(cr[1:], p - 1, 1 << n), _tv(cz, p, 1 << n)
-        # the 32-bit multiply-shift: k values with q + 1 preimages, the rest q,
-        # so sum |c m - 2^32| = k (m - k) + (m - k) k
-        def ms(m):
-            k = (1 << 32) % m
-            return 2 * k * (m - k) / (2 * (1 << 32) * m)
-        if 17 <= n <= 21:
+        assert (_tv(cr[1:], p - 1, 1 << n), _tv(cz, p, 1 << n)) == pytest.approx(_field_tv(n, p), rel=1e-12)
+    for lx in range(16, 33):
+        n, p = lx + 1, default_prime(lx)
+        tv_r, tv_z = _field_tv(n, p)
+        if n >= 17:
             assert tv_r <= 2 ** -15.4 and tv_z <= 2 ** -15.4, n
             assert tv_r <= 2 * ms(p - 1) and tv_z <= 2 * ms(p), n
         else:
-            assert tv_r > 2 ** 6 * ms(p - 1)                 # N = 17 is where N-bit fields stop costing bias
+            assert tv_r > 2 ** 6 * ms(p - 1)         # N = 17 is where N-bit fields stop costing bias
 
 
-def test_packed_masks_in_range_and_uniform():
+def test_stream_masks_in_range_and_uniform():
     N = 40000
-    for lx in (16, 17, 18, 19, 20):
+    for lx in (16, 17, 18, 19, 20, 24, 32):
         p = default_prime(lx)
         r, z = philox.draw_masks(11, 12, np.arange(N, dtype=U), lx + 1, p)
+        r, z = np.asarray(r, dtype=U), np.asarray(z, dtype=U)
         assert int(r.min()) >= 1 and int(r.max()) <= p - 1 and int(z.max()) <= p - 1
         # the top bits of r and z are uniform (bucketed by 2^(N - 6))
         sh = U(lx + 1 - 6)
         assert _chi2_ok(np.bincount((r.ravel() >> sh).astype(np.int64), minlength=64))
         assert _chi2_ok(np.bincount((z.ravel() >> sh).astype(np.int64), minlength=64))
-        # slots of one block are independent: (r_0, z_2) top-bit pairs uniform
+        # neighbouring fields are independent: (r_0, z_2) top-bit pairs uniform
         pair = (r[:, 0] >> U(lx + 1 - 3)) * U(8) + (z[:, 2] >> U(lx + 1 - 3))
         assert _chi2_ok(np.bincount(pair.astype(np.int64), minlength=64))
