@@ -451,6 +451,15 @@ __device__ __forceinline__ typename F::T submod(typename F::T a, typename F::T b
     return min(d, (FT)(d + f.p));
 }
 
+// Orders one wave's LDS accesses across its lanes: the lanes of a wave run
+// in lockstep and the LDS serves a wave's instructions in order, so only the
+// compiler must be kept from moving accesses across this point.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // r_s in Z_p^* and z_s in Z_p by multiply-shift of uniform 32-bit words
 // (p < 2^32): r = 1 + floor(R (p - 1) / 2^32), z = floor(Z p / 2^32).
 __device__ __forceinline__ uint32_t draw_r(uint32_t R, uint32_t p) { return 1u + __umulhi(R, p - 1u); }

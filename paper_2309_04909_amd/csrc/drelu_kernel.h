@@ -87,13 +87,17 @@ __device__ __forceinline__ typename F::T p2_least(typename F::T least, typename 
     using FT = typename F::T;
     if constexpr (F::kWrap) {
         const FT w = addmod(w0, w1, f);
-        return w < least ? w : least;
+        FT m = w < least ? w : least;
+        asm("" : "+v"(m));                          // slot by slot, as min3_in_order does
+        return m;
     } else if constexpr (sizeof(FT) == 4) {
         const FT s = w0 + w1;
         return min3_in_order(least, s, s - f.p);
     } else {
         const FT s = w0 + w1;
-        return min(least, min(s, (FT)(s - f.p)));
+        FT m = min(least, min(s, (FT)(s - f.p)));
+        asm("" : "+v"(m));                          // slot by slot, as min3_in_order does
+        return m;
     }
 }
 
@@ -248,55 +252,41 @@ __device__ __forceinline__ uint32_t shuffle_perm(const StreamAt& r01, uint32_t (
 
 // Layout of the masks r in Z_p^* and reshares z in Z_p of Alg. 7 in the
 // seed_01 stream TAG_MASK, per window count N and field:
-//  * the default prime at 17 <= N <= 21 (PACKED): three slots to a block,
-//    slot s of block s / 3 taking the N-bit fields at bits 2Nh and 2Nh + N
-//    of the block's 128 bits (h = s % 3); r = min(max(R, 1), p - 1),
-//    z = Z mod p.  The kernels keep both shifted left by SH = 32 - N, which
-//    the fields' mul_add_sh folds without a funnel shift.
+//  * the default prime at N >= 17 (STREAM): value v = 2s (r of slot s) or
+//    2s + 1 (z of slot s) is the N-bit field at bits [N v, N v + N) of the
+//    stream, whose bit i is bit i % 32 of word i / 32, word w being word
+//    w % 4 of block w / 4; r = min(max(R, 1), p - 1), z = Z mod p.  Up to
+//    N = 24 the kernels keep both shifted left by SH = 32 - N, which the
+//    fields' mul_add_sh folds without a funnel shift.
 //  * otherwise, p < 2^32: two slots to a block, words (0, 1) and (2, 3), by
 //    32-bit multiply-shift; p > 2^32: one slot per block, 64-bit words.
 template <int N, typename F>
 struct MaskDraws {
     static constexpr bool WIDE = std::is_same<typename F::T, uint64_t>::value;
-    static constexpr bool PACKED = F::kDefault && N >= 17 && 6 * N <= 128;
-    static constexpr int SPB = PACKED ? 3 : (WIDE ? 1 : 2);   // slots per block
-    static constexpr int SH = PACKED ? 32 - N : 0;            // shift of the kept r and z
+    static constexpr bool STREAM = F::kDefault && N >= 17;
+    static constexpr int SPB = WIDE ? 1 : 2;                                            // slots per block otherwise
+    static constexpr int NB = STREAM ? (2 * N * N + 127) / 128 : (N + SPB - 1) / SPB;   // blocks per element
+    static constexpr int SH = STREAM && N <= 24 ? 32 - N : 0;                           // shift of the kept r and z
 };
 
-// The N-bit field at bit O of a block's 128 bits, shifted to the top of a
-// 32-bit word (its low 32 - N bits zero).  O and N are compile-time.
-template <int N, int O>
-__device__ __forceinline__ uint32_t block_field_top(const Words4& w) {
-    constexpr int TOP = O + N;                     // the field ends below bit TOP
-    constexpr uint32_t KEEP = ~((1u << (32 - N)) - 1);
-    if constexpr (TOP <= 32) {
-        static_assert(O == 0, "only the first field ends inside word 0");
-        return w.w0 << (32 - N);
-    } else {
-        constexpr int LO = TOP - 32, K = LO / 32, S = LO % 32;   // the 32-bit window [LO, TOP)
-        const uint32_t ws[4] = {w.w0, w.w1, w.w2, w.w3};
-        if constexpr (S == 0)
-            return ws[K] & KEEP;
-        else
-            return __builtin_amdgcn_alignbit(ws[K + 1], ws[K], S) & KEEP;
-    }
+// r and z in the kept representation from the raw fields R, Z (STREAM,
+// already shifted left by SH).
+template <int N, typename F>
+__device__ __forceinline__ void stream_draws(typename F::T R, typename F::T Z, typename F::T& r,
+                                             typename F::T& z) {
+    using FT = typename F::T;
+    constexpr int SH = MaskDraws<N, F>::SH;
+    r = min(max(R, (FT)((FT)1 << SH)), (FT)((FT)(F::p - 1) << SH));    // clamp into Z_p^* (one v_med3)
+    if constexpr (SH > 0 && F::p == (1ull << N) - 1)
+        z = Z;                                      // Mersenne: Z <= p already stands for Z mod p
+    else
+        z = min(Z, (FT)(Z - ((FT)F::p << SH)));     // Z mod p (Z < 2p)
 }
 
-// Slot H's r and z of mask block w (H < SPB, compile-time), in the kept
-// representation of MaskDraws.
+// Slot H's r and z of mask block w without STREAM (H < SPB, compile-time).
 template <int N, typename F, int H>
 __device__ __forceinline__ void block_draws(const Words4& w, const F& f, typename F::T& r, typename F::T& z) {
-    using D = MaskDraws<N, F>;
-    if constexpr (D::PACKED) {
-        constexpr int SH = D::SH;
-        const uint32_t R = block_field_top<N, 2 * N * H>(w);
-        const uint32_t Z = block_field_top<N, 2 * N * H + N>(w);
-        r = min(max(R, 1u << SH), (F::p - 1) << SH);   // clamp into Z_p^* (one v_med3)
-        if constexpr (F::p == (1u << N) - 1)
-            z = Z;                                  // Mersenne: Z <= p already stands for Z mod p
-        else
-            z = min(Z, Z - (F::p << SH));           // Z mod p (Z < 2p)
-    } else if constexpr (D::WIDE) {
+    if constexpr (MaskDraws<N, F>::WIDE) {
         r = 1 + __umul64hi(join64(w.w0, w.w1), f.p - 1);
         z = __umul64hi(join64(w.w2, w.w3), f.p);
     } else {
@@ -305,28 +295,84 @@ __device__ __forceinline__ void block_draws(const Words4& w, const F& f, typenam
     }
 }
 
-// block_draws for a slot index h of the block that is constant after
-// unrolling (the branches not taken fold away).
+// The masks of one element slot after slot (j compile-time after unrolling):
+// with STREAM the block holding a field's last bit is fetched when the
+// previous field ended in an earlier block, and that block's last word kept
+// for a field that straddles the two (a field spans at most two words);
+// otherwise block j / SPB is fetched at its first slot.  Every decision
+// depends on j alone, so it folds away once the slot loop is unrolled.
 template <int N, typename F>
-__device__ __forceinline__ void block_draws_at(const Words4& w, int h, const F& f, typename F::T& r,
-                                               typename F::T& z) {
-    constexpr int SPB = MaskDraws<N, F>::SPB;
-    if (h == 0)
-        block_draws<N, F, 0>(w, f, r, z);
-    else if (h == 1)
-        block_draws<N, F, (SPB > 1 ? 1 : 0)>(w, f, r, z);
-    else
-        block_draws<N, F, (SPB > 2 ? 2 : 0)>(w, f, r, z);
-}
+struct MaskReader {
+    using FT = typename F::T;
+    using D = MaskDraws<N, F>;
+    Words4 cur = {0, 0, 0, 0};
+    uint32_t prev = 0;     // the last word of the block before cur
 
-// Slot j's r and z (j compile-time after unrolling): block j / SPB, fetched
-// into wm at the block's first slot and kept there for the rest.
+    // Word w of the stream, with block b current (w >= 4 b - 1).
+    __device__ __forceinline__ uint32_t word(int w, int b) const {
+        const int q = w - 4 * b;
+        return q < 0 ? prev : q == 0 ? cur.w0 : q == 1 ? cur.w1 : q == 2 ? cur.w2 : cur.w3;
+    }
+    // The raw field of value v (shifted left by SH).
+    __device__ __forceinline__ FT field(const StreamAt& r01, int v) {
+        const int o = N * v;
+        const int b = (o + N - 1) / 128;                    // the block of the field's last bit
+        if (o == 0 || (o - 1) / 128 != b) {                 // the previous field ended in an earlier block
+            prev = cur.w3;
+            cur = r01.block(TAG_MASK, (uint32_t)b);
+        }
+        if constexpr (D::SH > 0) {
+            constexpr uint32_t KEEP = ~((1u << D::SH) - 1);
+            const int lo = o + N - 32;              // the field is the top of the word [lo, lo + 32)
+            if (lo < 0) return word(0, b) << D::SH;
+            const int k = lo / 32, s = lo % 32;
+            if (s == 0) return word(k, b) & KEEP;
+            return __builtin_amdgcn_alignbit(word(k + 1, b), word(k, b), s) & KEEP;
+        } else if constexpr (D::WIDE) {
+            const int k = o / 32, s = o % 32;       // 33 bits: always two words
+            return (join64(word(k, b), word(k + 1, b)) >> s) & ((1ull << N) - 1);
+        } else {
+            const int k = o / 32, s = o % 32;
+            constexpr uint32_t M = N >= 32 ? ~0u : (1u << N) - 1;
+            if (s + N <= 32) return (word(k, b) >> s) & M;
+            return __builtin_amdgcn_alignbit(word(k + 1, b), word(k, b), s) & M;
+        }
+    }
+    __device__ __forceinline__ void slot(const StreamAt& r01, int j, const F& f, FT& r, FT& z) {
+        if constexpr (D::STREAM) {
+            const FT R = field(r01, 2 * j);
+            const FT Z = field(r01, 2 * j + 1);
+            stream_draws<N, F>(R, Z, r, z);
+        } else {
+            constexpr int SPB = D::SPB;
+            if (j % SPB == 0) cur = r01.block(TAG_MASK, (uint32_t)(j / SPB));
+            if (j % SPB == 0)
+                block_draws<N, F, 0>(cur, f, r, z);
+            else
+                block_draws<N, F, (SPB > 1 ? 1 : 0)>(cur, f, r, z);
+        }
+    }
+};
+
+// The raw field of value v (STREAM) from a group's words in LDS: W[-1] and
+// W[4 NB] are zero, so every read stays inside the array.
 template <int N, typename F>
-__device__ __forceinline__ void slot_draws(const StreamAt& r01, int j, Words4& wm, const F& f, typename F::T& r,
-                                           typename F::T& z) {
-    constexpr int SPB = MaskDraws<N, F>::SPB;
-    if (j % SPB == 0) wm = r01.block(TAG_MASK, (uint32_t)(j / SPB));
-    block_draws_at<N, F>(wm, j % SPB, f, r, z);
+__device__ __forceinline__ typename F::T stream_field_at(const uint32_t* W, uint32_t v) {
+    using D = MaskDraws<N, F>;
+    const int o = N * (int)v;
+    if constexpr (D::SH > 0) {
+        constexpr uint32_t KEEP = ~((1u << D::SH) - 1);
+        const int lo = o + N - 32;                  // > -32
+        const int k = ((lo + 32) >> 5) - 1;         // floor(lo / 32): -1 for v = 0
+        return __builtin_amdgcn_alignbit(W[k + 1], W[k], (uint32_t)lo & 31u) & KEEP;
+    } else if constexpr (D::WIDE) {
+        const int k = o >> 5;
+        return (join64(W[k], W[k + 1]) >> (o & 31)) & ((1ull << N) - 1);
+    } else {
+        const int k = o >> 5;
+        constexpr uint32_t M = N >= 32 ? ~0u : (1u << N) - 1;
+        return __builtin_amdgcn_alignbit(W[k + 1], W[k], (uint32_t)o & 31u) & M;
+    }
 }
 
 // Plain canonical values of kept draws (the record of the precomputed mode).
@@ -365,12 +411,12 @@ __device__ __forceinline__ T drelu_round1(T in0, T in1, uint64_t g, T mask, uint
     const T a0k = a0 >> k_lo, nb1k = nb1 >> k_lo;         // common low cut of every window
 
     FT least = f.p;                                        // P2: min over slots of w0 + w1 mod p
-    Words4 wm = {0, 0, 0, 0};
+    MaskReader<N, F> masks;
 #pragma unroll
     for (int j = 0; j < N; ++j) {
         // Mask r and reshare z of slot j.
         FT r, z;
-        slot_draws<N, F>(r01, j, wm, f, r, z);
+        masks.slot(r01, j, f, r, z);
         FT w0, w1;
         slot_messages<T, N, F, MaskDraws<N, F>::SH>(a0k, nb1k, shuffle_pos(A, j), r, z, f, w0, w1, least);
         if constexpr (CAP) {
@@ -436,20 +482,24 @@ __global__ BC_KERNEL_ATTRS void k_drelu(DreluKArgs A, F f_arg) {
 
 // Lane groups for small calls: G consecutive lanes share one element, so a
 // call of n elements still runs n * G threads.  Every lane of the group runs
-// the whole shuffle in its own LDS slice, lane l takes mask
-// block kG + l in round k (its two slots, or one slot when l_x = 32), and the
-// group's P2 minimum is combined by lane shuffles; lane 0 finishes and writes.
-// Results are those of drelu_element: same draws, same slots, same messages.
+// the whole shuffle in its own LDS slice.  Without STREAM lane l takes mask
+// block kG + l in round k and its slots (two, or one when l_x = 32); with
+// STREAM the lanes draw the blocks the same way into the group's words in
+// LDS and lane l then takes slots kG + l, reading its fields from there.
+// The group's P2 minimum is combined by lane shuffles; lane 0 finishes and
+// writes.  Results are those of drelu_element: same draws, same slots, same
+// messages.
 template <typename T, int N, typename F, bool RELU, int G>
 __device__ __forceinline__ void drelu_element_group(const T* __restrict__ X0, const T* __restrict__ X1, T* Y0, T* Y1,
                                                     uint64_t e, uint64_t g, uint32_t lane, T mask, T in_mask,
                                                     uint32_t k_in, uint32_t k_lo, const Stream& s01,
                                                     const Stream& s02, const Stream& s12, const F& f) {
     using FT = typename F::T;
-    constexpr bool WIDE = MaskDraws<N, F>::WIDE;
-    constexpr int SPB = MaskDraws<N, F>::SPB;               // slots per mask block
-    constexpr int SH = MaskDraws<N, F>::SH;
-    constexpr int NB = (N + SPB - 1) / SPB;                 // mask blocks
+    using D = MaskDraws<N, F>;
+    constexpr bool WIDE = D::WIDE;
+    constexpr int SPB = D::SPB;                             // slots per mask block without STREAM
+    constexpr int SH = D::SH;
+    constexpr int NB = D::NB;                               // mask blocks
     constexpr int ROUNDS = (NB + G - 1) / G;
 
     const T r0 = X0[e] & in_mask;
@@ -468,20 +518,58 @@ __device__ __forceinline__ void drelu_element_group(const T* __restrict__ X0, co
     const T a0k = a0 >> k_lo, nb1k = nb1 >> k_lo;
 
     FT least = f.p;
+    if constexpr (D::STREAM) {
+        // The group's 4 NB stream words, with a zero word on either side.
+        constexpr int STRIDE = 4 * NB + 2;
+        __shared__ uint32_t mw[(256 / G) * STRIDE];
+        uint32_t* W = mw + (threadIdx.x / G) * STRIDE + 1;
+        if (lane == 0) {
+            W[-1] = 0;
+            W[4 * NB] = 0;
+        }
 #pragma unroll
-    for (int k = 0; k < ROUNDS; ++k) {
-        const uint32_t blk = (uint32_t)(k * G) + lane;      // this lane's mask block
-        const Words4 w = r01.block(TAG_MASK, blk);
+        for (int k = 0; k < ROUNDS; ++k) {
+            const uint32_t blk = (uint32_t)(k * G) + lane;
+            if (blk < (uint32_t)NB) {
+                const Words4 w = r01.block(TAG_MASK, blk);
+                W[4 * blk] = w.w0;
+                W[4 * blk + 1] = w.w1;
+                W[4 * blk + 2] = w.w2;
+                W[4 * blk + 3] = w.w3;
+            }
+        }
+        wave_sync();                                        // the group's words before its reads
 #pragma unroll
-        for (int h = 0; h < SPB; ++h) {
-            // slot j = SPB * blk + h (past the last slot: any slot, its message is not counted)
-            const bool valid = SPB * blk + h < (uint32_t)N;
-            const uint32_t pos = shuffle_pos(A, valid ? SPB * blk + h : 0u);
+        for (int k = 0; k < (N + G - 1) / G; ++k) {
+            const uint32_t j = (uint32_t)(k * G) + lane;
+            const bool valid = j < (uint32_t)N;
+            const uint32_t js = valid ? j : 0u;             // past the last slot: any slot, not counted
             FT r, z;
-            block_draws_at<N, F>(w, h, f, r, z);
+            stream_draws<N, F>(stream_field_at<N, F>(W, 2 * js), stream_field_at<N, F>(W, 2 * js + 1), r, z);
             FT w0, w1, v = f.p;
-            slot_messages<T, N, F, SH>(a0k, nb1k, pos, r, z, f, w0, w1, v);
+            slot_messages<T, N, F, SH>(a0k, nb1k, shuffle_pos(A, js), r, z, f, w0, w1, v);
             least = (valid && v < least) ? v : least;
+        }
+        wave_sync();                                        // every read before the next element's words
+    } else {
+#pragma unroll
+        for (int k = 0; k < ROUNDS; ++k) {
+            const uint32_t blk = (uint32_t)(k * G) + lane;  // this lane's mask block
+            const Words4 w = r01.block(TAG_MASK, blk);
+#pragma unroll
+            for (int h = 0; h < SPB; ++h) {
+                // slot j = SPB * blk + h (past the last slot: any slot, its message is not counted)
+                const bool valid = SPB * blk + h < (uint32_t)N;
+                const uint32_t pos = shuffle_pos(A, valid ? SPB * blk + h : 0u);
+                FT r, z;
+                if (h == 0)
+                    block_draws<N, F, 0>(w, f, r, z);
+                else
+                    block_draws<N, F, (SPB > 1 ? 1 : 0)>(w, f, r, z);
+                FT w0, w1, v = f.p;
+                slot_messages<T, N, F, SH>(a0k, nb1k, pos, r, z, f, w0, w1, v);
+                least = (valid && v < least) ? v : least;
+            }
         }
     }
 #pragma unroll

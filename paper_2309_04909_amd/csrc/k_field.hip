@@ -1,7 +1,7 @@
 // Diagnostic: the Z_p multiply-add of the DReLU/ReLU kernels (the field that
 // with_field picks for l_x and p, in the operand representation the kernels
-// keep their masks in: shifted to the top of the word where the draws are
-// packed, see MaskDraws), applied elementwise to arrays, so the arithmetic
+// keep their masks in: shifted to the top of the word for the stream draws
+// up to N = 24, see MaskDraws), applied elementwise to arrays, so the arithmetic
 // can be checked against exact integers at its bounds.
 #include "drelu_kernel.h"
 

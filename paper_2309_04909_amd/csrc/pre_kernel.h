@@ -74,14 +74,14 @@ __global__ BC_KERNEL_ATTRS void k_expand(ExpandKArgs A, F f) {
         const uint32_t t = shuffle_perm<N>(r01, perm);
 #pragma unroll
         for (int k = 0; k < (N + 3) / 4; ++k) A.perm[(uint64_t)k * n + e] = k == 0 ? perm[0] | t << 7 : perm[k];
-        Words4 wm = {0, 0, 0, 0};
+        MaskReader<N, F> masks;
         uint64_t* rz = static_cast<uint64_t*>(A.rz);
         constexpr int K = RzLayout<N>::K;
         uint64_t acc = 0;                                  // the word being filled
 #pragma unroll
         for (int j = 0; j < N; ++j) {
             typename F::T r, z;
-            slot_draws<N, F>(r01, j, wm, f, r, z);
+            masks.slot(r01, j, f, r, z);
             plain_draws<N, F>(f, r, z);                   // the record keeps plain values
 #pragma unroll
             for (int h = 0; h < 2; ++h) {

@@ -92,11 +92,11 @@ __global__ BC_KERNEL_ATTRS void k_send(SplitKArgs A, F f_arg) {
         uint32_t words[W];
 #pragma unroll
         for (int k = 0; k < W; ++k) words[k] = 0;
-        Words4 wm = {0, 0, 0, 0};
+        MaskReader<N, F> masks;
 #pragma unroll
         for (int j = 0; j < N; ++j) {
             FT r, z;
-            slot_draws<N, F>(r01, j, wm, f, r, z);
+            masks.slot(r01, j, f, r, z);
             pack_slot<N>(words, j, (uint64_t)party_message<T, N, F, PARTY>(ak, shuffle_pos(sig, j), r, z, f));
         }
 #pragma unroll
