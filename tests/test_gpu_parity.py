@@ -330,12 +330,15 @@ def test_fused_trunc_rejects_mismatched_rings(B):
 
 
 @pytest.mark.parametrize("ell,lx,k_lo", [(64, 18, 13), (64, 32, 0), (64, 31, 0), (64, 7, 11), (51, 11, 13),
-                                         (32, 8, 8), (24, 7, 10), (64, 2, 5)])
+                                         (32, 8, 8), (24, 7, 10), (64, 2, 5), (64, 16, 13), (64, 21, 13),
+                                         (64, 23, 13), (64, 24, 13), (64, 27, 5)])
 def test_lane_groups_agree_with_one_lane(B, ell, lx, k_lo):
     """Small calls spread each element over 4 or 8 lanes (mask blocks split
-    among the lanes, P2's minimum combined by lane shuffles).  Forcing each
-    group size through the schedule table gives identical outputs, also for
-    fused truncation and element indices across 2^32."""
+    among the lanes, or for the mask bit stream drawn by the lanes into LDS
+    and read back per slot; P2's minimum combined by lane shuffles).  Forcing
+    each group size through the schedule table gives identical outputs, for
+    the stream's shifted (N = 17..24), 32-bit (N = 25..32) and 64-bit (N = 33)
+    fields alike, and for element indices across 2^32."""
     rng = np.random.default_rng(ell + 100 * lx + k_lo)
     prm = B.Params(ell, lx, k_lo)
     w = B.ring_width(ell)
