@@ -48,25 +48,58 @@ def _records(params: B.Params, segments):
 
 class RaggedBatch:
     def __init__(self, params: B.Params, seeds: B.Seeds, segments, tile_elems: int = 0, grid: int = 0):
+        self.segments = list(segments)
+        self._build(params, seeds, _records(params, self.segments), len(self.segments),
+                    self.segments[0].x0.device, sum(s.x0.numel() for s in self.segments), tile_elems, grid)
+
+    @classmethod
+    def from_records(cls, params: B.Params, seeds: B.Seeds, records, device, elements: int, tile_elems: int = 0,
+                     grid: int = 0, host_plan: torch.Tensor = None, dev_plan: torch.Tensor = None):
+        """A batch from a ready array of bicop._Segment records (raw device
+        pointers of contiguous share arrays of the ring's width on `device`,
+        which the caller vouches for; the C ABI still checks every record).
+        Serving builds its launches this way, without a tensor per segment,
+        and passes buffers of its own to build the plan in: a pinned byte
+        buffer and a device byte buffer of at least plan_bytes(n) bytes, which
+        must outlive the run (a device allocation can wait for the whole
+        device, so a loop that overlaps launches makes none per launch)."""
+        self = cls.__new__(cls)
+        self.segments = []
+        self._build(params, seeds, records, len(records), device, elements, tile_elems, grid, host_plan, dev_plan)
+        return self
+
+    @staticmethod
+    def plan_bytes(nseg: int) -> int:
+        return int(B.lib.bc_batch_plan_bytes(nseg))
+
+    def _build(self, params, seeds, recs, nseg, device, elements, tile_elems, grid, host_plan=None, dev_plan=None):
         self.params = params
         self.seeds = seeds
-        self.segments = list(segments)
         if tile_elems == 0:                          # autotuned tile size, else the library default
             tile_elems = int(B.SCHEDULES.get("batch_tile", 0))
         self.grid = grid
-        nseg = len(self.segments)
-        recs = _records(params, self.segments)
-        nbytes = int(B.lib.bc_batch_plan_bytes(nseg))
+        self.device = device
+        nbytes = self.plan_bytes(nseg)
         # The plan is built in pinned host memory and uploaded asynchronously
         # on the current stream (runs on that stream, or on streams ordered
         # after it, see it); the host copy stays alive with this object.
-        self.host_plan = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+        if host_plan is not None:
+            if not host_plan.is_pinned() or host_plan.dtype != torch.uint8 or host_plan.numel() < nbytes:
+                raise ValueError("host_plan must be a pinned uint8 buffer of at least plan_bytes(n) bytes")
+            self.host_plan = host_plan[:nbytes]
+        else:
+            self.host_plan = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
         B._check(B.lib.bc_batch_plan(recs, nseg, ctypes.byref(params.c()), tile_elems, self.host_plan.data_ptr(),
                                      nbytes), "batch_plan")
-        dev = self.segments[0].x0.device
-        self.dev_plan = self.host_plan.to(dev, non_blocking=True)
+        if dev_plan is not None:
+            if dev_plan.dtype != torch.uint8 or dev_plan.device != torch.device(device) or dev_plan.numel() < nbytes:
+                raise ValueError("dev_plan must be a uint8 buffer on the batch's device of at least plan_bytes(n) bytes")
+            self.dev_plan = dev_plan[:nbytes]
+            self.dev_plan.copy_(self.host_plan, non_blocking=True)
+        else:
+            self.dev_plan = self.host_plan.to(device, non_blocking=True)
         self._c_seeds = seeds.c()
-        self.elements = sum(s.x0.numel() for s in self.segments)
+        self.elements = elements
 
     def run(self, stream=None):
         """Enqueue the one persistent launch on `stream` (default: current)."""
@@ -79,7 +112,7 @@ class RaggedBatch:
         nothing is allocated.  Calls that overlap on one GPU race for that
         area; calls on one stream are ordered."""
         B._check(B.lib.bc_batch_run_static(self.host_plan.data_ptr(), ctypes.byref(self._c_seeds), self.grid,
-                                           B._stream(stream, self.segments[0].x0)), "batch_run_static")
+                                           B._stream(stream, self.dev_plan)), "batch_run_static")
 
     def capture(self):
         """Capture run() into a CUDA/HIP graph; returns the torch.cuda.CUDAGraph.

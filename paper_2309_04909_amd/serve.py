@@ -30,6 +30,7 @@ ring, or bc_drelu_pre / bc_relu_pre when alone), with the same results; a
 record is released when its launch has completed.
 """
 
+import ctypes
 import time
 from collections import deque
 from dataclasses import dataclass, field
@@ -55,6 +56,7 @@ class Job:
     admitted: float = None
     rand: torch.Tensor = None   # resident randomness record (prepare), or None
     k_in: int = 0               # truncate the input shares by k_in bits first (a layer chain's step)
+    out: tuple = None           # (y0, y1, first element) of its launch's output buffers while in flight
 
 
 @dataclass
@@ -63,26 +65,52 @@ class Launch:
     jobs: list
     batches: list = field(default_factory=list)
     records: list = field(default_factory=list)   # kept alive until the launch has completed
+    outputs: list = field(default_factory=list)   # the launch's output buffers, one pair per ring
+    pinned: list = field(default_factory=list)    # its (pinned, device) plan buffers, reused once it has completed
+    arena: list = field(default_factory=list)     # start offsets of its output ranges in the arena
     bytes: int = 0
 
 
 class Server:
     def __init__(self, pools, params, seeds: B.Seeds, hbm_budget: int, max_slots: int = 256, nstreams: int = 4,
-                 keep_outputs: bool = False, rand_budget: int = 0):
+                 keep_outputs: bool = False, rand_budget: int = 0, on_done=None, max_batch: int = 0):
         """pools[ell] = (x0, x1) device share pools; params[ell] = B.Params of that ring;
-        rand_budget = HBM bytes for resident randomness records (0 = none)."""
+        rand_budget = HBM bytes for resident randomness records (0 = none).
+        max_batch = jobs per launch (default max_slots / nstreams, so that
+        several launches are in flight and a retiring one frees slots for the
+        next while the others still run).
+        With keep_outputs every job keeps its own output tensors (job.y0,
+        job.y1); otherwise outputs live in an arena and are released when the
+        job's launch has completed, after on_done(job, y0, y1) (if given) has
+        returned: the callback must have finished reading them by then (copy
+        to the host, or clone and synchronize)."""
+        self.on_done = on_done
         self.rand_budget = rand_budget
         self.pools = pools
         self.params = params
         self.seeds = seeds
         self.budget = hbm_budget
         self.max_slots = max_slots
+        self.max_batch = max_batch if max_batch > 0 else max(1, max_slots // nstreams)
         self.streams = [torch.cuda.Stream() for _ in range(nstreams)]
         self.keep = keep_outputs
+        self._events = []                            # completion events of retired launches, reused
+        self._pinned = []                            # (pinned, device) plan buffers of retired launches, reused
+        self._arena = None                           # output arena (half the budget), without keep_outputs
+        self._arena_used = []                        # its ranges in flight: sorted (start, end) byte offsets
 
     def warmup(self):
         """One small call per ring, op and lane-group size, so that no job pays
-        for loading a kernel's code object on its first launch."""
+        for loading a kernel's code object on its first launch; the output
+        arena and the pinned plan buffers allocated up front, so that no launch
+        waits for an allocation."""
+        if not self.keep:
+            self._make_arena(next(iter(self.pools.values()))[0].device)
+        need = BT.RaggedBatch.plan_bytes(self.max_slots)
+        dev = next(iter(self.pools.values()))[0].device
+        while len(self._pinned) < 2 * len(self.streams):        # a plan per ring and stream
+            self._pinned.append((torch.empty(need, dtype=torch.uint8, pin_memory=True),
+                                 torch.empty(need, dtype=torch.uint8, device=dev)))
         for ell, (x0, x1) in self.pools.items():
             prm = self.params[ell]
             for fn in (B.drelu, B.relu):
@@ -122,50 +150,134 @@ class Server:
     def job_bytes(self, j: Job) -> int:
         return 4 * j.n * B.ring_width(j.ell)           # resident input shares + output shares
 
+    def _check_slice(self, j: Job):
+        x0 = self.pools[j.ell][0]
+        if j.n < 1 or j.offset < 0 or j.offset + j.n > x0.numel():
+            raise ValueError(f"job {j.jid}: elements [{j.offset}, {j.offset + j.n}) outside the pool of ring {j.ell}")
+
     def _launch(self, jobs, stream):
-        ev = torch.cuda.Event(enable_timing=True)
+        """One launch for the admitted jobs: per ring, one pair of output
+        buffers and one ragged batch built straight from raw segment records
+        (pointers into the ring's pool and the output buffers), or the plain
+        call for a ring with a single job."""
+        ev = self._events.pop() if self._events else torch.cuda.Event(enable_timing=True)
         L = Launch(ev, jobs)
+        m = (1 << 64) - 1
         with torch.cuda.stream(stream):
             by_ell = {}
             for j in jobs:
-                x0, x1 = self.pools[j.ell]
-                j.y0 = torch.empty(j.n, dtype=x0.dtype, device=x0.device)
-                j.y1 = torch.empty(j.n, dtype=x1.dtype, device=x1.device)
                 L.bytes += self.job_bytes(j)
-                seg = BT.Segment(x0[j.offset:j.offset + j.n], x1[j.offset:j.offset + j.n], j.y0, j.y1, op=j.op,
-                                 nonce=j.nonce, elem_base=0, k_in=j.k_in, rand=j.rand)
-                if j.rand is not None:               # released with the launch, once it has completed
-                    L.records.append(j.rand)
-                    j.rand = None
-                by_ell.setdefault(j.ell, []).append(seg)
-            for ell, segs in by_ell.items():
+                by_ell.setdefault(j.ell, []).append(j)
+            for ell, js in by_ell.items():
+                x0, x1 = self.pools[ell]
                 prm = self.params[ell]
-                if len(segs) == 1 and not (segs[0].rand is not None and segs[0].k_in):
-                    self._single(segs[0], prm, stream)       # one job: the plain call needs no plan
+                w = x0.element_size()
+                total = sum(j.n for j in js)
+                y0, y1 = self._outputs(total, x0, stream, L)
+                L.outputs.append((y0, y1))
+                if len(js) == 1 and not (js[0].rand is not None and js[0].k_in):
+                    j = js[0]                            # one job: the plain call needs no plan
+                    j.out = (y0, y1, 0)
+                    self._single(j, prm, x0[j.offset:j.offset + j.n], x1[j.offset:j.offset + j.n], y0, y1, stream)
+                    if j.rand is not None:
+                        L.records.append(j.rand)
+                        j.rand = None
                     continue
-                rb = BT.RaggedBatch(prm, self.seeds, segs)
+                recs = (B._Segment * len(js))()
+                p0, p1, q0, q1 = x0.data_ptr(), x1.data_ptr(), y0.data_ptr(), y1.data_ptr()
+                off = 0
+                for i, j in enumerate(js):
+                    rp = rd = None
+                    if j.rand is not None:               # released with the launch, once it has completed
+                        rp, rd = j.rand.data_ptr(), ctypes.pointer(B.rand_desc(j.rand))
+                        L.records.append(j.rand)
+                        j.rand = None
+                    recs[i] = B._Segment(p0 + w * j.offset, p1 + w * j.offset, q0 + w * off, q1 + w * off, j.n, 0,
+                                         j.nonce & m, j.op, j.k_in, rp, rd)
+                    j.out = (y0, y1, off)
+                    off += j.n
+                hp, dp = self._plan_buffer(len(js), x0.device)
+                L.pinned.append((hp, dp))
+                rb = BT.RaggedBatch.from_records(prm, self.seeds, recs, x0.device, total, host_plan=hp, dev_plan=dp)
                 rb.run(stream)
                 L.batches.append(rb)
             ev.record(stream)
         return L
 
-    def _single(self, sg, prm, stream):
-        out = (sg.y0, sg.y1)
-        relu = sg.op == B.BC_OP_RELU
-        if sg.rand is not None:                      # online kernel on the resident record
+    def _plan_buffer(self, nseg, device):
+        """A (pinned, device) buffer pair for a plan of nseg segments: a
+        retired launch's, or a new pair sized for max_slots segments.  Both
+        allocations are slow (a device allocation can wait for the whole
+        device), so warmup makes one pair per ring and stream up front."""
+        need = BT.RaggedBatch.plan_bytes(nseg)
+        for i, (h, _) in enumerate(self._pinned):
+            if h.numel() >= need:
+                return self._pinned.pop(i)
+        size = max(need, BT.RaggedBatch.plan_bytes(self.max_slots))
+        return (torch.empty(size, dtype=torch.uint8, pin_memory=True),
+                torch.empty(size, dtype=torch.uint8, device=device))
+
+    def _make_arena(self, device):
+        if self._arena is None:
+            self._arena = torch.empty(max(self.budget // 2, 256), dtype=torch.uint8, device=device)
+
+    def _arena_alloc(self, nbytes):
+        """First fit of nbytes (rounded to 256) among the ranges in flight, or None."""
+        nbytes = (nbytes + 255) & ~255
+        start = 0
+        for i, (a, b) in enumerate(self._arena_used):
+            if a - start >= nbytes:
+                self._arena_used.insert(i, (start, start + nbytes))
+                return start
+            start = b
+        if self._arena.numel() - start >= nbytes:
+            self._arena_used.append((start, start + nbytes))
+            return start
+        return None
+
+    def _arena_free(self, start):
+        for i, (a, _) in enumerate(self._arena_used):
+            if a == start:
+                del self._arena_used[i]
+                return
+
+    def _outputs(self, total, like, stream, L):
+        """A launch's output pair for one ring.  Without keep_outputs: a range
+        of the output arena, free again once the launch has completed (the
+        budget bounds the output bytes in flight by the arena's size; only
+        fragmentation can make it fall back).  Otherwise, or on that
+        fallback: new tensors of the launch's stream, which outlive it."""
+        w = like.element_size()
+        if not self.keep:
+            self._make_arena(like.device)
+            start = self._arena_alloc(2 * total * w)
+            if start is not None:
+                L.arena.append(start)
+                a = self._arena
+                return (a[start:start + total * w].view(like.dtype),
+                        a[start + total * w:start + 2 * total * w].view(like.dtype))
+        with torch.cuda.stream(stream):
+            return (torch.empty(total, dtype=like.dtype, device=like.device),
+                    torch.empty(total, dtype=like.dtype, device=like.device))
+
+    def _single(self, j, prm, x0, x1, y0, y1, stream):
+        out = (y0, y1)
+        relu = j.op == B.BC_OP_RELU
+        if j.rand is not None:                       # online kernel on the resident record
             fn = B.relu_pre if relu else B.drelu_pre
-            fn(sg.x0, sg.x1, prm, sg.rand, out=out, stream=stream)
-        elif sg.k_in:
+            fn(x0, x1, prm, j.rand, out=out, stream=stream)
+        elif j.k_in:
             fn = B.trunc_relu if relu else B.trunc_drelu
-            fn(sg.x0, sg.x1, prm.ell + sg.k_in, sg.k_in, prm, self._seeds(sg.nonce), elem_base=sg.elem_base, out=out,
-               stream=stream)
+            fn(x0, x1, prm.ell + j.k_in, j.k_in, prm, self._seeds(j.nonce), out=out, stream=stream)
         else:
             fn = B.relu if relu else B.drelu
-            fn(sg.x0, sg.x1, prm, self._seeds(sg.nonce), elem_base=sg.elem_base, out=out, stream=stream)
+            fn(x0, x1, prm, self._seeds(j.nonce), out=out, stream=stream)
 
     def run(self, jobs):
         """Serve `jobs` (arrival times relative to the start); returns them with
         completion times filled in."""
+        for j in jobs:
+            self._check_slice(j)
         pending = deque(sorted(jobs, key=lambda j: j.arrival))
         waiting = deque()
         inflight = []
@@ -183,18 +295,27 @@ class Server:
                     t_done = ref.elapsed_time(L.event) / 1e3
                     for j in L.jobs:
                         j.done = t_done
-                        if not self.keep:
-                            j.y0 = j.y1 = None
+                        y0, y1, off = j.out
+                        if self.keep:
+                            j.y0, j.y1 = y0[off:off + j.n], y1[off:off + j.n]
+                        if self.on_done is not None:
+                            self.on_done(j, y0[off:off + j.n], y1[off:off + j.n])
+                        j.out = None
                         finished.append(j)
                     used -= L.bytes
                     slots -= len(L.jobs)
+                    self._events.append(L.event)
+                    self._pinned.extend(L.pinned)
+                    for a in L.arena:
+                        self._arena_free(a)
                 else:
                     still.append(L)
             inflight = still
             while pending and pending[0].arrival <= now:
                 waiting.append(pending.popleft())
             admit = []
-            while waiting and slots + len(admit) < self.max_slots and len(inflight) < len(self.streams):
+            while (waiting and slots + len(admit) < self.max_slots and len(admit) < self.max_batch
+                   and len(inflight) < len(self.streams)):
                 j = waiting[0]
                 b = self.job_bytes(j)
                 if used + b > self.budget and (used > 0 or admit):

@@ -51,7 +51,10 @@ def test_results_identical_alone_and_in_the_mix():
         jobs.append(S.Job(i, t, n, 0 if op == "drelu" else 1, ell, int(rng.integers(0, pool_n - n + 1)), 7000 + i))
     # a tight budget and few slots force many small launches that overlap on 3 streams
     srv = S.Server(pools, params, B.Seeds(*seeds), hbm_budget=1 << 22, max_slots=5, nstreams=3, keep_outputs=True)
+    srv.warmup()                                            # kernels loaded, outputs reserved, plan buffers pinned
+    assert len(srv._pinned) == 2 * 3
     done = srv.run(jobs)
+    assert len(srv._pinned) >= 2 * 3                        # every launch's plan buffer came back
     assert len(done) == len(jobs) and all(j.done is not None and j.done >= j.arrival - 1e-3 for j in done)
     for j in done:
         x0, x1 = pools[j.ell]
@@ -67,6 +70,45 @@ def test_results_identical_alone_and_in_the_mix():
                            ell, lx, k_lo, default_prime(lx), seeds, j.nonce)
         assert np.array_equal(host(j.y0)[:k].astype(np.uint64), e0)
         assert np.array_equal(host(j.y1)[:k].astype(np.uint64), e1)
+
+
+def test_arena_outputs_in_the_mix():
+    """Without keep_outputs the launches write into the output arena, whose
+    ranges are reused as launches retire (a budget this small forces many
+    reuses); each job's result, copied out in the on_done callback before its
+    range is released, equals the single call on that job."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_04909_amd import bicop as B
+    from paper_2309_04909_amd import serve as S
+    pool_n = 1 << 18
+    settings = {64: (64, 18, 13), 32: (32, 8, 8)}
+    pools = {}
+    for ell in (64, 32):
+        _, (x0, x1) = W.serving_values(90 + ell, pool_n, ell)
+        pools[ell] = (dev(x0), dev(x1))
+    params = {ell: B.Params(*settings[ell]) for ell in settings}
+    seeds = (71, 72, 73)
+    rng = np.random.default_rng(5)
+    arr = W.serving_arrivals(6, 20000.0, 80, min_log2=4, max_log2=16)
+    jobs = [S.Job(i, t, n, 0 if op == "drelu" else 1, ell, int(rng.integers(0, pool_n - n + 1)), 5000 + i)
+            for i, (t, n, op, ell) in enumerate(arr)]
+    got = {}
+
+    def collect(j, y0, y1):
+        got[j.jid] = (y0.cpu(), y1.cpu())                  # a synchronous copy: done before the range is reused
+
+    srv = S.Server(pools, params, B.Seeds(*seeds), hbm_budget=1 << 22, max_slots=6, nstreams=3, on_done=collect)
+    srv.warmup()
+    assert srv._arena is not None and srv._arena.numel() == (1 << 22) // 2
+    done = srv.run(jobs)
+    assert len(done) == len(jobs) and len(got) == len(jobs) and not srv._arena_used
+    assert all(j.y0 is None and j.out is None for j in done)
+    for j in done:
+        x0, x1 = pools[j.ell]
+        fn = B.relu if j.op == B.BC_OP_RELU else B.drelu
+        a0, a1 = fn(x0[j.offset:j.offset + j.n], x1[j.offset:j.offset + j.n], params[j.ell], B.Seeds(*seeds, j.nonce))
+        assert same(a0.cpu(), got[j.jid][0]) and same(a1.cpu(), got[j.jid][1]), j.jid
 
 
 def test_precomputed_randomness_in_the_mix():
