@@ -220,6 +220,7 @@ struct FieldMersenne {
     // issue at about twice the rate with literal or VGPR operands as with an
     // SGPR operand.
     static constexpr uint32_t p = (1u << K) - 1;
+    static constexpr bool kLazy = true;       // the *_lazy forms: a value below 2p, 4p < 2^32
     __device__ __forceinline__ FieldMersenne vgpr() const { return *this; }
     __device__ __forceinline__ uint32_t mul(uint32_t a, uint32_t b) const {
         const uint64_t x = (uint64_t)a * b;
@@ -227,10 +228,14 @@ struct FieldMersenne {
         return min(s, s - p);             // s < p: s - p wraps above s
     }
     // a, b, c < p: x = a*b + c <= p^2 - p, so x >> K <= p - 2 and the fold is
-    // still below 2p; the addend rides in the multiply.
-    __device__ __forceinline__ uint32_t mul_add(uint32_t a, uint32_t b, uint32_t c) const {
+    // still below 2p; the addend rides in the multiply.  The lazy form stops
+    // before the conditional subtraction.
+    __device__ __forceinline__ uint32_t mul_add_lazy(uint32_t a, uint32_t b, uint32_t c) const {
         const uint64_t x = mad_u64_u32(a, b, c);
-        const uint32_t s = ((uint32_t)x & p) + (uint32_t)(x >> K);
+        return ((uint32_t)x & p) + (uint32_t)(x >> K);
+    }
+    __device__ __forceinline__ uint32_t mul_add(uint32_t a, uint32_t b, uint32_t c) const {
+        const uint32_t s = mul_add_lazy(a, b, c);
         return min(s, s - p);
     }
     // The same with b and c given shifted left by SH = 32 - K (b_sh = b 2^SH,
@@ -238,10 +243,14 @@ struct FieldMersenne {
     // splits at bit 32 into x >> K (high word) and (x mod 2^K) 2^SH (low
     // word), so the fold takes one shift instead of a funnel shift.
     template <int SH>
-    __device__ __forceinline__ uint32_t mul_add_sh(uint32_t a, uint32_t b_sh, uint32_t c_sh) const {
+    __device__ __forceinline__ uint32_t mul_add_sh_lazy(uint32_t a, uint32_t b_sh, uint32_t c_sh) const {
         static_assert(SH == 32 - K, "operands shifted to the top of the word");
         const uint64_t x = mad_u64_u32(a, b_sh, c_sh);
-        const uint32_t s = ((uint32_t)x >> SH) + (uint32_t)(x >> 32);
+        return ((uint32_t)x >> SH) + (uint32_t)(x >> 32);
+    }
+    template <int SH>
+    __device__ __forceinline__ uint32_t mul_add_sh(uint32_t a, uint32_t b_sh, uint32_t c_sh) const {
+        const uint32_t s = mul_add_sh_lazy<SH>(a, b_sh, c_sh);
         return min(s, s - p);
     }
 };
@@ -261,60 +270,61 @@ struct FieldPM {
     static constexpr bool kDefault = true;   // the largest prime below 2^K
     static constexpr uint32_t p = (uint32_t)((1ull << K) - CC);
     static constexpr uint32_t LOW = (uint32_t)((1ull << K) - 1);
+    static constexpr bool kLazy = K <= 30;   // the *_lazy forms: a value below 2p, 4p < 2^32
     __device__ __forceinline__ FieldPM vgpr() const { return *this; }
     __device__ __forceinline__ uint32_t mul(uint32_t a, uint32_t b) const { return mul_add(a, b, 0); }
-    __device__ __forceinline__ uint32_t mul_add(uint32_t a, uint32_t b, uint32_t d) const {
+    // Both folds, without the final conditional subtraction: below 2p (K < 32).
+    __device__ __forceinline__ uint32_t mul_add_lazy(uint32_t a, uint32_t b, uint32_t d) const {
+        static_assert(K < 32, "the 32-bit fold ends differently");
         if constexpr (K <= 12) {
             // x < p^2 < 2^24: every step in 32 bits with 24-bit multiply-adds
             const uint32_t x = __umul24(a, b) + d;
             const uint32_t t = __umul24(x >> K, CC) + (x & LOW);    // < (c + 1) 2^K
-            const uint32_t S = __umul24(t >> K, CC) + (t & LOW);    // < 2^K + c^2 < 2p
-            return min(S, S - p);
-        }
-        const uint64_t x = mad_u64_u32(a, b, d);
-        uint32_t H, L;
-        if constexpr (K == 32) {
-            H = (uint32_t)(x >> 32);
-            L = (uint32_t)x;
+            return __umul24(t >> K, CC) + (t & LOW);                // < 2^K + c^2 < 2p
         } else {
-            H = __builtin_amdgcn_alignbit((uint32_t)(x >> 32), (uint32_t)x, K);   // x >> K < 2^K <= 2^32
-            L = (uint32_t)x & LOW;
-        }
-        uint32_t H2, L2;
-        if constexpr (K <= 24) {
-            const uint32_t t = __umul24(H, CC) + L;                // < 2^(K + 6) <= 2^30
-            H2 = t >> K;
-            L2 = t & LOW;
-        } else {
-            const uint64_t t = mad_u64_u32(H, CC, L);               // < 2^(K + 6)
-            if constexpr (K == 32) {
-                H2 = (uint32_t)(t >> 32);
-                L2 = (uint32_t)t;
+            const uint64_t x = mad_u64_u32(a, b, d);
+            const uint32_t H = __builtin_amdgcn_alignbit((uint32_t)(x >> 32), (uint32_t)x, K);   // x >> K
+            const uint32_t L = (uint32_t)x & LOW;
+            uint32_t H2, L2;
+            if constexpr (K <= 24) {
+                const uint32_t t = __umul24(H, CC) + L;            // < 2^(K + 6) <= 2^30
+                H2 = t >> K;
+                L2 = t & LOW;
             } else {
+                const uint64_t t = mad_u64_u32(H, CC, L);           // < 2^(K + 6)
                 H2 = __builtin_amdgcn_alignbit((uint32_t)(t >> 32), (uint32_t)t, K);
                 L2 = (uint32_t)t & LOW;
             }
+            return L2 + __umul24(H2, CC);                          // < 2^K + c^2 < 2p
         }
-        if constexpr (K == 32) {
-            // S = L2 + c H2 < 2^32 + c^2 may exceed 32 bits; S >= p exactly when
-            // S + c reaches 2^32, and then S - p = (S + c) mod 2^32.
-            const uint64_t S = (uint64_t)L2 + __umul24(H2, CC);
-            const uint64_t R = S + CC;
-            return (R >> 32) ? (uint32_t)R : (uint32_t)S;
-        } else {
-            const uint32_t S = L2 + __umul24(H2, CC);              // < 2^K + c^2 < 2p
+    }
+    __device__ __forceinline__ uint32_t mul_add(uint32_t a, uint32_t b, uint32_t d) const {
+        if constexpr (K < 32) {
+            const uint32_t S = mul_add_lazy(a, b, d);
             return min(S, S - p);
         }
+        // K = 32: 64-bit folds, and S = L2 + c H2 < 2^32 + c^2 may exceed 32
+        // bits; S >= p exactly when S + c reaches 2^32, and then
+        // S - p = (S + c) mod 2^32.
+        const uint64_t x = mad_u64_u32(a, b, d);
+        const uint64_t t = mad_u64_u32((uint32_t)(x >> 32), CC, (uint32_t)x);   // < 2^38
+        const uint64_t S = (uint64_t)(uint32_t)t + __umul24((uint32_t)(t >> 32), CC);
+        const uint64_t R = S + CC;
+        return (R >> 32) ? (uint32_t)R : (uint32_t)S;
     }
     // mul_add with b and d given shifted left by SH = 32 - K (12 < K <= 24):
     // x 2^SH splits at bit 32 into H = x >> K and L 2^SH, L = x mod 2^K.
     template <int SH>
-    __device__ __forceinline__ uint32_t mul_add_sh(uint32_t a, uint32_t b_sh, uint32_t d_sh) const {
+    __device__ __forceinline__ uint32_t mul_add_sh_lazy(uint32_t a, uint32_t b_sh, uint32_t d_sh) const {
         static_assert(SH == 32 - K && K > 12 && K <= 24, "operands shifted to the top of the word");
         const uint64_t x = mad_u64_u32(a, b_sh, d_sh);
         const uint32_t H = (uint32_t)(x >> 32), L = (uint32_t)x >> SH;
         const uint32_t t = __umul24(H, CC) + L;                    // < 2^(K + 6) <= 2^30
-        const uint32_t S = (t & LOW) + __umul24(t >> K, CC);       // < 2^K + c^2 < 2p
+        return (t & LOW) + __umul24(t >> K, CC);                   // < 2^K + c^2 < 2p
+    }
+    template <int SH>
+    __device__ __forceinline__ uint32_t mul_add_sh(uint32_t a, uint32_t b_sh, uint32_t d_sh) const {
+        const uint32_t S = mul_add_sh_lazy<SH>(a, b_sh, d_sh);
         return min(S, S - p);
     }
 };

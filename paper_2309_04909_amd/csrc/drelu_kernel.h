@@ -61,14 +61,27 @@ __device__ __forceinline__ FT window(T a, uint32_t pos) {
 }
 
 // a * b + c in Z_p with b and c given shifted left by SH bits (SH = 0: the
-// plain values; see MaskDraws).
-template <int SH, typename F>
+// plain values; see MaskDraws).  LAZY: a value below 2p congruent to it
+// (the field's form without the final conditional subtraction).
+template <int SH, typename F, bool LAZY = false>
 __device__ __forceinline__ typename F::T field_mul_add(const F& f, typename F::T a, typename F::T b, typename F::T c) {
-    if constexpr (SH == 0)
+    if constexpr (LAZY) {
+        if constexpr (SH == 0)
+            return f.mul_add_lazy(a, b, c);
+        else
+            return f.template mul_add_sh_lazy<SH>(a, b, c);
+    } else if constexpr (SH == 0) {
         return f.mul_add(a, b, c);
-    else
+    } else {
         return f.template mul_add_sh<SH>(a, b, c);
+    }
 }
+
+// Whether field F offers the lazy forms (a value below 2p with 4p < 2^32).
+template <typename F, typename = void>
+struct HasLazy : std::false_type {};
+template <typename F>
+struct HasLazy<F, std::void_t<decltype(F::kLazy)>> : std::integral_constant<bool, F::kLazy> {};
 
 // v_min3_u32 written out: the compiler would otherwise re-associate P2's
 // running minimum into a tree over all slots, which defers every slot's
@@ -101,6 +114,16 @@ __device__ __forceinline__ typename F::T p2_least(typename F::T least, typename 
     }
 }
 
+// P2's running minimum from two lazy messages w0, w1 < 2p (4p < 2^32): their
+// sum t < 4p, u = t mod 2p by one conditional subtraction, then u and u - p
+// into the minimum as in p2_least; u is 0 or p exactly when t is 0 mod p.
+template <typename F>
+__device__ __forceinline__ uint32_t p2_least_lazy(uint32_t least, uint32_t w0, uint32_t w1, const F& f) {
+    const uint32_t t = w0 + w1;
+    const uint32_t u = min(t, t - 2 * f.p);
+    return min3_in_order(least, u, u - f.p);
+}
+
 // Windows through P2's reconstruction (Alg. 7) for one slot: the window
 // position `pos` (sigma of the slot), the slot's mask r and reshare z (both
 // shifted left by SH bits, see MaskDraws); returns both parties' messages
@@ -108,8 +131,11 @@ __device__ __forceinline__ typename F::T p2_least(typename F::T least, typename 
 // `least` (some slot is zero exactly when the minimum ends at 0).
 // a0 and nb1 are P0's share and P1's negated share, both shifted down by k_lo.
 // Every select is written as masks and adds so that it stays on the
-// full-rate VOP2 forms (no compare / cndmask pairs).
-template <typename T, int N, typename F, int SH = 0>
+// full-rate VOP2 forms (no compare / cndmask pairs).  With LAZY (callers
+// that only test the slot, not capture its messages) and a field that has
+// the lazy forms, w0 and w1 are left below 2p, one congruent value each, and
+// P2 reduces their sum once.
+template <typename T, int N, typename F, int SH = 0, bool LAZY = false>
 __device__ __forceinline__ void slot_messages(T a0, T nb1, uint32_t pos, typename F::T r, typename F::T z, const F& f,
                                               typename F::T& w0, typename F::T& w1, typename F::T& least) {
     using FT = typename F::T;
@@ -126,9 +152,15 @@ __device__ __forceinline__ void slot_messages(T a0, T nb1, uint32_t pos, typenam
     const FT s0 = ((W0 + u0n - 2) & WIN) + 1;
     const FT v1 = ((FT)0 - W1 - u1n) & WIN;              // P1: -cut_i - cut_{i+1}
     const FT s1 = v1 + (f.p - TWO_LX);
-    w0 = field_mul_add<SH>(f, s0, r, z);                           // mask, reshare
-    w1 = field_mul_add<SH>(f, s1, r, (FT)((f.p << SH) - z));       // P1: s1 r - z
-    least = p2_least(least, w0, w1, f);                            // P2 reconstructs and tests
+    if constexpr (LAZY && HasLazy<F>::value) {
+        w0 = field_mul_add<SH, F, true>(f, s0, r, z);
+        w1 = field_mul_add<SH, F, true>(f, s1, r, (FT)((f.p << SH) - z));
+        least = p2_least_lazy(least, w0, w1, f);
+    } else {
+        w0 = field_mul_add<SH>(f, s0, r, z);                           // mask, reshare
+        w1 = field_mul_add<SH>(f, s1, r, (FT)((f.p << SH) - z));       // P1: s1 r - z
+        least = p2_least(least, w0, w1, f);                            // P2 reconstructs and tests
+    }
 }
 
 // DReLU's end (Alg. 7): P2's fresh sharing (rho, D' - rho), then the unflip.
@@ -418,7 +450,7 @@ __device__ __forceinline__ T drelu_round1(T in0, T in1, uint64_t g, T mask, uint
         FT r, z;
         masks.slot(r01, j, f, r, z);
         FT w0, w1;
-        slot_messages<T, N, F, MaskDraws<N, F>::SH>(a0k, nb1k, shuffle_pos(A, j), r, z, f, w0, w1, least);
+        slot_messages<T, N, F, MaskDraws<N, F>::SH, !CAP>(a0k, nb1k, shuffle_pos(A, j), r, z, f, w0, w1, least);
         if constexpr (CAP) {
             cap[e * N + j] = w0;
             cap[(ncap + e) * N + j] = w1;
@@ -547,7 +579,7 @@ __device__ __forceinline__ void drelu_element_group(const T* __restrict__ X0, co
             FT r, z;
             stream_draws<N, F>(stream_field_at<N, F>(W, 2 * js), stream_field_at<N, F>(W, 2 * js + 1), r, z);
             FT w0, w1, v = f.p;
-            slot_messages<T, N, F, SH>(a0k, nb1k, shuffle_pos(A, js), r, z, f, w0, w1, v);
+            slot_messages<T, N, F, SH, true>(a0k, nb1k, shuffle_pos(A, js), r, z, f, w0, w1, v);
             least = (valid && v < least) ? v : least;
         }
         wave_sync();                                        // every read before the next element's words
@@ -567,7 +599,7 @@ __device__ __forceinline__ void drelu_element_group(const T* __restrict__ X0, co
                 else
                     block_draws<N, F, (SPB > 1 ? 1 : 0)>(w, f, r, z);
                 FT w0, w1, v = f.p;
-                slot_messages<T, N, F, SH>(a0k, nb1k, pos, r, z, f, w0, w1, v);
+                slot_messages<T, N, F, SH, true>(a0k, nb1k, pos, r, z, f, w0, w1, v);
                 least = (valid && v < least) ? v : least;
             }
         }

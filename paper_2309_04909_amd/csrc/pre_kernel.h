@@ -158,7 +158,7 @@ __device__ __forceinline__ void drelu_pre_element(const T* __restrict__ X0, cons
         const FT r = rv[0], z = rv[1];
         const uint32_t pos = (perm[j >> 2] >> (8 * (j & 3))) & 63u;
         FT w0, w1;
-        slot_messages<T, N, F>(a0k, nb1k, pos, r, z, f, w0, w1, least);
+        slot_messages<T, N, F, 0, !CAP>(a0k, nb1k, pos, r, z, f, w0, w1, least);
         if constexpr (CAP) {
             cap[e * N + j] = w0;
             cap[(n + e) * N + j] = w1;
