@@ -135,16 +135,19 @@ __device__ __forceinline__ uint32_t p2_least_lazy(uint32_t least, uint32_t w0, u
 // that only test the slot, not capture its messages) and a field that has
 // the lazy forms, w0 and w1 are left below 2p, one congruent value each, and
 // P2 reduces their sum once.
+// `more_mask` is all ones unless pos = l_x, zero there (u_{l_x+1} := 0); the
+// overload without it derives it from pos.
 template <typename T, int N, typename F, int SH = 0, bool LAZY = false>
-__device__ __forceinline__ void slot_messages(T a0, T nb1, uint32_t pos, typename F::T r, typename F::T z, const F& f,
-                                              typename F::T& w0, typename F::T& w1, typename F::T& least) {
+__device__ __forceinline__ void slot_messages(T a0, T nb1, uint32_t pos, uint32_t more_mask, typename F::T r,
+                                              typename F::T z, const F& f, typename F::T& w0, typename F::T& w1,
+                                              typename F::T& least) {
     using FT = typename F::T;
     constexpr int LX = N - 1;
     constexpr FT TWO_LX = (FT)1 << LX;                   // 2^l_x mod p = 2^l_x
     constexpr FT WIN = TWO_LX - 1;                       // Z_{2^l_x}
     const FT W0 = window<T, N, FT>(a0, pos);             // bits [k_lo + pos, k_lo + pos + l_x]
     const FT W1 = window<T, N, FT>(nb1, pos);
-    const FT more = (FT)(int64_t)((int32_t)(pos - (uint32_t)LX) >> 31);   // all ones unless pos = l_x
+    const FT more = (FT)(int64_t)(int32_t)more_mask;
     const FT u0n = (W0 >> 1) & more;                     // u_{i+1}, and u_{l_x+1} := 0
     const FT u1n = (W1 >> 1) & more;
     // adjacent sum and modulo switch (Alg. 6) for P0: v0 = u_i + u_{i+1} - 1 in Z_{2^l_x},
@@ -161,6 +164,13 @@ __device__ __forceinline__ void slot_messages(T a0, T nb1, uint32_t pos, typenam
         w1 = field_mul_add<SH>(f, s1, r, (FT)((f.p << SH) - z));       // P1: s1 r - z
         least = p2_least(least, w0, w1, f);                            // P2 reconstructs and tests
     }
+}
+
+template <typename T, int N, typename F, int SH = 0, bool LAZY = false>
+__device__ __forceinline__ void slot_messages(T a0, T nb1, uint32_t pos, typename F::T r, typename F::T z, const F& f,
+                                              typename F::T& w0, typename F::T& w1, typename F::T& least) {
+    const uint32_t more_mask = (uint32_t)((int32_t)(pos - (uint32_t)(N - 1)) >> 31);   // all ones unless pos = l_x
+    slot_messages<T, N, F, SH, LAZY>(a0, nb1, pos, more_mask, r, z, f, w0, w1, least);
 }
 
 // DReLU's end (Alg. 7): P2's fresh sharing (rho, D' - rho), then the unflip.
@@ -230,15 +240,23 @@ struct ShufflePlan {
 // Runs the shuffle in this thread's slice of a per-block LDS array (blocks of
 // at most 256 threads: every kernel is launched with __launch_bounds__(256))
 // and returns the slice: A[k] is byte 1024 (k / 4) + (k % 4) of it, so the 64
-// lanes of a wave touch 64 different banks whatever their k.  The slice stays
-// valid until the thread's next call.
+// lanes of a wave touch 64 different banks whatever their k.  With MORE the
+// slice also holds, from byte kMoreRow on, one byte per slot: 0 for the slot
+// that received the top position l_x (the last swap put it at slot j_{N-1},
+// and nothing moves it after), 0xFF for every other slot; shuffle_more reads
+// it back as the all-ones / zero mask of the slot's next window (u_{l_x+1} is
+// 0).  The slice stays valid until the thread's next call.
 template <int N>
+constexpr int kMoreRow = 1024 * ((N + 3) / 4);
+
+template <int N, bool MORE = false>
 __device__ __forceinline__ uint8_t* shuffle_fill(const StreamAt& r01, uint32_t& t) {
     constexpr ShufflePlan<N> plan{};
-    __shared__ uint32_t lds[((N + 3) / 4) * 256];
+    constexpr int W = (N + 3) / 4;
+    __shared__ uint32_t lds[(MORE ? 2 : 1) * W * 256];
     uint8_t* A = reinterpret_cast<uint8_t*>(lds) + 4 * threadIdx.x;
     Words4 w = {0, 0, 0, 0};
-    uint32_t lo = 0, hi = 0;
+    uint32_t lo = 0, hi = 0, last = 0;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         const int c = plan.chunk[k];
@@ -260,9 +278,22 @@ __device__ __forceinline__ uint8_t* shuffle_fill(const StreamAt& r01, uint32_t& 
             uint8_t* aj = A + (((d >> 2) << 10) | (d & 3u));
             A[1024 * (k >> 2) + (k & 3)] = *aj;                 // A[k] = A[j_k]
             *aj = (uint8_t)k;                                   // A[j_k] = k
+            last = d;
         }
     }
+    if constexpr (MORE) {
+#pragma unroll
+        for (int q = 0; q < W; ++q) reinterpret_cast<uint32_t*>(A + kMoreRow<N>)[256 * q] = ~0u;
+        A[kMoreRow<N> + (((last >> 2) << 10) | (last & 3u))] = 0;   // the slot of position l_x (N = 1: slot 0)
+    }
     return A;
+}
+
+// The next-window mask of slot s after shuffle_fill<N, true>: all ones, or
+// zero for the slot of position l_x (read sign-extended from its byte).
+template <int N>
+__device__ __forceinline__ uint32_t shuffle_more(const uint8_t* A, uint32_t s) {
+    return (uint32_t)(int32_t) reinterpret_cast<const int8_t*>(A)[kMoreRow<N> + (((s >> 2) << 10) | (s & 3u))];
 }
 
 // Window position of slot s after shuffle_fill.
@@ -434,7 +465,7 @@ __device__ __forceinline__ T drelu_round1(T in0, T in1, uint64_t g, T mask, uint
     // The flip bit t and the shuffle, both from seed_01.
     const StreamAt r01 = s01.at(g);
     uint32_t t;
-    const uint8_t* A = shuffle_fill<N>(r01, t);
+    const uint8_t* A = shuffle_fill<N, true>(r01, t);
 
     // Flip: [x] := (-1)^t [x]  (both parties).
     const T a0 = t ? (T)((T)0 - in0) & mask : in0;
@@ -450,7 +481,8 @@ __device__ __forceinline__ T drelu_round1(T in0, T in1, uint64_t g, T mask, uint
         FT r, z;
         masks.slot(r01, j, f, r, z);
         FT w0, w1;
-        slot_messages<T, N, F, MaskDraws<N, F>::SH, !CAP>(a0k, nb1k, shuffle_pos(A, j), r, z, f, w0, w1, least);
+        slot_messages<T, N, F, MaskDraws<N, F>::SH, !CAP>(a0k, nb1k, shuffle_pos(A, j), shuffle_more<N>(A, j), r, z,
+                                                          f, w0, w1, least);
         if constexpr (CAP) {
             cap[e * N + j] = w0;
             cap[(ncap + e) * N + j] = w1;
@@ -542,7 +574,7 @@ __device__ __forceinline__ void drelu_element_group(const T* __restrict__ X0, co
 
     const StreamAt r01 = s01.at(g);
     uint32_t t;
-    const uint8_t* A = shuffle_fill<N>(r01, t);
+    const uint8_t* A = shuffle_fill<N, true>(r01, t);
 
     const T a0 = t ? (T)((T)0 - in0) & mask : in0;
     const T a1 = t ? (T)((T)0 - in1) & mask : in1;
@@ -579,7 +611,8 @@ __device__ __forceinline__ void drelu_element_group(const T* __restrict__ X0, co
             FT r, z;
             stream_draws<N, F>(stream_field_at<N, F>(W, 2 * js), stream_field_at<N, F>(W, 2 * js + 1), r, z);
             FT w0, w1, v = f.p;
-            slot_messages<T, N, F, SH, true>(a0k, nb1k, shuffle_pos(A, js), r, z, f, w0, w1, v);
+            slot_messages<T, N, F, SH, true>(a0k, nb1k, shuffle_pos(A, js), shuffle_more<N>(A, js), r, z, f, w0, w1,
+                                             v);
             least = (valid && v < least) ? v : least;
         }
         wave_sync();                                        // every read before the next element's words
@@ -592,14 +625,15 @@ __device__ __forceinline__ void drelu_element_group(const T* __restrict__ X0, co
             for (int h = 0; h < SPB; ++h) {
                 // slot j = SPB * blk + h (past the last slot: any slot, its message is not counted)
                 const bool valid = SPB * blk + h < (uint32_t)N;
-                const uint32_t pos = shuffle_pos(A, valid ? SPB * blk + h : 0u);
+                const uint32_t js = valid ? SPB * blk + h : 0u;
+                const uint32_t pos = shuffle_pos(A, js);
                 FT r, z;
                 if (h == 0)
                     block_draws<N, F, 0>(w, f, r, z);
                 else
                     block_draws<N, F, (SPB > 1 ? 1 : 0)>(w, f, r, z);
                 FT w0, w1, v = f.p;
-                slot_messages<T, N, F, SH, true>(a0k, nb1k, pos, r, z, f, w0, w1, v);
+                slot_messages<T, N, F, SH, true>(a0k, nb1k, pos, shuffle_more<N>(A, js), r, z, f, w0, w1, v);
                 least = (valid && v < least) ? v : least;
             }
         }
