@@ -398,7 +398,7 @@ int bc_rss_relu(const void* x0, const void* x1, const void* x2, void* y0, void* 
  * (Alg. 7: flip, shuffle, masks, reshares, P2's reply; Alg. 8's
  * preprocessing), so it can be expanded ahead of time and kept resident; the
  * online call then streams shares plus this record.  The record keeps what
- * would cost the online phase its sort, its seed_01 draws or a message: the
+ * would cost the online phase its shuffle, its seed_01 draws or a message: the
  * flip and the shuffle, r and z, and for the ReLU P2's [c]_1 of the Beaver
  * triple.  What a party draws from seed_02 or seed_12 alone (rho, and the
  * parties' own triple shares) the online call regenerates from the seeds, so

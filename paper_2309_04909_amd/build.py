@@ -24,8 +24,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc" if os.path.exists("/opt/ro
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-command-line-argument",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    # let '#pragma unroll' fully unroll the 33-slot loops of l_x = 32 (else the
-    # sorted keys are indexed dynamically, through scratch)
+    # let '#pragma unroll' fully unroll the 33-slot loops of l_x = 32 (else
+    # the slot arrays are indexed dynamically, through scratch)
     "-mllvm", "-pragma-unroll-threshold=200000",
 ]
 
