@@ -173,12 +173,36 @@ __device__ __forceinline__ void slot_messages(T a0, T nb1, uint32_t pos, typenam
     slot_messages<T, N, F, SH, LAZY>(a0, nb1, pos, more_mask, r, z, f, w0, w1, least);
 }
 
-// DReLU's end (Alg. 7): P2's fresh sharing (rho, D' - rho), then the unflip.
+// (-1)^t v mod 2^l for v < 2^l (Alg. 7's flip).  A select: the select-free
+// form (v ^ -t) + t compiled to 36 more instructions and 74 VGPRs in the
+// N = 19 DReLU kernel.
+template <typename T>
+__device__ __forceinline__ T flip_by(T v, uint32_t t, T mask) {
+    return t ? (T)((T)0 - v) & mask : v;
+}
+
+// The shares a DReLU/ReLU works on, from the loaded ones: with k_in > 0 the
+// loaded shares are of Z_{2^(l + k_in)} (in_mask) and each party first
+// truncates its own by k_in bits (Alg. 5); with k_in = 0 and in_mask = mask
+// the same expressions are the plain shares.  P0 holds in0 = cut(x0, k_in);
+// P1 holds -n1 with n1 = cut(-x1, k_in), and n1, its negated share, is what it
+// cuts the windows from (Alg. 7).
+template <typename T>
+__device__ __forceinline__ void input_shares(T x0, T x1, T mask, T in_mask, uint32_t k_in, T& in0, T& n1) {
+    in0 = (T)((x0 & in_mask) >> k_in) & mask;
+    n1 = (T)((((T)0 - x1) & in_mask) >> k_in) & mask;
+}
+
+// DReLU's end (Alg. 7): P2's fresh sharing (rho, D' - rho), then the unflip:
+// y0 = t + (1 - 2t) rho, y1 = (1 - 2t)(D' - rho), select-free with tm = -t
+// (all ones when t = 1): (v ^ tm) - tm = (1 - 2t) v.  Each step keeps the low
+// l bits a function of the low l bits, so rho may carry bits above l and one
+// mask at the end reduces mod 2^l.
 template <typename T>
 __device__ __forceinline__ void drelu_finish(T dp, T rho, uint32_t t, T mask, T& y0, T& y1) {
-    const T d1 = (T)(dp - rho) & mask;
-    y0 = t ? (T)((T)1 - rho) & mask : rho;
-    y1 = t ? (T)((T)0 - d1) & mask : d1;
+    const T tm = (T)0 - (T)t;
+    y0 = (T)((rho ^ tm) + (T)(2 * t)) & mask;          // t = 1: ~rho + 2 = 1 - rho
+    y1 = (T)(((T)(dp - rho) ^ tm) - tm) & mask;
 }
 
 // Alg. 8's preprocessing draws of element g: [a]_0, [b]_0, [c]_0 from
@@ -450,12 +474,13 @@ __device__ __forceinline__ void plain_draws(const F& f, typename F::T& r, typena
 }
 
 // Alg. 7 from the flip through P2's zero test for one element: the 2-of-2
-// input (in0, in1) of Z_{2^l}, randomness of global index g.  Returns D'
+// input (in0, -n1) of Z_{2^l} (n1: P1's negated share, see input_shares),
+// randomness of global index g.  Returns D'
 // (1 when some slot reconstructs to 0) and the flip bit t.  With CAP the
 // round-1 messages go to cap[e * N + slot] (P0) and cap[(ncap + e) * N +
 // slot] (P1).
 template <typename T, int N, typename F, bool CAP>
-__device__ __forceinline__ T drelu_round1(T in0, T in1, uint64_t g, T mask, uint32_t k_lo, const Stream& s01,
+__device__ __forceinline__ T drelu_round1(T in0, T n1, uint64_t g, T mask, uint32_t k_lo, const Stream& s01,
                                           typename F::T* cap, uint64_t ncap, uint64_t e, const F& f,
                                           uint32_t& t_out) {
     using FT = typename F::T;
@@ -467,10 +492,10 @@ __device__ __forceinline__ T drelu_round1(T in0, T in1, uint64_t g, T mask, uint
     uint32_t t;
     const uint8_t* A = shuffle_fill<N, true>(r01, t);
 
-    // Flip: [x] := (-1)^t [x]  (both parties).
-    const T a0 = t ? (T)((T)0 - in0) & mask : in0;
-    const T a1 = t ? (T)((T)0 - in1) & mask : in1;
-    const T nb1 = (T)((T)0 - a1) & mask;                  // P1 cuts -[x]_1 mod 2^l
+    // Flip: [x] := (-1)^t [x]  (both parties); P1 cuts its negated share
+    // -(-1)^t [x]_1 = (-1)^t n1.
+    const T a0 = flip_by(in0, t, mask);
+    const T nb1 = flip_by(n1, t, mask);
     const T a0k = a0 >> k_lo, nb1k = nb1 >> k_lo;         // common low cut of every window
 
     FT least = f.p;                                        // P2: min over slots of w0 + w1 mod p
@@ -504,20 +529,18 @@ __device__ __forceinline__ void drelu_element(const T* __restrict__ X0, const T*
                                               typename F::T* cap, uint64_t ncap, uint64_t e, uint64_t g, T mask,
                                               T in_mask, uint32_t k_in, uint32_t k_lo, const Stream& s01,
                                               const Stream& s02, const Stream& s12, const F& f) {
-    const T r0 = X0[e] & in_mask;
-    const T r1 = X1[e] & in_mask;
-    const T in0 = (T)(r0 >> k_in) & mask;                                           // P0: cut(x0, k_in)
-    const T nr1 = (T)((T)0 - r1) & in_mask;                                          // -x1 in the input ring
-    const T in1 = (T)((T)0 - (T)(nr1 >> k_in)) & mask;                              // P1: -cut(-x1, k_in)
+    T in0, n1;
+    input_shares<T>(X0[e], X1[e], mask, in_mask, k_in, in0, n1);
 
     uint32_t t;
-    const T dp = drelu_round1<T, N, F, CAP>(in0, in1, g, mask, k_lo, s01, cap, ncap, e, f, t);
+    const T dp = drelu_round1<T, N, F, CAP>(in0, n1, g, mask, k_lo, s01, cap, ncap, e, f, t);
 
     T y0, y1;
     if constexpr (!RELU) {
         const Words4 w = s02.block(g, TAG_RESP, 0);               // rho from seed_02
-        drelu_finish<T>(dp, (T)join64(w.w0, w.w1) & mask, t, mask, y0, y1);
+        drelu_finish<T>(dp, (T)join64(w.w0, w.w1), t, mask, y0, y1);
     } else {
+        const T in1 = (T)((T)0 - n1) & mask;
         // Alg. 8 preprocessing; P2 forms [c]_1 = (a0 + a1)(b0 + b1) - c0.
         T ba0, bb0, bc0, ba1, bb1;
         beaver_shares<T>(s02, s12, g, mask, ba0, bb0, bc0, ba1, bb1);
@@ -566,19 +589,15 @@ __device__ __forceinline__ void drelu_element_group(const T* __restrict__ X0, co
     constexpr int NB = D::NB;                               // mask blocks
     constexpr int ROUNDS = (NB + G - 1) / G;
 
-    const T r0 = X0[e] & in_mask;
-    const T r1 = X1[e] & in_mask;
-    const T in0 = (T)(r0 >> k_in) & mask;
-    const T nr1 = (T)((T)0 - r1) & in_mask;
-    const T in1 = (T)((T)0 - (T)(nr1 >> k_in)) & mask;
+    T in0, n1;
+    input_shares<T>(X0[e], X1[e], mask, in_mask, k_in, in0, n1);
 
     const StreamAt r01 = s01.at(g);
     uint32_t t;
     const uint8_t* A = shuffle_fill<N, true>(r01, t);
 
-    const T a0 = t ? (T)((T)0 - in0) & mask : in0;
-    const T a1 = t ? (T)((T)0 - in1) & mask : in1;
-    const T nb1 = (T)((T)0 - a1) & mask;
+    const T a0 = flip_by(in0, t, mask);                  // the flip, as in drelu_round1
+    const T nb1 = flip_by(n1, t, mask);
     const T a0k = a0 >> k_lo, nb1k = nb1 >> k_lo;
 
     FT least = f.p;
@@ -654,8 +673,9 @@ __device__ __forceinline__ void drelu_element_group(const T* __restrict__ X0, co
     T y0, y1;
     if constexpr (!RELU) {
         const Words4 w = s02.block(g, TAG_RESP, 0);
-        drelu_finish<T>(dp, (T)join64(w.w0, w.w1) & mask, t, mask, y0, y1);
+        drelu_finish<T>(dp, (T)join64(w.w0, w.w1), t, mask, y0, y1);
     } else {
+        const T in1 = (T)((T)0 - n1) & mask;
         const StreamAt r02 = s02.at(g);
         const Words4 w0 = r02.block(TAG_BEAVER, 0);
         const Words4 w1 = r02.block(TAG_BEAVER, 1);

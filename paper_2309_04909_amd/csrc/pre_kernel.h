@@ -130,18 +130,14 @@ __device__ __forceinline__ void drelu_pre_element(const T* __restrict__ X0, cons
                                                   const Stream& s12, const F& f) {
     using FT = typename F::T;
     const uint64_t n = R.n;
-    const T r0 = X0[e] & in_mask;
-    const T r1 = X1[e] & in_mask;
-    const T in0 = (T)(r0 >> k_in) & mask;                                           // P0: cut(x0, k_in)
-    const T nr1 = (T)((T)0 - r1) & in_mask;                                          // -x1 in the input ring
-    const T in1 = (T)((T)0 - (T)(nr1 >> k_in)) & mask;                              // P1: -cut(-x1, k_in)
+    T in0, n1;
+    input_shares<T>(X0[e], X1[e], mask, in_mask, k_in, in0, n1);
     uint32_t perm[(N + 3) / 4];
 #pragma unroll
     for (int k = 0; k < (N + 3) / 4; ++k) perm[k] = R.perm[(uint64_t)k * n + e];
     const uint32_t t = (perm[0] >> 7) & 1u;
-    const T a0 = t ? (T)((T)0 - in0) & mask : in0;
-    const T a1 = t ? (T)((T)0 - in1) & mask : in1;
-    const T nb1 = (T)((T)0 - a1) & mask;
+    const T a0 = flip_by(in0, t, mask);                // the flip, as in drelu_round1
+    const T nb1 = flip_by(n1, t, mask);
     const T a0k = a0 >> k_lo, nb1k = nb1 >> k_lo;
     FT least = f.p;
     constexpr int K = RzLayout<N>::K;
@@ -168,8 +164,9 @@ __device__ __forceinline__ void drelu_pre_element(const T* __restrict__ X0, cons
     T y0, y1;
     if constexpr (!RELU) {
         const Words4 w = s02.block(g, TAG_RESP, 0);                 // rho, regenerated from seed_02
-        drelu_finish<T>(dp, (T)join64(w.w0, w.w1) & mask, t, mask, y0, y1);
+        drelu_finish<T>(dp, (T)join64(w.w0, w.w1), t, mask, y0, y1);
     } else {
+        const T in1 = (T)((T)0 - n1) & mask;
         T ba0, bb0, bc0, ba1, bb1;                                  // the parties' triple shares, regenerated
         beaver_shares<T>(s02, s12, g, mask, ba0, bb0, bc0, ba1, bb1);
         relu_finish<T>(dp, in0, in1, ba0, bb0, bc0, ba1, bb1, R.tail[e], t, mask, y0, y1);

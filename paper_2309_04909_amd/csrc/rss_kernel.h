@@ -69,10 +69,11 @@ __device__ __forceinline__ void rss_element(const RssKArgs& A, const T* __restri
                                             typename F::T* cap, uint64_t e, uint64_t g, T mask, const F& f) {
     const T x[3] = {X0[e], X1[e], X2[e]};
 
-    // round 1 and P2's zero test on the 2-of-2 input ([x]_0 + [x]_1, [x]_2)
+    // round 1 and P2's zero test on the 2-of-2 input ([x]_0 + [x]_1, [x]_2),
+    // whose second holder cuts its negated share -[x]_2
     uint32_t t;
-    const T dp = drelu_round1<T, N, F, CAP>((T)(x[0] + x[1]) & mask, x[2] & mask, g, mask, A.k_lo, A.s01, cap, A.n,
-                                            e, f, t);
+    const T nx2 = (T)((T)0 - x[2]) & mask;
+    const T dp = drelu_round1<T, N, F, CAP>((T)(x[0] + x[1]) & mask, nx2, g, mask, A.k_lo, A.s01, cap, A.n, e, f, t);
 
     // preprocessing: [t], [s], [s][t]
     const StreamAt r012 = A.s012.at(g);

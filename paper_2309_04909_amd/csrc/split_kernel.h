@@ -87,8 +87,8 @@ __global__ BC_KERNEL_ATTRS void k_send(SplitKArgs A, F f_arg) {
         const StreamAt r01 = A.s01.at(g);
         uint32_t t;
         const uint8_t* sig = shuffle_fill<N>(r01, t);
-        const T a = t ? (T)((T)0 - x) & mask : x;                    // flip
-        const T ak = (PARTY == 0 ? a : (T)((T)0 - a) & mask) >> A.k_lo;
+        // the flipped share (-1)^t x; P1 cuts its negation (-1)^(t+1) x
+        const T ak = flip_by(x, PARTY == 0 ? t : t ^ 1u, mask) >> A.k_lo;
         uint32_t words[W];
 #pragma unroll
         for (int k = 0; k < W; ++k) words[k] = 0;
@@ -147,9 +147,9 @@ __global__ __launch_bounds__(256) void k_finish(SplitKArgs A) {
         const uint32_t t = A.s01.block(A.elem_base + e, TAG_SHUFFLE, 0).w1 >> 31;
         const T d = D[e] & mask;
         if constexpr (PARTY == 0)
-            Y[e] = t ? (T)((T)1 - d) & mask : d;
+            Y[e] = (T)((d ^ ((T)0 - (T)t)) + (T)(2 * t)) & mask;      // t + (1 - 2t) d
         else
-            Y[e] = t ? (T)((T)0 - d) & mask : d;
+            Y[e] = flip_by(d, t, mask);                              // (1 - 2t) d
     }
 }
 
