@@ -263,24 +263,33 @@ struct ShufflePlan {
 
 // Runs the shuffle in this thread's slice of a per-block LDS array (blocks of
 // at most 256 threads: every kernel is launched with __launch_bounds__(256))
-// and returns the slice: A[k] is byte 1024 (k / 4) + (k % 4) of it, so the 64
-// lanes of a wave touch 64 different banks whatever their k.  With MORE the
-// slice also holds, from byte kMoreRow on, one byte per slot: 0 for the slot
-// that received the top position l_x (the last swap put it at slot j_{N-1},
-// and nothing moves it after), 0xFF for every other slot; shuffle_more reads
-// it back as the all-ones / zero mask of the slot's next window (u_{l_x+1} is
-// 0).  The slice stays valid until the thread's next call.
+// and returns the slice.  Entry A[k] is E bytes at byte k ROW of the slice,
+// ROW = 256 E, so entry k of the 256 threads is one contiguous row and the
+// address of a drawn index j is one multiply-add.  With E = 4 the 64 lanes of
+// a wave touch 64 different banks whatever their k; E = 4 while 8 blocks of N
+// rows fit the compute unit's 160 KiB of LDS (N <= 20), else E = 2.  Byte 0
+// of an entry is the window position; its top byte is 0 for the slot that
+// received the top position l_x (the last swap puts it at slot j_{N-1}, and
+// nothing moves it after) and 0xFF for every other slot, which shuffle_more
+// reads back as the all-ones / zero mask of the slot's next window
+// (u_{l_x+1} is 0).  The slice stays valid until the thread's next call.
 template <int N>
-constexpr int kMoreRow = 1024 * ((N + 3) / 4);
+struct ShuffleSlice {
+    static constexpr int E = N <= 20 ? 4 : 2;               // bytes per entry
+    static constexpr int ROW = 256 * E;
+    using U = typename std::conditional<E == 4, uint32_t, uint16_t>::type;
+    static constexpr U FLAG = (U)((U)0xFF << (8 * (E - 1)));   // top byte of a slot below l_x
+};
 
-template <int N, bool MORE = false>
+template <int N>
 __device__ __forceinline__ uint8_t* shuffle_fill(const StreamAt& r01, uint32_t& t) {
+    using S = ShuffleSlice<N>;
+    using U = typename S::U;
     constexpr ShufflePlan<N> plan{};
-    constexpr int W = (N + 3) / 4;
-    __shared__ uint32_t lds[(MORE ? 2 : 1) * W * 256];
-    uint8_t* A = reinterpret_cast<uint8_t*>(lds) + 4 * threadIdx.x;
+    __shared__ U lds[N * 256];
+    uint8_t* A = reinterpret_cast<uint8_t*>(lds + threadIdx.x);
     Words4 w = {0, 0, 0, 0};
-    uint32_t lo = 0, hi = 0, last = 0;
+    uint32_t lo = 0, hi = 0;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         const int c = plan.chunk[k];
@@ -297,32 +306,27 @@ __device__ __forceinline__ uint8_t* shuffle_fill(const StreamAt& r01, uint32_t& 
         const uint32_t d = (uint32_t)(ph >> 32);              // t, or j_k <= k
         if (k == 0) {
             t = d;
-            A[0] = 0;
+            *reinterpret_cast<U*>(A) = N == 1 ? (U)0 : S::FLAG;  // A[0] = 0
         } else {
-            uint8_t* aj = A + (((d >> 2) << 10) | (d & 3u));
-            A[1024 * (k >> 2) + (k & 3)] = *aj;                 // A[k] = A[j_k]
-            *aj = (uint8_t)k;                                   // A[j_k] = k
-            last = d;
+            U* aj = reinterpret_cast<U*>(A + d * S::ROW);
+            *reinterpret_cast<U*>(A + k * S::ROW) = *aj;        // A[k] = A[j_k]
+            *aj = k == N - 1 ? (U)k : (U)(S::FLAG | (U)k);      // A[j_k] = k
         }
-    }
-    if constexpr (MORE) {
-#pragma unroll
-        for (int q = 0; q < W; ++q) reinterpret_cast<uint32_t*>(A + kMoreRow<N>)[256 * q] = ~0u;
-        A[kMoreRow<N> + (((last >> 2) << 10) | (last & 3u))] = 0;   // the slot of position l_x (N = 1: slot 0)
     }
     return A;
 }
 
-// The next-window mask of slot s after shuffle_fill<N, true>: all ones, or
-// zero for the slot of position l_x (read sign-extended from its byte).
+// The next-window mask of slot s after shuffle_fill: all ones, or zero for
+// the slot of position l_x (the entry's top byte, read sign-extended).
 template <int N>
 __device__ __forceinline__ uint32_t shuffle_more(const uint8_t* A, uint32_t s) {
-    return (uint32_t)(int32_t) reinterpret_cast<const int8_t*>(A)[kMoreRow<N> + (((s >> 2) << 10) | (s & 3u))];
+    return (uint32_t)(int32_t) reinterpret_cast<const int8_t*>(A)[s * ShuffleSlice<N>::ROW + ShuffleSlice<N>::E - 1];
 }
 
 // Window position of slot s after shuffle_fill.
+template <int N>
 __device__ __forceinline__ uint32_t shuffle_pos(const uint8_t* A, uint32_t s) {
-    return A[((s >> 2) << 10) | (s & 3u)];
+    return A[s * ShuffleSlice<N>::ROW];
 }
 
 // The shuffle as words: byte q of perm[k] is the position of slot 4k + q
@@ -332,8 +336,12 @@ __device__ __forceinline__ uint32_t shuffle_perm(const StreamAt& r01, uint32_t (
     uint32_t t;
     const uint8_t* A = shuffle_fill<N>(r01, t);
 #pragma unroll
-    for (int k = 0; k < (N + 3) / 4; ++k) perm[k] = reinterpret_cast<const uint32_t*>(A)[256 * k];
-    if constexpr (N % 4 != 0) perm[(N + 3) / 4 - 1] &= (1u << (8 * (N % 4))) - 1u;
+    for (int k = 0; k < (N + 3) / 4; ++k) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int q = 0; q < 4 && 4 * k + q < N; ++q) v |= shuffle_pos<N>(A, (uint32_t)(4 * k + q)) << (8 * q);
+        perm[k] = v;
+    }
     return t;
 }
 
@@ -490,7 +498,7 @@ __device__ __forceinline__ T drelu_round1(T in0, T n1, uint64_t g, T mask, uint3
     // The flip bit t and the shuffle, both from seed_01.
     const StreamAt r01 = s01.at(g);
     uint32_t t;
-    const uint8_t* A = shuffle_fill<N, true>(r01, t);
+    const uint8_t* A = shuffle_fill<N>(r01, t);
 
     // Flip: [x] := (-1)^t [x]  (both parties); P1 cuts its negated share
     // -(-1)^t [x]_1 = (-1)^t n1.
@@ -506,7 +514,7 @@ __device__ __forceinline__ T drelu_round1(T in0, T n1, uint64_t g, T mask, uint3
         FT r, z;
         masks.slot(r01, j, f, r, z);
         FT w0, w1;
-        slot_messages<T, N, F, MaskDraws<N, F>::SH, !CAP>(a0k, nb1k, shuffle_pos(A, j), shuffle_more<N>(A, j), r, z,
+        slot_messages<T, N, F, MaskDraws<N, F>::SH, !CAP>(a0k, nb1k, shuffle_pos<N>(A, j), shuffle_more<N>(A, j), r, z,
                                                           f, w0, w1, least);
         if constexpr (CAP) {
             cap[e * N + j] = w0;
@@ -594,7 +602,7 @@ __device__ __forceinline__ void drelu_element_group(const T* __restrict__ X0, co
 
     const StreamAt r01 = s01.at(g);
     uint32_t t;
-    const uint8_t* A = shuffle_fill<N, true>(r01, t);
+    const uint8_t* A = shuffle_fill<N>(r01, t);
 
     const T a0 = flip_by(in0, t, mask);                  // the flip, as in drelu_round1
     const T nb1 = flip_by(n1, t, mask);
@@ -630,7 +638,7 @@ __device__ __forceinline__ void drelu_element_group(const T* __restrict__ X0, co
             FT r, z;
             stream_draws<N, F>(stream_field_at<N, F>(W, 2 * js), stream_field_at<N, F>(W, 2 * js + 1), r, z);
             FT w0, w1, v = f.p;
-            slot_messages<T, N, F, SH, true>(a0k, nb1k, shuffle_pos(A, js), shuffle_more<N>(A, js), r, z, f, w0, w1,
+            slot_messages<T, N, F, SH, true>(a0k, nb1k, shuffle_pos<N>(A, js), shuffle_more<N>(A, js), r, z, f, w0, w1,
                                              v);
             least = (valid && v < least) ? v : least;
         }
@@ -645,7 +653,7 @@ __device__ __forceinline__ void drelu_element_group(const T* __restrict__ X0, co
                 // slot j = SPB * blk + h (past the last slot: any slot, its message is not counted)
                 const bool valid = SPB * blk + h < (uint32_t)N;
                 const uint32_t js = valid ? SPB * blk + h : 0u;
-                const uint32_t pos = shuffle_pos(A, js);
+                const uint32_t pos = shuffle_pos<N>(A, js);
                 FT r, z;
                 if (h == 0)
                     block_draws<N, F, 0>(w, f, r, z);

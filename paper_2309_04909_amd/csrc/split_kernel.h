@@ -97,7 +97,7 @@ __global__ BC_KERNEL_ATTRS void k_send(SplitKArgs A, F f_arg) {
         for (int j = 0; j < N; ++j) {
             FT r, z;
             masks.slot(r01, j, f, r, z);
-            pack_slot<N>(words, j, (uint64_t)party_message<T, N, F, PARTY>(ak, shuffle_pos(sig, j), r, z, f));
+            pack_slot<N>(words, j, (uint64_t)party_message<T, N, F, PARTY>(ak, shuffle_pos<N>(sig, j), r, z, f));
         }
 #pragma unroll
         for (int k = 0; k < W; ++k) M[(uint64_t)k * A.n + e] = words[k];
