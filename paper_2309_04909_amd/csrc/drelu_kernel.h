@@ -533,12 +533,12 @@ __device__ __forceinline__ T drelu_round1(T in0, T n1, uint64_t g, T mask, uint3
 // (in_mask) and are first truncated by k_in bits into Z_{2^l} (Alg. 5); with
 // k_in = 0 and in_mask = mask the same expressions are the plain load.
 template <typename T, int N, typename F, bool RELU, bool CAP>
-__device__ __forceinline__ void drelu_element(const T* __restrict__ X0, const T* __restrict__ X1, T* Y0, T* Y1,
-                                              typename F::T* cap, uint64_t ncap, uint64_t e, uint64_t g, T mask,
-                                              T in_mask, uint32_t k_in, uint32_t k_lo, const Stream& s01,
-                                              const Stream& s02, const Stream& s12, const F& f) {
+__device__ __forceinline__ void drelu_element_of(T x0, T x1, T* Y0, T* Y1, typename F::T* cap, uint64_t ncap,
+                                                 uint64_t e, uint64_t g, T mask, T in_mask, uint32_t k_in,
+                                                 uint32_t k_lo, const Stream& s01, const Stream& s02,
+                                                 const Stream& s12, const F& f) {
     T in0, n1;
-    input_shares<T>(X0[e], X1[e], mask, in_mask, k_in, in0, n1);
+    input_shares<T>(x0, x1, mask, in_mask, k_in, in0, n1);
 
     uint32_t t;
     const T dp = drelu_round1<T, N, F, CAP>(in0, n1, g, mask, k_lo, s01, cap, ncap, e, f, t);
@@ -559,7 +559,21 @@ __device__ __forceinline__ void drelu_element(const T* __restrict__ X0, const T*
     Y1[e] = y1;
 }
 
-// One call: grid-stride over the n elements of one share pair.
+// drelu_element_of on the loaded shares X0[e], X1[e].
+template <typename T, int N, typename F, bool RELU, bool CAP>
+__device__ __forceinline__ void drelu_element(const T* __restrict__ X0, const T* __restrict__ X1, T* Y0, T* Y1,
+                                              typename F::T* cap, uint64_t ncap, uint64_t e, uint64_t g, T mask,
+                                              T in_mask, uint32_t k_in, uint32_t k_lo, const Stream& s01,
+                                              const Stream& s02, const Stream& s12, const F& f) {
+    drelu_element_of<T, N, F, RELU, CAP>(X0[e], X1[e], Y0, Y1, cap, ncap, e, g, mask, in_mask, k_in, k_lo, s01, s02,
+                                         s12, f);
+}
+
+// One call: grid-stride over the n elements of one share pair.  Each thread
+// loads its next element's shares before computing the current one, so the
+// loads have a whole element's work to land: with other traffic on the
+// memory system (the truncation beside it), a load at the top of each element
+// stalled the kernel.
 template <typename T, int N, typename F, bool RELU, bool CAP>
 __global__ BC_KERNEL_ATTRS void k_drelu(DreluKArgs A, F f_arg) {
     const F f = f_arg.vgpr();
@@ -570,9 +584,23 @@ __global__ BC_KERNEL_ATTRS void k_drelu(DreluKArgs A, F f_arg) {
     typename F::T* cap = static_cast<typename F::T*>(A.cap);
     const T mask = in_vgpr((T)A.ring_mask);
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < A.n; e += stride)
-        drelu_element<T, N, F, RELU, CAP>(X0, X1, Y0, Y1, cap, A.n, e, A.elem_base + e, mask, (T)A.in_mask, A.k_in,
-                                          A.k_lo, A.s01, A.s02, A.s12, f);
+    uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= A.n) return;
+    T x0 = X0[e], x1 = X1[e];
+    // Wait for the first shares before the loop: its head then waits on no
+    // memory operation (later entries have only the last stores outstanding).
+    asm volatile("" : "+v"(x0), "+v"(x1));
+    for (;;) {
+        const uint64_t en = e + stride;
+        const uint64_t ec = en < A.n ? en : e;           // after the last: a reload of this element
+        const T x0n = X0[ec], x1n = X1[ec];
+        drelu_element_of<T, N, F, RELU, CAP>(x0, x1, Y0, Y1, cap, A.n, e, A.elem_base + e, mask, (T)A.in_mask,
+                                             A.k_in, A.k_lo, A.s01, A.s02, A.s12, f);
+        if (en >= A.n) break;
+        e = en;
+        x0 = x0n;
+        x1 = x1n;
+    }
 }
 
 // Lane groups for small calls: G consecutive lanes share one element, so a
