@@ -371,3 +371,34 @@ def test_lane_groups_fused_truncation(B):
         t0, t1 = B.trunc_det(dev(x0), dev(x1), 64, 13)
         r0, r1 = B.relu(t0, t1, prm, sd)
         assert same(f0, r0) and same(f1, r1)
+
+
+@pytest.mark.parametrize("op", ["drelu", "relu"])
+@pytest.mark.parametrize("ell,lx,k_lo", [(64, 18, 13), (32, 8, 8)])
+def test_narrow_grid_many_elements_per_thread(B, op, ell, lx, k_lo):
+    """The one-call kernel on one block per compute unit: each thread walks
+    three or four elements, loading each element's shares one element ahead,
+    and the last stride is ragged.  Every element against the oracle (Alg. 7 /
+    Alg. 8), and the same with the tuned grid."""
+    rng = np.random.default_rng(4242 + lx)
+    p = default_prime(lx)
+    seeds = (0x243F6A8885A308D3, 0x13198A2E03707344, 0xA4093822299F31D0 + lx)
+    nonce = 0x5EED + lx
+    prm, sd = B.Params(ell, lx, k_lo), B.Seeds(*seeds, nonce)
+    w = B.ring_width(ell)
+    code = B.BC_OP_RELU if op == "relu" else B.BC_OP_DRELU
+    fn = B.relu if op == "relu" else B.drelu
+    n = 3 * 256 * 256 + 1001
+    x0, x1 = _inputs(rng, n, ell, lx, k_lo)
+    before = B.get_schedule("fused", lx + 1, w, code)
+    try:
+        B.set_schedule("fused", lx + 1, 1, w, code)
+        y0, y1 = fn(dev(x0), dev(x1), prm, sd, elem_base=3)
+    finally:
+        B.set_schedule("fused", lx + 1, before, w, code)
+    ofn = OPR.drelu if op == "drelu" else OPR.relu
+    e0, e1, _, _ = ofn(x0.astype(np.uint64), x1.astype(np.uint64), ell, lx, k_lo, p, seeds, nonce, elem_base=3)
+    assert np.array_equal(host(y0).astype(np.uint64), e0)
+    assert np.array_equal(host(y1).astype(np.uint64), e1)
+    z0, z1 = fn(dev(x0), dev(x1), prm, sd, elem_base=3)
+    assert same(z0, y0) and same(z1, y1)
