@@ -45,19 +45,26 @@ struct DreluKArgs {
     Stream s01, s02, s12;
 };
 
+// The share already shifted down by k_lo (pos <= l_x), shifted down by pos:
+// bits [0, l_x] are the window, bits above it are left for the caller to
+// mask.  With 64-bit shares: when bits [0, 2 l_x] fit in 32 bits a 32-bit
+// shift of the low word, else (windows of at most 32 bits) one
+// v_alignbit_b32 of the two halves does the variable shift.
+template <typename T, int N, typename FT>
+__device__ __forceinline__ FT window_low(T a, uint32_t pos) {
+    if constexpr (sizeof(T) == 8 && 2 * N - 1 <= 32)     // bits [0, 2 l_x] fit in the low word
+        return (FT)((uint32_t)a >> pos);
+    else if constexpr (sizeof(T) == 8 && N <= 32)
+        return (FT)__builtin_amdgcn_alignbit((uint32_t)(a >> 32), (uint32_t)a, pos);
+    else
+        return (FT)(a >> pos);
+}
+
 // Bits [pos, pos + l_x] of a share already shifted down by k_lo (pos <= l_x).
-// With 64-bit shares: when bits [0, 2 l_x] fit in 32 bits a 32-bit shift of
-// the low word, else (windows of at most 32 bits) one v_alignbit_b32 of the
-// two halves does the variable shift.
 template <typename T, int N, typename FT>
 __device__ __forceinline__ FT window(T a, uint32_t pos) {
     constexpr FT WIN1 = (FT)((2ull << (N - 1)) - 1);     // l_x + 1 bits
-    if constexpr (sizeof(T) == 8 && 2 * N - 1 <= 32)     // bits [0, 2 l_x] fit in the low word
-        return (FT)((uint32_t)a >> pos) & WIN1;
-    else if constexpr (sizeof(T) == 8 && N <= 32)
-        return (FT)__builtin_amdgcn_alignbit((uint32_t)(a >> 32), (uint32_t)a, pos) & WIN1;
-    else
-        return (FT)(a >> pos) & WIN1;
+    return window_low<T, N, FT>(a, pos) & WIN1;
 }
 
 // a * b + c in Z_p with b and c given shifted left by SH bits (SH = 0: the
@@ -135,26 +142,38 @@ __device__ __forceinline__ uint32_t p2_least_lazy(uint32_t least, uint32_t w0, u
 // that only test the slot, not capture its messages) and a field that has
 // the lazy forms, w0 and w1 are left below 2p, one congruent value each, and
 // P2 reduces their sum once.
-// `more_mask` is all ones unless pos = l_x, zero there (u_{l_x+1} := 0); the
-// overload without it derives it from pos.
+// `next_w` is the width of u_{i+1}: l_x, or 0 when pos = l_x (u_{l_x+1} :=
+// 0); the overload without it derives it from pos.
 template <typename T, int N, typename F, int SH = 0, bool LAZY = false>
-__device__ __forceinline__ void slot_messages(T a0, T nb1, uint32_t pos, uint32_t more_mask, typename F::T r,
+__device__ __forceinline__ void slot_messages(T a0, T nb1, uint32_t pos, uint32_t next_w, typename F::T r,
                                               typename F::T z, const F& f, typename F::T& w0, typename F::T& w1,
                                               typename F::T& least) {
     using FT = typename F::T;
     constexpr int LX = N - 1;
     constexpr FT TWO_LX = (FT)1 << LX;                   // 2^l_x mod p = 2^l_x
     constexpr FT WIN = TWO_LX - 1;                       // Z_{2^l_x}
-    const FT W0 = window<T, N, FT>(a0, pos);             // bits [k_lo + pos, k_lo + pos + l_x]
-    const FT W1 = window<T, N, FT>(nb1, pos);
-    const FT more = (FT)(int64_t)(int32_t)more_mask;
-    const FT u0n = (W0 >> 1) & more;                     // u_{i+1}, and u_{l_x+1} := 0
-    const FT u1n = (W1 >> 1) & more;
+    // W: bits [k_lo + pos, k_lo + pos + l_x] in bits [0, l_x]; with 32-bit
+    // field elements the bits above are left in place, since u_{i+1} reads
+    // bits [1, 1 + next_w) only and everything after is reduced mod 2^l_x
+    FT W0, W1, u0n, u1n;                                 // u_{i+1}, and u_{l_x+1} := 0
+    if constexpr (sizeof(FT) == 4) {
+        W0 = window_low<T, N, FT>(a0, pos);
+        W1 = window_low<T, N, FT>(nb1, pos);
+        u0n = __builtin_amdgcn_ubfe(W0, 1, next_w);
+        u1n = __builtin_amdgcn_ubfe(W1, 1, next_w);
+    } else {
+        W0 = window<T, N, FT>(a0, pos);
+        W1 = window<T, N, FT>(nb1, pos);
+        const FT more = (FT)0 - (FT)(next_w != 0);
+        u0n = (W0 >> 1) & more;
+        u1n = (W1 >> 1) & more;
+    }
     // adjacent sum and modulo switch (Alg. 6) for P0: v0 = u_i + u_{i+1} - 1 in Z_{2^l_x},
     // s0 = v0, or 2^l_x when v0 = 0, which is ((v0 - 1) mod 2^l_x) + 1.
     const FT s0 = ((W0 + u0n - 2) & WIN) + 1;
-    const FT v1 = ((FT)0 - W1 - u1n) & WIN;              // P1: -cut_i - cut_{i+1}
-    const FT s1 = v1 + (f.p - TWO_LX);
+    // P1: v1 = -(cut_i + cut_{i+1}) in Z_{2^l_x} and s1 = v1 + p - 2^l_x,
+    // which is (p - 1) - ((cut_i + cut_{i+1} - 1) mod 2^l_x)
+    const FT s1 = (f.p - 1) - ((W1 + u1n - 1) & WIN);
     if constexpr (LAZY && HasLazy<F>::value) {
         w0 = field_mul_add<SH, F, true>(f, s0, r, z);
         w1 = field_mul_add<SH, F, true>(f, s1, r, (FT)((f.p << SH) - z));
@@ -170,7 +189,7 @@ template <typename T, int N, typename F, int SH = 0, bool LAZY = false>
 __device__ __forceinline__ void slot_messages(T a0, T nb1, uint32_t pos, typename F::T r, typename F::T z, const F& f,
                                               typename F::T& w0, typename F::T& w1, typename F::T& least) {
     const uint32_t more_mask = (uint32_t)((int32_t)(pos - (uint32_t)(N - 1)) >> 31);   // all ones unless pos = l_x
-    slot_messages<T, N, F, SH, LAZY>(a0, nb1, pos, more_mask, r, z, f, w0, w1, least);
+    slot_messages<T, N, F, SH, LAZY>(a0, nb1, pos, (uint32_t)(N - 1) & more_mask, r, z, f, w0, w1, least);
 }
 
 // (-1)^t v mod 2^l for v < 2^l (Alg. 7's flip).  A select: the select-free
@@ -268,17 +287,17 @@ struct ShufflePlan {
 // address of a drawn index j is one multiply-add.  With E = 4 the 64 lanes of
 // a wave touch 64 different banks whatever their k; E = 4 while 8 blocks of N
 // rows fit the compute unit's 160 KiB of LDS (N <= 20), else E = 2.  Byte 0
-// of an entry is the window position; its top byte is 0 for the slot that
-// received the top position l_x (the last swap puts it at slot j_{N-1}, and
-// nothing moves it after) and 0xFF for every other slot, which shuffle_more
-// reads back as the all-ones / zero mask of the slot's next window
-// (u_{l_x+1} is 0).  The slice stays valid until the thread's next call.
+// of an entry is the window position; its top byte is the width of the
+// slot's next window u_{i+1}: 0 for the slot that received the top position
+// l_x (u_{l_x+1} is 0; the last swap puts it at slot j_{N-1}, and nothing
+// moves it after) and l_x for every other slot (shuffle_next_width).  The
+// slice stays valid until the thread's next call.
 template <int N>
 struct ShuffleSlice {
     static constexpr int E = N <= 20 ? 4 : 2;               // bytes per entry
     static constexpr int ROW = 256 * E;
     using U = typename std::conditional<E == 4, uint32_t, uint16_t>::type;
-    static constexpr U FLAG = (U)((U)0xFF << (8 * (E - 1)));   // top byte of a slot below l_x
+    static constexpr U FLAG = (U)((U)(N - 1) << (8 * (E - 1)));  // top byte of a slot below l_x
 };
 
 template <int N>
@@ -316,11 +335,11 @@ __device__ __forceinline__ uint8_t* shuffle_fill(const StreamAt& r01, uint32_t& 
     return A;
 }
 
-// The next-window mask of slot s after shuffle_fill: all ones, or zero for
-// the slot of position l_x (the entry's top byte, read sign-extended).
+// The width of slot s's next window after shuffle_fill: l_x, or 0 for the
+// slot of position l_x (the entry's top byte).
 template <int N>
-__device__ __forceinline__ uint32_t shuffle_more(const uint8_t* A, uint32_t s) {
-    return (uint32_t)(int32_t) reinterpret_cast<const int8_t*>(A)[s * ShuffleSlice<N>::ROW + ShuffleSlice<N>::E - 1];
+__device__ __forceinline__ uint32_t shuffle_next_width(const uint8_t* A, uint32_t s) {
+    return A[s * ShuffleSlice<N>::ROW + ShuffleSlice<N>::E - 1];
 }
 
 // Window position of slot s after shuffle_fill.
@@ -514,7 +533,7 @@ __device__ __forceinline__ T drelu_round1(T in0, T n1, uint64_t g, T mask, uint3
         FT r, z;
         masks.slot(r01, j, f, r, z);
         FT w0, w1;
-        slot_messages<T, N, F, MaskDraws<N, F>::SH, !CAP>(a0k, nb1k, shuffle_pos<N>(A, j), shuffle_more<N>(A, j), r, z,
+        slot_messages<T, N, F, MaskDraws<N, F>::SH, !CAP>(a0k, nb1k, shuffle_pos<N>(A, j), shuffle_next_width<N>(A, j), r, z,
                                                           f, w0, w1, least);
         if constexpr (CAP) {
             cap[e * N + j] = w0;
@@ -666,7 +685,7 @@ __device__ __forceinline__ void drelu_element_group(const T* __restrict__ X0, co
             FT r, z;
             stream_draws<N, F>(stream_field_at<N, F>(W, 2 * js), stream_field_at<N, F>(W, 2 * js + 1), r, z);
             FT w0, w1, v = f.p;
-            slot_messages<T, N, F, SH, true>(a0k, nb1k, shuffle_pos<N>(A, js), shuffle_more<N>(A, js), r, z, f, w0, w1,
+            slot_messages<T, N, F, SH, true>(a0k, nb1k, shuffle_pos<N>(A, js), shuffle_next_width<N>(A, js), r, z, f, w0, w1,
                                              v);
             least = (valid && v < least) ? v : least;
         }
@@ -688,7 +707,7 @@ __device__ __forceinline__ void drelu_element_group(const T* __restrict__ X0, co
                 else
                     block_draws<N, F, (SPB > 1 ? 1 : 0)>(w, f, r, z);
                 FT w0, w1, v = f.p;
-                slot_messages<T, N, F, SH, true>(a0k, nb1k, pos, shuffle_more<N>(A, js), r, z, f, w0, w1, v);
+                slot_messages<T, N, F, SH, true>(a0k, nb1k, pos, shuffle_next_width<N>(A, js), r, z, f, w0, w1, v);
                 least = (valid && v < least) ? v : least;
             }
         }

@@ -45,7 +45,7 @@ __device__ __forceinline__ typename F::T party_message(T ak, uint32_t pos, typen
         const FT s0 = ((Wv + un - 2) & WIN) + 1;                     // v0, or 2^l_x when v0 = 0
         return field_mul_add<SH>(f, s0, r, z);
     } else {
-        const FT s1 = (((FT)0 - Wv - un) & WIN) + (f.p - TWO_LX);    // v1 + p - 2^l_x
+        const FT s1 = (f.p - 1) - ((Wv + un - 1) & WIN);             // v1 + p - 2^l_x, v1 = -(Wv + un)
         return field_mul_add<SH>(f, s1, r, (FT)((f.p << SH) - z));
     }
 }
