@@ -38,6 +38,7 @@ struct DreluKArgs {
     void* y1;
     void* cap;
     uint64_t n;
+    uint64_t ncap;        // elements of the whole call (the capture's P1 half starts at ncap * N)
     uint64_t elem_base;
     uint64_t ring_mask;   // 2^l - 1
     uint64_t in_mask;     // 2^l_in - 1 of the input ring (l_in = l + k_in)
@@ -208,8 +209,13 @@ __device__ __forceinline__ T flip_by(T v, uint32_t t, T mask) {
 // cuts the windows from (Alg. 7).
 template <typename T>
 __device__ __forceinline__ void input_shares(T x0, T x1, T mask, T in_mask, uint32_t k_in, T& in0, T& n1) {
-    in0 = (T)((x0 & in_mask) >> k_in) & mask;
-    n1 = (T)((((T)0 - x1) & in_mask) >> k_in) & mask;
+    if (k_in == 0) {                                  // the plain shares (in_mask = mask): a uniform branch
+        in0 = x0 & mask;
+        n1 = (T)((T)0 - x1) & mask;
+    } else {
+        in0 = (T)((x0 & in_mask) >> k_in) & mask;
+        n1 = (T)((((T)0 - x1) & in_mask) >> k_in) & mask;
+    }
 }
 
 // DReLU's end (Alg. 7): P2's fresh sharing (rho, D' - rho), then the unflip:
@@ -546,13 +552,14 @@ __device__ __forceinline__ T drelu_round1(T in0, T n1, uint64_t g, T mask, uint3
 
 // One element, all three parties.  N = l_x + 1 windows, fixed at compile
 // time: every loop over windows and slots is unrolled and all window masks
-// are constants.  Reads X0[e], X1[e], writes Y0[e], Y1[e]; the randomness
-// belongs to global index g.  With CAP, the round-1 messages are captured
+// are constants.  From the loaded shares x0, x1 to the output shares y0,
+// y1; the randomness belongs to global index g, and e is the element's
+// index in the call (for the capture).  With CAP, the round-1 messages are captured
 // (drelu_round1).  With k_in > 0 the inputs are shares of Z_{2^(l + k_in)}
 // (in_mask) and are first truncated by k_in bits into Z_{2^l} (Alg. 5); with
 // k_in = 0 and in_mask = mask the same expressions are the plain load.
 template <typename T, int N, typename F, bool RELU, bool CAP>
-__device__ __forceinline__ void drelu_element_of(T x0, T x1, T* Y0, T* Y1, typename F::T* cap, uint64_t ncap,
+__device__ __forceinline__ void drelu_element_of(T x0, T x1, T& y0, T& y1, typename F::T* cap, uint64_t ncap,
                                                  uint64_t e, uint64_t g, T mask, T in_mask, uint32_t k_in,
                                                  uint32_t k_lo, const Stream& s01, const Stream& s02,
                                                  const Stream& s12, const F& f) {
@@ -562,7 +569,6 @@ __device__ __forceinline__ void drelu_element_of(T x0, T x1, T* Y0, T* Y1, typen
     uint32_t t;
     const T dp = drelu_round1<T, N, F, CAP>(in0, n1, g, mask, k_lo, s01, cap, ncap, e, f, t);
 
-    T y0, y1;
     if constexpr (!RELU) {
         const Words4 w = s02.block(g, TAG_RESP, 0);               // rho from seed_02
         drelu_finish<T>(dp, (T)join64(w.w0, w.w1), t, mask, y0, y1);
@@ -574,25 +580,43 @@ __device__ __forceinline__ void drelu_element_of(T x0, T x1, T* Y0, T* Y1, typen
         const T bc1 = (T)((T)(ba0 + ba1) * (T)(bb0 + bb1) - bc0) & mask;
         relu_finish<T>(dp, in0, in1, ba0, bb0, bc0, ba1, bb1, bc1, t, mask, y0, y1);
     }
-    Y0[e] = y0;
-    Y1[e] = y1;
 }
 
-// drelu_element_of on the loaded shares X0[e], X1[e].
+// drelu_element_of from X0[e], X1[e] to Y0[e], Y1[e].
 template <typename T, int N, typename F, bool RELU, bool CAP>
 __device__ __forceinline__ void drelu_element(const T* __restrict__ X0, const T* __restrict__ X1, T* Y0, T* Y1,
                                               typename F::T* cap, uint64_t ncap, uint64_t e, uint64_t g, T mask,
                                               T in_mask, uint32_t k_in, uint32_t k_lo, const Stream& s01,
                                               const Stream& s02, const Stream& s12, const F& f) {
-    drelu_element_of<T, N, F, RELU, CAP>(X0[e], X1[e], Y0, Y1, cap, ncap, e, g, mask, in_mask, k_in, k_lo, s01, s02,
+    T y0, y1;
+    drelu_element_of<T, N, F, RELU, CAP>(X0[e], X1[e], y0, y1, cap, ncap, e, g, mask, in_mask, k_in, k_lo, s01, s02,
                                          s12, f);
+    Y0[e] = y0;
+    Y1[e] = y1;
 }
 
-// One call: grid-stride over the n elements of one share pair.  Each thread
-// loads its next element's shares before computing the current one, so the
-// loads have a whole element's work to land: with other traffic on the
-// memory system (the truncation beside it), a load at the top of each element
-// stalled the kernel.
+// Elements of one k_drelu launch: at most 2^28, so that element indices and
+// byte offsets (and an index plus the grid's stride) stay in 32 bits; the
+// host runs a larger call as launches over consecutive ranges, each with
+// its own element offset, which gives the results of one launch.
+constexpr uint64_t kLaunchElems = 1ull << 28;
+
+// Element i of p, addressed as p plus a 32-bit byte offset (the load or
+// store then takes p from scalar registers and the offset from one VGPR).
+template <typename T>
+__device__ __forceinline__ T load_at(const T* p, uint32_t i) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + (uint32_t)(i * (uint32_t)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ void store_at(T* p, uint32_t i, T v) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(p) + (uint32_t)(i * (uint32_t)sizeof(T))) = v;
+}
+
+// One launch: grid-stride over its n <= kLaunchElems elements of one share
+// pair.  Each thread loads its next element's shares before computing the
+// current one, so the loads have a whole element's work to land: with other
+// traffic on the memory system (the truncation beside it), a load at the top
+// of each element stalled the kernel.
 template <typename T, int N, typename F, bool RELU, bool CAP>
 __global__ BC_KERNEL_ATTRS void k_drelu(DreluKArgs A, F f_arg) {
     const F f = f_arg.vgpr();
@@ -602,20 +626,24 @@ __global__ BC_KERNEL_ATTRS void k_drelu(DreluKArgs A, F f_arg) {
     T* Y1 = static_cast<T*>(A.y1);
     typename F::T* cap = static_cast<typename F::T*>(A.cap);
     const T mask = in_vgpr((T)A.ring_mask);
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= A.n) return;
-    T x0 = X0[e], x1 = X1[e];
+    const uint32_t n = (uint32_t)A.n;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    T x0 = load_at(X0, e), x1 = load_at(X1, e);
     // Wait for the first shares before the loop: its head then waits on no
     // memory operation (later entries have only the last stores outstanding).
     asm volatile("" : "+v"(x0), "+v"(x1));
     for (;;) {
-        const uint64_t en = e + stride;
-        const uint64_t ec = en < A.n ? en : e;           // after the last: a reload of this element
-        const T x0n = X0[ec], x1n = X1[ec];
-        drelu_element_of<T, N, F, RELU, CAP>(x0, x1, Y0, Y1, cap, A.n, e, A.elem_base + e, mask, (T)A.in_mask,
+        const uint32_t en = e + stride;
+        const uint32_t ec = en < n ? en : e;             // after the last: a reload of this element
+        const T x0n = load_at(X0, ec), x1n = load_at(X1, ec);
+        T y0, y1;
+        drelu_element_of<T, N, F, RELU, CAP>(x0, x1, y0, y1, cap, A.ncap, e, A.elem_base + e, mask, (T)A.in_mask,
                                              A.k_in, A.k_lo, A.s01, A.s02, A.s12, f);
-        if (en >= A.n) break;
+        store_at(Y0, e, y0);
+        store_at(Y1, e, y1);
+        if (en >= n) break;
         e = en;
         x0 = x0n;
         x1 = x1n;
@@ -785,6 +813,7 @@ inline DreluKArgs make_kargs(const DreluLaunch& L) {
     A.y1 = L.y1;
     A.cap = L.cap;
     A.n = L.n;
+    A.ncap = L.n;
     A.elem_base = L.elem_base;
     A.ring_mask = L.ell >= 64 ? ~0ull : ((1ull << L.ell) - 1);
     A.in_mask = L.ell + L.k_in >= 64 ? ~0ull : ((1ull << (L.ell + L.k_in)) - 1);
@@ -803,10 +832,27 @@ hipError_t launch_field(const DreluLaunch& L, const F& f, hipStream_t st) {
         hipLaunchKernelGGL((k_drelu_group<T, N, F, RELU, 8>), dim3(L.grid), dim3(L.block), 0, st, A, f);
     else if (L.group == 4)
         hipLaunchKernelGGL((k_drelu_group<T, N, F, RELU, 4>), dim3(L.grid), dim3(L.block), 0, st, A, f);
-    else if (L.cap)
-        hipLaunchKernelGGL((k_drelu<T, N, F, RELU, true>), dim3(L.grid), dim3(L.block), 0, st, A, f);
-    else
-        hipLaunchKernelGGL((k_drelu<T, N, F, RELU, false>), dim3(L.grid), dim3(L.block), 0, st, A, f);
+    else {
+        // consecutive ranges of at most kLaunchElems elements
+        for (uint64_t off = 0; off < L.n; off += kLaunchElems) {
+            DreluKArgs R = A;
+            R.n = L.n - off < kLaunchElems ? L.n - off : kLaunchElems;
+            R.x0 = static_cast<const T*>(A.x0) + off;
+            R.x1 = static_cast<const T*>(A.x1) + off;
+            R.y0 = static_cast<T*>(A.y0) + off;
+            R.y1 = static_cast<T*>(A.y1) + off;
+            R.elem_base = A.elem_base + off;
+            if (L.cap) {
+                R.cap = static_cast<typename F::T*>(A.cap) + off * N;
+                hipLaunchKernelGGL((k_drelu<T, N, F, RELU, true>), dim3(L.grid), dim3(L.block), 0, st, R, f);
+            } else {
+                hipLaunchKernelGGL((k_drelu<T, N, F, RELU, false>), dim3(L.grid), dim3(L.block), 0, st, R, f);
+            }
+            const hipError_t err = hipGetLastError();
+            if (err != hipSuccess) return err;
+        }
+        return hipSuccess;
+    }
     return hipGetLastError();
 }
 

@@ -240,3 +240,33 @@ def test_layer_chain_73859072(B, oracle_pool):
         t0, t1 = OPR.trunc_det(x0[idx], x1[idx], 64, 13, 0)
         o0, o1, _, _ = OPR.relu(t0, t1, 51, 7, 11, 251, SEEDS, 200 + i, g=idx.astype(U64))
         assert np.array_equal(host(s.y0)[idx], o0) and np.array_equal(host(s.y1)[idx], o1), f"segment {i}"
+
+
+@pytest.mark.parametrize("op", ["drelu", "relu"])
+def test_call_above_one_launch(B, op):
+    """A call of 2^28 + 5 elements runs as two launches (one launch indexes
+    elements and byte offsets in 32 bits): outputs around the boundary and on
+    random samples equal the oracle's (Alg. 7 / Alg. 8), and the elements past
+    the boundary equal a call on them alone with their element offset."""
+    lx, k_lo, half = 18, 13, 1 << 28
+    n = half + 5
+    prm = B.Params(64, lx, k_lo)
+    nonce = 0xB16 + (op == "relu")
+    sd = B.Seeds(*SEEDS, nonce)
+    fn = B.relu if op == "relu" else B.drelu
+    gen = torch.Generator(device="cuda").manual_seed(17)
+    x0 = torch.randint(-(1 << 62), 1 << 62, (n,), device="cuda", dtype=torch.int64, generator=gen)
+    x1 = torch.randint(-(1 << 62), 1 << 62, (n,), device="cuda", dtype=torch.int64, generator=gen)
+    y0, y1 = (y.view(torch.int64) for y in fn(x0, x1, prm, sd))
+    rng = np.random.default_rng(23)
+    idx = np.unique(np.concatenate([np.arange(half - 3, n), np.arange(4), rng.integers(0, n, size=300)]))
+    it = torch.from_numpy(idx.astype(np.int64)).cuda()
+    xs0, xs1 = host(x0[it]), host(x1[it])
+    ofn = OPR.relu if op == "relu" else OPR.drelu
+    e0, e1, _, _ = ofn(xs0, xs1, 64, lx, k_lo, default_prime(lx), SEEDS, nonce, g=idx.astype(U64))
+    assert np.array_equal(host(y0[it]), e0) and np.array_equal(host(y1[it]), e1)
+    t0, t1 = fn(x0[half:], x1[half:], prm, sd, elem_base=half)
+    assert torch.equal(t0.view(torch.int64), y0[half:])
+    assert torch.equal(t1.view(torch.int64), y1[half:])
+    del x0, x1, y0, y1
+    torch.cuda.empty_cache()
