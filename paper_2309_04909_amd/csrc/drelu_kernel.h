@@ -328,11 +328,15 @@ __device__ __forceinline__ uint8_t* shuffle_fill(const StreamAt& r01, uint32_t& 
         const uint64_t ph = (uint64_t)hi * m + (uint32_t)(pl >> 32);
         lo = (uint32_t)pl;
         hi = (uint32_t)ph;
-        const uint32_t d = (uint32_t)(ph >> 32);              // t, or j_k <= k
+        uint32_t d = (uint32_t)(ph >> 32);                    // t, or j_k <= k
         if (k == 0) {
             t = d;
             *reinterpret_cast<U*>(A) = N == 1 ? (U)0 : S::FLAG;  // A[0] = 0
         } else {
+            // d as a register of its own: the entry's address is then one
+            // shift-add, where the compiler would otherwise cut d * ROW out
+            // of the 64-bit product with an alignbit and a mask
+            asm("" : "+v"(d));
             U* aj = reinterpret_cast<U*>(A + d * S::ROW);
             *reinterpret_cast<U*>(A + k * S::ROW) = *aj;        // A[k] = A[j_k]
             *aj = k == N - 1 ? (U)k : (U)(S::FLAG | (U)k);      // A[j_k] = k
