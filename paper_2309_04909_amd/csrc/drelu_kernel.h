@@ -606,14 +606,15 @@ __device__ __forceinline__ void drelu_element(const T* __restrict__ X0, const T*
 constexpr uint64_t kLaunchElems = 1ull << 28;
 
 // Element i of p, addressed as p plus a 32-bit byte offset (the load or
-// store then takes p from scalar registers and the offset from one VGPR).
+// store then takes p from scalar registers and the offset from one VGPR),
+// nontemporal (ld_nt / st_nt).
 template <typename T>
 __device__ __forceinline__ T load_at(const T* p, uint32_t i) {
-    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + (uint32_t)(i * (uint32_t)sizeof(T)));
+    return ld_nt(reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + (uint32_t)(i * (uint32_t)sizeof(T))));
 }
 template <typename T>
 __device__ __forceinline__ void store_at(T* p, uint32_t i, T v) {
-    *reinterpret_cast<T*>(reinterpret_cast<char*>(p) + (uint32_t)(i * (uint32_t)sizeof(T))) = v;
+    st_nt(reinterpret_cast<T*>(reinterpret_cast<char*>(p) + (uint32_t)(i * (uint32_t)sizeof(T))), v);
 }
 
 // One launch: grid-stride over its n <= kLaunchElems elements of one share

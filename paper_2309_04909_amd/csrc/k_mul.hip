@@ -74,10 +74,10 @@ __global__ __launch_bounds__(256) void k_mul(MulKArgs A) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t nv = A.n / V;
     for (uint64_t v = tid; v < nv; v += stride) {
-        const vec_t<T, V> a = *reinterpret_cast<const vec_t<T, V>*>(X0 + v * V);
-        const vec_t<T, V> b = *reinterpret_cast<const vec_t<T, V>*>(X1 + v * V);
-        const vec_t<T, V> c = *reinterpret_cast<const vec_t<T, V>*>(Y0 + v * V);
-        const vec_t<T, V> d = *reinterpret_cast<const vec_t<T, V>*>(Y1 + v * V);
+        const vec_t<T, V> a = ld_nt(reinterpret_cast<const vec_t<T, V>*>(X0 + v * V));
+        const vec_t<T, V> b = ld_nt(reinterpret_cast<const vec_t<T, V>*>(X1 + v * V));
+        const vec_t<T, V> c = ld_nt(reinterpret_cast<const vec_t<T, V>*>(Y0 + v * V));
+        const vec_t<T, V> d = ld_nt(reinterpret_cast<const vec_t<T, V>*>(Y1 + v * V));
         vec_t<T, V> o0, o1;
 #pragma unroll
         for (int k = 0; k < V; ++k) {
@@ -86,8 +86,8 @@ __global__ __launch_bounds__(256) void k_mul(MulKArgs A) {
             o0[k] = r0;
             o1[k] = r1;
         }
-        *reinterpret_cast<vec_t<T, V>*>(Z0 + v * V) = o0;
-        *reinterpret_cast<vec_t<T, V>*>(Z1 + v * V) = o1;
+        st_nt(reinterpret_cast<vec_t<T, V>*>(Z0 + v * V), o0);
+        st_nt(reinterpret_cast<vec_t<T, V>*>(Z1 + v * V), o1);
     }
     for (uint64_t i = nv * V + tid; i < A.n; i += stride) {
         T r0, r1;

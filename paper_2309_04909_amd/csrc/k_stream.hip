@@ -60,8 +60,8 @@ __global__ __launch_bounds__(256) void k_map2(const TI* x0, const TI* x1, TO* y0
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t nv = n / V;
     for (uint64_t v = tid; v < nv; v += stride) {
-        const vec_t<TI, V> a = *reinterpret_cast<const vec_t<TI, V>*>(x0 + v * V);
-        const vec_t<TI, V> b = *reinterpret_cast<const vec_t<TI, V>*>(x1 + v * V);
+        const vec_t<TI, V> a = ld_nt(reinterpret_cast<const vec_t<TI, V>*>(x0 + v * V));
+        const vec_t<TI, V> b = ld_nt(reinterpret_cast<const vec_t<TI, V>*>(x1 + v * V));
         vec_t<TO, V> c, d;
 #pragma unroll
         for (int k = 0; k < V; ++k) {
@@ -70,8 +70,8 @@ __global__ __launch_bounds__(256) void k_map2(const TI* x0, const TI* x1, TO* y0
             c[k] = ck;
             d[k] = dk;
         }
-        *reinterpret_cast<vec_t<TO, V>*>(y0 + v * V) = c;
-        *reinterpret_cast<vec_t<TO, V>*>(y1 + v * V) = d;
+        st_nt(reinterpret_cast<vec_t<TO, V>*>(y0 + v * V), c);
+        st_nt(reinterpret_cast<vec_t<TO, V>*>(y1 + v * V), d);
     }
     for (uint64_t i = nv * V + tid; i < n; i += stride) {
         TO c, d;

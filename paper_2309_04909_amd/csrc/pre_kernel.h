@@ -73,7 +73,7 @@ __global__ BC_KERNEL_ATTRS void k_expand(ExpandKArgs A, F f) {
         uint32_t perm[(N + 3) / 4];
         const uint32_t t = shuffle_perm<N>(r01, perm);
 #pragma unroll
-        for (int k = 0; k < (N + 3) / 4; ++k) A.perm[(uint64_t)k * n + e] = k == 0 ? perm[0] | t << 7 : perm[k];
+        for (int k = 0; k < (N + 3) / 4; ++k) st_nt(&A.perm[(uint64_t)k * n + e], k == 0 ? perm[0] | t << 7 : perm[k]);
         MaskReader<N, F> masks;
         uint64_t* rz = static_cast<uint64_t*>(A.rz);
         constexpr int K = RzLayout<N>::K;
@@ -88,7 +88,7 @@ __global__ BC_KERNEL_ATTRS void k_expand(ExpandKArgs A, F f) {
                 const int v = 2 * j + h;
                 acc |= (uint64_t)(h ? z : r) << (N * (v % K) % 64);
                 if (v % K == K - 1 || v == 2 * N - 1) {
-                    rz[(uint64_t)(v / K) * n + e] = acc;
+                    st_nt(&rz[(uint64_t)(v / K) * n + e], acc);
                     acc = 0;
                 }
             }
@@ -96,7 +96,7 @@ __global__ BC_KERNEL_ATTRS void k_expand(ExpandKArgs A, F f) {
         if constexpr (RELU) {
             T ba0, bb0, bc0, ba1, bb1;
             beaver_shares<T>(A.s02, A.s12, g, mask, ba0, bb0, bc0, ba1, bb1);
-            static_cast<T*>(A.tail)[e] = (T)((T)(ba0 + ba1) * (T)(bb0 + bb1) - bc0) & mask;   // P2's [c]_1
+            st_nt(&static_cast<T*>(A.tail)[e], (T)((T)((T)(ba0 + ba1) * (T)(bb0 + bb1) - bc0) & mask));   // P2's [c]_1
         }
     }
 }
@@ -131,10 +131,10 @@ __device__ __forceinline__ void drelu_pre_element(const T* __restrict__ X0, cons
     using FT = typename F::T;
     const uint64_t n = R.n;
     T in0, n1;
-    input_shares<T>(X0[e], X1[e], mask, in_mask, k_in, in0, n1);
+    input_shares<T>(ld_nt(&X0[e]), ld_nt(&X1[e]), mask, in_mask, k_in, in0, n1);
     uint32_t perm[(N + 3) / 4];
 #pragma unroll
-    for (int k = 0; k < (N + 3) / 4; ++k) perm[k] = R.perm[(uint64_t)k * n + e];
+    for (int k = 0; k < (N + 3) / 4; ++k) perm[k] = ld_nt(&R.perm[(uint64_t)k * n + e]);
     const uint32_t t = (perm[0] >> 7) & 1u;
     const T a0 = flip_by(in0, t, mask);                // the flip, as in drelu_round1
     const T nb1 = flip_by(n1, t, mask);
@@ -148,7 +148,7 @@ __device__ __forceinline__ void drelu_pre_element(const T* __restrict__ X0, cons
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int v = 2 * j + h;
-            if (v % K == 0) cur = R.rz[(uint64_t)(v / K) * n + e];
+            if (v % K == 0) cur = ld_nt(&R.rz[(uint64_t)(v / K) * n + e]);
             rv[h] = (FT)((cur >> (N * (v % K) % 64)) & RzLayout<N>::FIELD);
         }
         const FT r = rv[0], z = rv[1];
@@ -169,10 +169,10 @@ __device__ __forceinline__ void drelu_pre_element(const T* __restrict__ X0, cons
         const T in1 = (T)((T)0 - n1) & mask;
         T ba0, bb0, bc0, ba1, bb1;                                  // the parties' triple shares, regenerated
         beaver_shares<T>(s02, s12, g, mask, ba0, bb0, bc0, ba1, bb1);
-        relu_finish<T>(dp, in0, in1, ba0, bb0, bc0, ba1, bb1, R.tail[e], t, mask, y0, y1);
+        relu_finish<T>(dp, in0, in1, ba0, bb0, bc0, ba1, bb1, ld_nt(&R.tail[e]), t, mask, y0, y1);
     }
-    Y0[e] = y0;
-    Y1[e] = y1;
+    st_nt(&Y0[e], y0);
+    st_nt(&Y1[e], y1);
 }
 
 // Online call: grid-stride over the n elements of one share pair.

@@ -100,7 +100,7 @@ __global__ BC_KERNEL_ATTRS void k_send(SplitKArgs A, F f_arg) {
             pack_slot<N>(words, j, (uint64_t)party_message<T, N, F, PARTY>(ak, shuffle_pos<N>(sig, j), r, z, f));
         }
 #pragma unroll
-        for (int k = 0; k < W; ++k) M[(uint64_t)k * A.n + e] = words[k];
+        for (int k = 0; k < W; ++k) st_nt(&M[(uint64_t)k * A.n + e], words[k]);
     }
 }
 
@@ -119,8 +119,8 @@ __global__ BC_KERNEL_ATTRS void k_reply(SplitKArgs A, F f_arg) {
         uint32_t w0[W], w1[W];
 #pragma unroll
         for (int k = 0; k < W; ++k) {
-            w0[k] = M0[(uint64_t)k * A.n + e];
-            w1[k] = M1[(uint64_t)k * A.n + e];
+            w0[k] = ld_nt(&M0[(uint64_t)k * A.n + e]);
+            w1[k] = ld_nt(&M1[(uint64_t)k * A.n + e]);
         }
         FT least = f.p;
 #pragma unroll
@@ -131,8 +131,8 @@ __global__ BC_KERNEL_ATTRS void k_reply(SplitKArgs A, F f_arg) {
         const T dp = least == 0 ? 1 : 0;                              // D'
         const Words4 w = A.s02.block(A.elem_base + e, TAG_RESP, 0);    // rho from seed_02
         const T rho = (T)join64(w.w0, w.w1) & mask;
-        D0[e] = rho;
-        D1[e] = (T)(dp - rho) & mask;
+        st_nt(&D0[e], rho);
+        st_nt(&D1[e], (T)((T)(dp - rho) & mask));
     }
 }
 
