@@ -593,10 +593,10 @@ __device__ __forceinline__ void drelu_element(const T* __restrict__ X0, const T*
                                               T in_mask, uint32_t k_in, uint32_t k_lo, const Stream& s01,
                                               const Stream& s02, const Stream& s12, const F& f) {
     T y0, y1;
-    drelu_element_of<T, N, F, RELU, CAP>(X0[e], X1[e], y0, y1, cap, ncap, e, g, mask, in_mask, k_in, k_lo, s01, s02,
-                                         s12, f);
-    Y0[e] = y0;
-    Y1[e] = y1;
+    drelu_element_of<T, N, F, RELU, CAP>(ld_nt(&X0[e]), ld_nt(&X1[e]), y0, y1, cap, ncap, e, g, mask, in_mask, k_in,
+                                         k_lo, s01, s02, s12, f);
+    st_nt(&Y0[e], y0);
+    st_nt(&Y1[e], y1);
 }
 
 // Elements of one k_drelu launch: at most 2^28, so that element indices and
@@ -678,7 +678,7 @@ __device__ __forceinline__ void drelu_element_group(const T* __restrict__ X0, co
     constexpr int ROUNDS = (NB + G - 1) / G;
 
     T in0, n1;
-    input_shares<T>(X0[e], X1[e], mask, in_mask, k_in, in0, n1);
+    input_shares<T>(ld_nt(&X0[e]), ld_nt(&X1[e]), mask, in_mask, k_in, in0, n1);
 
     const StreamAt r01 = s01.at(g);
     uint32_t t;
@@ -777,8 +777,8 @@ __device__ __forceinline__ void drelu_element_group(const T* __restrict__ X0, co
         relu_finish<T>(dp, in0, in1, ba0, bb0, bc0, ba1, bb1, bc1, t, mask, y0, y1);
     }
     if (lane == 0) {
-        Y0[e] = y0;
-        Y1[e] = y1;
+        st_nt(&Y0[e], y0);
+        st_nt(&Y1[e], y1);
     }
 }
 

@@ -67,7 +67,7 @@ template <typename T, int N, typename F, bool RELU, bool CAP>
 __device__ __forceinline__ void rss_element(const RssKArgs& A, const T* __restrict__ X0, const T* __restrict__ X1,
                                             const T* __restrict__ X2, T* Y0, T* Y1, T* Y2,
                                             typename F::T* cap, uint64_t e, uint64_t g, T mask, const F& f) {
-    const T x[3] = {X0[e], X1[e], X2[e]};
+    const T x[3] = {ld_nt(&X0[e]), ld_nt(&X1[e]), ld_nt(&X2[e])};
 
     // round 1 and P2's zero test on the 2-of-2 input ([x]_0 + [x]_1, [x]_2),
     // whose second holder cuts its negated share -[x]_2
@@ -108,13 +108,13 @@ __device__ __forceinline__ void rss_element(const RssKArgs& A, const T* __restri
         const T gr[3] = {(T)(gb0 - gb2), (T)(gb1 - gb0), (T)(gb2 - gb1)};
         T z[3];
         rss_product<T>(x, y, gr, z);
-        Y0[e] = z[0] & mask;
-        Y1[e] = z[1] & mask;
-        Y2[e] = z[2] & mask;
+        st_nt(&Y0[e], (T)(z[0] & mask));
+        st_nt(&Y1[e], (T)(z[1] & mask));
+        st_nt(&Y2[e], (T)(z[2] & mask));
     } else {
-        Y0[e] = y[0] & mask;
-        Y1[e] = y[1] & mask;
-        Y2[e] = y[2] & mask;
+        st_nt(&Y0[e], (T)(y[0] & mask));
+        st_nt(&Y1[e], (T)(y[1] & mask));
+        st_nt(&Y2[e], (T)(y[2] & mask));
     }
 }
 
