@@ -617,6 +617,27 @@ __device__ __forceinline__ void store_at(T* p, uint32_t i, T v) {
     st_nt(reinterpret_cast<T*>(reinterpret_cast<char*>(p) + (uint32_t)(i * (uint32_t)sizeof(T))), v);
 }
 
+// Element i of the buffer r (a raw buffer of 4- or 8-byte elements), loaded
+// nontemporal; an element past the buffer's end reads as 0 without a memory
+// access (the buffer's range check).
+template <typename T>
+__device__ __forceinline__ T load_buf(__amdgpu_buffer_rsrc_t r, uint32_t i) {
+    constexpr int kNontemporal = 2;
+    if constexpr (sizeof(T) == 8) {
+        const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, i * 8u, 0, kNontemporal);
+        return (T)w[0] | ((T)w[1] << 32);
+    } else {
+        return (T)__builtin_amdgcn_raw_buffer_load_b32(r, i * 4u, 0, kNontemporal);
+    }
+}
+
+// A raw buffer over n elements of T at p (word 3: the gfx9 data format of
+// raw, unswizzled buffers).
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const T* p, uint32_t n) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(p), (short)0, (int)(n * (uint32_t)sizeof(T)), 0x00020000);
+}
+
 // One launch: grid-stride over its n <= kLaunchElems elements of one share
 // pair.  Each thread loads its next element's shares before computing the
 // current one, so the loads have a whole element's work to land: with other
@@ -635,14 +656,14 @@ __global__ BC_KERNEL_ATTRS void k_drelu(DreluKArgs A, F f_arg) {
     const uint32_t stride = gridDim.x * blockDim.x;
     uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
+    const __amdgpu_buffer_rsrc_t B0 = buffer_of(X0, n), B1 = buffer_of(X1, n);
     T x0 = load_at(X0, e), x1 = load_at(X1, e);
     // Wait for the first shares before the loop: its head then waits on no
     // memory operation (later entries have only the last stores outstanding).
     asm volatile("" : "+v"(x0), "+v"(x1));
     for (;;) {
         const uint32_t en = e + stride;
-        const uint32_t ec = en < n ? en : e;             // after the last: a reload of this element
-        const T x0n = load_at(X0, ec), x1n = load_at(X1, ec);
+        const T x0n = load_buf<T>(B0, en), x1n = load_buf<T>(B1, en);   // past the last: 0, no access
         T y0, y1;
         drelu_element_of<T, N, F, RELU, CAP>(x0, x1, y0, y1, cap, A.ncap, e, A.elem_base + e, mask, (T)A.in_mask,
                                              A.k_in, A.k_lo, A.s01, A.s02, A.s12, f);
