@@ -85,6 +85,15 @@ __device__ __forceinline__ typename F::T field_mul_add(const F& f, typename F::T
     }
 }
 
+// P1's reshare addend p - z, kept shifted by SH like z, from a z whose low
+// SH bits may carry stray bits (stream_draws): they are masked first.
+template <int SH, typename F>
+__device__ __forceinline__ typename F::T reshare_neg(const F& f, typename F::T z) {
+    using FT = typename F::T;
+    constexpr FT KEEP = (FT)~(((FT)1 << SH) - 1);
+    return (FT)((f.p << SH) - (FT)(z & KEEP));
+}
+
 // Whether field F offers the lazy forms (a value below 2p with 4p < 2^32).
 template <typename F, typename = void>
 struct HasLazy : std::false_type {};
@@ -177,11 +186,11 @@ __device__ __forceinline__ void slot_messages(T a0, T nb1, uint32_t pos, uint32_
     const FT s1 = (f.p - 1) - ((W1 + u1n - 1) & WIN);
     if constexpr (LAZY && HasLazy<F>::value) {
         w0 = field_mul_add<SH, F, true>(f, s0, r, z);
-        w1 = field_mul_add<SH, F, true>(f, s1, r, (FT)((f.p << SH) - z));
+        w1 = field_mul_add<SH, F, true>(f, s1, r, reshare_neg<SH>(f, z));
         least = p2_least_lazy(least, w0, w1, f);
     } else {
         w0 = field_mul_add<SH>(f, s0, r, z);                           // mask, reshare
-        w1 = field_mul_add<SH>(f, s1, r, (FT)((f.p << SH) - z));       // P1: s1 r - z
+        w1 = field_mul_add<SH>(f, s1, r, reshare_neg<SH>(f, z));       // P1: s1 r - z
         least = p2_least(least, w0, w1, f);                            // P2 reconstructs and tests
     }
 }
@@ -400,11 +409,17 @@ __device__ __forceinline__ void stream_draws(typename F::T R, typename F::T Z, t
                                              typename F::T& z) {
     using FT = typename F::T;
     constexpr int SH = MaskDraws<N, F>::SH;
-    r = min(max(R, (FT)((FT)1 << SH)), (FT)((FT)(F::p - 1) << SH));    // clamp into Z_p^* (one v_med3)
+    constexpr FT KEEP = (FT)~(((FT)1 << SH) - 1);
+    // r: clamp into Z_p^* (one v_med3); its low SH bits cleared, so that a
+    // product r s has zero low SH bits.  z keeps whatever bits R and Z carry
+    // below SH: an addend's low SH bits then stay below bit SH of a r + z
+    // and never reach the folded value, and a subtraction from it masks them
+    // first (reshare_neg).
+    r = min(max((FT)(R & KEEP), (FT)((FT)1 << SH)), (FT)((FT)(F::p - 1) << SH));
     if constexpr (SH > 0 && F::p == (1ull << N) - 1)
         z = Z;                                      // Mersenne: Z <= p already stands for Z mod p
     else
-        z = min(Z, (FT)(Z - ((FT)F::p << SH)));     // Z mod p (Z < 2p)
+        z = min(Z, (FT)(Z - ((FT)F::p << SH)));     // Z mod p (Z < 2p; the low SH bits decide nothing)
 }
 
 // Slot H's r and z of mask block w without STREAM (H < SPB, compile-time).
@@ -437,7 +452,8 @@ struct MaskReader {
         const int q = w - 4 * b;
         return q < 0 ? prev : q == 0 ? cur.w0 : q == 1 ? cur.w1 : q == 2 ? cur.w2 : cur.w3;
     }
-    // The raw field of value v (shifted left by SH).
+    // The raw field of value v (shifted left by SH; with SH > 0 the low SH
+    // bits are left as they come, see stream_draws).
     __device__ __forceinline__ FT field(const StreamAt& r01, int v) {
         const int o = N * v;
         const int b = (o + N - 1) / 128;                    // the block of the field's last bit
@@ -446,12 +462,11 @@ struct MaskReader {
             cur = r01.block(TAG_MASK, (uint32_t)b);
         }
         if constexpr (D::SH > 0) {
-            constexpr uint32_t KEEP = ~((1u << D::SH) - 1);
             const int lo = o + N - 32;              // the field is the top of the word [lo, lo + 32)
             if (lo < 0) return word(0, b) << D::SH;
             const int k = lo / 32, s = lo % 32;
-            if (s == 0) return word(k, b) & KEEP;
-            return __builtin_amdgcn_alignbit(word(k + 1, b), word(k, b), s) & KEEP;
+            if (s == 0) return word(k, b);
+            return __builtin_amdgcn_alignbit(word(k + 1, b), word(k, b), s);
         } else if constexpr (D::WIDE) {
             const int k = o / 32, s = o % 32;       // 33 bits: always two words
             return (join64(word(k, b), word(k + 1, b)) >> s) & ((1ull << N) - 1);
@@ -485,10 +500,9 @@ __device__ __forceinline__ typename F::T stream_field_at(const uint32_t* W, uint
     using D = MaskDraws<N, F>;
     const int o = N * (int)v;
     if constexpr (D::SH > 0) {
-        constexpr uint32_t KEEP = ~((1u << D::SH) - 1);
         const int lo = o + N - 32;                  // > -32
         const int k = ((lo + 32) >> 5) - 1;         // floor(lo / 32): -1 for v = 0
-        return __builtin_amdgcn_alignbit(W[k + 1], W[k], (uint32_t)lo & 31u) & KEEP;
+        return __builtin_amdgcn_alignbit(W[k + 1], W[k], (uint32_t)lo & 31u);   // low SH bits as they come
     } else if constexpr (D::WIDE) {
         const int k = o >> 5;
         return (join64(W[k], W[k + 1]) >> (o & 31)) & ((1ull << N) - 1);

@@ -46,7 +46,7 @@ __device__ __forceinline__ typename F::T party_message(T ak, uint32_t pos, typen
         return field_mul_add<SH>(f, s0, r, z);
     } else {
         const FT s1 = (f.p - 1) - ((Wv + un - 1) & WIN);             // v1 + p - 2^l_x, v1 = -(Wv + un)
-        return field_mul_add<SH>(f, s1, r, (FT)((f.p << SH) - z));
+        return field_mul_add<SH>(f, s1, r, reshare_neg<SH>(f, z));
     }
 }
 
