@@ -35,7 +35,7 @@ using vec_t = T __attribute__((ext_vector_type(V)));
 
 // Loads and stores of data that a call reads or writes once (shares,
 // records, messages), marked nontemporal: on gfx950 the truncation stream
-// went from 5.6 to 6.3 TB/s with them.
+// went from 5.6 to 6.2 TB/s with them.
 template <typename P>
 __device__ __forceinline__ P ld_nt(const P* p) {
     return __builtin_nontemporal_load(p);
