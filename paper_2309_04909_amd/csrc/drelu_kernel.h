@@ -652,20 +652,14 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const T* p, uint32_t
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(p), (short)0, (int)(n * (uint32_t)sizeof(T)), 0x00020000);
 }
 
-// One launch: grid-stride over its n <= kLaunchElems elements of one share
-// pair.  Each thread loads its next element's shares before computing the
-// current one, so the loads have a whole element's work to land: with other
-// traffic on the memory system (the truncation beside it), a load at the top
-// of each element stalled the kernel.
+// The loop of one k_drelu launch (see k_drelu), with the ring mask given.
 template <typename T, int N, typename F, bool RELU, bool CAP>
-__global__ BC_KERNEL_ATTRS void k_drelu(DreluKArgs A, F f_arg) {
-    const F f = f_arg.vgpr();
+__device__ __forceinline__ void drelu_launch_loop(const DreluKArgs& A, const F& f, T mask) {
     const T* X0 = static_cast<const T*>(A.x0);
     const T* X1 = static_cast<const T*>(A.x1);
     T* Y0 = static_cast<T*>(A.y0);
     T* Y1 = static_cast<T*>(A.y1);
     typename F::T* cap = static_cast<typename F::T*>(A.cap);
-    const T mask = in_vgpr((T)A.ring_mask);
     const uint32_t n = (uint32_t)A.n;
     const uint32_t stride = gridDim.x * blockDim.x;
     uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -688,6 +682,26 @@ __global__ BC_KERNEL_ATTRS void k_drelu(DreluKArgs A, F f_arg) {
         x0 = x0n;
         x1 = x1n;
     }
+}
+
+// One launch: grid-stride over its n <= kLaunchElems elements of one share
+// pair.  Each thread loads its next element's shares before computing the
+// current one, so the loads have a whole element's work to land: with other
+// traffic on the memory system (the truncation beside it), a load at the top
+// of each element stalled the kernel.
+template <typename T, int N, typename F, bool RELU, bool CAP>
+__global__ BC_KERNEL_ATTRS void k_drelu(DreluKArgs A, F f_arg) {
+    const F f = f_arg.vgpr();
+    // A full-width ring (l = 64 in 64-bit storage, l = 32 in 32-bit) makes
+    // every reduction mod 2^l a no-op: that loop runs with the mask as a
+    // constant, so the compiler drops the masking instructions.
+    if constexpr (!CAP) {
+        if ((T)A.ring_mask == (T)~(T)0) {
+            drelu_launch_loop<T, N, F, RELU, CAP>(A, f, (T)~(T)0);
+            return;
+        }
+    }
+    drelu_launch_loop<T, N, F, RELU, CAP>(A, f, in_vgpr((T)A.ring_mask));
 }
 
 // Lane groups for small calls: G consecutive lanes share one element, so a
