@@ -21,20 +21,15 @@ struct BatchKArgs {
 // come from the record, as in bc_drelu_pre / bc_relu_pre), with the same
 // per-segment input truncation.
 // Each block takes tiles blockIdx.x, blockIdx.x + gridDim.x, ... until
-// total_tiles: every wave reaches the exit.
+// total_tiles: every wave reaches the exit.  This is the walk, with the ring
+// mask given; k_batch below calls it.
 template <typename T, int N, typename F>
-__global__ BC_KERNEL_ATTRS void k_batch(const BatchPlanHeader* __restrict__ hdr,
-                                               const bc_segment* __restrict__ segs,
-                                               const uint64_t* __restrict__ tile_begin, BatchKArgs A, F f_arg) {
-    // The device plan must still be the one this launch was built from: a
-    // plan whose memory was freed and reused fails these checks, and then no
-    // block walks it.
-    if (hdr->magic != kBatchMagic || hdr->nseg != A.nseg || hdr->total_tiles != A.total_tiles) return;
-    const F f = f_arg.vgpr();
+__device__ __forceinline__ void batch_walk(const bc_segment* __restrict__ segs,
+                                           const uint64_t* __restrict__ tile_begin, const BatchKArgs& A, const F& f,
+                                           T mask) {
     const uint32_t nseg = A.nseg;
     const uint64_t total = A.total_tiles;
     const uint64_t tile = A.tile_elems;
-    const T mask = in_vgpr((T)A.ring_mask);
     for (uint64_t t = blockIdx.x; t < total; t += gridDim.x) {
         // segment of tile t: largest s with tile_begin[s] <= t (uniform search)
         uint32_t lo = 0, hi = nseg;
@@ -79,6 +74,23 @@ __global__ BC_KERNEL_ATTRS void k_batch(const BatchPlanHeader* __restrict__ hdr,
                                                      A.k_lo, s01, s02, s12, f);
         }
     }
+}
+
+// A full-width ring (l = 64 in 64-bit storage, l = 32 in 32-bit) walks the
+// tiles with the ring mask as a constant (see k_drelu).
+template <typename T, int N, typename F>
+__global__ BC_KERNEL_ATTRS void k_batch(const BatchPlanHeader* __restrict__ hdr,
+                                               const bc_segment* __restrict__ segs,
+                                               const uint64_t* __restrict__ tile_begin, BatchKArgs A, F f_arg) {
+    // The device plan must still be the one this launch was built from: a
+    // plan whose memory was freed and reused fails these checks, and then no
+    // block walks it.
+    if (hdr->magic != kBatchMagic || hdr->nseg != A.nseg || hdr->total_tiles != A.total_tiles) return;
+    const F f = f_arg.vgpr();
+    if ((T)A.ring_mask == (T)~(T)0)
+        batch_walk<T, N, F>(segs, tile_begin, A, f, (T)~(T)0);
+    else
+        batch_walk<T, N, F>(segs, tile_begin, A, f, in_vgpr((T)A.ring_mask));
 }
 
 template <typename T, int N, typename F>
