@@ -488,7 +488,8 @@ uint64_t bc_batch_plan_bytes(uint32_t nseg);
 /* Host only.  Validates every segment against `prm` (one setting for the
  * whole batch) and writes the plan into host memory `plan`, of plan_bytes
  * bytes.  Each segment is cut into tiles of tile_elems elements (0 = default
- * 1024).  The caller then copies the plan, byte for byte, to device memory
+ * 1024; at most 2^20, so that a tile is indexed in 32 bits; BC_ERR_ARG
+ * above).  The caller then copies the plan, byte for byte, to device memory
  * it owns.  nseg in [1, 2^20]. */
 int bc_batch_plan(const bc_segment* segs, uint32_t nseg, const bc_drelu_params* prm, uint32_t tile_elems,
                   void* plan, uint64_t plan_bytes);

@@ -395,6 +395,7 @@ int batch_plan(const bc_segment* segs, uint32_t nseg, const bc_drelu_params* prm
     int rc = check_params(prm, &r);
     if (rc) return rc;
     if (tile_elems == 0) tile_elems = 1024;
+    if (tile_elems > (1u << 20)) return fail(BC_ERR_ARG, "tile_elems = %u above 2^20", tile_elems);
     const uint32_t w = width_of_ring(r.ell);
     uint8_t* base = static_cast<uint8_t*>(plan);
     bc::BatchPlanHeader* h = reinterpret_cast<bc::BatchPlanHeader*>(base);

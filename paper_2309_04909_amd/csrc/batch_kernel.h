@@ -13,6 +13,36 @@ struct BatchKArgs {
     uint32_t k01a, k01b, k02a, k02b, k12a, k12b;
 };
 
+// The fused elements [e0, e1) of one tile (at most a tile's elements, so
+// 32-bit offsets from the tile's start): each thread walks its elements with
+// the next one's shares loaded before the current one is computed (raw
+// buffer loads over the tile, which read 0 past its end), as k_drelu does.
+template <typename T, int N, typename F, bool RELU>
+__device__ __forceinline__ void tile_elements(const T* X0, const T* X1, T* Y0, T* Y1, uint64_t e0, uint64_t e1,
+                                              uint64_t base, T mask, T in_mask, uint32_t k_in, uint32_t k_lo,
+                                              const Stream& s01, const Stream& s02, const Stream& s12, const F& f) {
+    const uint32_t m = (uint32_t)(e1 - e0);
+    uint32_t i = threadIdx.x;
+    if (i >= m) return;
+    const T* x0 = X0 + e0;
+    const T* x1 = X1 + e0;
+    const __amdgpu_buffer_rsrc_t B0 = buffer_of(x0, m), B1 = buffer_of(x1, m);
+    T a0 = load_at(x0, i), a1 = load_at(x1, i);
+    for (;;) {
+        const uint32_t in = i + blockDim.x;
+        const T a0n = load_buf<T>(B0, in), a1n = load_buf<T>(B1, in);
+        T y0, y1;
+        drelu_element_of<T, N, F, RELU, false>(a0, a1, y0, y1, nullptr, 0, e0 + i, base + e0 + i, mask, in_mask, k_in,
+                                               k_lo, s01, s02, s12, f);
+        store_at(Y0 + e0, i, y0);
+        store_at(Y1 + e0, i, y1);
+        if (in >= m) break;
+        i = in;
+        a0 = a0n;
+        a1 = a1n;
+    }
+}
+
 // Ragged batch: a persistent grid walks the tiles of every segment.  Tile t
 // belongs to the segment s with tile_begin[s] <= t < tile_begin[s + 1]; each
 // segment has its own op, nonce and global element offset, so every element
@@ -65,13 +95,9 @@ __device__ __forceinline__ void batch_walk(const bc_segment* __restrict__ segs,
                                                              k_in, A.k_lo, s02, s12, f);
             }
         } else if (S.op == BC_OP_RELU) {
-            for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x)
-                drelu_element<T, N, F, true, false>(X0, X1, Y0, Y1, nullptr, 0, e, base + e, mask, in_mask, k_in,
-                                                    A.k_lo, s01, s02, s12, f);
+            tile_elements<T, N, F, true>(X0, X1, Y0, Y1, e0, e1, base, mask, in_mask, k_in, A.k_lo, s01, s02, s12, f);
         } else {
-            for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x)
-                drelu_element<T, N, F, false, false>(X0, X1, Y0, Y1, nullptr, 0, e, base + e, mask, in_mask, k_in,
-                                                     A.k_lo, s01, s02, s12, f);
+            tile_elements<T, N, F, false>(X0, X1, Y0, Y1, e0, e1, base, mask, in_mask, k_in, A.k_lo, s01, s02, s12, f);
         }
     }
 }

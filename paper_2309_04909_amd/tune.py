@@ -220,7 +220,7 @@ def tune_batch(reps, batch=8):
         segs.append(BT.Segment(x0, x1, torch.empty_like(x0), torch.empty_like(x1), op=B.BC_OP_RELU, nonce=i))
     best = None
     for tile in TILES:
-        for bpc in (2, 4, 8, 16, 32):
+        for bpc in (4, 8, 16, 32, 64, 128):
             B.set_schedule("batch", 8, bpc, 8, 0)
             rb = BT.RaggedBatch(prm, B.Seeds(1, 2, 3), segs, tile_elems=tile)
             ms = _time(rb.run, reps)

@@ -169,6 +169,8 @@ def test_batch_plan_validation_on_host():
     assert list(tb) == [0, 5, 5]                                  # ceil(5000 / 1024) tiles, then the empty one
     assert L.bc_batch_plan(seg, 2, ctypes.byref(prm), 1024, buf, nbytes - 1) == -7
     assert L.bc_batch_plan(seg, 0, ctypes.byref(prm), 1024, buf, nbytes) == -8
+    assert L.bc_batch_plan(seg, 2, ctypes.byref(prm), 1 << 20, buf, nbytes) == 0    # the largest tile
+    assert L.bc_batch_plan(seg, 2, ctypes.byref(prm), (1 << 20) + 1, buf, nbytes) == -8
     seg[1].op = 5
     assert L.bc_batch_plan(seg, 2, ctypes.byref(prm), 1024, buf, nbytes) == -8
     seg[1].op = B.BC_OP_DRELU
