@@ -177,19 +177,31 @@ __device__ __forceinline__ void drelu_pre_element(const T* __restrict__ X0, cons
 
 // Online call: grid-stride over the n elements of one share pair.
 template <typename T, int N, typename F, bool RELU, bool CAP>
-__global__ BC_KERNEL_ATTRS void k_drelu_pre(PreKArgs A, F f_arg) {
-    const F f = f_arg.vgpr();
+__device__ __forceinline__ void drelu_pre_loop(const PreKArgs& A, const F& f, T mask) {
     const T* X0 = static_cast<const T*>(A.x0);
     const T* X1 = static_cast<const T*>(A.x1);
     T* Y0 = static_cast<T*>(A.y0);
     T* Y1 = static_cast<T*>(A.y1);
     typename F::T* cap = static_cast<typename F::T*>(A.cap);
     const RecordView<T> R{A.perm, static_cast<const uint64_t*>(A.rz), static_cast<const T*>(A.tail), A.n};
-    const T mask = in_vgpr((T)A.ring_mask);
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < A.n; e += stride)
         drelu_pre_element<T, N, F, RELU, CAP>(X0, X1, Y0, Y1, cap, R, e, A.elem_base + e, mask, mask, 0, A.k_lo,
                                               A.s02, A.s12, f);
+}
+
+// On a full-width ring the loop runs with the ring mask as a constant (see
+// k_drelu).
+template <typename T, int N, typename F, bool RELU, bool CAP>
+__global__ BC_KERNEL_ATTRS void k_drelu_pre(PreKArgs A, F f_arg) {
+    const F f = f_arg.vgpr();
+    if constexpr (!CAP) {
+        if ((T)A.ring_mask == (T)~(T)0) {
+            drelu_pre_loop<T, N, F, RELU, CAP>(A, f, (T)~(T)0);
+            return;
+        }
+    }
+    drelu_pre_loop<T, N, F, RELU, CAP>(A, f, in_vgpr((T)A.ring_mask));
 }
 
 template <typename T, int N, typename F>

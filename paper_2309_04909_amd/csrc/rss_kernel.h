@@ -120,8 +120,7 @@ __device__ __forceinline__ void rss_element(const RssKArgs& A, const T* __restri
 
 // One call: grid-stride over the n elements of one share triple.
 template <typename T, int N, typename F, bool RELU, bool CAP>
-__global__ BC_KERNEL_ATTRS void k_rss(RssKArgs A, F f_arg) {
-    const F f = f_arg.vgpr();
+__device__ __forceinline__ void rss_loop(const RssKArgs& A, const F& f, T mask) {
     const T* X0 = static_cast<const T*>(A.x0);
     const T* X1 = static_cast<const T*>(A.x1);
     const T* X2 = static_cast<const T*>(A.x2);
@@ -129,10 +128,23 @@ __global__ BC_KERNEL_ATTRS void k_rss(RssKArgs A, F f_arg) {
     T* Y1 = static_cast<T*>(A.y1);
     T* Y2 = static_cast<T*>(A.y2);
     typename F::T* cap = static_cast<typename F::T*>(A.cap);
-    const T mask = in_vgpr((T)A.ring_mask);
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < A.n; e += stride)
         rss_element<T, N, F, RELU, CAP>(A, X0, X1, X2, Y0, Y1, Y2, cap, e, A.elem_base + e, mask, f);
+}
+
+// On a full-width ring the loop runs with the ring mask as a constant (see
+// k_drelu).
+template <typename T, int N, typename F, bool RELU, bool CAP>
+__global__ BC_KERNEL_ATTRS void k_rss(RssKArgs A, F f_arg) {
+    const F f = f_arg.vgpr();
+    if constexpr (!CAP) {
+        if ((T)A.ring_mask == (T)~(T)0) {
+            rss_loop<T, N, F, RELU, CAP>(A, f, (T)~(T)0);
+            return;
+        }
+    }
+    rss_loop<T, N, F, RELU, CAP>(A, f, in_vgpr((T)A.ring_mask));
 }
 
 inline Stream stream_of(const StreamKey& k) { return Stream{k.k0, k.k1, k.n0, k.n1}; }
