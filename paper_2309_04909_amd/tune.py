@@ -33,18 +33,25 @@ BPC = [1, 2, 4, 8, 16, 32, 64]
 TILES = [256, 512, 1024, 2048, 4096, 8192]
 
 
-def _time(fn, reps=10, warm=2):
+def _time(fn, reps=10, warm=2, rounds=3):
+    """Milliseconds per call: the best of `rounds` timings of `reps` calls
+    (a single round caught clock ramps and let close candidates swap places
+    between tuning runs)."""
     for _ in range(warm):
         fn()
     torch.cuda.synchronize()
     a = torch.cuda.Event(enable_timing=True)
     b = torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(reps):
-        fn()
-    b.record()
-    torch.cuda.synchronize()
-    return a.elapsed_time(b) / reps
+    best = None
+    for _ in range(rounds):
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        best = ms if best is None or ms < best else best
+    return best
 
 
 def _time_graph(fn, reps=20, replays=5):
@@ -209,27 +216,36 @@ def tune_stream(n, reps):
              "n": n}]
 
 
-def tune_batch(reps, batch=8):
-    """ResNet-18-shaped ragged batch (l = 64, l_x = 7): tile size x grid."""
+def tune_batch(reps, batches=(1, 32)):
+    """ResNet-18-shaped ragged batch (l = 64, l_x = 7): tile size x grid,
+    timed at each batch size and chosen by the summed time relative to each
+    size's best (large tiles suit batch 32 and starve batch 1)."""
     from . import batch as BT
     import workloads as W
     prm = B.Params(64, 7, 11)
-    segs = []
-    for i, n in enumerate(W.resnet18_sizes(batch)):
-        x0, x1 = _shares(n, 64, 100 + i)
-        segs.append(BT.Segment(x0, x1, torch.empty_like(x0), torch.empty_like(x1), op=B.BC_OP_RELU, nonce=i))
-    best = None
-    for tile in TILES:
-        for bpc in (4, 8, 16, 32, 64, 128):
-            B.set_schedule("batch", 8, bpc, 8, 0)
-            rb = BT.RaggedBatch(prm, B.Seeds(1, 2, 3), segs, tile_elems=tile)
-            ms = _time(rb.run, reps)
-            print(f"  batch tile={tile:5d} bpc={bpc:3d}: {ms:.3f} ms", flush=True)
-            if best is None or ms < best[2]:
-                best = (tile, bpc, ms)
-    B.set_schedule("batch", 8, best[1], 8, 0)
-    return [{"kind": "batch", "npos": 8, "width": 8, "op": 0, "blocks_per_cu": best[1], "ms": round(best[2], 4)}], \
-        best[0]
+    times = {}
+    for batch in batches:
+        segs = []
+        for i, n in enumerate(W.resnet18_sizes(batch)):
+            x0, x1 = _shares(n, 64, 100 + i)
+            segs.append(BT.Segment(x0, x1, torch.empty_like(x0), torch.empty_like(x1), op=B.BC_OP_RELU, nonce=i))
+        for tile in TILES:
+            for bpc in (4, 8, 16, 32, 64, 128):
+                B.set_schedule("batch", 8, bpc, 8, 0)
+                rb = BT.RaggedBatch(prm, B.Seeds(1, 2, 3), segs, tile_elems=tile)
+                ms = _time(rb.run, reps)
+                times[(batch, tile, bpc)] = ms
+                print(f"  batch {batch:2d} tile={tile:5d} bpc={bpc:3d}: {ms:.3f} ms", flush=True)
+        del segs
+    low = {b: min(v for (bb, _, _), v in times.items() if bb == b) for b in batches}
+    score = {}
+    for (b, tile, bpc), ms in times.items():
+        score[(tile, bpc)] = score.get((tile, bpc), 0.0) + ms / low[b]
+    tile, bpc = min(score, key=score.get)
+    B.set_schedule("batch", 8, bpc, 8, 0)
+    ms = times[(max(batches), tile, bpc)]
+    return [{"kind": "batch", "npos": 8, "width": 8, "op": 0, "blocks_per_cu": bpc, "ms": round(ms, 4),
+             "batches": list(batches)}], tile
 
 
 def main():
@@ -240,7 +256,7 @@ def main():
     if not torch.cuda.is_available():
         print("the autotuner needs a GPU", file=sys.stderr)
         sys.exit(2)
-    n = 1 << (21 if a.quick else 23)
+    n = 1 << (21 if a.quick else 24)              # the size bench.py times
     reps = 5 if a.quick else 10
     t0 = time.time()
     grid = []
